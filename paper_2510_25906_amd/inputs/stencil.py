@@ -1,0 +1,370 @@
+"""Seeded stencil construction: central, directional and MUSCL stencils.
+
+The paper builds its central stencil with the stencil-based compact (SBC)
+algorithm, which it only cites (Section 2.1, after the definition of the
+central stencil); its directional stencils are lower-order stencils contained
+in the central one (Section 2.3), and neither construction is given.  These
+builders follow fixed rules instead (listed in the design notes):
+
+* central: grow face-neighbour layers over periodic images until at least
+  ``2M`` candidates are known, force-include every face neighbour, then take
+  the ``M`` nearest by centroid distance; ties break on the quantised relative
+  offset, then on the cell id, so uniform meshes get translation-invariant
+  stencils.  ``M = 2K`` where K is the number of non-constant unknowns of a
+  degree-r polynomial in d dimensions (Section 2.1, definition of K(r, d)).
+* directional: one per face; members are central-stencil cells whose centroid
+  lies in the cone (sector in 2D) spanned from the cell centroid by the face,
+  the face neighbour first, nearest first, filled from the half-space beyond
+  the face and then from the rest of the central stencil up to ``2d``.
+* MUSCL: the face neighbours, padded with the nearest central members up to
+  ``d + 1`` cells.
+
+Every stencil entry is a pair (cell id, periodic image shift); the image
+shift multiplies the mesh period.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from math import comb
+
+import numpy as np
+
+from .mesh import Mesh, simplex_decomposition, TYPE_NVTX, CELL_FACES
+
+
+def n_unknowns(r: int, d: int) -> int:
+    """Number of non-constant coefficients of a degree-r polynomial in d dims."""
+    return comb(r + d, d) - 1
+
+
+def nf_max(d: int) -> int:
+    return 4 if d == 2 else 6
+
+
+@dataclass
+class Stencils:
+    r: int
+    M: int
+    Md: int
+    central: np.ndarray        # int32 [N, M]
+    central_shift: np.ndarray  # int8 [N, M, d]
+    dir: np.ndarray            # int32 [N, NFMAX, Md]
+    dir_shift: np.ndarray      # int8 [N, NFMAX, Md, d]
+    n_dir: np.ndarray          # int32 [N] number of directional stencils (= faces)
+    muscl: np.ndarray          # int32 [N, NFMAX]
+    muscl_shift: np.ndarray    # int8 [N, NFMAX, d]
+    n_muscl: np.ndarray        # int32 [N]
+
+
+def cell_centroids(mesh: Mesh):
+    """Volume-weighted centroids and volumes from the simplex tiling."""
+    d = mesh.dim
+    N = mesh.n_cells
+    cen = np.zeros((N, d))
+    vol = np.zeros(N)
+    for t in np.unique(mesh.cell_type):
+        cells = np.nonzero(mesh.cell_type == t)[0]
+        nv = TYPE_NVTX[int(t)]
+        cv = np.stack([mesh.cell_vtx[mesh.cell_vtx_off[cells] + k] for k in range(nv)], 1)
+        X = mesh.vertices[cv]  # [n, nv, d]
+        acc_v = np.zeros(cells.size)
+        acc_c = np.zeros((cells.size, d))
+        for simp in simplex_decomposition(int(t)):
+            P = X[:, list(simp)]
+            J = P[:, 1:] - P[:, :1]
+            v = np.abs(np.linalg.det(J)) / (2.0 if d == 2 else 6.0)
+            acc_v += v
+            acc_c += v[:, None] * P.mean(1)
+        vol[cells] = acc_v
+        cen[cells] = acc_c / acc_v[:, None]
+    return cen, vol
+
+
+def _adjacency(mesh: Mesh):
+    fc = mesh.face_cells.astype(np.int64)
+    inner = fc[:, 1] >= 0
+    l, r = fc[inner, 0], fc[inner, 1]
+    sh = mesh.face_shift[inner].astype(np.int64)
+    src = np.concatenate([l, r])
+    dst = np.concatenate([r, l])
+    ssh = np.concatenate([sh, -sh])
+    order = np.lexsort((dst, src))
+    src, dst, ssh = src[order], dst[order], ssh[order]
+    off = np.zeros(mesh.n_cells + 1, np.int64)
+    np.add.at(off, src + 1, 1)
+    return np.cumsum(off), dst, ssh
+
+
+_SB = 5  # bits per shift component
+
+
+def _encode(s, c, sh, d):
+    k = (s.astype(np.int64) << 22) | c.astype(np.int64)
+    for j in range(d):
+        k = (k << _SB) | ((sh[:, j] + (1 << (_SB - 1))) & ((1 << _SB) - 1))
+    return k
+
+
+def _decode(k, d):
+    sh = np.zeros((k.shape[0], d), np.int64)
+    for j in range(d - 1, -1, -1):
+        sh[:, j] = (k & ((1 << _SB) - 1)) - (1 << (_SB - 1))
+        k = k >> _SB
+    c = k & ((1 << 22) - 1)
+    s = k >> 22
+    return s, c, sh
+
+
+def _degenerate(take, s_all, off, h, d, r, N, M):
+    """Cells whose selected centroids cannot separate the degree-r monomials."""
+    exps = [e for e in np.ndindex(*([r + 1] * d)) if 1 <= sum(e) <= r]
+    o = off[take] / h[s_all[take]][:, None]
+    order = np.argsort(s_all[take], kind="stable")
+    o = o[order].reshape(N, M, d)
+    V = np.ones((N, M, len(exps)))
+    for k, e in enumerate(exps):
+        for j in range(d):
+            V[:, :, k] *= o[:, :, j] ** e[j]
+    bad = np.zeros(N, bool)
+    for a in range(0, N, 65536):
+        sv = np.linalg.svd(V[a:a + 65536], compute_uv=False)
+        bad[a:a + 65536] = sv[:, -1] < 1e-6 * sv[:, 0]
+    return bad
+
+
+def build_stencils(mesh: Mesh, r: int) -> Stencils:
+    d = mesh.dim
+    N = mesh.n_cells
+    if N >= (1 << 21):
+        raise ValueError("stencil builder supports fewer than 2^21 cells")
+    K = n_unknowns(r, d)
+    M = 2 * K
+    Md = 2 * d
+    NF = nf_max(d)
+    cen, vol = cell_centroids(mesh)
+    h = vol ** (1.0 / d)
+    period = mesh.period if mesh.period is not None else np.zeros(d)
+    adj_off, adj_dst, adj_sh = _adjacency(mesh)
+    deg = np.diff(adj_off)
+
+    # ---- breadth-first growth over (cell, image) pairs ----------------------
+    ids = np.arange(N, dtype=np.int64)
+    visited = _encode(ids, ids, np.zeros((N, d), np.int64), d)
+    layer_keys = [visited]
+    layer_ids = [np.zeros(N, np.int64)]
+    front_s, front_c, front_sh = ids, ids, np.zeros((N, d), np.int64)
+    count = np.ones(N, np.int64)
+    target = 2 * M + 1
+    for layer in range(1, 64):
+        need = count[front_s] < target
+        fs, fcc, fsh = front_s[need], front_c[need], front_sh[need]
+        if fs.size == 0:
+            break
+        rep = deg[fcc]
+        es = np.repeat(fs, rep)
+        esh = np.repeat(fsh, rep, axis=0)
+        starts = np.repeat(adj_off[fcc], rep)
+        within = np.arange(es.size) - np.repeat(np.cumsum(rep) - rep, rep)
+        eidx = starts + within
+        ec = adj_dst[eidx]
+        esh = esh + adj_sh[eidx]
+        keys = np.unique(_encode(es, ec, esh, d))
+        keys = keys[~np.isin(keys, visited, assume_unique=True)]
+        if keys.size == 0:
+            break
+        visited = np.union1d(visited, keys)
+        layer_keys.append(keys)
+        layer_ids.append(np.full(keys.size, layer, np.int64))
+        front_s, front_c, front_sh = _decode(keys, d)
+        count = np.bincount(_decode(visited, d)[0], minlength=N)
+    all_keys = np.concatenate(layer_keys)
+    all_layer = np.concatenate(layer_ids)
+    s_all, c_all, sh_all = _decode(all_keys, d)
+    self_mask = (s_all == c_all) & np.all(sh_all == 0, axis=1)
+    s_all, c_all, sh_all, hop = s_all[~self_mask], c_all[~self_mask], sh_all[~self_mask], all_layer[~self_mask]
+    if np.any(np.bincount(s_all, minlength=N) < M):
+        raise ValueError("mesh too small for a central stencil of %d cells" % M)
+
+    off = cen[c_all] + sh_all * period - cen[s_all]
+    hs = h[s_all][:, None]
+    qoff = np.rint(off / hs * 1e6).astype(np.int64)
+    qd = np.rint((off ** 2).sum(1) / hs[:, 0] ** 2 * 1e8).astype(np.int64)
+    # forced face neighbours
+    fn_key = _encode(np.repeat(ids, deg), adj_dst, adj_sh, d)
+    forced = np.isin(_encode(s_all, c_all, sh_all, d), fn_key)
+
+    def select(primary):
+        sort_keys = [c_all] + [qoff[:, j] for j in range(d - 1, -1, -1)] + [qd, primary, ~forced, s_all]
+        order = np.lexsort(tuple(sort_keys))
+        s_o = s_all[order]
+        first = np.searchsorted(s_o, ids)
+        rank = np.arange(s_o.size) - first[s_o]
+        return order[rank < M]
+
+    take = select(np.zeros_like(hop))
+    if mesh.period is None or np.any(mesh.face_cells[:, 1] < 0):
+        # one-sided stencils at boundaries can be degenerate (e.g. too few cell
+        # layers normal to a wall): rebuild those greedily, nearest first,
+        # accepting a candidate only while it adds a new direction in the space
+        # of degree-r monomials of the centroid offsets, then fill by distance
+        bad = np.nonzero(_degenerate(take, s_all, off, h, d, r, N, M))[0]
+        if bad.size:
+            order = np.lexsort(tuple([c_all] + [qoff[:, j] for j in range(d - 1, -1, -1)]
+                                     + [qd, ~forced, s_all]))
+            s_o = s_all[order]
+            starts = np.searchsorted(s_o, bad)
+            ends = np.searchsorted(s_o, bad, side="right")
+            exps = [e for e in np.ndindex(*([r + 1] * d)) if 1 <= sum(e) <= r]
+            repl = {}
+            for c, a, b in zip(bad, starts, ends):
+                cand = order[a:b]
+                o = off[cand] / h[c]
+                V = np.ones((cand.size, len(exps)))
+                for k, e in enumerate(exps):
+                    for j in range(d):
+                        V[:, k] *= o[:, j] ** e[j]
+                Qb = np.zeros((0, len(exps)))
+                chosen = []
+                for t in range(cand.size):
+                    if forced[cand[t]] or Qb.shape[0] < len(exps):
+                        v = V[t] - Qb.T @ (Qb @ V[t])
+                        nv = np.linalg.norm(v)
+                        if forced[cand[t]] or nv > 1e-6 * np.linalg.norm(V[t]):
+                            chosen.append(t)
+                            if nv > 1e-6 * np.linalg.norm(V[t]) and Qb.shape[0] < len(exps):
+                                Qb = np.vstack([Qb, v / nv])
+                for t in range(cand.size):
+                    if len(chosen) >= M:
+                        break
+                    if t not in chosen:
+                        chosen.append(t)
+                repl[int(c)] = cand[np.array(sorted(chosen[:M]))]
+            keep = ~np.isin(s_all[take], bad)
+            take = np.concatenate([take[keep]] + [repl[int(c)] for c in bad])
+            take = take[np.argsort(s_all[take], kind="stable")]
+    sel_s, sel_c, sel_sh = s_all[take], c_all[take], sh_all[take]
+    sel_qd, sel_qoff = qd[take], qoff[take]
+    # final nearest-first order
+    sort_keys = [sel_c] + [sel_qoff[:, j] for j in range(d - 1, -1, -1)] + [sel_qd, sel_s]
+    o2 = np.lexsort(tuple(sort_keys))
+    central = sel_c[o2].reshape(N, M).astype(np.int32)
+    central_shift = sel_sh[o2].reshape(N, M, d).astype(np.int8)
+    coff = (cen[central] + central_shift * period - cen[:, None, :])  # [N, M, d]
+
+    # ---- face data per cell (in cell_face order) -----------------------------
+    nfc = np.diff(mesh.cell_face_off)
+    fverts_rel = np.zeros((N, NF, 4, d))   # face vertices relative to cell centroid
+    f_nverts = np.zeros((N, NF), np.int64)
+    f_valid = np.zeros((N, NF), bool)
+    f_nbr = np.full((N, NF), -1, np.int64)
+    f_nbr_sh = np.zeros((N, NF, d), np.int64)
+    for k in range(NF):
+        has = nfc > k
+        cells = np.nonzero(has)[0]
+        f = mesh.cell_face[mesh.cell_face_off[cells] + k]
+        side = mesh.cell_face_side[mesh.cell_face_off[cells] + k]
+        f_valid[cells, k] = True
+        nv = np.diff(mesh.face_vtx_off)[f]
+        f_nverts[cells, k] = nv
+        for j in range(4):
+            ok = nv > j
+            vv = mesh.face_vtx[mesh.face_vtx_off[f] + np.minimum(j, nv - 1)]
+            pos = mesh.vertices[vv]
+            # the right cell sees the face shifted back by its image
+            pos = pos - (side[:, None] == 1) * mesh.face_shift[f].astype(np.float64) * period
+            fverts_rel[cells, k, j] = np.where(ok[:, None], pos - cen[cells], 0.0)
+        l, rr = mesh.face_cells[f, 0], mesh.face_cells[f, 1]
+        nb = np.where(side == 0, rr, l)
+        nsh = np.where((side == 0)[:, None], mesh.face_shift[f], -mesh.face_shift[f].astype(np.int64))
+        f_nbr[cells, k] = nb
+        f_nbr_sh[cells, k] = np.where((nb >= 0)[:, None], nsh, 0)
+        # a right-side cell sees the face with reversed orientation
+        for n_ in (2, 3, 4):
+            sel = (side == 1) & (nv == n_)
+            if np.any(sel):
+                rc = cells[sel]
+                fverts_rel[rc, k, :n_] = fverts_rel[rc, k, :n_][:, ::-1]
+
+    # position of each face neighbour inside the central stencil
+    def member_pos(cell_ids, nb, nbsh):
+        eq = (central[cell_ids] == nb[:, None]) & np.all(central_shift[cell_ids] == nbsh[:, None, :], 2)
+        pos = np.argmax(eq, 1)
+        pos[~eq.any(1)] = -1
+        return pos
+
+    # ---- directional stencils ------------------------------------------------
+    dir_pos = np.zeros((N, NF, Md), np.int64)
+    tol = 1e-9
+    dist2 = (coff ** 2).sum(2)  # [N, M]
+    for k in range(NF):
+        cells = np.nonzero(f_valid[:, k])[0]
+        if cells.size == 0:
+            continue
+        V = fverts_rel[cells, k]  # [n, 4, d]
+        nv = f_nverts[cells, k]
+        P = coff[cells]           # [n, M, d]
+        inside = np.ones((cells.size, M), bool)
+        if d == 2:
+            a, b = V[:, 0], V[:, 1]
+            cr_a = a[:, None, 0] * P[:, :, 1] - a[:, None, 1] * P[:, :, 0]
+            cr_b = P[:, :, 0] * b[:, None, 1] - P[:, :, 1] * b[:, None, 0]
+            scale = (np.linalg.norm(a, axis=1) * np.linalg.norm(P, axis=2).T).T * tol
+            inside &= (cr_a >= -scale) & (cr_b >= -scale)
+            normal = np.stack([b[:, 1] - a[:, 1], a[:, 0] - b[:, 0]], 1)
+        else:
+            normal = np.zeros((cells.size, 3))
+            for j in range(4):
+                jn = (j + 1) % 4
+                vj = V[:, j]
+                vn = np.where((jn < nv)[:, None], V[:, jn % 4], V[:, 0])
+                use = j < nv
+                nk = np.cross(vj, vn)
+                normal += np.where(use[:, None], nk, 0.0)
+                dots = np.einsum("nd,nmd->nm", nk, P)
+                scale = np.linalg.norm(nk, axis=1)[:, None] * np.linalg.norm(P, axis=2) * tol
+                inside &= np.where(use[:, None], dots >= -scale, True)
+        half = np.einsum("nd,nmd->nm", normal, P) > 0
+        fpos = member_pos(cells, f_nbr[cells, k], f_nbr_sh[cells, k])
+        is_fn = np.zeros((cells.size, M), bool)
+        okf = fpos >= 0
+        is_fn[np.nonzero(okf)[0], fpos[okf]] = True
+        # priority: face neighbour, sector/cone, half-space, rest; then distance
+        pri = np.where(is_fn, 0, np.where(inside, 1, np.where(half, 2, 3)))
+        key = pri * 10 ** 12 + np.rint(dist2[cells] / (h[cells, None] ** 2) * 1e8).astype(np.int64)
+        # stable tie-break by stencil position (which is already nearest-first and deterministic)
+        o = np.argsort(key, axis=1, kind="stable")[:, :Md]
+        dir_pos[cells, k] = o
+    rows = np.arange(N)[:, None, None]
+    dir_ids = central[rows, dir_pos].astype(np.int32)
+    dir_sh = central_shift[rows, dir_pos].astype(np.int8)
+    n_dir = nfc.astype(np.int32)
+    for k in range(NF):
+        dir_ids[~f_valid[:, k], k] = -1
+        dir_sh[~f_valid[:, k], k] = 0
+
+    # ---- MUSCL stencils --------------------------------------------------------
+    muscl = np.full((N, NF), -1, np.int32)
+    muscl_sh = np.zeros((N, NF, d), np.int8)
+    n_muscl = np.zeros(N, np.int32)
+    has_nb = (f_nbr >= 0) & f_valid
+    # face neighbours first, in cell-face order
+    rank = np.cumsum(has_nb, axis=1) - 1
+    rr, kk = np.nonzero(has_nb)
+    muscl[rr, rank[rr, kk]] = f_nbr[rr, kk]
+    muscl_sh[rr, rank[rr, kk]] = f_nbr_sh[rr, kk]
+    n_muscl[:] = has_nb.sum(1)
+    for c in np.nonzero(n_muscl < d + 1)[0]:
+        lst = [(int(muscl[c, j]), tuple(int(x) for x in muscl_sh[c, j])) for j in range(n_muscl[c])]
+        for m in range(M):
+            cand = (int(central[c, m]), tuple(int(x) for x in central_shift[c, m]))
+            if cand not in lst:
+                lst.append(cand)
+            if len(lst) >= d + 1:
+                break
+        n_muscl[c] = len(lst)
+        for j, (cc, ss) in enumerate(lst):
+            muscl[c, j] = cc
+            muscl_sh[c, j] = ss
+    return Stencils(r=r, M=M, Md=Md, central=central, central_shift=central_shift,
+                    dir=dir_ids, dir_shift=dir_sh, n_dir=n_dir, muscl=muscl,
+                    muscl_shift=muscl_sh, n_muscl=n_muscl)

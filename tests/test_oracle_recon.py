@@ -1,0 +1,298 @@
+"""Pins of the oracle's reconstruction steps (Sections 2.1-2.5)."""
+import numpy as np
+import pytest
+
+from oracle import OracleModel, flux
+from oracle.reconstruction import monomials, LIN, CW, MU, FO
+from paper_2510_25906_amd.inputs import configs, fields
+from paper_2510_25906_amd.inputs.mesh import quad_tri_2d, hex_3d
+from paper_2510_25906_amd.inputs.stencil import build_stencils
+from paper_2510_25906_amd.inputs.params import Params, preset, ALL_CWENOZ, ALL_MUSCL, ALL_LINEAR
+
+
+def mixed_2d(n=12, frac=0.4, seed=0):
+    rng = np.random.default_rng(seed)
+    return quad_tri_2d(n, n, lo=(-0.5, -0.5), hi=(0.5, 0.5), split=rng.random((n, n)) < frac)
+
+
+def interior_cells(model, margin):
+    """Cells whose whole central stencil is at least ``margin`` cells away from the boundary."""
+    c = model.geo.cen
+    lo, hi = c.min(0), c.max(0)
+    span = (hi - lo).max()
+    return np.nonzero(np.all((c > lo + margin * span) & (c < hi - margin * span), axis=1))[0]
+
+
+@pytest.mark.parametrize("case", [("mixed2d", 2), ("mixed2d", 3), ("hex3d", 2), ("hex3d", 3)])
+def test_polynomial_exactness(case):
+    """Cell averages of a degree-r polynomial reproduce it exactly at the face points."""
+    kind, r = case
+    if kind == "mixed2d":
+        mesh = mixed_2d(12)
+    else:
+        mesh = hex_3d(7, 7, 7, lo=(-1, -1, -1), hi=(1, 1, 1))
+    st = build_stencils(mesh, r)
+    d = mesh.dim
+    _, _, ev = fields.random_polynomial(d, r, d + 2, seed=3)
+    U = fields.cell_average(mesh, ev, nq=r + 2)
+    om = OracleModel(mesh, st, Params(order_r=r))
+    cells = np.arange(mesh.n_cells)
+    _, fv, _ = om.linear(cells, U)
+    for i, c in enumerate(cells):
+        k = om.geo.c_ngp[c]
+        exact = ev(om.geo.c_x[c, :k])
+        assert np.allclose(fv[i, :k], exact, rtol=1e-9, atol=1e-9 * np.abs(exact).max())
+
+
+def test_basis_means_vanish_by_independent_quadrature():
+    """int over V_0' of phi_k = 0 (Section 2.1), checked with a Gauss rule."""
+    mesh = mixed_2d(6)
+    st = build_stencils(mesh, 3)
+    om = OracleModel(mesh, st, Params(order_r=3))
+    for t in (0, 1):
+        cells = np.nonzero(mesh.cell_type == t)[0][:5]
+        pts, w = fields.cell_quadrature(mesh, cells, 5)
+        tab = om.tables(cells)
+        xi = (pts - om.geo.cen[cells][:, None, :]) / om.geo.h[cells][:, None, None]
+        phi = monomials(xi, om.exps) - tab["psibar"][:, None, :]
+        integ = np.einsum("cqk,cq->ck", phi, w)
+        assert np.abs(integ).max() < 1e-13
+
+
+def test_smoothness_indicator_by_hand():
+    """SI of p = xi1^2 + 3 xi1 xi2 (Eq. SI1, reference-frame derivatives)."""
+    mesh = mixed_2d(6)
+    st = build_stencils(mesh, 2)
+    om = OracleModel(mesh, st, Params(order_r=2))
+    cells = np.array([0, 7, 20])
+    tab = om.tables(cells)
+    # coefficients in the hierarchical basis (xi1, xi2, xi1^2, xi1 xi2, xi2^2)
+    a = np.array([0.0, 0.0, 1.0, 3.0, 0.0])
+    si_oracle = np.einsum("k,nkq,q->n", a, tab["OI"], a)
+    for i, c in enumerate(cells):
+        pts, w = fields.cell_quadrature(mesh, np.array([c]), 6)
+        xi = (pts[0] - om.geo.cen[c]) / om.geo.h[c]
+        wx = w[0] / om.geo.h[c] ** 2
+        x1, x2 = xi[:, 0], xi[:, 1]
+        integrand = (2 * x1 + 3 * x2) ** 2 + (3 * x1) ** 2 + 2.0 ** 2 + 3.0 ** 2 + 0.0
+        assert si_oracle[i] == pytest.approx((integrand * wx).sum(), rel=1e-12)
+
+
+def test_cwenoz_reduces_to_linear_on_affine_data():
+    """Affine data: every candidate polynomial is the same plane, so SI_s are equal,
+    tau = 0 and the nonlinear weights are the linear weights (Section 2.3)."""
+    mesh = mixed_2d(10)
+    st = build_stencils(mesh, 3)
+    g = np.array([[0.3, -1.2, 0.7, 2.0], [1.1, 0.4, -0.5, 0.2]])
+    U = fields.cell_average(mesh, lambda p: np.array([2.0, 0.5, -0.3, 7.0]) + p @ g, nq=3)
+    om = OracleModel(mesh, st, Params(order_r=3, scheme_mode=ALL_CWENOZ))
+    cells = interior_cells(om, 0.25)
+    fv_cw, info = om.cwenoz(cells, U)
+    _, fv_lin, _ = om.linear(cells, U)
+    assert np.allclose(info["om1"], info["lam1"], rtol=0, atol=1e-12)
+    nd = st.n_dir[cells]
+    assert np.allclose(info["oms"][:, :3], (info["lams"])[:, None, None], atol=1e-12)
+    assert np.allclose(fv_cw, fv_lin, atol=1e-11)
+
+
+def test_cwenoz_weights_convex_and_mean_preserving():
+    w = configs.c1_density_jump(16, 2)
+    om = OracleModel(w.mesh, w.stencils, w.params.with_(scheme_mode=ALL_CWENOZ))
+    cells = np.arange(w.mesh.n_cells)
+    fv, info = om.cwenoz(cells, w.U)
+    tot = info["om1"] + info["oms"].sum(1)
+    assert np.allclose(tot, 1.0, atol=1e-14)
+    assert info["om1"].min() >= 0 and info["oms"].min() >= 0
+    # across the jump the central weight must drop well below lambda_1
+    assert info["om1"].min() < 0.5
+
+
+def test_nad_smooth_vortex_all_linear():
+    """Section 3.1 and Table 1: no troubled cells on the smooth isentropic vortex."""
+    for n in (16, 32, 64):
+        w = configs.vortex_2d(n, 2)
+        om = OracleModel(w.mesh, w.stencils, w.params)
+        cls, _ = om.cell_classes(np.arange(w.mesh.n_cells), w.U)
+        assert np.all(cls == LIN)
+
+
+def test_nad_step_tags_jump_cells():
+    w = configs.c1_density_jump(32, 2)
+    mesh = w.mesh
+    om = OracleModel(mesh, w.stencils, w.params)
+    cells = np.arange(mesh.n_cells)
+    cls, extra = om.cell_classes(cells, w.U)
+    # faces on the jump x = 0.5 (and the periodic wrap x = 0)
+    fx = np.array([mesh.vertices[mesh.face_vertices(f)][:, 0] for f in range(mesh.n_faces)])
+    on_jump = np.all(np.isclose(fx, 0.5), 1) | np.all(np.isclose(fx, 0.0), 1) | np.all(np.isclose(fx, 1.0), 1)
+    touching = np.unique(mesh.face_cells[on_jump].ravel())
+    assert np.all(cls[touching] >= CW)
+    # preset (d): linear and MUSCL only, the jump cells are MUSCL
+    om_d = OracleModel(mesh, w.stencils, w.params.with_(**dict(preset("d_linear_muscl").__dict__,
+                                                              order_r=2)))
+    cls_d, _ = om_d.cell_classes(cells, w.U)
+    assert np.all(cls_d[touching] == MU)
+    assert not np.any(cls_d == CW)
+    # dilation: a cell's class is at least its face neighbours' own class
+    own = extra["own"]
+    for j in range(om.nbr.shape[1]):
+        nb = om.nbr[:, j]
+        ok = nb >= 0
+        assert np.all(cls[ok] >= own[nb[ok]])
+
+
+@pytest.mark.parametrize("name", ["c_linear_cwenoz", "d_linear_muscl", "e_muscl_cwenoz"])
+def test_nad_presets(name):
+    """Section 2.5, Fig. NADMargin (c)-(e): each two-scheme preset removes one scheme."""
+    w = configs.c2_riemann(24, 3)
+    cells = np.arange(w.mesh.n_cells)
+    om = OracleModel(w.mesh, w.stencils, preset(name, order_r=3, kappa=0.0))
+    own, info = om.own_class(cells, w.U)
+    cls, _ = om.cell_classes(cells, w.U)
+    if name == "c_linear_cwenoz":
+        assert not np.any(cls == MU) and np.any(cls == CW)
+    if name == "d_linear_muscl":
+        assert not np.any(cls == CW) and np.any(cls == MU)
+    if name == "e_muscl_cwenoz":
+        # no linear cell unless every variable sits exactly at its interval midpoint
+        assert not np.any(own == LIN)
+
+
+def test_muscl_bj_bounds_and_affine_exactness():
+    w = configs.c1_density_jump(16, 2)
+    om = OracleModel(w.mesh, w.stencils, w.params.with_(scheme_mode=ALL_MUSCL))
+    cells = np.arange(w.mesh.n_cells)
+    fv, info = om.muscl(cells, w.U)
+    m, M = om.nad_bounds(cells, w.U)
+    assert np.all(fv >= m[:, None, :] - 1e-14) and np.all(fv <= M[:, None, :] + 1e-14)
+    assert np.all((info["theta"] >= 0) & (info["theta"] <= 1))
+    # uniform quads + affine data: the limiter is inactive
+    mesh = quad_tri_2d(8, 8, lo=(0, 0), hi=(1, 1))
+    st = build_stencils(mesh, 2)
+    U = fields.cell_average(mesh, lambda p: np.array([1.0, 0.2, 0.1, 3.0]) + p @ np.array(
+        [[0.5, 0.1, 0.0, 1.0], [0.25, 0.0, 0.3, -0.5]]), nq=3)
+    om2 = OracleModel(mesh, st, Params(order_r=2, scheme_mode=ALL_MUSCL))
+    inner = interior_cells(om2, 0.1)
+    _, info2 = om2.muscl(inner, U)
+    assert np.allclose(info2["theta"], 1.0, atol=1e-12)
+
+
+def test_harten_check_and_first_order_fallback():
+    w = configs.c1_density_jump(16, 2)
+    U = w.U.copy()
+    U[37, 0] = -0.5  # non-physical density in one cell
+    om = OracleModel(w.mesh, w.stencils, w.params)
+    fv, cls = om.reconstruct_cells(np.arange(w.mesh.n_cells), U)
+    assert cls[37] == FO
+    assert np.all(fv[37, :om.geo.c_ngp[37]] == U[37])
+    # every accepted reconstruction satisfies the bound on density and pressure
+    ok = cls != FO
+    g = w.params.gamma
+    rho = fv[..., 0]
+    rb = U[:, 0][:, None]
+    valid = np.arange(fv.shape[1])[None, :] < om.geo.c_ngp[:, None]
+    assert np.all(~valid[ok] | (np.abs(rho - rb)[ok] <= 0.9 * np.abs(rb)[ok] + 1e-15))
+
+
+def test_free_stream_preservation():
+    w = configs.c2_riemann(16, 3)
+    U = np.tile(fields.prim_to_cons(np.array([1.3, 0.4, -0.2, 2.0])), (w.mesh.n_cells, 1))
+    om = OracleModel(w.mesh, w.stencils, w.params)
+    R, fs, cls = flux.residual(om, U)
+    assert np.all(cls == LIN)
+    assert np.allclose(fs, U[0][None, :, None], rtol=0, atol=1e-13)
+    assert np.abs(R).max() < 1e-12
+
+
+def test_conservation_telescopes_on_periodic_mesh():
+    for w in (configs.c1_density_jump(16, 2), configs.vortex_2d(16, 3)):
+        om = OracleModel(w.mesh, w.stencils, w.params)
+        R, _, _ = flux.residual(om, w.U)
+        tot = (R * om.geo.vol[None, :]).sum(1)
+        assert np.abs(tot).max() < 1e-12 * np.abs(R * om.geo.vol).max() * w.mesh.n_cells
+
+
+@pytest.mark.parametrize("r", [2, 3])
+def test_convergence_order_smooth(r):
+    """Face-state error against exact point values decays at order r + 1."""
+    errs = []
+    ns = (16, 32, 64)
+    for n in ns:
+        w = configs.c1_density_jump(n, r, jump=False)
+        om = OracleModel(w.mesh, w.stencils, w.params.with_(scheme_mode=ALL_LINEAR))
+        cells = np.arange(w.mesh.n_cells)
+        _, fv, _ = om.linear(cells, w.U)
+        ex = fields.density_jump_2d(om.geo.c_x, jump=False)
+        e = np.abs(fv - ex)[..., 0]
+        errs.append(e.max())
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert orders[-1] > r + 1 - 0.3
+
+
+def test_independent_least_squares_brute_force():
+    """The linear coefficients equal a least-squares solve assembled with a Gauss
+    rule instead of the exact simplex integrals, and solved by QR."""
+    mesh = mixed_2d(8)
+    r = 3
+    st = build_stencils(mesh, r)
+    rng = np.random.default_rng(11)
+    U = rng.normal(size=(mesh.n_cells, 4))
+    om = OracleModel(mesh, st, Params(order_r=r))
+    cells = np.array([5, 30, 41])
+    a, fv, tab = om.linear(cells, U)
+    for i, c in enumerate(cells):
+        xc, h = om.geo.cen[c], om.geo.h[c]
+        pts0, w0 = fields.cell_quadrature(mesh, np.array([c]), 6)
+        xi0 = (pts0[0] - xc) / h
+        w0 = w0[0] / h ** 2
+        mean = (monomials(xi0, om.exps) * w0[:, None]).sum(0) / w0.sum()
+        rows, rhs = [], []
+        for m in st.central[c]:
+            pts, wq = fields.cell_quadrature(mesh, np.array([m]), 6)
+            xi = (pts[0] - xc) / h
+            wq = wq[0] / h ** 2
+            rows.append(((monomials(xi, om.exps) - mean) * wq[:, None]).sum(0))
+            rhs.append(wq.sum() * (U[m] - U[c]))
+        A = np.array(rows)
+        q_, r_ = np.linalg.qr(A)
+        sol = np.linalg.solve(r_, q_.T @ np.array(rhs))
+        assert np.allclose(sol, a[i], rtol=1e-10, atol=1e-10 * np.abs(sol).max())
+
+
+def test_rankine_hugoniot_matches_paper_post_shock_state():
+    path = __file__.replace("test_oracle_recon.py", "golden/shu_osher_post_shock.txt")
+    rho, u, p = np.loadtxt(path)
+    r2, u2, p2 = fields.rankine_hugoniot(3.0)
+    assert r2 == pytest.approx(rho, abs=1e-6)
+    assert u2 == pytest.approx(u, abs=1e-6)
+    assert p2 == pytest.approx(p, abs=1e-4)
+
+
+def test_riemann_states_match_paper():
+    path = __file__.replace("test_oracle_recon.py", "golden/riemann_2d_states.txt")
+    rows = [l.split() for l in open(path) if not l.startswith("#")]
+    for key, *vals in rows:
+        assert tuple(float(v) for v in vals) == fields.RIEMANN_2D[key]
+
+
+def test_hllc_hll_consistency_and_symmetry():
+    rng = np.random.default_rng(4)
+    for d in (2, 3):
+        prim = np.concatenate([rng.uniform(0.5, 2, (50, 1)), rng.normal(size=(50, d)),
+                               rng.uniform(0.5, 2, (50, 1))], 1)
+        UL = fields.prim_to_cons(prim)
+        prim2 = prim * rng.uniform(0.8, 1.2, prim.shape)
+        UR = fields.prim_to_cons(prim2)
+        n = rng.normal(size=(50, d))
+        n /= np.linalg.norm(n, axis=1, keepdims=True)
+        for fn in (flux.hllc, flux.hll):
+            assert np.allclose(fn(UL, UL, n, 1.4), flux.euler_flux(UL, n, 1.4), rtol=1e-13, atol=1e-13)
+            assert np.allclose(fn(UL, UR, n, 1.4), -fn(UR, UL, -n, 1.4), rtol=1e-12, atol=1e-12)
+        # supersonic to the right: the upwind (left) flux
+        prim_s = prim.copy()
+        prim_s[:, 1:1 + d] = 10.0 * n
+        prim_s2 = prim2.copy()
+        prim_s2[:, 1:1 + d] = 10.0 * n
+        Ls, Rs = fields.prim_to_cons(prim_s), fields.prim_to_cons(prim_s2)
+        for fn in (flux.hllc, flux.hll):
+            assert np.allclose(fn(Ls, Rs, n, 1.4), flux.euler_flux(Ls, n, 1.4), rtol=1e-13)
