@@ -1,0 +1,198 @@
+/*
+ * hfv.h -- C ABI of the MI355X hybrid finite-volume reconstruction library.
+ *
+ * The library implements the per-cell reconstruction stage of the hybrid
+ * scheme of Tong & Tsoutsanis, "A Hybrid Finite-Volume Reconstruction
+ * Framework for Efficient High-Order Shock-Capturing on Unstructured Meshes"
+ * (arXiv 2510.25906):
+ *   - linear least-squares reconstruction with per-cell pseudo-inverses
+ *     (Section 2.1, Eqs. AVGVariables1-dofMatrix),
+ *   - the single-step numerical admissibility detector, NAD (Section 2.5,
+ *     Eqs. DMP-NADDeactivatedCriteria_2) tagging each cell linear / CWENOZ /
+ *     MUSCL, with its von Neumann neighbourhood,
+ *   - CWENOZ on weakly non-smooth cells (Section 2.3),
+ *   - Barth-Jespersen limited MUSCL on discontinuous cells (Section 2.2),
+ *   - the Harten bound check with first-order fallback (Section 2.4,
+ *     Eq. harten_jump_fix),
+ *   - face Gauss-point states, HLLC / HLL fluxes and the residual
+ *     (Section 2, Eq. EulerEquationsDetails with F_v = 0).
+ *
+ * Conventions shared by every entry point:
+ *   - Status codes only; nothing throws or exits across the ABI.
+ *   - Host pointers (mesh, stencils, params) are read during the call and
+ *     not retained.  Device pointers are caller-owned and must stay valid
+ *     until the work enqueued on `stream` has completed.
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *     Hot calls only enqueue work; they never synchronise the host.
+ *   - Precision (64 or 32) is fixed at create; every device array of
+ *     conserved variables, states and residuals is double or float to match.
+ *   - Conserved variables are structure-of-arrays [nvar][n_cells] with
+ *     nvar = dim + 2: (rho, rho u, rho v[, rho w], E).
+ *   - Face states are [2][nvar][n_gp]: side 0 is the face's left cell
+ *     (face_cells[f][0]), side 1 its right cell; Gauss points are numbered
+ *     face by face in face order.  At boundary faces side 1 holds the
+ *     transmissive ghost state (a copy of side 0).
+ *   - A context is not thread-safe; calls that overlap on one context race.
+ */
+#ifndef HFV_H
+#define HFV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hfv_ctx hfv_ctx;
+
+typedef enum {
+  HFV_OK = 0,
+  HFV_ERR_PARAM = -1, /* invalid parameter value or NULL argument */
+  HFV_ERR_MESH = -2,  /* inconsistent mesh or stencil data */
+  HFV_ERR_RANK = -3,  /* a least-squares system is rank deficient / ill conditioned (cell id in last_error) */
+  HFV_ERR_DTYPE = -4, /* precision mismatch */
+  HFV_ERR_HIP = -5,   /* a HIP runtime call failed */
+  HFV_ERR_OOM = -6,   /* device allocation failed */
+  HFV_ERR_STATE = -7  /* call not valid in the context's state */
+} hfv_status;
+
+/* element types: local vertex orders
+ *   TRI (0,1,2) and QUAD (0,1,2,3) counter-clockwise; TET positively oriented;
+ *   PYR base (0..3) counter-clockwise seen from the apex 4; PRISM bottom (0,1,2),
+ *   top (3,4,5); HEX bottom (0..3), top (4..7).  Faces must be planar. */
+enum { HFV_TRI = 0, HFV_QUAD = 1, HFV_TET = 2, HFV_PYR = 3, HFV_PRISM = 4, HFV_HEX = 5 };
+/* scheme modes: the hybrid (Section 2.5) or one scheme everywhere */
+enum { HFV_HYBRID = 0, HFV_ALL_LINEAR = 1, HFV_ALL_CWENOZ = 2, HFV_ALL_MUSCL = 3 };
+enum { HFV_HLLC = 0, HFV_HLL = 1 };
+/* CWENOZ weight form: Z form w_s = l_s (1 + (tau/(eps+SI_s))^b) (default) or the
+ * printed placement l_s (1 + tau^b/(eps+SI_s)) of Section 2.3 */
+enum { HFV_WENOZ_POW = 0, HFV_LITERAL = 1 };
+/* cell classes written to cell_class[] */
+enum { HFV_CLASS_LINEAR = 0, HFV_CLASS_CWENOZ = 1, HFV_CLASS_MUSCL = 2, HFV_CLASS_FIRST_ORDER = 3 };
+
+/* Mesh (Section 2: mixed elements, faces with Gauss quadrature).
+ * face_vtx lists each face's vertices oriented so that the right-hand-rule
+ * normal points out of face_cells[f][0]; face_cells[f][1] = -1 marks a
+ * boundary face (transmissive ghost).  face_shift[f] (optional) gives the
+ * periodic image of the right cell: its coordinates plus face_shift[f]*period
+ * place it next to the left cell. */
+typedef struct {
+  int32_t dim, n_vertices, n_cells, n_faces;
+  const double *vertices;       /* [n_vertices][dim] */
+  const int8_t *cell_type;      /* [n_cells] */
+  const int32_t *cell_vtx_off;  /* [n_cells+1] */
+  const int32_t *cell_vtx;      /* [cell_vtx_off[n_cells]] */
+  const int32_t *face_cells;    /* [n_faces][2] */
+  const int32_t *face_vtx_off;  /* [n_faces+1] */
+  const int32_t *face_vtx;      /* [face_vtx_off[n_faces]] */
+  const int8_t *face_shift;     /* [n_faces][dim] or NULL */
+  const double *period;         /* [dim] or NULL (required when shifts are given) */
+} hfv_mesh;
+
+/* Stencils (Section 2.1 central stencil of M = 2K cells excluding the cell;
+ * Section 2.3 directional stencils, one per face, of Md = 2*dim cells
+ * contained in the central stencil; Section 2.2 MUSCL neighbours).  Every
+ * entry is a cell id plus an optional periodic image shift (multiplies
+ * period).  Padding entries are -1. */
+typedef struct {
+  int32_t M;                    /* central stencil size, must equal 2K */
+  int32_t nf_max;               /* row stride of dir / muscl: 4 in 2D, 6 in 3D */
+  int32_t Md;                   /* directional stencil size, must equal 2*dim */
+  const int32_t *central;       /* [n_cells][M] */
+  const int8_t *central_shift;  /* [n_cells][M][dim] or NULL */
+  const int32_t *dir;           /* [n_cells][nf_max][Md] */
+  const int8_t *dir_shift;      /* [n_cells][nf_max][Md][dim] or NULL */
+  const int32_t *n_dir;         /* [n_cells] directional stencils per cell */
+  const int32_t *muscl;         /* [n_cells][nf_max] */
+  const int8_t *muscl_shift;    /* [n_cells][nf_max][dim] or NULL */
+  const int32_t *n_muscl;       /* [n_cells] */
+} hfv_stencils;
+
+/* Parameters.  order_r is the polynomial degree r (order r+1, Section 2.1).
+ * NAD margins alpha/beta (Eqs. marginm, marginw), deactivation
+ * delta U < (kappa h_c)^n_exp (Eq. NADDeactivatedCriteria), CWENOZ lambda_1',
+ * eps, b (Section 2.3), Harten theta, eps (Eq. harten_jump_fix). */
+typedef struct {
+  int32_t order_r, scheme_mode, precision, riemann, cweno_form, reserved;
+  double gamma, alpha_m, beta_m, alpha_w, beta_w, kappa, n_exp, lambda1_prime, eps_w, b_w,
+      tvd_theta, tvd_eps;
+} hfv_params;
+
+/* Build a context: validates the mesh and stencils, uploads them, and
+ * computes on the GPU in FP64 the geometry, the exact least-squares
+ * matrices, their pseudo-inverses by Householder QR (computed once,
+ * Section 2.1), the directional and MUSCL pseudo-inverses and the
+ * oscillation-indicator matrices (Section 2.3); FP32 contexts then keep FP32
+ * copies.  Synchronises `stream` once at the end (rank report).
+ * Returns HFV_ERR_RANK (cell id in hfv_last_error) for a degenerate stencil.
+ * On success *out owns all device tables; release with hfv_destroy. */
+hfv_status hfv_create(const hfv_mesh *mesh, const hfv_stencils *st, const hfv_params *p, void *stream,
+                      hfv_ctx **out);
+
+/* Change run-time parameters (scheme_mode, riemann, cweno_form, margins,
+ * deactivation, CWENOZ and Harten constants).  order_r and precision must
+ * equal the values given at create (HFV_ERR_PARAM otherwise). */
+hfv_status hfv_set_params(hfv_ctx *ctx, const hfv_params *p);
+
+/* Reconstruction (Section 2.5 flowchart): linear candidate and NAD on every
+ * cell, tagging of the von Neumann neighbourhood, CWENOZ / MUSCL on the
+ * tagged cells through per-class work lists, Harten check on every cell.
+ *   U            device [nvar][n_cells] cell averages
+ *   face_states  device [2][nvar][n_gp] output
+ *   cell_class   device [n_cells] uint8 output (HFV_CLASS_*)
+ * Asynchronous on `stream`. */
+hfv_status hfv_reconstruct(hfv_ctx *ctx, const void *U, void *face_states, uint8_t *cell_class, void *stream);
+
+/* Residual R_i = -(1/|V_i|) sum_f sum_alpha F(U_L, U_R) w_alpha |S_f| of
+ * Eq. EulerEquationsDetails (F_v = 0) with HLLC or HLL fluxes (Section 2.4).
+ *   R            device [nvar][n_cells] output
+ *   face_states  device [2][nvar][n_gp] output, or NULL to use internal storage
+ *   cell_class   device [n_cells] output, or NULL to use internal storage
+ * Deterministic: no floating-point atomics. */
+hfv_status hfv_residual(hfv_ctx *ctx, const void *U, void *R, void *face_states, uint8_t *cell_class,
+                        void *stream);
+
+/* Vector-Jacobian product of the residual with the cell classes frozen (a
+ * project addition, not in the paper):  gU = (dR/dU)^T gR, every switch
+ * (class, Harten fallback, limiter argmin, Riemann branch) held at the
+ * value the forward evaluation of U takes.
+ *   cell_class  device [n_cells] classes from hfv_residual on the same U
+ *   gR, gU      device [nvar][n_cells] */
+hfv_status hfv_residual_vjp(hfv_ctx *ctx, const void *U, const uint8_t *cell_class, const void *gR, void *gU,
+                            void *stream);
+
+/* Queries (synchronous for the class counts, which read device counters). */
+enum {
+  HFV_Q_N_CELLS = 0, HFV_Q_N_FACES = 1, HFV_Q_N_GP = 2, HFV_Q_NVAR = 3, HFV_Q_K = 4, HFV_Q_M = 5,
+  HFV_Q_PRECISION = 6, HFV_Q_DIM = 7, HFV_Q_TABLE_BYTES = 8,
+  HFV_Q_COUNT_CWENOZ = 9, HFV_Q_COUNT_MUSCL = 10, HFV_Q_COUNT_FIRST = 11, HFV_Q_NGP_CELL_MAX = 12
+};
+hfv_status hfv_query(const hfv_ctx *ctx, int32_t what, int64_t *out);
+
+/* Copy a precomputed table to host memory (for inspection and tests).
+ * Layouts (ctx precision unless stated):
+ *   HFV_T_PINV   [K][M][n_cells]   pseudo-inverse with |V_m'| folded in
+ *   HFV_T_OI     [K(K+1)/2][n_cells] oscillation-indicator matrix, packed upper triangle
+ *   HFV_T_PSIBAR [K][n_cells]      basis means
+ *   HFV_T_GEOM   [dim+2][n_cells]  double: centroid, volume, h_c
+ *   HFV_T_PDIR   [nf_max][dim][Md][n_cells] directional pseudo-inverses
+ *   HFV_T_PMUS   [dim][nf_max][n_cells] MUSCL pseudo-inverses
+ * `bytes` must equal the table size. */
+enum { HFV_T_PINV = 0, HFV_T_OI = 1, HFV_T_PSIBAR = 2, HFV_T_GEOM = 3, HFV_T_PDIR = 4, HFV_T_PMUS = 5 };
+hfv_status hfv_copy_table(const hfv_ctx *ctx, int32_t which, void *host_dst, int64_t bytes);
+
+/* Tuning: lanes per cell (1, 2 or 4 in 2D; 1 or 5 in 3D), threads per block
+ * and the cap on resident blocks of the class-list kernels.  0 keeps the
+ * current value. */
+hfv_status hfv_set_launch(hfv_ctx *ctx, int32_t lanes_per_cell, int32_t block, int32_t list_blocks);
+
+/* Message of the last failure on this context (or of the last failed
+ * create when ctx is NULL); never NULL. */
+const char *hfv_last_error(const hfv_ctx *ctx);
+
+void hfv_destroy(hfv_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HFV_H */

@@ -1,0 +1,290 @@
+// C ABI of the hfv library: argument validation, ownership, dispatch.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "hfv_internal.hpp"
+
+namespace hfv {
+hfv_status refresh_thresholds(hfv_ctx *ctx, hipStream_t s);
+}
+
+using namespace hfv;
+
+static thread_local std::string g_create_err;
+
+static const int kTypeDim[6] = {2, 2, 3, 3, 3, 3};
+static const int kTypeNv[6] = {3, 4, 4, 5, 6, 8};
+static const int kTypeNf[6] = {3, 4, 4, 5, 5, 6};
+
+static hfv_status check_params(const hfv_params *p, std::string &err) {
+  if (!(p->gamma > 1.0)) return err = "gamma must exceed 1", HFV_ERR_PARAM;
+  if (!(p->lambda1_prime > 1.0)) return err = "lambda1_prime must exceed 1", HFV_ERR_PARAM;
+  if (!(p->alpha_m >= 0.0) || !(p->beta_m >= 0.0) || !(p->alpha_w >= 0.0))
+    return err = "NAD margins alpha_m, beta_m, alpha_w must be non-negative", HFV_ERR_PARAM;
+  if (!std::isfinite(p->beta_w)) return err = "beta_w must be finite", HFV_ERR_PARAM;
+  if (!(p->kappa >= 0.0) || !(p->n_exp > 0.0)) return err = "deactivation needs kappa >= 0, n > 0", HFV_ERR_PARAM;
+  if (!(p->eps_w > 0.0) || !(p->b_w > 0.0)) return err = "CWENOZ eps and b must be positive", HFV_ERR_PARAM;
+  if (!(p->tvd_theta > 0.0) || !(p->tvd_eps > 0.0)) return err = "Harten theta and eps must be positive", HFV_ERR_PARAM;
+  if (p->scheme_mode < 0 || p->scheme_mode > 3) return err = "unknown scheme_mode", HFV_ERR_PARAM;
+  if (p->riemann < 0 || p->riemann > 1) return err = "unknown riemann solver", HFV_ERR_PARAM;
+  if (p->cweno_form < 0 || p->cweno_form > 1) return err = "unknown cweno_form", HFV_ERR_PARAM;
+  return HFV_OK;
+}
+
+static void copy_params(hfv_ctx *ctx, const hfv_params *p) {
+  ctx->p.order_r = p->order_r;
+  ctx->p.mode = p->scheme_mode;
+  ctx->p.riemann = p->riemann;
+  ctx->p.form = p->cweno_form;
+  ctx->p.gamma = p->gamma;
+  ctx->p.alpha_m = p->alpha_m;
+  ctx->p.beta_m = p->beta_m;
+  ctx->p.alpha_w = p->alpha_w;
+  ctx->p.beta_w = p->beta_w;
+  ctx->p.kappa = p->kappa;
+  ctx->p.n_exp = p->n_exp;
+  ctx->p.lam1p = p->lambda1_prime;
+  ctx->p.eps_w = p->eps_w;
+  ctx->p.b_w = p->b_w;
+  ctx->p.theta = p->tvd_theta;
+  ctx->p.tvd_eps = p->tvd_eps;
+}
+
+static hfv_status validate(const hfv_mesh *m, const hfv_stencils *st, const hfv_params *p, std::string &err) {
+  if (!m || !st || !p) return err = "NULL mesh, stencils or params", HFV_ERR_PARAM;
+  hfv_status e = check_params(p, err);
+  if (e != HFV_OK) return e;
+  const int d = m->dim;
+  if (d != 2 && d != 3) return err = "dim must be 2 or 3", HFV_ERR_PARAM;
+  if (p->order_r < 1 || p->order_r > 4) return err = "order_r must be in 1..4", HFV_ERR_PARAM;
+  if (p->precision != 64 && p->precision != 32) return err = "precision must be 64 or 32", HFV_ERR_DTYPE;
+  if (m->n_cells <= 0 || m->n_faces <= 0 || m->n_vertices <= 0) return err = "empty mesh", HFV_ERR_MESH;
+  if (!m->vertices || !m->cell_type || !m->cell_vtx_off || !m->cell_vtx || !m->face_cells || !m->face_vtx_off ||
+      !m->face_vtx)
+    return err = "NULL mesh array", HFV_ERR_MESH;
+  if (m->face_shift && !m->period) return err = "face_shift given without period", HFV_ERR_MESH;
+  const int N = m->n_cells, NF = m->n_faces, NFM = nf_max(d), K = n_unknowns(d, p->order_r);
+  if ((long)N * 2 * K * 8 > (1L << 46)) return err = "mesh too large", HFV_ERR_MESH;
+  if (m->cell_vtx_off[0] != 0) return err = "cell_vtx_off[0] must be 0", HFV_ERR_MESH;
+  for (int c = 0; c < N; ++c) {
+    int t = m->cell_type[c];
+    if (t < 0 || t > 5 || kTypeDim[t] != d) return err = "bad cell type at cell " + std::to_string(c), HFV_ERR_MESH;
+    if (m->cell_vtx_off[c + 1] - m->cell_vtx_off[c] != kTypeNv[t])
+      return err = "vertex count does not match type at cell " + std::to_string(c), HFV_ERR_MESH;
+  }
+  for (long i = 0; i < m->cell_vtx_off[N]; ++i)
+    if (m->cell_vtx[i] < 0 || m->cell_vtx[i] >= m->n_vertices) return err = "cell vertex out of range", HFV_ERR_MESH;
+  std::vector<int> nfc(N, 0);
+  if (m->face_vtx_off[0] != 0) return err = "face_vtx_off[0] must be 0", HFV_ERR_MESH;
+  for (int f = 0; f < NF; ++f) {
+    int l = m->face_cells[2 * f], r = m->face_cells[2 * f + 1];
+    if (l < 0 || l >= N || r < -1 || r >= N) return err = "face_cells out of range at face " + std::to_string(f), HFV_ERR_MESH;
+    nfc[l]++;
+    if (r >= 0) nfc[r]++;
+    int nv = m->face_vtx_off[f + 1] - m->face_vtx_off[f];
+    if ((d == 2 && nv != 2) || (d == 3 && nv != 3 && nv != 4))
+      return err = "bad face vertex count at face " + std::to_string(f), HFV_ERR_MESH;
+    for (int k = m->face_vtx_off[f]; k < m->face_vtx_off[f + 1]; ++k)
+      if (m->face_vtx[k] < 0 || m->face_vtx[k] >= m->n_vertices) return err = "face vertex out of range", HFV_ERR_MESH;
+  }
+  for (int c = 0; c < N; ++c)
+    if (nfc[c] != kTypeNf[(int)m->cell_type[c]])
+      return err = "cell " + std::to_string(c) + " has " + std::to_string(nfc[c]) + " faces", HFV_ERR_MESH;
+  if (st->M != 2 * K) return err = "central stencil size must be 2K = " + std::to_string(2 * K), HFV_ERR_MESH;
+  if (st->nf_max != NFM || st->Md != 2 * d) return err = "stencil strides do not match dim", HFV_ERR_MESH;
+  if (!st->central || !st->dir || !st->n_dir || !st->muscl || !st->n_muscl) return err = "NULL stencil array", HFV_ERR_MESH;
+  if ((st->central_shift || st->dir_shift || st->muscl_shift) && !m->period)
+    return err = "stencil shifts given without period", HFV_ERR_MESH;
+  for (long i = 0; i < (long)N * st->M; ++i)
+    if (st->central[i] < 0 || st->central[i] >= N) return err = "central stencil entry out of range", HFV_ERR_MESH;
+  for (int c = 0; c < N; ++c) {
+    if (st->n_dir[c] < 1 || st->n_dir[c] > NFM) return err = "n_dir out of range at cell " + std::to_string(c), HFV_ERR_MESH;
+    if (st->n_muscl[c] < d || st->n_muscl[c] > NFM) return err = "n_muscl out of range at cell " + std::to_string(c), HFV_ERR_MESH;
+    for (int s = 0; s < st->n_dir[c]; ++s)
+      for (int q = 0; q < st->Md; ++q) {
+        int v = st->dir[((long)c * NFM + s) * st->Md + q];
+        if (v < 0 || v >= N) return err = "directional stencil entry out of range at cell " + std::to_string(c), HFV_ERR_MESH;
+      }
+    for (int q = 0; q < st->n_muscl[c]; ++q) {
+      int v = st->muscl[(long)c * NFM + q];
+      if (v < 0 || v >= N) return err = "MUSCL stencil entry out of range at cell " + std::to_string(c), HFV_ERR_MESH;
+    }
+  }
+  return HFV_OK;
+}
+
+extern "C" {
+
+hfv_status hfv_create(const hfv_mesh *mesh, const hfv_stencils *st, const hfv_params *p, void *stream,
+                      hfv_ctx **out) {
+  if (!out) return HFV_ERR_PARAM;
+  *out = nullptr;
+  g_create_err.clear();
+  hfv_status e = validate(mesh, st, p, g_create_err);
+  if (e != HFV_OK) return e;
+  hfv_ctx *ctx = new (std::nothrow) hfv_ctx();
+  if (!ctx) return g_create_err = "host allocation failed", HFV_ERR_OOM;
+  const int d = mesh->dim;
+  ctx->dim = d;
+  ctx->r = p->order_r;
+  ctx->prec = p->precision;
+  ctx->N = mesh->n_cells;
+  ctx->NF = mesh->n_faces;
+  ctx->K = n_unknowns(d, p->order_r);
+  ctx->M = 2 * ctx->K;
+  ctx->Md = 2 * d;
+  ctx->NFM = nf_max(d);
+  ctx->nvar = d + 2;
+  ctx->lanes = d + 2;
+  copy_params(ctx, p);
+  hipStream_t s = (hipStream_t)stream;
+  if (hipGetDevice(&ctx->device) != hipSuccess) {
+    g_create_err = "no HIP device";
+    delete ctx;
+    return HFV_ERR_HIP;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) ctx->n_cu = prop.multiProcessorCount;
+  ctx->list_blocks = 8 * ctx->n_cu;
+  e = setup_tables(ctx, mesh, st, s);
+  if (e == HFV_OK) {
+    const size_t ts = ctx->prec == 64 ? 8 : 4;
+    const int N = ctx->N;
+    if ((e = dev_alloc(ctx, (void **)&ctx->own, N)) == HFV_OK &&
+        (e = dev_alloc(ctx, (void **)&ctx->cls_ws, N)) == HFV_OK &&
+        (e = dev_alloc(ctx, (void **)&ctx->lists, sizeof(int) * 3 * (size_t)N)) == HFV_OK &&
+        (e = dev_alloc(ctx, (void **)&ctx->counts, sizeof(int) * 4)) == HFV_OK &&
+        (e = dev_alloc(ctx, &ctx->fs_ws, ts * 2 * ctx->nvar * (size_t)ctx->NGPT)) == HFV_OK &&
+        (e = dev_alloc(ctx, &ctx->fflux, ts * ctx->nvar * (size_t)ctx->NF)) == HFV_OK) {
+      if (hipMemsetAsync(ctx->counts, 0, sizeof(int) * 4, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess) {
+        ctx->err = "workspace initialisation failed";
+        e = HFV_ERR_HIP;
+      }
+    }
+  }
+  if (e != HFV_OK) {
+    g_create_err = ctx->err;
+    hfv_destroy(ctx);
+    return e;
+  }
+  *out = ctx;
+  return HFV_OK;
+}
+
+hfv_status hfv_set_params(hfv_ctx *ctx, const hfv_params *p) {
+  if (!ctx || !p) return HFV_ERR_PARAM;
+  if (p->order_r != ctx->r || p->precision != ctx->prec) {
+    ctx->err = "order_r and precision are fixed at create";
+    return HFV_ERR_PARAM;
+  }
+  hfv_status e = check_params(p, ctx->err);
+  if (e != HFV_OK) return e;
+  const bool thr = p->kappa != ctx->p.kappa || p->n_exp != ctx->p.n_exp;
+  copy_params(ctx, p);
+  if (thr) {
+    e = refresh_thresholds(ctx, nullptr);
+    if (e != HFV_OK) return e;
+    if (hipDeviceSynchronize() != hipSuccess) return ctx->err = "threshold refresh failed", HFV_ERR_HIP;
+  }
+  return HFV_OK;
+}
+
+hfv_status hfv_set_launch(hfv_ctx *ctx, int32_t lanes, int32_t block, int32_t list_blocks) {
+  if (!ctx) return HFV_ERR_PARAM;
+  if (lanes) {
+    bool ok = lanes == 1 || lanes == ctx->nvar || (ctx->dim == 2 && lanes == 2);
+    if (!ok) return ctx->err = "lanes per cell must be 1 or nvar (or 2 in 2D)", HFV_ERR_PARAM;
+    ctx->lanes = lanes;
+  }
+  if (block) {
+    if (block % 64 != 0 || block < 64 || block > 256) return ctx->err = "block must be 64, 128, 192 or 256", HFV_ERR_PARAM;
+    ctx->block = block;
+  }
+  if (list_blocks) {
+    if (list_blocks < 1) return ctx->err = "list_blocks must be positive", HFV_ERR_PARAM;
+    ctx->list_blocks = list_blocks;
+  }
+  return HFV_OK;
+}
+
+hfv_status hfv_reconstruct(hfv_ctx *ctx, const void *U, void *fs, uint8_t *cls, void *stream) {
+  if (!ctx) return HFV_ERR_PARAM;
+  if (!U || !fs || !cls) return ctx->err = "NULL device pointer", HFV_ERR_PARAM;
+  return run_reconstruct(ctx, U, fs, cls, (hipStream_t)stream);
+}
+
+hfv_status hfv_residual(hfv_ctx *ctx, const void *U, void *R, void *fs, uint8_t *cls, void *stream) {
+  if (!ctx) return HFV_ERR_PARAM;
+  if (!U || !R) return ctx->err = "NULL device pointer", HFV_ERR_PARAM;
+  hipStream_t s = (hipStream_t)stream;
+  void *f = fs ? fs : ctx->fs_ws;
+  uint8_t *c = cls ? cls : ctx->cls_ws;
+  hfv_status e = run_reconstruct(ctx, U, f, c, s);
+  if (e != HFV_OK) return e;
+  return run_residual_tail(ctx, f, R, s);
+}
+
+hfv_status hfv_residual_vjp(hfv_ctx *ctx, const void *U, const uint8_t *cls, const void *gR, void *gU,
+                            void *stream) {
+  if (!ctx) return HFV_ERR_PARAM;
+  if (!U || !cls || !gR || !gU) return ctx->err = "NULL device pointer", HFV_ERR_PARAM;
+  return run_vjp(ctx, U, cls, gR, gU, (hipStream_t)stream);
+}
+
+hfv_status hfv_query(const hfv_ctx *ctx, int32_t what, int64_t *out) {
+  if (!ctx || !out) return HFV_ERR_PARAM;
+  switch (what) {
+    case HFV_Q_N_CELLS: *out = ctx->N; return HFV_OK;
+    case HFV_Q_N_FACES: *out = ctx->NF; return HFV_OK;
+    case HFV_Q_N_GP: *out = ctx->NGPT; return HFV_OK;
+    case HFV_Q_NVAR: *out = ctx->nvar; return HFV_OK;
+    case HFV_Q_K: *out = ctx->K; return HFV_OK;
+    case HFV_Q_M: *out = ctx->M; return HFV_OK;
+    case HFV_Q_PRECISION: *out = ctx->prec; return HFV_OK;
+    case HFV_Q_DIM: *out = ctx->dim; return HFV_OK;
+    case HFV_Q_TABLE_BYTES: *out = (int64_t)ctx->table_bytes; return HFV_OK;
+    case HFV_Q_NGP_CELL_MAX: *out = ctx->NGPC; return HFV_OK;
+    case HFV_Q_COUNT_CWENOZ:
+    case HFV_Q_COUNT_MUSCL:
+    case HFV_Q_COUNT_FIRST: {
+      int c[4];
+      if (hipMemcpy(c, ctx->counts, sizeof c, hipMemcpyDeviceToHost) != hipSuccess) return HFV_ERR_HIP;
+      *out = c[1 + what - HFV_Q_COUNT_CWENOZ];
+      return HFV_OK;
+    }
+  }
+  return HFV_ERR_PARAM;
+}
+
+hfv_status hfv_copy_table(const hfv_ctx *ctx, int32_t which, void *dst, int64_t bytes) {
+  if (!ctx || !dst) return HFV_ERR_PARAM;
+  const size_t ts = ctx->prec == 64 ? 8 : 4;
+  const size_t N = ctx->N;
+  const void *src = nullptr;
+  size_t n = 0;
+  const bool d64 = ctx->prec == 64;
+  switch (which) {
+    case HFV_T_PINV: src = d64 ? (const void *)ctx->t64.P : ctx->t32.P; n = ts * ctx->K * ctx->M * N; break;
+    case HFV_T_OI: src = d64 ? (const void *)ctx->t64.OI : ctx->t32.OI; n = ts * ctx->K * (ctx->K + 1) / 2 * N; break;
+    case HFV_T_PSIBAR: src = d64 ? (const void *)ctx->t64.psibar : ctx->t32.psibar; n = ts * ctx->K * N; break;
+    case HFV_T_GEOM: src = ctx->geom; n = 8 * (ctx->dim + 2) * N; break;
+    case HFV_T_PDIR: src = d64 ? (const void *)ctx->t64.Pdir : ctx->t32.Pdir; n = ts * ctx->NFM * ctx->dim * ctx->Md * N; break;
+    case HFV_T_PMUS: src = d64 ? (const void *)ctx->t64.Pmus : ctx->t32.Pmus; n = ts * ctx->dim * ctx->NFM * N; break;
+    default: return HFV_ERR_PARAM;
+  }
+  if ((int64_t)n != bytes) return HFV_ERR_PARAM;
+  if (hipMemcpy(dst, src, n, hipMemcpyDeviceToHost) != hipSuccess) return HFV_ERR_HIP;
+  return HFV_OK;
+}
+
+const char *hfv_last_error(const hfv_ctx *ctx) { return ctx ? ctx->err.c_str() : g_create_err.c_str(); }
+
+void hfv_destroy(hfv_ctx *ctx) {
+  if (!ctx) return;
+  for (void *p : ctx->allocs) (void)hipFree(p);
+  delete ctx;
+}
+
+}  // extern "C"

@@ -1,0 +1,830 @@
+// Hot path of the hybrid reconstruction (Section 2.5, Fig. HybridWENOFlowchart).
+//
+//   k_linear     linear least-squares candidate of every cell (Section 2.1),
+//                its face Gauss-point states, the NAD class of the cell
+//                (Eqs. DMP, NADMUSCL, NADCWENOZ, marginm, marginw, with the
+//                deactivation of Eq. NADDeactivatedCriteria) and the Harten
+//                check of the candidate (Eq. harten_jump_fix)
+//   k_classify   tagging of the flagged cells' von Neumann neighbourhood and
+//                wave-ballot / prefix compaction into per-class work lists
+//   k_cwenoz     CWENOZ on the class-1 list (Section 2.3)
+//   k_muscl      Barth-Jespersen limited MUSCL on the class-2 list (Section 2.2)
+//   k_first      first-order states on cells that failed the Harten check
+//   k_flux       HLLC / HLL flux integrated over each face's Gauss points
+//   k_gather     residual of Eq. EulerEquationsDetails, fixed-order sums
+//
+// Work mapping: G lanes of a 64-wide wave share one cell, each lane owning
+// NV/G conserved variables (per-variable reconstruction, Section 2.3).  The
+// per-cell matrices are stored [row][cell] so a wave's loads of one matrix
+// entry are contiguous across its cells.
+#include "hfv_internal.hpp"
+
+namespace hfv {
+
+template <typename T>
+struct HotArgs {
+  int N, NGPT, mode, form;
+  const T *U;
+  T *fs;
+  uint8_t *own;
+  uint8_t *cls;
+  int *lists;
+  int *counts;
+  Tables<T> t;
+  T gamma, alpha_m, beta_m, alpha_w, beta_w, lam1p, eps_w, b_w, theta, tvd_eps;
+};
+
+template <int G>
+struct Lane {
+  int item, sub, base;
+  bool ok;
+  __device__ Lane() {
+    constexpr int CPW = 64 / G;
+    const int lane = threadIdx.x & 63;
+    const long wave = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    item = (int)(wave * CPW + lane / G);
+    sub = lane % G;
+    base = lane - sub;
+    ok = lane < CPW * G;
+  }
+};
+
+template <int G, typename V>
+__device__ inline V group_sum(V x, int base) {
+  if constexpr (G == 1) return x;
+  V s = 0;
+#pragma unroll
+  for (int t = 0; t < G; ++t) s += __shfl(x, base + t);
+  return s;
+}
+template <int G>
+__device__ inline int group_max(int x, int base) {
+  if constexpr (G == 1) return x;
+  int s = x;
+#pragma unroll
+  for (int t = 0; t < G; ++t) s = max(s, __shfl(x, base + t));
+  return s;
+}
+template <int G>
+__device__ inline bool group_all(bool x, int base) {
+  if constexpr (G == 1) return x;
+  int s = 1;
+#pragma unroll
+  for (int t = 0; t < G; ++t) s &= __shfl((int)x, base + t);
+  return s != 0;
+}
+
+// All NV values of a state whose variables are spread over the group.
+template <int NV, int G, typename T>
+__device__ inline void group_state(const T (&mine)[NV / G], T (&all)[NV], int base) {
+  constexpr int VPL = NV / G;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    if constexpr (G == 1)
+      all[v] = mine[v];
+    else
+      all[v] = __shfl(mine[v % VPL], base + v / VPL);
+  }
+}
+
+// Harten bound check at one point for density and pressure (Eq. harten_jump_fix).
+template <int NV, typename T>
+__device__ inline bool harten_point(const T (&q)[NV], T rho_b, T p_b, const HotArgs<T> &a) {
+  const T rho = q[0];
+  if (!(fabs(rho - rho_b) <= a.theta * fmax(fabs(rho_b), a.tvd_eps))) return false;
+  T m2 = 0;
+#pragma unroll
+  for (int j = 1; j < NV - 1; ++j) m2 += q[j] * q[j];
+  const T p = (a.gamma - (T)1) * (q[NV - 1] - (T)0.5 * m2 / rho);
+  return fabs(p - p_b) <= a.theta * fmax(fabs(p_b), a.tvd_eps);
+}
+
+template <int NV, typename T>
+__device__ inline T pressure(const T (&q)[NV], T gamma) {
+  T m2 = 0;
+#pragma unroll
+  for (int j = 1; j < NV - 1; ++j) m2 += q[j] * q[j];
+  return (gamma - (T)1) * (q[NV - 1] - (T)0.5 * m2 / q[0]);
+}
+
+// phi_k(xi) = xi^alpha_k - psi_bar_k for the hierarchical monomial basis.
+template <int DIM, int R, typename T>
+__device__ inline void basis_at(const T (&xi)[DIM], const T (&psb)[n_unknowns(DIM, R)],
+                                T (&phi)[n_unknowns(DIM, R)]) {
+  constexpr Exps<DIM, 1, R> E{};
+  constexpr int K = n_unknowns(DIM, R);
+  T pw[DIM][R + 1];
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) {
+    pw[j][0] = (T)1;
+#pragma unroll
+    for (int p = 1; p <= R; ++p) pw[j][p] = pw[j][p - 1] * xi[j];
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    T m = pw[0][E.e[k][0]];
+#pragma unroll
+    for (int j = 1; j < DIM; ++j) m *= pw[j][E.e[k][j]];
+    phi[k] = m - psb[k];
+  }
+}
+
+// a[k][q] = sum_m P[k][m] (U_{s_m} - U_i)   (Section 2.1, a = A^+ b)
+template <int DIM, int R, int VPL, typename T>
+__device__ inline void lsq_coeffs(const HotArgs<T> &a, int cell, int v0, const T (&u0)[VPL],
+                                  T (&co)[n_unknowns(DIM, R)][VPL]) {
+  constexpr int K = n_unknowns(DIM, R), M = 2 * K;
+  const int N = a.N;
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int q = 0; q < VPL; ++q) co[k][q] = (T)0;
+#pragma unroll 2
+  for (int m = 0; m < M; ++m) {
+    const int j = a.t.sten[(long)m * N + cell];
+    T du[VPL];
+#pragma unroll
+    for (int q = 0; q < VPL; ++q) du[q] = a.U[(long)(v0 + q) * N + j] - u0[q];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const T p = a.t.P[((long)k * M + m) * N + cell];
+#pragma unroll
+      for (int q = 0; q < VPL; ++q) co[k][q] += p * du[q];
+    }
+  }
+}
+
+template <int NV, typename T>
+__device__ inline void store(const HotArgs<T> &a, int dst, int v, T val) {
+  const long d = dst & ~(1 << 30);
+  a.fs[d + (long)v * a.NGPT] = val;
+  if (dst & (1 << 30)) a.fs[d + (long)(NV + v) * a.NGPT] = val;  // boundary: transmissive ghost
+}
+
+// ---------------------------------------------------------------------------
+// K1: linear candidate, face states, NAD own class, Harten flag.
+template <int DIM, int R, typename T, int G>
+__global__ __launch_bounds__(256) void k_linear(HotArgs<T> a) {
+  constexpr int NV = DIM + 2, K = n_unknowns(DIM, R), VPL = NV / G, NFM = nf_max(DIM);
+  if (blockIdx.x == 0 && threadIdx.x < 4) a.counts[threadIdx.x] = 0;
+  Lane<G> L;
+  const int cell = L.item;
+  if (!L.ok || cell >= a.N) return;
+  const int N = a.N, v0 = L.sub * VPL;
+  T u0[VPL];
+#pragma unroll
+  for (int q = 0; q < VPL; ++q) u0[q] = a.U[(long)(v0 + q) * N + cell];
+  T co[K][VPL];
+  lsq_coeffs<DIM, R, VPL, T>(a, cell, v0, u0, co);
+
+  // NAD bounds over the cell and its face neighbours; deactivation norms
+  T mn[VPL], mx[VPL];
+#pragma unroll
+  for (int q = 0; q < VPL; ++q) mn[q] = mx[q] = u0[q];
+  T dmax = -INFINITY, dmin = INFINITY;
+  bool has_nb = false;
+  const int nf = a.t.nfc[cell];
+#pragma unroll
+  for (int f = 0; f < NFM; ++f) {
+    if (f < nf) {
+      const int j = a.t.nbr[(long)f * N + cell];
+      if (j >= 0) {
+        T s2 = 0;
+#pragma unroll
+        for (int q = 0; q < VPL; ++q) {
+          const T u = a.U[(long)(v0 + q) * N + j];
+          mn[q] = fmin(mn[q], u);
+          mx[q] = fmax(mx[q], u);
+          s2 += (u - u0[q]) * (u - u0[q]);
+        }
+        s2 = group_sum<G>(s2, L.base);
+        const T nrm = sqrt(s2);
+        dmax = fmax(dmax, nrm);
+        dmin = fmin(dmin, nrm);
+        has_nb = true;
+      }
+    }
+  }
+  T all0[NV];
+  group_state<NV, G, T>(u0, all0, L.base);
+  const T rho_b = all0[0];
+  const T p_b = pressure<NV, T>(all0, a.gamma);
+
+  T psb[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) psb[k] = a.t.psibar[(long)k * N + cell];
+  T exc[VPL];
+#pragma unroll
+  for (int q = 0; q < VPL; ++q) exc[q] = -INFINITY;
+  bool hok = true;
+  const int ng = a.t.ngp[cell];
+  for (int g = 0; g < ng; ++g) {
+    T xi[DIM];
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) xi[j] = a.t.gpxi[((long)g * DIM + j) * N + cell];
+    T phi[K];
+    basis_at<DIM, R, T>(xi, psb, phi);
+    T val[VPL];
+#pragma unroll
+    for (int q = 0; q < VPL; ++q) {
+      T s = 0;
+#pragma unroll
+      for (int k = 0; k < K; ++k) s += co[k][q] * phi[k];
+      val[q] = u0[q] + s;
+      exc[q] = fmax(exc[q], fmax(mn[q] - val[q], val[q] - mx[q]));
+    }
+    T all[NV];
+    group_state<NV, G, T>(val, all, L.base);
+    hok = hok && harten_point<NV, T>(all, rho_b, p_b, a);
+    const int dst = a.t.gpdst[(long)g * N + cell];
+#pragma unroll
+    for (int q = 0; q < VPL; ++q) store<NV, T>(a, dst, v0 + q, val[q]);
+  }
+  int c = 0;
+  if (a.mode == HFV_HYBRID) {
+#pragma unroll
+    for (int q = 0; q < VPL; ++q) {
+      const T Rg = mx[q] - mn[q];
+      const T dm = fmax(a.alpha_m, a.beta_m * Rg);
+      const T sgn = (T)((a.beta_w > 0) - (a.beta_w < 0));
+      const T dw = sgn * fmax(a.alpha_w, fabs(a.beta_w * Rg));
+      const int cq = exc[q] <= dw ? HFV_CLASS_LINEAR : (exc[q] >= dm ? HFV_CLASS_MUSCL : HFV_CLASS_CWENOZ);
+      c = max(c, cq);
+    }
+    c = group_max<G>(c, L.base);
+    const T dU = has_nb ? dmax - dmin : (T)0;
+    if (dU < a.t.thr[cell]) c = HFV_CLASS_LINEAR;
+  }
+  if (L.sub == 0) a.own[cell] = (uint8_t)(c | (hok ? 0 : 4));
+}
+
+// K2: final class (dilation over face neighbours) and per-class lists.
+template <typename T>
+__global__ __launch_bounds__(256) void k_classify(HotArgs<T> a, int nfm) {
+  const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = cell < a.N;
+  int c = 0;
+  if (valid) {
+    const int o = a.own[cell];
+    c = o & 3;
+    if (a.mode == HFV_HYBRID) {
+      const int nf = a.t.nfc[cell];
+      for (int f = 0; f < nf; ++f) {
+        const int j = a.t.nbr[(long)f * a.N + cell];
+        if (j >= 0) c = max(c, a.own[j] & 3);
+      }
+    } else {
+      c = HFV_CLASS_LINEAR;
+    }
+    if (c == HFV_CLASS_LINEAR && (o & 4)) c = HFV_CLASS_FIRST_ORDER;
+    a.cls[cell] = (uint8_t)c;
+  }
+  const int lane = threadIdx.x & 63;
+  const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+  for (int k = 1; k <= 3; ++k) {
+    const unsigned long long mask = __ballot(valid && c == k);
+    if (mask) {
+      const int leader = __ffsll((long long)mask) - 1;
+      int basepos = 0;
+      if (lane == leader) basepos = atomicAdd(&a.counts[k], __popcll(mask));
+      basepos = __shfl(basepos, leader);
+      if (valid && c == k) a.lists[(long)(k - 1) * a.N + basepos + __popcll(mask & lt)] = cell;
+    }
+  }
+}
+
+// K3: CWENOZ over list 1 (or every cell when lists == nullptr).
+template <int DIM, int R, typename T, int G>
+__global__ __launch_bounds__(256) void k_cwenoz(HotArgs<T> a, int direct) {
+  constexpr int NV = DIM + 2, K = n_unknowns(DIM, R), VPL = NV / G, NFM = nf_max(DIM), MD = 2 * DIM;
+  constexpr int CPW = 64 / G;
+  const int total = direct ? a.N : a.counts[1];
+  Lane<G> L;
+  if (!L.ok) return;
+  const long stride = (long)gridDim.x * (blockDim.x / 64) * CPW;
+  for (long item = L.item; item < total; item += stride) {
+    const int cell = direct ? (int)item : a.lists[item];
+    const int N = a.N, v0 = L.sub * VPL;
+    T u0[VPL];
+#pragma unroll
+    for (int q = 0; q < VPL; ++q) u0[q] = a.U[(long)(v0 + q) * N + cell];
+    T co[K][VPL];
+    lsq_coeffs<DIM, R, VPL, T>(a, cell, v0, u0, co);
+    // directional degree-1 fits (Section 2.3)
+    const int nd = a.t.ndir[cell];
+    T ad[NFM][DIM][VPL];
+#pragma unroll
+    for (int s = 0; s < NFM; ++s) {
+#pragma unroll
+      for (int j = 0; j < DIM; ++j)
+#pragma unroll
+        for (int q = 0; q < VPL; ++q) ad[s][j][q] = (T)0;
+      if (s < nd) {
+#pragma unroll
+        for (int m = 0; m < MD; ++m) {
+          const int jc = a.t.dsten[((long)s * MD + m) * N + cell];
+          T du[VPL];
+#pragma unroll
+          for (int q = 0; q < VPL; ++q) du[q] = a.U[(long)(v0 + q) * N + jc] - u0[q];
+#pragma unroll
+          for (int j = 0; j < DIM; ++j) {
+            const T p = a.t.Pdir[(((long)s * DIM + j) * MD + m) * N + cell];
+#pragma unroll
+            for (int q = 0; q < VPL; ++q) ad[s][j][q] += p * du[q];
+          }
+        }
+      }
+    }
+    const T lam1 = (T)1 - (T)1 / a.lam1p;
+    const T lams = ((T)1 - lam1) / (T)nd;
+    // p_1 = (p_opt - sum lambda_s p_s) / lambda_1, in place
+#pragma unroll
+    for (int j = 0; j < DIM; ++j)
+#pragma unroll
+      for (int q = 0; q < VPL; ++q) {
+        T sdir = 0;
+#pragma unroll
+        for (int s = 0; s < NFM; ++s) sdir += ad[s][j][q];
+        co[j][q] = co[j][q] - lams * sdir;
+      }
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int q = 0; q < VPL; ++q) co[k][q] /= lam1;
+    // smoothness indicators SI = a^T OI a, accumulated in double
+    double si1[VPL], sis[NFM][VPL];
+#pragma unroll
+    for (int q = 0; q < VPL; ++q) {
+      si1[q] = 0;
+#pragma unroll
+      for (int s = 0; s < NFM; ++s) sis[s][q] = 0;
+    }
+    {
+      int pidx = 0;
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int kq = k; kq < K; ++kq, ++pidx) {
+          const double o = (double)a.t.OI[(long)pidx * N + cell] * (kq == k ? 1.0 : 2.0);
+#pragma unroll
+          for (int q = 0; q < VPL; ++q) si1[q] += o * (double)co[k][q] * (double)co[kq][q];
+          if (kq < DIM) {
+#pragma unroll
+            for (int s = 0; s < NFM; ++s)
+#pragma unroll
+              for (int q = 0; q < VPL; ++q) sis[s][q] += o * (double)ad[s][k][q] * (double)ad[s][kq][q];
+          }
+        }
+    }
+    // nonlinear weights
+    double om1[VPL], oms[NFM][VPL];
+#pragma unroll
+    for (int q = 0; q < VPL; ++q) {
+      double tau = 0;
+#pragma unroll
+      for (int s = 0; s < NFM; ++s)
+        if (s < nd) tau += fabs(sis[s][q] - si1[q]);
+      tau /= (double)nd;
+      const double eps = (double)a.eps_w, b = (double)a.b_w;
+      double w1, tot;
+      if (a.form == HFV_WENOZ_POW) {
+        w1 = (double)lam1 * (1.0 + pow(tau / (eps + si1[q]), b));
+      } else {
+        w1 = (double)lam1 * (1.0 + pow(tau, b) / (eps + si1[q]));
+      }
+      tot = w1;
+#pragma unroll
+      for (int s = 0; s < NFM; ++s) {
+        double ws = 0;
+        if (s < nd) {
+          ws = a.form == HFV_WENOZ_POW ? (double)lams * (1.0 + pow(tau / (eps + sis[s][q]), b))
+                                       : (double)lams * (1.0 + pow(tau, b) / (eps + sis[s][q]));
+        }
+        oms[s][q] = ws;
+        tot += ws;
+      }
+      om1[q] = w1 / tot;
+#pragma unroll
+      for (int s = 0; s < NFM; ++s) oms[s][q] /= tot;
+    }
+    // CWENOZ coefficients: omega_1 a_1 + sum_s omega_s a_s
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int q = 0; q < VPL; ++q) {
+        T v = (T)om1[q] * co[k][q];
+        if (k < DIM) {
+#pragma unroll
+          for (int s = 0; s < NFM; ++s) v += (T)oms[s][q] * ad[s][k][q];
+        }
+        co[k][q] = v;
+      }
+    // face states, Harten check
+    T all0[NV];
+    group_state<NV, G, T>(u0, all0, L.base);
+    const T rho_b = all0[0];
+    const T p_b = pressure<NV, T>(all0, a.gamma);
+    T psb[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) psb[k] = a.t.psibar[(long)k * N + cell];
+    const int ng = a.t.ngp[cell];
+    bool hok = true;
+    for (int g = 0; g < ng; ++g) {
+      T xi[DIM];
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) xi[j] = a.t.gpxi[((long)g * DIM + j) * N + cell];
+      T phi[K];
+      basis_at<DIM, R, T>(xi, psb, phi);
+      T val[VPL];
+#pragma unroll
+      for (int q = 0; q < VPL; ++q) {
+        T s = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) s += co[k][q] * phi[k];
+        val[q] = u0[q] + s;
+      }
+      T all[NV];
+      group_state<NV, G, T>(val, all, L.base);
+      hok = hok && harten_point<NV, T>(all, rho_b, p_b, a);
+      const int dst = a.t.gpdst[(long)g * N + cell];
+#pragma unroll
+      for (int q = 0; q < VPL; ++q) store<NV, T>(a, dst, v0 + q, hok ? val[q] : u0[q]);
+      if (!hok) {
+        // first-order fallback: overwrite every point of the cell with U_i
+        for (int g2 = 0; g2 < ng; ++g2) {
+          const int d2 = a.t.gpdst[(long)g2 * N + cell];
+#pragma unroll
+          for (int q = 0; q < VPL; ++q) store<NV, T>(a, d2, v0 + q, u0[q]);
+        }
+        break;
+      }
+    }
+    if (L.sub == 0) a.cls[cell] = hok ? HFV_CLASS_CWENOZ : HFV_CLASS_FIRST_ORDER;
+  }
+}
+
+// K4: MUSCL with the Barth-Jespersen limiter over list 2.
+template <int DIM, int R, typename T, int G>
+__global__ __launch_bounds__(256) void k_muscl(HotArgs<T> a, int direct) {
+  constexpr int NV = DIM + 2, VPL = NV / G, NFM = nf_max(DIM);
+  constexpr int CPW = 64 / G;
+  const int total = direct ? a.N : a.counts[2];
+  Lane<G> L;
+  if (!L.ok) return;
+  const long stride = (long)gridDim.x * (blockDim.x / 64) * CPW;
+  for (long item = L.item; item < total; item += stride) {
+    const int cell = direct ? (int)item : a.lists[(long)a.N + item];
+    const int N = a.N, v0 = L.sub * VPL;
+    T u0[VPL];
+#pragma unroll
+    for (int q = 0; q < VPL; ++q) u0[q] = a.U[(long)(v0 + q) * N + cell];
+    T gr[DIM][VPL];
+#pragma unroll
+    for (int j = 0; j < DIM; ++j)
+#pragma unroll
+      for (int q = 0; q < VPL; ++q) gr[j][q] = 0;
+    const int nm = a.t.nmus[cell];
+#pragma unroll
+    for (int m = 0; m < NFM; ++m) {
+      if (m < nm) {
+        const int jc = a.t.msten[(long)m * N + cell];
+        T du[VPL];
+#pragma unroll
+        for (int q = 0; q < VPL; ++q) du[q] = a.U[(long)(v0 + q) * N + jc] - u0[q];
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) {
+          const T p = a.t.Pmus[((long)j * NFM + m) * N + cell];
+#pragma unroll
+          for (int q = 0; q < VPL; ++q) gr[j][q] += p * du[q];
+        }
+      }
+    }
+    T mn[VPL], mx[VPL];
+#pragma unroll
+    for (int q = 0; q < VPL; ++q) mn[q] = mx[q] = u0[q];
+    const int nf = a.t.nfc[cell];
+#pragma unroll
+    for (int f = 0; f < NFM; ++f) {
+      if (f < nf) {
+        const int j = a.t.nbr[(long)f * N + cell];
+        if (j >= 0) {
+#pragma unroll
+          for (int q = 0; q < VPL; ++q) {
+            const T u = a.U[(long)(v0 + q) * N + j];
+            mn[q] = fmin(mn[q], u);
+            mx[q] = fmax(mx[q], u);
+          }
+        }
+      }
+    }
+    T psb[DIM];
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) psb[j] = a.t.psibar[(long)j * N + cell];
+    const int ng = a.t.ngp[cell];
+    T th[VPL];
+#pragma unroll
+    for (int q = 0; q < VPL; ++q) th[q] = (T)1;
+    for (int g = 0; g < ng; ++g) {
+      T phi[DIM];
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) phi[j] = a.t.gpxi[((long)g * DIM + j) * N + cell] - psb[j];
+#pragma unroll
+      for (int q = 0; q < VPL; ++q) {
+        T d = 0;
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) d += gr[j][q] * phi[j];
+        T ratio = (T)1;
+        if (d > 0)
+          ratio = fmin((T)1, (mx[q] - u0[q]) / d);
+        else if (d < 0)
+          ratio = fmin((T)1, (mn[q] - u0[q]) / d);
+        th[q] = fmin(th[q], ratio);
+      }
+    }
+    T all0[NV];
+    group_state<NV, G, T>(u0, all0, L.base);
+    const T rho_b = all0[0];
+    const T p_b = pressure<NV, T>(all0, a.gamma);
+    bool hok = true;
+    for (int g = 0; g < ng && hok; ++g) {
+      T phi[DIM];
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) phi[j] = a.t.gpxi[((long)g * DIM + j) * N + cell] - psb[j];
+      T val[VPL];
+#pragma unroll
+      for (int q = 0; q < VPL; ++q) {
+        T d = 0;
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) d += gr[j][q] * phi[j];
+        val[q] = u0[q] + th[q] * d;
+      }
+      T all[NV];
+      group_state<NV, G, T>(val, all, L.base);
+      hok = harten_point<NV, T>(all, rho_b, p_b, a);
+    }
+    for (int g = 0; g < ng; ++g) {
+      T phi[DIM];
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) phi[j] = a.t.gpxi[((long)g * DIM + j) * N + cell] - psb[j];
+      const int dst = a.t.gpdst[(long)g * N + cell];
+#pragma unroll
+      for (int q = 0; q < VPL; ++q) {
+        T d = 0;
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) d += gr[j][q] * phi[j];
+        store<NV, T>(a, dst, v0 + q, hok ? u0[q] + th[q] * d : u0[q]);
+      }
+    }
+    if (L.sub == 0) a.cls[cell] = hok ? HFV_CLASS_MUSCL : HFV_CLASS_FIRST_ORDER;
+  }
+}
+
+// K5: first-order states (cell average at every Gauss point) over list 3.
+template <int NV, typename T>
+__global__ __launch_bounds__(256) void k_first(HotArgs<T> a) {
+  const int total = a.counts[3];
+  for (long item = (long)blockIdx.x * blockDim.x + threadIdx.x; item < total;
+       item += (long)gridDim.x * blockDim.x) {
+    const int cell = a.lists[2L * a.N + item];
+    const int ng = a.t.ngp[cell];
+    for (int g = 0; g < ng; ++g) {
+      const int dst = a.t.gpdst[(long)g * a.N + cell];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) store<NV, T>(a, dst, v, a.U[(long)v * a.N + cell]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Riemann fluxes (Section 2.4): HLLC and HLL with Davis wave-speed estimates.
+template <int DIM, typename T>
+__device__ inline void euler_flux(const T (&q)[DIM + 2], const T (&n)[DIM], T p, T un, T (&F)[DIM + 2]) {
+  F[0] = q[0] * un;
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) F[1 + j] = q[1 + j] * un + p * n[j];
+  F[DIM + 1] = un * (q[DIM + 1] + p);
+}
+
+template <int DIM, typename T>
+__device__ inline void riemann(const T (&qL)[DIM + 2], const T (&qR)[DIM + 2], const T (&n)[DIM], T gamma,
+                               int hllc, T (&F)[DIM + 2]) {
+  constexpr int NV = DIM + 2;
+  const T rL = qL[0], rR = qR[0];
+  T vL[DIM], vR[DIM], unL = 0, unR = 0, kL = 0, kR = 0;
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) {
+    vL[j] = qL[1 + j] / rL;
+    vR[j] = qR[1 + j] / rR;
+    unL += vL[j] * n[j];
+    unR += vR[j] * n[j];
+    kL += vL[j] * vL[j];
+    kR += vR[j] * vR[j];
+  }
+  const T pL = (gamma - 1) * (qL[NV - 1] - (T)0.5 * rL * kL);
+  const T pR = (gamma - 1) * (qR[NV - 1] - (T)0.5 * rR * kR);
+  const T cL = sqrt(gamma * pL / rL), cR = sqrt(gamma * pR / rR);
+  const T SL = fmin(unL - cL, unR - cR), SR = fmax(unL + cL, unR + cR);
+  T FL[NV], FR[NV];
+  euler_flux<DIM, T>(qL, n, pL, unL, FL);
+  euler_flux<DIM, T>(qR, n, pR, unR, FR);
+  if (SL >= 0) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) F[v] = FL[v];
+    return;
+  }
+  if (!hllc) {
+    if (SR <= 0) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) F[v] = FR[v];
+      return;
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) F[v] = (SR * FL[v] - SL * FR[v] + SL * SR * (qR[v] - qL[v])) / (SR - SL);
+    return;
+  }
+  const T Ss = (pR - pL + rL * unL * (SL - unL) - rR * unR * (SR - unR)) / (rL * (SL - unL) - rR * (SR - unR));
+  if (Ss >= 0) {
+    const T fac = rL * (SL - unL) / (SL - Ss);
+    F[0] = FL[0] + SL * (fac - qL[0]);
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) F[1 + j] = FL[1 + j] + SL * (fac * (vL[j] + (Ss - unL) * n[j]) - qL[1 + j]);
+    F[NV - 1] = FL[NV - 1] + SL * (fac * (qL[NV - 1] / rL + (Ss - unL) * (Ss + pL / (rL * (SL - unL)))) -
+                                   qL[NV - 1]);
+  } else if (SR > 0) {
+    const T fac = rR * (SR - unR) / (SR - Ss);
+    F[0] = FR[0] + SR * (fac - qR[0]);
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) F[1 + j] = FR[1 + j] + SR * (fac * (vR[j] + (Ss - unR) * n[j]) - qR[1 + j]);
+    F[NV - 1] = FR[NV - 1] + SR * (fac * (qR[NV - 1] / rR + (Ss - unR) * (Ss + pR / (rR * (SR - unR)))) -
+                                   qR[NV - 1]);
+  } else {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) F[v] = FR[v];
+  }
+}
+
+template <int DIM, typename T>
+__global__ __launch_bounds__(256) void k_flux(int NF, int NGPT, const T *fs, const int *gp_off, const T *fn,
+                                              const T *gpw, T gamma, int hllc, T *Ff) {
+  constexpr int NV = DIM + 2;
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= NF) return;
+  T n[DIM];
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) n[j] = fn[(long)j * NF + f];
+  T acc[NV] = {};
+  for (int g = gp_off[f]; g < gp_off[f + 1]; ++g) {
+    T qL[NV], qR[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      qL[v] = fs[(long)v * NGPT + g];
+      qR[v] = fs[(long)(NV + v) * NGPT + g];
+    }
+    T F[NV];
+    riemann<DIM, T>(qL, qR, n, gamma, hllc, F);
+    const T w = gpw[g];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] += w * F[v];
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) Ff[(long)v * NF + f] = acc[v];
+}
+
+template <int NV, typename T>
+__global__ __launch_bounds__(256) void k_gather(int N, int NF, const int *cf_off, const int *cf, const T *Ff,
+                                                const T *ivol, T *R) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= N) return;
+  T acc[NV] = {};
+  for (int e = cf_off[c]; e < cf_off[c + 1]; ++e) {
+    const int code = cf[e];
+    const int f = code & 0x7fffffff;
+    const T sg = (code < 0) ? (T)1 : (T)-1;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] += sg * Ff[(long)v * NF + f];
+  }
+  const T iv = ivol[c];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) R[(long)v * N + c] = acc[v] * iv;
+}
+
+// ---------------------------------------------------------------------------
+static inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
+
+template <typename T>
+static HotArgs<T> make_args(hfv_ctx *ctx, Tables<T> &t, const void *U, void *fs, uint8_t *cls) {
+  HotArgs<T> a;
+  a.N = ctx->N;
+  a.NGPT = ctx->NGPT;
+  a.mode = ctx->p.mode;
+  a.form = ctx->p.form;
+  a.U = (const T *)U;
+  a.fs = (T *)fs;
+  a.own = ctx->own;
+  a.cls = cls;
+  a.lists = ctx->lists;
+  a.counts = ctx->counts;
+  a.t = t;
+  a.gamma = (T)ctx->p.gamma;
+  a.alpha_m = (T)ctx->p.alpha_m;
+  a.beta_m = (T)ctx->p.beta_m;
+  a.alpha_w = (T)ctx->p.alpha_w;
+  a.beta_w = (T)ctx->p.beta_w;
+  a.lam1p = (T)ctx->p.lam1p;
+  a.eps_w = (T)ctx->p.eps_w;
+  a.b_w = (T)ctx->p.b_w;
+  a.theta = (T)ctx->p.theta;
+  a.tvd_eps = (T)ctx->p.tvd_eps;
+  return a;
+}
+
+__global__ void k_zero4(int *c) {
+  if (threadIdx.x < 4) c[threadIdx.x] = 0;
+}
+
+template <int DIM, int R, typename T, int G>
+static hfv_status recon_impl(hfv_ctx *ctx, Tables<T> &t, const void *U, void *fs, uint8_t *cls, hipStream_t s) {
+  HotArgs<T> a = make_args<T>(ctx, t, U, fs, cls);
+  const int B = ctx->block;
+  const long items = (long)ctx->N;
+  const long waves = (items + 64 / G - 1) / (64 / G);
+  const unsigned grid_cells = nblk(waves * 64, B);
+  const unsigned grid_list = std::min<unsigned>(grid_cells, (unsigned)ctx->list_blocks);
+  const int mode = ctx->p.mode;
+  if (mode == HFV_ALL_CWENOZ) {
+    k_zero4<<<1, 64, 0, s>>>(ctx->counts);
+    k_cwenoz<DIM, R, T, G><<<grid_list, B, 0, s>>>(a, 1);
+  } else if (mode == HFV_ALL_MUSCL) {
+    k_zero4<<<1, 64, 0, s>>>(ctx->counts);
+    k_muscl<DIM, R, T, G><<<grid_list, B, 0, s>>>(a, 1);
+  } else {
+    k_linear<DIM, R, T, G><<<grid_cells, B, 0, s>>>(a);
+    k_classify<T><<<nblk(ctx->N, 256), 256, 0, s>>>(a, ctx->NFM);
+    if (mode == HFV_HYBRID) {
+      k_cwenoz<DIM, R, T, G><<<grid_list, B, 0, s>>>(a, 0);
+      k_muscl<DIM, R, T, G><<<grid_list, B, 0, s>>>(a, 0);
+    }
+    k_first<DIM + 2, T><<<std::min<unsigned>(nblk(ctx->N, 256), 1024), 256, 0, s>>>(a);
+  }
+  HFV_HIP(hipGetLastError());
+  return HFV_OK;
+}
+
+template <int DIM, int R, typename T>
+static hfv_status recon_lanes(hfv_ctx *ctx, Tables<T> &t, const void *U, void *fs, uint8_t *cls, hipStream_t s) {
+  switch (ctx->lanes) {
+    case 1: return recon_impl<DIM, R, T, 1>(ctx, t, U, fs, cls, s);
+    case DIM + 2: return recon_impl<DIM, R, T, DIM + 2>(ctx, t, U, fs, cls, s);
+    default:
+      if constexpr (DIM == 2) {
+        if (ctx->lanes == 2) return recon_impl<DIM, R, T, 2>(ctx, t, U, fs, cls, s);
+      }
+      ctx->err = "unsupported lanes per cell";
+      return HFV_ERR_PARAM;
+  }
+}
+
+template <typename T>
+static hfv_status recon_t(hfv_ctx *ctx, Tables<T> &t, const void *U, void *fs, uint8_t *cls, hipStream_t s) {
+  switch (ctx->dim * 10 + ctx->r) {
+    case 21: return recon_lanes<2, 1, T>(ctx, t, U, fs, cls, s);
+    case 22: return recon_lanes<2, 2, T>(ctx, t, U, fs, cls, s);
+    case 23: return recon_lanes<2, 3, T>(ctx, t, U, fs, cls, s);
+    case 24: return recon_lanes<2, 4, T>(ctx, t, U, fs, cls, s);
+    case 31: return recon_lanes<3, 1, T>(ctx, t, U, fs, cls, s);
+    case 32: return recon_lanes<3, 2, T>(ctx, t, U, fs, cls, s);
+    case 33: return recon_lanes<3, 3, T>(ctx, t, U, fs, cls, s);
+    case 34: return recon_lanes<3, 4, T>(ctx, t, U, fs, cls, s);
+  }
+  ctx->err = "unsupported (dim, order_r)";
+  return HFV_ERR_PARAM;
+}
+
+hfv_status run_reconstruct(hfv_ctx *ctx, const void *U, void *fs, uint8_t *cls, hipStream_t s) {
+  return ctx->prec == 64 ? recon_t<double>(ctx, ctx->t64, U, fs, cls, s)
+                         : recon_t<float>(ctx, ctx->t32, U, fs, cls, s);
+}
+
+template <typename T>
+static hfv_status tail_t(hfv_ctx *ctx, Tables<T> &t, const void *fs, void *R, hipStream_t s) {
+  const int hllc = ctx->p.riemann == HFV_HLLC;
+  T *Ff = (T *)ctx->fflux;
+  if (ctx->dim == 2) {
+    k_flux<2, T><<<nblk(ctx->NF, 256), 256, 0, s>>>(ctx->NF, ctx->NGPT, (const T *)fs, t.gp_off, t.fnormal, t.gpw,
+                                                     (T)ctx->p.gamma, hllc, Ff);
+    k_gather<4, T><<<nblk(ctx->N, 256), 256, 0, s>>>(ctx->N, ctx->NF, t.cf_off, t.cf, Ff, t.ivol, (T *)R);
+  } else {
+    k_flux<3, T><<<nblk(ctx->NF, 256), 256, 0, s>>>(ctx->NF, ctx->NGPT, (const T *)fs, t.gp_off, t.fnormal, t.gpw,
+                                                     (T)ctx->p.gamma, hllc, Ff);
+    k_gather<5, T><<<nblk(ctx->N, 256), 256, 0, s>>>(ctx->N, ctx->NF, t.cf_off, t.cf, Ff, t.ivol, (T *)R);
+  }
+  HFV_HIP(hipGetLastError());
+  return HFV_OK;
+}
+
+hfv_status run_residual_tail(hfv_ctx *ctx, const void *fs, void *R, hipStream_t s) {
+  return ctx->prec == 64 ? tail_t<double>(ctx, ctx->t64, fs, R, s) : tail_t<float>(ctx, ctx->t32, fs, R, s);
+}
+
+}  // namespace hfv

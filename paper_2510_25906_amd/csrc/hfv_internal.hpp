@@ -1,0 +1,131 @@
+// Internal declarations of the hfv library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/hfv.h"
+
+namespace hfv {
+
+__host__ __device__ constexpr int binom(int n, int k) {
+  int r = 1;
+  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+  return r;
+}
+// Non-constant unknowns of a degree-r polynomial in d dimensions (Section 2.1).
+__host__ __device__ constexpr int n_unknowns(int d, int r) { return binom(r + d, d) - 1; }
+__host__ __device__ constexpr int nf_max(int d) { return d == 2 ? 4 : 6; }
+__host__ __device__ constexpr int max_gp_cell(int d, int r) {
+  return d == 2 ? 4 * ((r + 2) / 2) : 6 * ((r + 2) / 2) * ((r + 2) / 2);
+}
+
+// Exponents of the monomials of degree lo..hi, ordered by degree and then in
+// descending lexicographic order (the hierarchical basis order).
+template <int DIM, int LO, int HI>
+struct Exps {
+  static constexpr int count() { return binom(HI + DIM, DIM) - (LO > 0 ? binom(LO - 1 + DIM, DIM) : 0); }
+  int e[count() > 0 ? count() : 1][DIM];
+  constexpr Exps() : e{} {
+    int k = 0;
+    for (int deg = LO; deg <= HI; ++deg) {
+      if (DIM == 2) {
+        for (int a = deg; a >= 0; --a) {
+          e[k][0] = a;
+          e[k][DIM - 1] = deg - a;
+          ++k;
+        }
+      } else {
+        for (int a = deg; a >= 0; --a)
+          for (int b = deg - a; b >= 0; --b) {
+            e[k][0] = a;
+            e[k][1 % DIM] = b;
+            e[k][DIM - 1] = deg - a - b;
+            ++k;
+          }
+      }
+    }
+  }
+};
+
+// Device tables of one context.  Per-cell arrays are [row][n_cells] so that
+// consecutive cells are consecutive in memory.
+template <typename T>
+struct Tables {
+  int *sten = nullptr;     // [M][N]
+  T *P = nullptr;          // [K][M][N]   pseudo-inverse times |V_m'|
+  T *psibar = nullptr;     // [K][N]
+  T *gpxi = nullptr;       // [NGPC][DIM][N] Gauss points in the cell frame
+  int *gpdst = nullptr;    // [NGPC][N]  side*nvar*NGPT + g, bit 30: boundary ghost
+  uint8_t *ngp = nullptr;  // [N]
+  int *nbr = nullptr;      // [NFM][N]   face neighbours, -1 at boundaries
+  uint8_t *nfc = nullptr;  // [N]
+  T *thr = nullptr;        // [N]  NAD deactivation threshold (kappa h)^n
+  T *OI = nullptr;         // [K(K+1)/2][N]
+  int *dsten = nullptr;    // [NFM][Md][N]
+  T *Pdir = nullptr;       // [NFM][DIM][Md][N]
+  uint8_t *ndir = nullptr; // [N]
+  int *msten = nullptr;    // [NFM][N]
+  T *Pmus = nullptr;       // [DIM][NFM][N]
+  uint8_t *nmus = nullptr; // [N]
+  // faces
+  T *fnormal = nullptr;    // [DIM][NF]
+  int *gp_off = nullptr;   // [NF+1]
+  T *gpw = nullptr;        // [NGPT] weight x surface Jacobian
+  int *face_cells = nullptr; // [2][NF]
+  int *cf_off = nullptr;   // [N+1]
+  int *cf = nullptr;       // [..] face | (side << 31)
+  T *ivol = nullptr;       // [N]
+};
+
+struct Params {
+  int order_r, mode, riemann, form;
+  double gamma, alpha_m, beta_m, alpha_w, beta_w, kappa, n_exp, lam1p, eps_w, b_w, theta, tvd_eps;
+};
+
+}  // namespace hfv
+
+struct hfv_ctx {
+  int dim = 0, r = 0, prec = 64, N = 0, NF = 0, NGPT = 0, NGPC = 0, K = 0, M = 0, Md = 0, NFM = 0, nvar = 0;
+  hfv::Params p{};
+  hfv::Tables<double> t64;
+  hfv::Tables<float> t32;
+  // double geometry kept for queries: [DIM+2][N] centroid, volume, h
+  double *geom = nullptr;
+  // workspace
+  uint8_t *own = nullptr;      // [N]
+  uint8_t *cls_ws = nullptr;   // [N]
+  int *lists = nullptr;        // [3][N]
+  int *counts = nullptr;       // [4]
+  void *fs_ws = nullptr;       // [2][nvar][NGPT]
+  void *fflux = nullptr;       // [nvar][NF]
+  void *vjp_ws = nullptr;      // adjoint workspace
+  size_t table_bytes = 0;
+  // launch configuration
+  int lanes = 1, block = 256, list_blocks = 2048;
+  int device = 0, n_cu = 256;
+  std::vector<void *> allocs;
+  std::string err;
+};
+
+namespace hfv {
+
+hfv_status setup_tables(hfv_ctx *ctx, const hfv_mesh *mesh, const hfv_stencils *st, hipStream_t s);
+hfv_status run_reconstruct(hfv_ctx *ctx, const void *U, void *fs, uint8_t *cls, hipStream_t s);
+hfv_status run_residual_tail(hfv_ctx *ctx, const void *fs, void *R, hipStream_t s);
+hfv_status run_vjp(hfv_ctx *ctx, const void *U, const uint8_t *cls, const void *gR, void *gU, hipStream_t s);
+hfv_status dev_alloc(hfv_ctx *ctx, void **p, size_t bytes);
+
+}  // namespace hfv
+
+#define HFV_HIP(call)                                                                 \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess) {                                                           \
+      ctx->err = std::string(#call) + ": " + hipGetErrorString(e_);                   \
+      return HFV_ERR_HIP;                                                             \
+    }                                                                                 \
+  } while (0)

@@ -1,0 +1,240 @@
+"""Python binding of the hfv C ABI (argument marshalling only).
+
+Every step of the reconstruction runs in the HIP library ``libhfv.so``; this
+module converts meshes, stencils and parameters to the ABI structs and hands
+torch device tensors to it.  There is no fallback: a missing or unloadable
+library raises at import of ``load()``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from .inputs.params import Params
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhfv.so")
+_lib = None
+
+HFV_OK = 0
+ERRORS = {-1: "HFV_ERR_PARAM", -2: "HFV_ERR_MESH", -3: "HFV_ERR_RANK", -4: "HFV_ERR_DTYPE",
+          -5: "HFV_ERR_HIP", -6: "HFV_ERR_OOM", -7: "HFV_ERR_STATE"}
+Q = dict(N_CELLS=0, N_FACES=1, N_GP=2, NVAR=3, K=4, M=5, PRECISION=6, DIM=7, TABLE_BYTES=8,
+         COUNT_CWENOZ=9, COUNT_MUSCL=10, COUNT_FIRST=11, NGP_CELL_MAX=12)
+TABLES = dict(PINV=0, OI=1, PSIBAR=2, GEOM=3, PDIR=4, PMUS=5)
+
+_p = C.c_void_p
+_i32p = C.POINTER(C.c_int32)
+_i8p = C.POINTER(C.c_int8)
+_f64p = C.POINTER(C.c_double)
+
+
+class HfvMesh(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n_vertices", C.c_int32), ("n_cells", C.c_int32), ("n_faces", C.c_int32),
+                ("vertices", _f64p), ("cell_type", _i8p), ("cell_vtx_off", _i32p), ("cell_vtx", _i32p),
+                ("face_cells", _i32p), ("face_vtx_off", _i32p), ("face_vtx", _i32p), ("face_shift", _i8p),
+                ("period", _f64p)]
+
+
+class HfvStencils(C.Structure):
+    _fields_ = [("M", C.c_int32), ("nf_max", C.c_int32), ("Md", C.c_int32), ("central", _i32p),
+                ("central_shift", _i8p), ("dir", _i32p), ("dir_shift", _i8p), ("n_dir", _i32p),
+                ("muscl", _i32p), ("muscl_shift", _i8p), ("n_muscl", _i32p)]
+
+
+class HfvParams(C.Structure):
+    _fields_ = [("order_r", C.c_int32), ("scheme_mode", C.c_int32), ("precision", C.c_int32),
+                ("riemann", C.c_int32), ("cweno_form", C.c_int32), ("reserved", C.c_int32),
+                ("gamma", C.c_double), ("alpha_m", C.c_double), ("beta_m", C.c_double), ("alpha_w", C.c_double),
+                ("beta_w", C.c_double), ("kappa", C.c_double), ("n_exp", C.c_double),
+                ("lambda1_prime", C.c_double), ("eps_w", C.c_double), ("b_w", C.c_double),
+                ("tvd_theta", C.c_double), ("tvd_eps", C.c_double)]
+
+
+def load():
+    """Load libhfv.so and declare the ABI; raises if the library is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"hfv HIP library not built: {LIB_PATH} missing (run __graft_entry__.build())")
+    lib = C.CDLL(LIB_PATH)
+    lib.hfv_create.argtypes = [C.POINTER(HfvMesh), C.POINTER(HfvStencils), C.POINTER(HfvParams), _p,
+                               C.POINTER(_p)]
+    lib.hfv_set_params.argtypes = [_p, C.POINTER(HfvParams)]
+    lib.hfv_reconstruct.argtypes = [_p, _p, _p, _p, _p]
+    lib.hfv_residual.argtypes = [_p, _p, _p, _p, _p, _p]
+    lib.hfv_residual_vjp.argtypes = [_p, _p, _p, _p, _p, _p]
+    lib.hfv_query.argtypes = [_p, C.c_int32, C.POINTER(C.c_int64)]
+    lib.hfv_copy_table.argtypes = [_p, C.c_int32, _p, C.c_int64]
+    lib.hfv_set_launch.argtypes = [_p, C.c_int32, C.c_int32, C.c_int32]
+    lib.hfv_last_error.argtypes = [_p]
+    lib.hfv_last_error.restype = C.c_char_p
+    lib.hfv_destroy.argtypes = [_p]
+    lib.hfv_destroy.restype = None
+    for name in ("hfv_create", "hfv_set_params", "hfv_reconstruct", "hfv_residual", "hfv_residual_vjp",
+                 "hfv_query", "hfv_copy_table", "hfv_set_launch"):
+        getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+class HfvError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype)) if a is not None else None
+
+
+def params_struct(p: Params, precision: int) -> HfvParams:
+    return HfvParams(order_r=p.order_r, scheme_mode=p.scheme_mode, precision=precision, riemann=p.riemann,
+                     cweno_form=p.cweno_form, reserved=0, gamma=p.gamma, alpha_m=p.alpha_m, beta_m=p.beta_m,
+                     alpha_w=p.alpha_w, beta_w=p.beta_w, kappa=p.kappa, n_exp=p.n_exp,
+                     lambda1_prime=p.lambda1_prime, eps_w=p.eps_w, b_w=p.b_w, tvd_theta=p.tvd_theta,
+                     tvd_eps=p.tvd_eps)
+
+
+def _stream_handle(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class Context:
+    """A reconstruction context: device tables for one mesh, stencil set, order and precision."""
+
+    def __init__(self, mesh, stencils, params: Params, precision: int = 64, stream=None):
+        import torch
+        self.lib = load()
+        self.precision = precision
+        self.dtype = torch.float64 if precision == 64 else torch.float32
+        self.params = params
+        d = mesh.dim
+        keep = []
+
+        def arr(x, dt):
+            a = np.ascontiguousarray(x, dtype=dt)
+            keep.append(a)
+            return a
+
+        per = arr(mesh.period, np.float64) if mesh.period is not None else None
+        self._mesh = HfvMesh(
+            dim=d, n_vertices=mesh.vertices.shape[0], n_cells=mesh.n_cells, n_faces=mesh.n_faces,
+            vertices=_ptr(arr(mesh.vertices, np.float64), C.c_double),
+            cell_type=_ptr(arr(mesh.cell_type, np.int8), C.c_int8),
+            cell_vtx_off=_ptr(arr(mesh.cell_vtx_off, np.int32), C.c_int32),
+            cell_vtx=_ptr(arr(mesh.cell_vtx, np.int32), C.c_int32),
+            face_cells=_ptr(arr(mesh.face_cells, np.int32), C.c_int32),
+            face_vtx_off=_ptr(arr(mesh.face_vtx_off, np.int32), C.c_int32),
+            face_vtx=_ptr(arr(mesh.face_vtx, np.int32), C.c_int32),
+            face_shift=_ptr(arr(mesh.face_shift, np.int8), C.c_int8) if per is not None else None,
+            period=_ptr(per, C.c_double) if per is not None else None)
+        st = stencils
+        self._st = HfvStencils(
+            M=st.M, nf_max=st.dir.shape[1], Md=st.Md,
+            central=_ptr(arr(st.central, np.int32), C.c_int32),
+            central_shift=_ptr(arr(st.central_shift, np.int8), C.c_int8) if per is not None else None,
+            dir=_ptr(arr(st.dir, np.int32), C.c_int32),
+            dir_shift=_ptr(arr(st.dir_shift, np.int8), C.c_int8) if per is not None else None,
+            n_dir=_ptr(arr(st.n_dir, np.int32), C.c_int32),
+            muscl=_ptr(arr(st.muscl, np.int32), C.c_int32),
+            muscl_shift=_ptr(arr(st.muscl_shift, np.int8), C.c_int8) if per is not None else None,
+            n_muscl=_ptr(arr(st.n_muscl, np.int32), C.c_int32))
+        self._p = params_struct(params, precision)
+        h = C.c_void_p()
+        torch.cuda.init()
+        rc = self.lib.hfv_create(C.byref(self._mesh), C.byref(self._st), C.byref(self._p),
+                                 _stream_handle(stream), C.byref(h))
+        if rc != HFV_OK:
+            raise HfvError(rc, self.lib.hfv_last_error(None).decode())
+        self.h = h
+        self.n_cells = self.query("N_CELLS")
+        self.n_faces = self.query("N_FACES")
+        self.n_gp = self.query("N_GP")
+        self.nvar = self.query("NVAR")
+        self.K = self.query("K")
+        self.M = self.query("M")
+        self.dim = d
+
+    def _check(self, rc):
+        if rc != HFV_OK:
+            raise HfvError(rc, self.lib.hfv_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.hfv_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def query(self, what: str) -> int:
+        out = C.c_int64()
+        self._check(self.lib.hfv_query(self.h, Q[what], C.byref(out)))
+        return out.value
+
+    def set_params(self, params: Params):
+        self.params = params
+        self._p = params_struct(params, self.precision)
+        self._check(self.lib.hfv_set_params(self.h, C.byref(self._p)))
+
+    def set_launch(self, lanes=0, block=0, list_blocks=0):
+        self._check(self.lib.hfv_set_launch(self.h, lanes, block, list_blocks))
+
+    def table(self, name: str) -> np.ndarray:
+        N, K, M, d = self.n_cells, self.K, self.M, self.dim
+        nfm = 4 if d == 2 else 6
+        shapes = dict(PINV=(K, M, N), OI=(K * (K + 1) // 2, N), PSIBAR=(K, N), GEOM=(d + 2, N),
+                      PDIR=(nfm, d, 2 * d, N), PMUS=(d, nfm, N))
+        dt = np.float64 if (name == "GEOM" or self.precision == 64) else np.float32
+        out = np.empty(shapes[name], dt)
+        self._check(self.lib.hfv_copy_table(self.h, TABLES[name], out.ctypes.data_as(C.c_void_p), out.nbytes))
+        return out
+
+    def _chk_u(self, U):
+        import torch
+        if U.dtype != self.dtype or not U.is_cuda or tuple(U.shape) != (self.nvar, self.n_cells) \
+                or not U.is_contiguous():
+            raise HfvError(-4, f"U must be a contiguous {self.dtype} CUDA tensor of shape "
+                               f"({self.nvar}, {self.n_cells})")
+        return U
+
+    def new_face_states(self):
+        import torch
+        return torch.empty((2, self.nvar, self.n_gp), dtype=self.dtype, device="cuda")
+
+    def reconstruct(self, U, face_states=None, cell_class=None, stream=None):
+        import torch
+        self._chk_u(U)
+        fs = face_states if face_states is not None else self.new_face_states()
+        cls = cell_class if cell_class is not None else torch.empty(self.n_cells, dtype=torch.uint8,
+                                                                     device="cuda")
+        self._check(self.lib.hfv_reconstruct(self.h, C.c_void_p(U.data_ptr()), C.c_void_p(fs.data_ptr()),
+                                             C.c_void_p(cls.data_ptr()), _stream_handle(stream)))
+        return fs, cls
+
+    def residual(self, U, R=None, face_states=None, cell_class=None, stream=None):
+        import torch
+        self._chk_u(U)
+        R = R if R is not None else torch.empty_like(U)
+        fsp = C.c_void_p(face_states.data_ptr()) if face_states is not None else None
+        clp = C.c_void_p(cell_class.data_ptr()) if cell_class is not None else None
+        self._check(self.lib.hfv_residual(self.h, C.c_void_p(U.data_ptr()), C.c_void_p(R.data_ptr()), fsp, clp,
+                                          _stream_handle(stream)))
+        return R
+
+    def residual_vjp(self, U, cell_class, gR, gU=None, stream=None):
+        import torch
+        self._chk_u(U)
+        gU = gU if gU is not None else torch.empty_like(U)
+        self._check(self.lib.hfv_residual_vjp(self.h, C.c_void_p(U.data_ptr()), C.c_void_p(cell_class.data_ptr()),
+                                              C.c_void_p(gR.data_ptr()), C.c_void_p(gU.data_ptr()),
+                                              _stream_handle(stream)))
+        return gU

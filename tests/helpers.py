@@ -1,0 +1,54 @@
+"""Shared test helpers: tolerance checks and near-threshold accounting."""
+from __future__ import annotations
+
+import numpy as np
+
+
+def state_scale(U):
+    """S_v = max over cells of |U_v|  (floor for zero-mean components)."""
+    return np.abs(U).max(0)
+
+
+def rel_err(x, ref, scale_b):
+    """max |x - ref| / max(|ref|, S_v); ``scale_b`` is S_v broadcast against ``ref``."""
+    den = np.maximum(np.abs(ref), scale_b)
+    return float(np.nanmax(np.abs(x - ref) / den))
+
+
+def cell_face_values(fs, geo, cells):
+    """Per-cell Gauss-point values [n, NGPC, nvar] gathered from face states [2, nvar, NGPT]."""
+    out = np.full((len(cells), geo.c_gidx.shape[1], fs.shape[1]), np.nan)
+    for i, c in enumerate(cells):
+        k = geo.c_ngp[c]
+        out[i, :k] = fs[geo.c_side[c, :k], :, geo.c_gidx[c, :k]]
+    return out
+
+
+def near_threshold(om, U, cells, tol):
+    """Cells whose class decision lies within ``tol`` (relative) of a threshold.
+
+    NAD: |d - delta_w| or |d - delta_m| within tol * S with S = max(|m|, |M|, R)
+    for a variable whose stencil range is non-zero; deactivation:
+    |dU - (kappa h)^n| within tol * max(dU, (kappa h)^n); Harten: any point of
+    the linear candidate within tol of its bound.
+    """
+    own, info = om.own_class(cells, U)
+    S = np.maximum(np.maximum(np.abs(info["m"]), np.abs(info["M"])), info["R"])
+    live = info["R"] > 0
+    dv = info["dv"]
+    nad = live & ((np.abs(dv - info["wmarg"]) <= tol * S) | (np.abs(dv - info["dmarg"]) <= tol * S))
+    flag = nad.any(1)
+    flag |= np.abs(info["dU"] - info["thr"]) <= tol * np.maximum(info["dU"], info["thr"])
+    _, fv, _ = om.linear(cells, U)
+    g = om.p.gamma
+    ngp = om.geo.c_ngp[cells]
+    valid = np.arange(fv.shape[1])[None, :] < ngp[:, None]
+    Ub = U[cells]
+    rb = Ub[:, 0][:, None]
+    pb = ((g - 1) * (Ub[:, -1] - 0.5 * (Ub[:, 1:-1] ** 2).sum(1) / Ub[:, 0]))[:, None]
+    with np.errstate(all="ignore"):
+        pr = (g - 1) * (fv[..., -1] - 0.5 * (fv[..., 1:-1] ** 2).sum(-1) / fv[..., 0])
+        hr = np.abs(np.abs(fv[..., 0] - rb) - om.p.tvd_theta * np.abs(rb)) <= tol * np.abs(rb)
+        hp = np.abs(np.abs(pr - pb) - om.p.tvd_theta * np.abs(pb)) <= tol * np.abs(pb)
+    flag |= np.any(valid & (hr | hp), axis=1)
+    return flag

@@ -1,0 +1,197 @@
+"""GPU path (through the C ABI) against the FP64 oracle.
+
+FP64: classes bit-exact, states and residuals within 1e-12 relative
+(|x - x_ref| <= 1e-12 max(|x_ref|, S_v), S_v = max_cells |U_v|).
+FP32: states within 1e-5 relative, class flips only in cells flagged within
+1e-6 of a threshold (or their face neighbours, through the tagging step).
+"""
+import numpy as np
+import pytest
+
+from helpers import state_scale, rel_err, cell_face_values, near_threshold
+from oracle import OracleModel, flux
+from paper_2510_25906_amd.inputs import configs, fields
+from paper_2510_25906_amd.inputs.params import HYBRID, ALL_LINEAR, ALL_CWENOZ, ALL_MUSCL, preset
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def hfv():
+    from paper_2510_25906_amd import hfv as H
+    H.load()
+    assert torch.cuda.is_available()
+    return H
+
+
+def to_dev(U, dtype):
+    return torch.tensor(np.ascontiguousarray(U.T), dtype=dtype, device="cuda")
+
+
+def dilated_flags(om, flags_cells, cells):
+    out = flags_cells.copy()
+    idx = {int(c): i for i, c in enumerate(cells)}
+    for i, c in enumerate(cells):
+        for j in om.nbr[c]:
+            if j >= 0 and int(j) in idx and flags_cells[idx[int(j)]]:
+                out[i] = True
+    return out
+
+
+@pytest.fixture(scope="module")
+def c1():
+    w = configs.c1_density_jump(32, 2)
+    om = OracleModel(w.mesh, w.stencils, w.params)
+    return w, om
+
+
+@pytest.mark.parametrize("mode", [HYBRID, ALL_LINEAR, ALL_CWENOZ, ALL_MUSCL])
+def test_c1_fp64_reconstruct_and_residual(hfv, c1, mode):
+    w, om0 = c1
+    p = w.params.with_(scheme_mode=mode)
+    om = OracleModel(w.mesh, w.stencils, p)
+    om._tab = om0._tab
+    R_o, fs_o, cls_o = flux.residual(om, w.U)
+    print(f"c1 fp64 mode={mode} classes={np.bincount(cls_o, minlength=4)}", flush=True)
+    flags = near_threshold(om, w.U, np.arange(w.mesh.n_cells), 1e-12)
+    assert not flags.any(), "seed has FP64 near-ties; choose another"
+    ctx = hfv.Context(w.mesh, w.stencils, p, 64)
+    Ud = to_dev(w.U, torch.float64)
+    fs = ctx.new_face_states()
+    cls = torch.empty(w.mesh.n_cells, dtype=torch.uint8, device="cuda")
+    R = ctx.residual(Ud, face_states=fs, cell_class=cls)
+    torch.cuda.synchronize()
+    cls_g = cls.cpu().numpy()
+    assert np.array_equal(cls_g, cls_o), np.nonzero(cls_g != cls_o)[0][:20]
+    S = state_scale(w.U)
+    assert rel_err(fs.cpu().numpy(), fs_o, S[None, :, None]) <= 1e-12
+    assert rel_err(R.cpu().numpy(), R_o, np.abs(R_o).max(1)[:, None]) <= 1e-11
+    ctx.close()
+
+
+def test_c1_tables_match_oracle(hfv, c1):
+    w, om = c1
+    ctx = hfv.Context(w.mesh, w.stencils, w.params, 64)
+    cells = np.arange(w.mesh.n_cells)
+    tab = om.tables(cells)
+    P = ctx.table("PINV")                    # [K, M, N]
+    Po = np.transpose(tab["P"], (1, 2, 0))
+    assert np.abs(P - Po).max() <= 1e-12 * np.abs(Po).max()
+    OI = ctx.table("OI")
+    K = om.K
+    iu = np.triu_indices(K)
+    OIo = tab["OI"][:, iu[0], iu[1]].T
+    assert np.abs(OI - OIo).max() <= 1e-12 * np.abs(OIo).max()
+    geom = ctx.table("GEOM")
+    assert np.allclose(geom[:2].T, om.geo.cen, rtol=0, atol=1e-14)
+    assert np.allclose(geom[2], om.geo.vol, rtol=1e-13)
+    Pd = ctx.table("PDIR")                   # [NFM, d, Md, N]
+    assert np.abs(Pd - np.transpose(tab["Pdir"], (1, 2, 3, 0))).max() <= 1e-11 * np.abs(Pd).max()
+    Pm = ctx.table("PMUS")                   # [d, NFM, N]
+    assert np.abs(Pm - np.transpose(tab["Pmus"], (1, 2, 0))).max() <= 1e-11 * np.abs(Pm).max()
+    ctx.close()
+
+
+@pytest.mark.parametrize("lanes", [1, 2, 4])
+def test_c1_launch_shapes_agree(hfv, c1, lanes):
+    w, _ = c1
+    ctx = hfv.Context(w.mesh, w.stencils, w.params, 64)
+    Ud = to_dev(w.U, torch.float64)
+    fs0, c0 = ctx.reconstruct(Ud)
+    ctx.set_launch(lanes=lanes, block=128, list_blocks=3)
+    fs1, c1_ = ctx.reconstruct(Ud)
+    torch.cuda.synchronize()
+    assert torch.equal(c0, c1_)
+    assert torch.allclose(fs0, fs1, rtol=1e-13, atol=1e-13)
+    ctx.close()
+
+
+def test_c1_fp32(hfv, c1):
+    w, om = c1
+    R_o, fs_o, cls_o = flux.residual(om, w.U)
+    cells = np.arange(w.mesh.n_cells)
+    flags = dilated_flags(om, near_threshold(om, w.U, cells, 1e-6), cells)
+    ctx = hfv.Context(w.mesh, w.stencils, w.params, 32)
+    Ud = to_dev(w.U, torch.float32)
+    fs = ctx.new_face_states()
+    cls = torch.empty(w.mesh.n_cells, dtype=torch.uint8, device="cuda")
+    R = ctx.residual(Ud, face_states=fs, cell_class=cls)
+    torch.cuda.synchronize()
+    cls_g = cls.cpu().numpy()
+    flip = cls_g != cls_o
+    assert not np.any(flip & ~flags), np.nonzero(flip & ~flags)[0][:10]
+    ok = ~flip
+    S = state_scale(w.U)
+    fv_g = cell_face_values(fs.cpu().numpy().astype(np.float64), om.geo, cells)
+    fv_o = cell_face_values(fs_o, om.geo, cells)
+    assert rel_err(fv_g[ok], fv_o[ok], S[None, None, :]) <= 1e-5
+    ctx.close()
+
+
+def test_c2_sampled_full_size(hfv):
+    """85k-cell mixed mesh, r = 3, in the benchmark's launch shape: sampled cells."""
+    w = configs.c2_riemann(256, 3)
+    rng = np.random.default_rng(7)
+    for prec, tol in ((64, 1e-12), (32, 1e-5)):
+        for mode in (HYBRID, ALL_CWENOZ, ALL_LINEAR):
+            p = w.params.with_(scheme_mode=mode)
+            om = OracleModel(w.mesh, w.stencils, p)
+            cells = np.unique(np.concatenate([rng.choice(w.mesh.n_cells, 300, replace=False),
+                                              np.arange(0, 40)]))
+            fv_o, cls_o = om.reconstruct_cells(cells, w.U)
+            flags = dilated_flags(om, near_threshold(om, w.U, cells, 1e-12 if prec == 64 else 1e-6), cells)
+            print(f"c2 prec={prec} mode={mode} sampled={cells.size} flagged={flags.sum()}", flush=True)
+            ctx = hfv.Context(w.mesh, w.stencils, p, prec)
+            Ud = to_dev(w.U, torch.float64 if prec == 64 else torch.float32)
+            fs, cls = ctx.reconstruct(Ud)
+            torch.cuda.synchronize()
+            cls_g = cls.cpu().numpy()[cells]
+            flip = cls_g != cls_o
+            if prec == 64:
+                assert not flip.any(), cells[flip][:10]
+            else:
+                assert not np.any(flip & ~flags)
+            fv_g = cell_face_values(fs.cpu().numpy().astype(np.float64), om.geo, cells)
+            S = state_scale(w.U)
+            ok = ~flip
+            assert rel_err(fv_g[ok], fv_o[ok], S[None, None, :]) <= tol
+            ctx.close()
+
+
+def test_free_stream_and_conservation(hfv):
+    w = configs.c1_density_jump(32, 2)
+    ctx = hfv.Context(w.mesh, w.stencils, w.params, 64)
+    U = np.tile(fields.prim_to_cons(np.array([1.3, 0.4, -0.2, 2.0])), (w.mesh.n_cells, 1))
+    R = ctx.residual(to_dev(U, torch.float64)).cpu().numpy()
+    assert np.abs(R).max() < 1e-12
+    R2 = ctx.residual(to_dev(w.U, torch.float64)).cpu().numpy()
+    vol = ctx.table("GEOM")[2]
+    assert np.abs((R2 * vol).sum(1)).max() < 1e-12 * np.abs(R2 * vol).sum()
+    ctx.close()
+
+
+def test_harten_fallback_on_negative_density(hfv):
+    w = configs.c1_density_jump(32, 2)
+    U = w.U.copy()
+    U[37, 0] = -0.5
+    ctx = hfv.Context(w.mesh, w.stencils, w.params, 64)
+    fs, cls = ctx.reconstruct(to_dev(U, torch.float64))
+    torch.cuda.synchronize()
+    assert int(cls[37]) == 3
+    ctx.close()
+
+
+def test_rank_deficient_stencil_is_reported(hfv):
+    w = configs.c1_density_jump(8, 2)
+    st = w.stencils
+    bad = st.central.copy()
+    bad[5, :] = bad[5, 0]  # every stencil member the same cell
+    from dataclasses import replace
+    shift = st.central_shift.copy()
+    shift[5, :] = shift[5, 0]
+    st2 = replace(st, central=bad, central_shift=shift)
+    with pytest.raises(hfv.HfvError) as ei:
+        hfv.Context(w.mesh, st2, w.params, 64)
+    assert "HFV_ERR_RANK" in str(ei.value) and "cell 5" in str(ei.value)
