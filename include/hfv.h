@@ -186,6 +186,19 @@ hfv_status hfv_copy_table(const hfv_ctx *ctx, int32_t which, void *host_dst, int
  * current value. */
 hfv_status hfv_set_launch(hfv_ctx *ctx, int32_t lanes_per_cell, int32_t block, int32_t list_blocks);
 
+/* Kernel timing with HIP events recorded on the launch stream.
+ * hfv_profile_enable arms up to `capacity` timed launches of the kernels
+ * selected by `slot_mask` (bit i = HFV_SLOT_i); capacity 0 disables.
+ * hfv_profile_read synchronises on the recorded events, writes per-slot sums
+ * of the launch durations in milliseconds and launch counts (arrays of
+ * HFV_NSLOTS), and re-arms the buffer. */
+enum {
+  HFV_SLOT_LINEAR = 0, HFV_SLOT_CLASSIFY = 1, HFV_SLOT_CWENOZ = 2, HFV_SLOT_MUSCL = 3, HFV_SLOT_FIRST = 4,
+  HFV_SLOT_FLUX = 5, HFV_SLOT_GATHER = 6, HFV_SLOT_VJP = 7, HFV_NSLOTS = 8
+};
+hfv_status hfv_profile_enable(hfv_ctx *ctx, int32_t capacity, int32_t slot_mask);
+hfv_status hfv_profile_read(hfv_ctx *ctx, double *ms_sum, int64_t *launches);
+
 /* Message of the last failure on this context (or of the last failed
  * create when ctx is NULL); never NULL. */
 const char *hfv_last_error(const hfv_ctx *ctx);

@@ -279,10 +279,52 @@ hfv_status hfv_copy_table(const hfv_ctx *ctx, int32_t which, void *dst, int64_t 
   return HFV_OK;
 }
 
+hfv_status hfv_profile_enable(hfv_ctx *ctx, int32_t capacity, int32_t slot_mask) {
+  if (!ctx || capacity < 0) return HFV_ERR_PARAM;
+  for (auto &e : ctx->prof_pool) {
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
+  }
+  ctx->prof_pool.clear();
+  ctx->prof_next = 0;
+  ctx->prof_mask = capacity > 0 ? slot_mask : 0;
+  for (int i = 0; i < capacity; ++i) {
+    hfv_ctx::ProfEv e{0, nullptr, nullptr};
+    if (hipEventCreate(&e.a) != hipSuccess || hipEventCreate(&e.b) != hipSuccess) {
+      ctx->err = "hipEventCreate failed";
+      return HFV_ERR_HIP;
+    }
+    ctx->prof_pool.push_back(e);
+  }
+  return HFV_OK;
+}
+
+hfv_status hfv_profile_read(hfv_ctx *ctx, double *ms_sum, int64_t *launches) {
+  if (!ctx || !ms_sum || !launches) return HFV_ERR_PARAM;
+  for (int i = 0; i < HFV_NSLOTS; ++i) {
+    ms_sum[i] = 0;
+    launches[i] = 0;
+  }
+  for (int i = 0; i < ctx->prof_next; ++i) {
+    auto &e = ctx->prof_pool[i];
+    if (hipEventSynchronize(e.b) != hipSuccess) return ctx->err = "hipEventSynchronize failed", HFV_ERR_HIP;
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, e.a, e.b) != hipSuccess) return ctx->err = "hipEventElapsedTime failed", HFV_ERR_HIP;
+    ms_sum[e.slot] += ms;
+    launches[e.slot] += 1;
+  }
+  ctx->prof_next = 0;
+  return HFV_OK;
+}
+
 const char *hfv_last_error(const hfv_ctx *ctx) { return ctx ? ctx->err.c_str() : g_create_err.c_str(); }
 
 void hfv_destroy(hfv_ctx *ctx) {
   if (!ctx) return;
+  for (auto &e : ctx->prof_pool) {
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
+  }
   for (void *p : ctx->allocs) (void)hipFree(p);
   delete ctx;
 }

@@ -259,8 +259,9 @@ __global__ __launch_bounds__(256) void k_linear(HotArgs<T> a) {
 }
 
 // K2: final class (dilation over face neighbours) and per-class lists.
+constexpr int CLASSIFY_BLOCK = 1024;
 template <typename T>
-__global__ __launch_bounds__(256) void k_classify(HotArgs<T> a, int nfm) {
+__global__ __launch_bounds__(CLASSIFY_BLOCK) void k_classify(HotArgs<T> a, int nfm) {
   const int cell = blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = cell < a.N;
   int c = 0;
@@ -279,18 +280,35 @@ __global__ __launch_bounds__(256) void k_classify(HotArgs<T> a, int nfm) {
     if (c == HFV_CLASS_LINEAR && (o & 4)) c = HFV_CLASS_FIRST_ORDER;
     a.cls[cell] = (uint8_t)c;
   }
-  const int lane = threadIdx.x & 63;
+  // Compaction: wave ballots give each lane its rank inside the wave; the
+  // waves of the block combine their counts in LDS and the block reserves its
+  // range of each list with one atomic per class.
+  constexpr int NW = CLASSIFY_BLOCK / 64;
+  __shared__ int wcount[3][NW];
+  __shared__ int wbase[3][NW];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  unsigned long long masks[3];
 #pragma unroll
-  for (int k = 1; k <= 3; ++k) {
-    const unsigned long long mask = __ballot(valid && c == k);
-    if (mask) {
-      const int leader = __ffsll((long long)mask) - 1;
-      int basepos = 0;
-      if (lane == leader) basepos = atomicAdd(&a.counts[k], __popcll(mask));
-      basepos = __shfl(basepos, leader);
-      if (valid && c == k) a.lists[(long)(k - 1) * a.N + basepos + __popcll(mask & lt)] = cell;
+  for (int k = 0; k < 3; ++k) {
+    masks[k] = __ballot(valid && c == k + 1);
+    if (lane == 0) wcount[k][wave] = __popcll(masks[k]);
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    const int k = threadIdx.x;
+    int tot = 0;
+    for (int w = 0; w < NW; ++w) {
+      wbase[k][w] = tot;
+      tot += wcount[k][w];
     }
+    const int start = tot ? atomicAdd(&a.counts[k + 1], tot) : 0;
+    for (int w = 0; w < NW; ++w) wbase[k][w] += start;
+  }
+  __syncthreads();
+  if (valid && c >= 1) {
+    const int k = c - 1;
+    a.lists[(long)k * a.N + wbase[k][wave] + __popcll(masks[k] & lt)] = cell;
   }
 }
 
@@ -754,18 +772,18 @@ static hfv_status recon_impl(hfv_ctx *ctx, Tables<T> &t, const void *U, void *fs
   const int mode = ctx->p.mode;
   if (mode == HFV_ALL_CWENOZ) {
     k_zero4<<<1, 64, 0, s>>>(ctx->counts);
-    k_cwenoz<DIM, R, T, G><<<grid_list, B, 0, s>>>(a, 1);
+    { ProfScope ps(ctx, HFV_SLOT_CWENOZ, s); k_cwenoz<DIM, R, T, G><<<grid_list, B, 0, s>>>(a, 1); }
   } else if (mode == HFV_ALL_MUSCL) {
     k_zero4<<<1, 64, 0, s>>>(ctx->counts);
-    k_muscl<DIM, R, T, G><<<grid_list, B, 0, s>>>(a, 1);
+    { ProfScope ps(ctx, HFV_SLOT_MUSCL, s); k_muscl<DIM, R, T, G><<<grid_list, B, 0, s>>>(a, 1); }
   } else {
-    k_linear<DIM, R, T, G><<<grid_cells, B, 0, s>>>(a);
-    k_classify<T><<<nblk(ctx->N, 256), 256, 0, s>>>(a, ctx->NFM);
+    { ProfScope ps(ctx, HFV_SLOT_LINEAR, s); k_linear<DIM, R, T, G><<<grid_cells, B, 0, s>>>(a); }
+    { ProfScope ps(ctx, HFV_SLOT_CLASSIFY, s); k_classify<T><<<nblk(ctx->N, CLASSIFY_BLOCK), CLASSIFY_BLOCK, 0, s>>>(a, ctx->NFM); }
     if (mode == HFV_HYBRID) {
-      k_cwenoz<DIM, R, T, G><<<grid_list, B, 0, s>>>(a, 0);
-      k_muscl<DIM, R, T, G><<<grid_list, B, 0, s>>>(a, 0);
+      { ProfScope ps(ctx, HFV_SLOT_CWENOZ, s); k_cwenoz<DIM, R, T, G><<<grid_list, B, 0, s>>>(a, 0); }
+      { ProfScope ps(ctx, HFV_SLOT_MUSCL, s); k_muscl<DIM, R, T, G><<<grid_list, B, 0, s>>>(a, 0); }
     }
-    k_first<DIM + 2, T><<<std::min<unsigned>(nblk(ctx->N, 256), 1024), 256, 0, s>>>(a);
+    { ProfScope ps(ctx, HFV_SLOT_FIRST, s); k_first<DIM + 2, T><<<std::min<unsigned>(nblk(ctx->N, 256), 1024), 256, 0, s>>>(a); }
   }
   HFV_HIP(hipGetLastError());
   return HFV_OK;
@@ -810,14 +828,19 @@ template <typename T>
 static hfv_status tail_t(hfv_ctx *ctx, Tables<T> &t, const void *fs, void *R, hipStream_t s) {
   const int hllc = ctx->p.riemann == HFV_HLLC;
   T *Ff = (T *)ctx->fflux;
+  const unsigned gf = nblk(ctx->NF, 256), gc = nblk(ctx->N, 256);
   if (ctx->dim == 2) {
-    k_flux<2, T><<<nblk(ctx->NF, 256), 256, 0, s>>>(ctx->NF, ctx->NGPT, (const T *)fs, t.gp_off, t.fnormal, t.gpw,
-                                                     (T)ctx->p.gamma, hllc, Ff);
-    k_gather<4, T><<<nblk(ctx->N, 256), 256, 0, s>>>(ctx->N, ctx->NF, t.cf_off, t.cf, Ff, t.ivol, (T *)R);
+    { ProfScope ps(ctx, HFV_SLOT_FLUX, s);
+      k_flux<2, T><<<gf, 256, 0, s>>>(ctx->NF, ctx->NGPT, (const T *)fs, t.gp_off, t.fnormal, t.gpw,
+                                       (T)ctx->p.gamma, hllc, Ff); }
+    { ProfScope ps(ctx, HFV_SLOT_GATHER, s);
+      k_gather<4, T><<<gc, 256, 0, s>>>(ctx->N, ctx->NF, t.cf_off, t.cf, Ff, t.ivol, (T *)R); }
   } else {
-    k_flux<3, T><<<nblk(ctx->NF, 256), 256, 0, s>>>(ctx->NF, ctx->NGPT, (const T *)fs, t.gp_off, t.fnormal, t.gpw,
-                                                     (T)ctx->p.gamma, hllc, Ff);
-    k_gather<5, T><<<nblk(ctx->N, 256), 256, 0, s>>>(ctx->N, ctx->NF, t.cf_off, t.cf, Ff, t.ivol, (T *)R);
+    { ProfScope ps(ctx, HFV_SLOT_FLUX, s);
+      k_flux<3, T><<<gf, 256, 0, s>>>(ctx->NF, ctx->NGPT, (const T *)fs, t.gp_off, t.fnormal, t.gpw,
+                                       (T)ctx->p.gamma, hllc, Ff); }
+    { ProfScope ps(ctx, HFV_SLOT_GATHER, s);
+      k_gather<5, T><<<gc, 256, 0, s>>>(ctx->N, ctx->NF, t.cf_off, t.cf, Ff, t.ivol, (T *)R); }
   }
   HFV_HIP(hipGetLastError());
   return HFV_OK;

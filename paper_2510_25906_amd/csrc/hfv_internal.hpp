@@ -107,6 +107,13 @@ struct hfv_ctx {
   // launch configuration
   int lanes = 1, block = 256, list_blocks = 2048;
   int device = 0, n_cu = 256;
+  // kernel timing (hfv_profile_*)
+  struct ProfEv {
+    int slot;
+    hipEvent_t a, b;
+  };
+  std::vector<ProfEv> prof_pool;
+  int prof_next = 0, prof_mask = 0;
   std::vector<void *> allocs;
   std::string err;
 };
@@ -118,6 +125,23 @@ hfv_status run_reconstruct(hfv_ctx *ctx, const void *U, void *fs, uint8_t *cls, 
 hfv_status run_residual_tail(hfv_ctx *ctx, const void *fs, void *R, hipStream_t s);
 hfv_status run_vjp(hfv_ctx *ctx, const void *U, const uint8_t *cls, const void *gR, void *gU, hipStream_t s);
 hfv_status dev_alloc(hfv_ctx *ctx, void **p, size_t bytes);
+
+// Brackets one kernel launch with HIP events when its slot is being timed.
+struct ProfScope {
+  hfv_ctx *ctx;
+  hipStream_t s;
+  int idx = -1;
+  ProfScope(hfv_ctx *c, int slot, hipStream_t st) : ctx(c), s(st) {
+    if ((c->prof_mask >> slot) & 1 && c->prof_next < (int)c->prof_pool.size()) {
+      idx = c->prof_next++;
+      c->prof_pool[idx].slot = slot;
+      (void)hipEventRecord(c->prof_pool[idx].a, s);
+    }
+  }
+  ~ProfScope() {
+    if (idx >= 0) (void)hipEventRecord(ctx->prof_pool[idx].b, s);
+  }
+};
 
 }  // namespace hfv
 

@@ -22,6 +22,7 @@ ERRORS = {-1: "HFV_ERR_PARAM", -2: "HFV_ERR_MESH", -3: "HFV_ERR_RANK", -4: "HFV_
           -5: "HFV_ERR_HIP", -6: "HFV_ERR_OOM", -7: "HFV_ERR_STATE"}
 Q = dict(N_CELLS=0, N_FACES=1, N_GP=2, NVAR=3, K=4, M=5, PRECISION=6, DIM=7, TABLE_BYTES=8,
          COUNT_CWENOZ=9, COUNT_MUSCL=10, COUNT_FIRST=11, NGP_CELL_MAX=12)
+SLOTS = dict(linear=0, classify=1, cwenoz=2, muscl=3, first=4, flux=5, gather=6, vjp=7)
 TABLES = dict(PINV=0, OI=1, PSIBAR=2, GEOM=3, PDIR=4, PMUS=5)
 
 _p = C.c_void_p
@@ -69,12 +70,14 @@ def load():
     lib.hfv_query.argtypes = [_p, C.c_int32, C.POINTER(C.c_int64)]
     lib.hfv_copy_table.argtypes = [_p, C.c_int32, _p, C.c_int64]
     lib.hfv_set_launch.argtypes = [_p, C.c_int32, C.c_int32, C.c_int32]
+    lib.hfv_profile_enable.argtypes = [_p, C.c_int32, C.c_int32]
+    lib.hfv_profile_read.argtypes = [_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     lib.hfv_last_error.argtypes = [_p]
     lib.hfv_last_error.restype = C.c_char_p
     lib.hfv_destroy.argtypes = [_p]
     lib.hfv_destroy.restype = None
     for name in ("hfv_create", "hfv_set_params", "hfv_reconstruct", "hfv_residual", "hfv_residual_vjp",
-                 "hfv_query", "hfv_copy_table", "hfv_set_launch"):
+                 "hfv_query", "hfv_copy_table", "hfv_set_launch", "hfv_profile_enable", "hfv_profile_read"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -187,6 +190,17 @@ class Context:
 
     def set_launch(self, lanes=0, block=0, list_blocks=0):
         self._check(self.lib.hfv_set_launch(self.h, lanes, block, list_blocks))
+
+    def profile_enable(self, capacity: int, slots=None):
+        mask = 0xff if slots is None else sum(1 << SLOTS[k] for k in slots)
+        self._check(self.lib.hfv_profile_enable(self.h, capacity, mask))
+
+    def profile_read(self):
+        """{slot: (total ms, launches)} of the timed launches since the last read."""
+        ms = (C.c_double * 8)()
+        n = (C.c_int64 * 8)()
+        self._check(self.lib.hfv_profile_read(self.h, ms, n))
+        return {k: (ms[i], n[i]) for k, i in SLOTS.items() if n[i]}
 
     def table(self, name: str) -> np.ndarray:
         N, K, M, d = self.n_cells, self.K, self.M, self.dim
