@@ -103,10 +103,12 @@ def _dirichlet_terms(alpha: tuple, d: int):
     return np.array(coefs), np.array(exps)
 
 
-def simplex_monomial_integrals(S: np.ndarray, exps: np.ndarray) -> np.ndarray:
-    """Exact integrals of x^alpha over simplices.
+def simplex_monomial_integrals_expanded(S: np.ndarray, exps: np.ndarray) -> np.ndarray:
+    """Exact integrals of x^alpha over simplices by the full multinomial
+    expansion in the barycentric coordinates of all d+1 vertices.
 
     S: [n, d+1, d] simplex vertices; exps: [K, d] exponents.  Returns [n, K].
+    (Slow; kept as an independent check of ``simplex_monomial_integrals``.)
     """
     n, dp1, d = S.shape
     J = S[:, 1:] - S[:, :1]
@@ -124,4 +126,71 @@ def simplex_monomial_integrals(S: np.ndarray, exps: np.ndarray) -> np.ndarray:
         for c, e in zip(coef, E):
             acc += c * np.prod(pw[:, li, ji, e].reshape(n, -1), axis=1)
         out[:, k] = factorial(d) * vol * acc
+    return out
+
+
+@lru_cache(maxsize=None)
+def _ref_simplex_tables(d: int, deg: int):
+    """Exponents kappa (|kappa| <= deg) of the reference-simplex coordinates,
+    their exact integrals kappa! / (d + |kappa|)! over the unit simplex, and the
+    index shift tables for multiplying by one coordinate."""
+    ks = [k for k in itertools.product(range(deg + 1), repeat=d) if sum(k) <= deg]
+    ks.sort(key=lambda k: (sum(k), tuple(-x for x in k)))
+    index = {k: i for i, k in enumerate(ks)}
+    ref = np.array([np.prod([factorial(x) for x in k]) / factorial(d + sum(k)) for k in ks])
+    # up[l][i] = index of kappa_i + e_l (or -1 when the degree would exceed deg)
+    up = np.full((d, len(ks)), -1, np.int64)
+    for i, k in enumerate(ks):
+        for l in range(d):
+            kk = list(k)
+            kk[l] += 1
+            up[l, i] = index.get(tuple(kk), -1)
+    return ks, ref, up
+
+
+def simplex_monomial_integrals(S: np.ndarray, exps: np.ndarray) -> np.ndarray:
+    """Exact integrals of x^alpha over simplices.
+
+    With x = v_0 + J lam (lam the coordinates of the reference simplex), x^alpha
+    is a polynomial in lam, built exactly by multiplying one affine factor
+    x_j = v_0j + sum_l J_jl lam_l at a time; every lam^kappa then integrates to
+    kappa! / (d + |kappa|)! over the reference simplex (the Dirichlet
+    integral), and the result is scaled by |det J|.
+
+    S: [n, d+1, d] simplex vertices; exps: [K, d] exponents.  Returns [n, K].
+    """
+    n, dp1, d = S.shape
+    if len(exps) == 0:
+        return np.zeros((n, 0))
+    J = S[:, 1:] - S[:, :1]           # J[:, l, j] = v_{l+1, j} - v_{0, j}
+    detJ = np.abs(np.linalg.det(J))
+    maxdeg = int(exps.sum(1).max())
+    ks, ref, up = _ref_simplex_tables(d, maxdeg)
+    nk = len(ks)
+    # polynomials are stored coefficient-major: [n_kappa, n_simplices]
+    polys = {(0,) * d: np.zeros((nk, n))}
+    polys[(0,) * d][0, :] = 1.0
+    srcs = [np.nonzero(up[l] >= 0)[0] for l in range(d)]
+
+    def mul_coord(P, j):
+        """P(lam) * (v_0j + sum_l J_lj lam_l)."""
+        out = P * S[:, 0, j][None, :]
+        for l in range(d):
+            src = srcs[l]
+            out[up[l, src]] += P[src] * J[:, l, j][None, :]
+        return out
+
+    def get(alpha):
+        if alpha in polys:
+            return polys[alpha]
+        j = next(i for i, a in enumerate(alpha) if a > 0)
+        lower = list(alpha)
+        lower[j] -= 1
+        P = mul_coord(get(tuple(lower)), j)
+        polys[alpha] = P
+        return P
+
+    out = np.empty((n, exps.shape[0]))
+    for k, alpha in enumerate(exps):
+        out[:, k] = detJ * (ref @ get(tuple(int(a) for a in alpha)))
     return out

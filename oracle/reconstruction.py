@@ -145,7 +145,7 @@ class OracleModel:
         n = cells.size
         st = self.st
         # own moments up to degree 2r (for the basis means and OI)
-        E2 = all_exponents(d, 2 * r)
+        E2 = all_exponents(d, max(r, 2 * r - 2))
         S, own = cell_simplices(self.mesh, cells)
         xc = self.geo.cen[cells][own]
         hh = self.geo.h[cells][own]
@@ -173,6 +173,9 @@ class OracleModel:
         P = Ad * Vp[:, None, :]
         sv = np.linalg.svd(A, compute_uv=False)
         cond = sv[:, 0] / sv[:, -1]
+        if np.any(~(cond < 1e12)):
+            bad = int(cells[np.argmax(~(cond < 1e12))])
+            raise np.linalg.LinAlgError(f"central least-squares system of cell {bad} is rank deficient")
         # directional degree-1 fits (Section 2.3, r = 1 for directional stencils)
         NF = st.dir.shape[1]
         Md = st.dir.shape[2]
@@ -181,6 +184,8 @@ class OracleModel:
                                         st.dir_shift[cells].reshape(n, NF * Md, d), self.exps[:d])
         Ad_dir = Id.reshape(n, NF, Md, d) - Vd.reshape(n, NF, Md)[..., None] * psibar[:, None, None, :d]
         Pdir = np.linalg.pinv(Ad_dir) * Vd.reshape(n, NF, 1, Md)   # [n, NF, d, Md]
+        # padding slots (cells with fewer faces than NF) hold no stencil
+        Pdir = Pdir * (np.arange(NF)[None, :] < st.n_dir[cells][:, None])[..., None, None]
         # MUSCL degree-1 fit over face neighbours
         NM = st.muscl.shape[1]
         mid = np.where(st.muscl[cells] >= 0, st.muscl[cells], cells[:, None])

@@ -12,7 +12,7 @@ from dataclasses import dataclass
 import numpy as np
 
 from .mesh import Mesh, quad_tri_2d, hex_3d
-from .stencil import Stencils, build_stencils
+from .stencil import Stencils, build_stencils, build_stencils_periodic_hex
 from . import fields
 from .params import Params
 
@@ -103,8 +103,8 @@ def c2_riemann(n=256, r=3, frac=0.3, noise=0.01) -> Workload:
 def tgv_hex(n=64, r=4, perturb=True) -> Workload:
     """Periodic [0, 2 pi)^3, n^3 hexahedra, Taylor-Green vortex at Mach 1.25."""
     L = 2 * np.pi
-    mk = lambda: hex_3d(n, n, n, hi=(L, L, L), periodic=True, name=f"hex{n}")
-    mesh, st = mesh_and_stencils(f"hex{n}_r{r}", mk, r)
+    mesh = hex_3d(n, n, n, hi=(L, L, L), periodic=True, name=f"hex{n}")
+    st = build_stencils_periodic_hex(mesh, (n, n, n), r) if n > 16 else build_stencils(mesh, r)
     pert = fields.tgv_perturbation(seed=1) if perturb else None
     U = fields.cell_average(mesh, lambda p: fields.prim_to_cons(fields.tgv_prim(p, perturb=pert)),
                             nq=max(3, (r + 3) // 2 + 1))

@@ -294,3 +294,39 @@ def simplex_decomposition(cell_type: int):
         PRISM: [(0, 1, 2, 3), (1, 2, 3, 4), (2, 3, 4, 5)],
         HEX: [(0, 1, 2, 6), (0, 3, 2, 6), (0, 3, 7, 6), (0, 4, 7, 6), (0, 4, 5, 6), (0, 1, 5, 6)],
     }[cell_type]
+
+
+# The six tetrahedra of a cube along its main diagonal (local cube vertex
+# numbering as for HEX): every tetrahedron is a monotone path 0 -> a -> b -> 6.
+_KUHN = [(0, 1, 2, 6), (0, 3, 2, 6), (0, 3, 7, 6), (0, 4, 7, 6), (0, 4, 5, 6), (0, 1, 5, 6)]
+
+
+def tet_box(nx, ny, nz, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), jitter=0.0, seed=0, name=""):
+    """Conforming tetrahedral mesh of a box: every cube cut into six tetrahedra
+    along its main diagonal; interior vertices optionally jittered (seeded)."""
+    xs = np.linspace(lo[0], hi[0], nx + 1)
+    ys = np.linspace(lo[1], hi[1], ny + 1)
+    zs = np.linspace(lo[2], hi[2], nz + 1)
+    Z, Y, X = np.meshgrid(zs, ys, xs, indexing="ij")
+    vertices = np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1)
+    if jitter > 0:
+        rng = np.random.default_rng(seed)
+        h = np.array([(hi[0] - lo[0]) / nx, (hi[1] - lo[1]) / ny, (hi[2] - lo[2]) / nz])
+        Kv, Jv, Iv = np.meshgrid(np.arange(nz + 1), np.arange(ny + 1), np.arange(nx + 1), indexing="ij")
+        inner = ((Iv > 0) & (Iv < nx) & (Jv > 0) & (Jv < ny) & (Kv > 0) & (Kv < nz)).ravel()
+        vertices[inner] += jitter * h * rng.uniform(-1, 1, size=(int(inner.sum()), 3))
+    K, J, I = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    I, J, K = I.ravel(), J.ravel(), K.ravel()
+    vid = lambda i, j, k: (k * (ny + 1) + j) * (nx + 1) + i
+    cube = np.stack([vid(I, J, K), vid(I + 1, J, K), vid(I + 1, J + 1, K), vid(I, J + 1, K),
+                     vid(I, J, K + 1), vid(I + 1, J, K + 1), vid(I + 1, J + 1, K + 1),
+                     vid(I, J + 1, K + 1)], 1)
+    tets = np.concatenate([cube[:, list(t)] for t in _KUHN], 0)
+    order = np.argsort(np.tile(np.arange(cube.shape[0]), len(_KUHN)), kind="stable")
+    tets = tets[order]
+    P = vertices[tets]
+    det = np.linalg.det(P[:, 1:] - P[:, :1])
+    neg = det < 0
+    tets[neg, 1], tets[neg, 2] = tets[neg, 2].copy(), tets[neg, 1].copy()
+    canon = np.arange(vertices.shape[0], dtype=np.int64)
+    return _assemble(3, vertices, np.full(tets.shape[0], TET, np.int8), tets, canon, None, name)

@@ -323,7 +323,8 @@ def build_stencils(mesh: Mesh, r: int) -> Stencils:
                 dots = np.einsum("nd,nmd->nm", nk, P)
                 scale = np.linalg.norm(nk, axis=1)[:, None] * np.linalg.norm(P, axis=2) * tol
                 inside &= np.where(use[:, None], dots >= -scale, True)
-        half = np.einsum("nd,nmd->nm", normal, P) > 0
+        half = np.einsum("nd,nmd->nm", normal, P) > \
+            tol * np.linalg.norm(normal, axis=1)[:, None] * np.linalg.norm(P, axis=2)
         fpos = member_pos(cells, f_nbr[cells, k], f_nbr_sh[cells, k])
         is_fn = np.zeros((cells.size, M), bool)
         okf = fpos >= 0
@@ -368,3 +369,80 @@ def build_stencils(mesh: Mesh, r: int) -> Stencils:
     return Stencils(r=r, M=M, Md=Md, central=central, central_shift=central_shift,
                     dir=dir_ids, dir_shift=dir_sh, n_dir=n_dir, muscl=muscl,
                     muscl_shift=muscl_sh, n_muscl=n_muscl)
+
+
+def build_stencils_periodic_hex(mesh: Mesh, dims, r: int, n_small: int = 12) -> Stencils:
+    """Stencils of a uniform periodic hexahedral mesh (cells numbered x-fastest).
+
+    Such a mesh is translation invariant, so every cell's stencils are the
+    translates of one template.  The template comes from ``build_stencils`` on a
+    small periodic mesh of the same spacing (checked against several of its
+    cells), and is replicated here by index arithmetic.
+    """
+    from .mesh import hex_3d
+    nx, ny, nz = dims
+    d = 3
+    L = mesh.period
+    hx, hy, hz = L[0] / nx, L[1] / ny, L[2] / nz
+    ns = n_small
+    ms = hex_3d(ns, ns, ns, hi=(ns * hx, ns * hy, ns * hz), periodic=True)
+    ss = build_stencils(ms, r)
+
+    def pos(c, n3):
+        a, b, _ = n3
+        return np.stack([c % a, (c // a) % b, c // (a * b)], -1)
+
+    n_s = (ns, ns, ns)
+    ref = 0
+    toff = pos(ss.central[ref], n_s) + ss.central_shift[ref] * ns - pos(np.array(ref), n_s)
+
+    def face_dirs(m, c_arr, n3):
+        """Neighbour offsets of every face of each cell, in cell-face order: [n, 6, 3]."""
+        out = np.zeros((c_arr.size, 6, 3), np.int64)
+        for k in range(6):
+            f = m.cell_face[m.cell_face_off[c_arr] + k]
+            side = m.cell_face_side[m.cell_face_off[c_arr] + k]
+            l, rr = m.face_cells[f, 0], m.face_cells[f, 1]
+            nb = np.where(side == 0, rr, l)
+            sh = np.where((side == 0)[:, None], m.face_shift[f], -m.face_shift[f].astype(np.int64))
+            out[:, k] = pos(nb, n3) + sh * np.array(n3) - pos(c_arr, n3)
+        return out
+
+    tdir = {}
+    fd0 = face_dirs(ms, np.array([ref]), n_s)[0]
+    for k in range(6):
+        tdir[tuple(fd0[k])] = pos(ss.dir[ref, k], n_s) + ss.dir_shift[ref, k] * ns - pos(np.array(ref), n_s)
+    # the template must describe every cell of the small mesh
+    for c in (1, ns + 2, ns * ns * 3 + ns + 5, ms.n_cells - 1):
+        off_c = pos(ss.central[c], n_s) + ss.central_shift[c] * ns - pos(np.array(c), n_s)
+        if not np.array_equal(off_c, toff):
+            raise RuntimeError("central stencil template is not translation invariant")
+        fdc = face_dirs(ms, np.array([c]), n_s)[0]
+        for k in range(6):
+            o = pos(ss.dir[c, k], n_s) + ss.dir_shift[c, k] * ns - pos(np.array(c), n_s)
+            if not np.array_equal(o, tdir[tuple(fdc[k])]):
+                raise RuntimeError("directional stencil template is not translation invariant")
+
+    N = mesh.n_cells
+    n3 = np.array([nx, ny, nz])
+    cells = np.arange(N)
+    P = pos(cells, (nx, ny, nz))
+
+    def place(offsets):  # offsets [..., 3] relative to each cell -> ids, shifts
+        q = P.reshape((N,) + (1,) * (offsets.ndim - 2) + (3,)) + offsets
+        sh = np.floor_divide(q, n3)
+        w = q - sh * n3
+        ids = w[..., 0] + nx * (w[..., 1] + ny * w[..., 2])
+        return ids.astype(np.int32), sh.astype(np.int8)
+
+    central, central_shift = place(toff[None])
+    fd = face_dirs(mesh, cells, (nx, ny, nz))
+    dir_off = np.zeros((N, 6, ss.Md, 3), np.int64)
+    for key, val in tdir.items():
+        msk = np.all(fd == np.array(key), axis=2)
+        dir_off[msk] = val
+    dir_ids, dir_sh = place(dir_off)
+    mus_ids, mus_sh = place(fd)
+    return Stencils(r=r, M=ss.M, Md=ss.Md, central=central, central_shift=central_shift, dir=dir_ids,
+                    dir_shift=dir_sh, n_dir=np.full(N, 6, np.int32), muscl=mus_ids, muscl_shift=mus_sh,
+                    n_muscl=np.full(N, 6, np.int32))

@@ -11,7 +11,7 @@ def state_scale(U):
 
 def rel_err(x, ref, scale_b):
     """max |x - ref| / max(|ref|, S_v); ``scale_b`` is S_v broadcast against ``ref``."""
-    den = np.maximum(np.abs(ref), scale_b)
+    den = np.maximum(np.maximum(np.abs(ref), scale_b), 1e-300)
     return float(np.nanmax(np.abs(x - ref) / den))
 
 

@@ -109,3 +109,13 @@ def test_geometry_closure_and_measure():
     assert g3.vol.sum() == pytest.approx(6.0, rel=1e-14)
     assert np.allclose(np.add.reduceat(g3.gp_wS, g3.gp_off[:-1]), g3.area, rtol=1e-14)
     assert np.diff(g3.gp_off).max() == 9
+
+
+def test_fast_and_expanded_simplex_integrals_agree():
+    rng = np.random.default_rng(9)
+    for d in (2, 3):
+        S = rng.normal(size=(7, d + 1, d))
+        exps = np.array([e for e in np.ndindex(*([5] * d)) if sum(e) <= 4])
+        a = Q.simplex_monomial_integrals(S, exps)
+        b = Q.simplex_monomial_integrals_expanded(S, exps)
+        assert np.allclose(a, b, rtol=1e-11, atol=1e-13)
