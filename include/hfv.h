@@ -152,6 +152,12 @@ hfv_status hfv_reconstruct(hfv_ctx *ctx, const void *U, void *face_states, uint8
 hfv_status hfv_residual(hfv_ctx *ctx, const void *U, void *R, void *face_states, uint8_t *cell_class,
                         void *stream);
 
+/* Residual with given cell classes (the switches of a previous evaluation
+ * held fixed): the reconstruction of each cell follows cell_class, with no
+ * NAD and no Harten re-check.  The residual a VJP linearises.
+ *   cell_class  device [n_cells] classes (HFV_CLASS_*), read only */
+hfv_status hfv_residual_frozen(hfv_ctx *ctx, const void *U, const uint8_t *cell_class, void *R, void *stream);
+
 /* Vector-Jacobian product of the residual with the cell classes frozen (a
  * project addition, not in the paper):  gU = (dR/dU)^T gR, every switch
  * (class, Harten fallback, limiter argmin, Riemann branch) held at the

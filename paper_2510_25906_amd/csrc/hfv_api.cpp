@@ -226,6 +226,15 @@ hfv_status hfv_residual(hfv_ctx *ctx, const void *U, void *R, void *fs, uint8_t 
   return run_residual_tail(ctx, f, R, s);
 }
 
+hfv_status hfv_residual_frozen(hfv_ctx *ctx, const void *U, const uint8_t *cls, void *R, void *stream) {
+  if (!ctx) return HFV_ERR_PARAM;
+  if (!U || !cls || !R) return ctx->err = "NULL device pointer", HFV_ERR_PARAM;
+  hipStream_t s = (hipStream_t)stream;
+  hfv_status e = run_reconstruct_frozen(ctx, U, ctx->fs_ws, cls, s);
+  if (e != HFV_OK) return e;
+  return run_residual_tail(ctx, ctx->fs_ws, R, s);
+}
+
 hfv_status hfv_residual_vjp(hfv_ctx *ctx, const void *U, const uint8_t *cls, const void *gR, void *gU,
                             void *stream) {
   if (!ctx) return HFV_ERR_PARAM;

@@ -1,0 +1,255 @@
+// Device code shared by the forward and adjoint kernels.
+#pragma once
+
+#include "hfv_internal.hpp"
+
+namespace hfv {
+
+
+template <typename T>
+struct HotArgs {
+  int N, NGPT, mode, form;
+  int frozen;              // adjoint recompute: classes given, no NAD or Harten re-check
+  const uint8_t *cls_in;   // given classes when frozen
+  const T *U;
+  T *fs;
+  uint8_t *own;
+  uint8_t *cls;
+  int *lists;
+  int *counts;
+  Tables<T> t;
+  T gamma, alpha_m, beta_m, alpha_w, beta_w, lam1p, eps_w, b_w, theta, tvd_eps;
+};
+
+template <int G>
+struct Lane {
+  int item, sub, base;
+  bool ok;
+  __device__ Lane() {
+    constexpr int CPW = 64 / G;
+    const int lane = threadIdx.x & 63;
+    const long wave = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    item = (int)(wave * CPW + lane / G);
+    sub = lane % G;
+    base = lane - sub;
+    ok = lane < CPW * G;
+  }
+};
+
+template <int G, typename V>
+__device__ inline V group_sum(V x, int base) {
+  if constexpr (G == 1) return x;
+  V s = 0;
+#pragma unroll
+  for (int t = 0; t < G; ++t) s += __shfl(x, base + t);
+  return s;
+}
+template <int G>
+__device__ inline int group_max(int x, int base) {
+  if constexpr (G == 1) return x;
+  int s = x;
+#pragma unroll
+  for (int t = 0; t < G; ++t) s = max(s, __shfl(x, base + t));
+  return s;
+}
+template <int G>
+__device__ inline bool group_all(bool x, int base) {
+  if constexpr (G == 1) return x;
+  int s = 1;
+#pragma unroll
+  for (int t = 0; t < G; ++t) s &= __shfl((int)x, base + t);
+  return s != 0;
+}
+
+// All NV values of a state whose variables are spread over the group.
+template <int NV, int G, typename T>
+__device__ inline void group_state(const T (&mine)[NV / G], T (&all)[NV], int base) {
+  constexpr int VPL = NV / G;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    if constexpr (G == 1)
+      all[v] = mine[v];
+    else
+      all[v] = __shfl(mine[v % VPL], base + v / VPL);
+  }
+}
+
+// Harten bound check at one point for density and pressure (Eq. harten_jump_fix).
+template <int NV, typename T>
+__device__ inline bool harten_point(const T (&q)[NV], T rho_b, T p_b, const HotArgs<T> &a) {
+  const T rho = q[0];
+  if (!(fabs(rho - rho_b) <= a.theta * fmax(fabs(rho_b), a.tvd_eps))) return false;
+  T m2 = 0;
+#pragma unroll
+  for (int j = 1; j < NV - 1; ++j) m2 += q[j] * q[j];
+  const T p = (a.gamma - (T)1) * (q[NV - 1] - (T)0.5 * m2 / rho);
+  return fabs(p - p_b) <= a.theta * fmax(fabs(p_b), a.tvd_eps);
+}
+
+template <int NV, typename T>
+__device__ inline T pressure(const T (&q)[NV], T gamma) {
+  T m2 = 0;
+#pragma unroll
+  for (int j = 1; j < NV - 1; ++j) m2 += q[j] * q[j];
+  return (gamma - (T)1) * (q[NV - 1] - (T)0.5 * m2 / q[0]);
+}
+
+// phi_k(xi) = xi^alpha_k - psi_bar_k for the hierarchical monomial basis.
+template <int DIM, int R, typename T>
+__device__ inline void basis_at(const T (&xi)[DIM], const T (&psb)[n_unknowns(DIM, R)],
+                                T (&phi)[n_unknowns(DIM, R)]) {
+  constexpr Exps<DIM, 1, R> E{};
+  constexpr int K = n_unknowns(DIM, R);
+  T pw[DIM][R + 1];
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) {
+    pw[j][0] = (T)1;
+#pragma unroll
+    for (int p = 1; p <= R; ++p) pw[j][p] = pw[j][p - 1] * xi[j];
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    T m = pw[0][E.e[k][0]];
+#pragma unroll
+    for (int j = 1; j < DIM; ++j) m *= pw[j][E.e[k][j]];
+    phi[k] = m - psb[k];
+  }
+}
+
+// a[k][q] = sum_m P[k][m] (U_{s_m} - U_i)   (Section 2.1, a = A^+ b)
+template <int DIM, int R, int VPL, typename T>
+__device__ inline void lsq_coeffs(const HotArgs<T> &a, int cell, int v0, const T (&u0)[VPL],
+                                  T (&co)[n_unknowns(DIM, R)][VPL]) {
+  constexpr int K = n_unknowns(DIM, R), M = 2 * K;
+  const int N = a.N;
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int q = 0; q < VPL; ++q) co[k][q] = (T)0;
+#pragma unroll 2
+  for (int m = 0; m < M; ++m) {
+    const int j = a.t.sten[(long)m * N + cell];
+    T du[VPL];
+#pragma unroll
+    for (int q = 0; q < VPL; ++q) du[q] = a.U[(long)(v0 + q) * N + j] - u0[q];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const T p = a.t.P[((long)k * M + m) * N + cell];
+#pragma unroll
+      for (int q = 0; q < VPL; ++q) co[k][q] += p * du[q];
+    }
+  }
+}
+
+template <int NV, typename T>
+__device__ inline void store(const HotArgs<T> &a, int dst, int v, T val) {
+  const long d = dst & ~(1 << 30);
+  a.fs[d + (long)v * a.NGPT] = val;
+  if (dst & (1 << 30)) a.fs[d + (long)(NV + v) * a.NGPT] = val;  // boundary: transmissive ghost
+}
+
+// ---------------------------------------------------------------------------
+// Forward-mode dual number (one tangent) for exact Jacobian columns of the
+// Riemann fluxes in the adjoint; branches follow the primal value.
+using ::fmax;
+using ::fmin;
+using ::sqrt;
+template <typename T>
+struct Dual {
+  T v, d;
+  __device__ Dual() : v(0), d(0) {}
+  __device__ Dual(T a) : v(a), d(0) {}
+  __device__ Dual(T a, T b) : v(a), d(b) {}
+};
+template <typename T> __device__ inline Dual<T> operator+(Dual<T> a, Dual<T> b) { return {a.v + b.v, a.d + b.d}; }
+template <typename T> __device__ inline Dual<T> operator-(Dual<T> a, Dual<T> b) { return {a.v - b.v, a.d - b.d}; }
+template <typename T> __device__ inline Dual<T> operator-(Dual<T> a) { return {-a.v, -a.d}; }
+template <typename T> __device__ inline Dual<T> operator*(Dual<T> a, Dual<T> b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
+template <typename T> __device__ inline Dual<T> operator/(Dual<T> a, Dual<T> b) {
+  const T q = a.v / b.v;
+  return {q, (a.d - q * b.d) / b.v};
+}
+template <typename T> __device__ inline Dual<T> operator+(T a, Dual<T> b) { return {a + b.v, b.d}; }
+template <typename T> __device__ inline Dual<T> operator-(T a, Dual<T> b) { return {a - b.v, -b.d}; }
+template <typename T> __device__ inline Dual<T> operator*(T a, Dual<T> b) { return {a * b.v, a * b.d}; }
+template <typename T> __device__ inline Dual<T> operator*(Dual<T> a, T b) { return {a.v * b, a.d * b}; }
+template <typename T> __device__ inline Dual<T> &operator+=(Dual<T> &a, Dual<T> b) { a = a + b; return a; }
+template <typename T> __device__ inline Dual<T> sqrt(Dual<T> a) {
+  const T r = sqrt(a.v);
+  return {r, a.d / (2 * r)};
+}
+template <typename T> __device__ inline Dual<T> fmin(Dual<T> a, Dual<T> b) { return a.v <= b.v ? a : b; }
+template <typename T> __device__ inline Dual<T> fmax(Dual<T> a, Dual<T> b) { return a.v >= b.v ? a : b; }
+template <typename T> __device__ inline T primal(T a) { return a; }
+template <typename T> __device__ inline T primal(Dual<T> a) { return a.v; }
+
+// Riemann fluxes (Section 2.4): HLLC and HLL with Davis wave-speed estimates.
+// S is the state type (a scalar or a dual number), T the scalar type.
+template <int DIM, typename S, typename T>
+__device__ inline void euler_flux(const S (&q)[DIM + 2], const T (&n)[DIM], S p, S un, S (&F)[DIM + 2]) {
+  F[0] = q[0] * un;
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) F[1 + j] = q[1 + j] * un + p * n[j];
+  F[DIM + 1] = un * (q[DIM + 1] + p);
+}
+
+template <int DIM, typename S, typename T>
+__device__ inline void riemann(const S (&qL)[DIM + 2], const S (&qR)[DIM + 2], const T (&n)[DIM], T gamma,
+                               int hllc, S (&F)[DIM + 2]) {
+  constexpr int NV = DIM + 2;
+  const S rL = qL[0], rR = qR[0];
+  S vL[DIM], vR[DIM], unL = S(0), unR = S(0), kL = S(0), kR = S(0);
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) {
+    vL[j] = qL[1 + j] / rL;
+    vR[j] = qR[1 + j] / rR;
+    unL += vL[j] * n[j];
+    unR += vR[j] * n[j];
+    kL += vL[j] * vL[j];
+    kR += vR[j] * vR[j];
+  }
+  const T gm1 = gamma - (T)1, half = (T)0.5;
+  const S pL = gm1 * (qL[NV - 1] - half * rL * kL);
+  const S pR = gm1 * (qR[NV - 1] - half * rR * kR);
+  const S cL = sqrt(gamma * pL / rL), cR = sqrt(gamma * pR / rR);
+  const S SL = fmin(unL - cL, unR - cR), SR = fmax(unL + cL, unR + cR);
+  S FL[NV], FR[NV];
+  euler_flux<DIM, S, T>(qL, n, pL, unL, FL);
+  euler_flux<DIM, S, T>(qR, n, pR, unR, FR);
+  if (primal(SL) >= (T)0) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) F[v] = FL[v];
+    return;
+  }
+  if (!hllc) {
+    if (primal(SR) <= (T)0) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) F[v] = FR[v];
+      return;
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) F[v] = (SR * FL[v] - SL * FR[v] + SL * SR * (qR[v] - qL[v])) / (SR - SL);
+    return;
+  }
+  const S Ss = (pR - pL + rL * unL * (SL - unL) - rR * unR * (SR - unR)) / (rL * (SL - unL) - rR * (SR - unR));
+  if (primal(Ss) >= (T)0) {
+    const S fac = rL * (SL - unL) / (SL - Ss);
+    F[0] = FL[0] + SL * (fac - qL[0]);
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) F[1 + j] = FL[1 + j] + SL * (fac * (vL[j] + (Ss - unL) * n[j]) - qL[1 + j]);
+    F[NV - 1] = FL[NV - 1] + SL * (fac * (qL[NV - 1] / rL + (Ss - unL) * (Ss + pL / (rL * (SL - unL)))) -
+                                   qL[NV - 1]);
+  } else if (primal(SR) > (T)0) {
+    const S fac = rR * (SR - unR) / (SR - Ss);
+    F[0] = FR[0] + SR * (fac - qR[0]);
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) F[1 + j] = FR[1 + j] + SR * (fac * (vR[j] + (Ss - unR) * n[j]) - qR[1 + j]);
+    F[NV - 1] = FR[NV - 1] + SR * (fac * (qR[NV - 1] / rR + (Ss - unR) * (Ss + pR / (rR * (SR - unR)))) -
+                                   qR[NV - 1]);
+  } else {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) F[v] = FR[v];
+  }
+}
+
+}  // namespace hfv

@@ -17,149 +17,9 @@
 // NV/G conserved variables (per-variable reconstruction, Section 2.3).  The
 // per-cell matrices are stored [row][cell] so a wave's loads of one matrix
 // entry are contiguous across its cells.
-#include "hfv_internal.hpp"
+#include "hfv_device.hpp"
 
 namespace hfv {
-
-template <typename T>
-struct HotArgs {
-  int N, NGPT, mode, form;
-  const T *U;
-  T *fs;
-  uint8_t *own;
-  uint8_t *cls;
-  int *lists;
-  int *counts;
-  Tables<T> t;
-  T gamma, alpha_m, beta_m, alpha_w, beta_w, lam1p, eps_w, b_w, theta, tvd_eps;
-};
-
-template <int G>
-struct Lane {
-  int item, sub, base;
-  bool ok;
-  __device__ Lane() {
-    constexpr int CPW = 64 / G;
-    const int lane = threadIdx.x & 63;
-    const long wave = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    item = (int)(wave * CPW + lane / G);
-    sub = lane % G;
-    base = lane - sub;
-    ok = lane < CPW * G;
-  }
-};
-
-template <int G, typename V>
-__device__ inline V group_sum(V x, int base) {
-  if constexpr (G == 1) return x;
-  V s = 0;
-#pragma unroll
-  for (int t = 0; t < G; ++t) s += __shfl(x, base + t);
-  return s;
-}
-template <int G>
-__device__ inline int group_max(int x, int base) {
-  if constexpr (G == 1) return x;
-  int s = x;
-#pragma unroll
-  for (int t = 0; t < G; ++t) s = max(s, __shfl(x, base + t));
-  return s;
-}
-template <int G>
-__device__ inline bool group_all(bool x, int base) {
-  if constexpr (G == 1) return x;
-  int s = 1;
-#pragma unroll
-  for (int t = 0; t < G; ++t) s &= __shfl((int)x, base + t);
-  return s != 0;
-}
-
-// All NV values of a state whose variables are spread over the group.
-template <int NV, int G, typename T>
-__device__ inline void group_state(const T (&mine)[NV / G], T (&all)[NV], int base) {
-  constexpr int VPL = NV / G;
-#pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    if constexpr (G == 1)
-      all[v] = mine[v];
-    else
-      all[v] = __shfl(mine[v % VPL], base + v / VPL);
-  }
-}
-
-// Harten bound check at one point for density and pressure (Eq. harten_jump_fix).
-template <int NV, typename T>
-__device__ inline bool harten_point(const T (&q)[NV], T rho_b, T p_b, const HotArgs<T> &a) {
-  const T rho = q[0];
-  if (!(fabs(rho - rho_b) <= a.theta * fmax(fabs(rho_b), a.tvd_eps))) return false;
-  T m2 = 0;
-#pragma unroll
-  for (int j = 1; j < NV - 1; ++j) m2 += q[j] * q[j];
-  const T p = (a.gamma - (T)1) * (q[NV - 1] - (T)0.5 * m2 / rho);
-  return fabs(p - p_b) <= a.theta * fmax(fabs(p_b), a.tvd_eps);
-}
-
-template <int NV, typename T>
-__device__ inline T pressure(const T (&q)[NV], T gamma) {
-  T m2 = 0;
-#pragma unroll
-  for (int j = 1; j < NV - 1; ++j) m2 += q[j] * q[j];
-  return (gamma - (T)1) * (q[NV - 1] - (T)0.5 * m2 / q[0]);
-}
-
-// phi_k(xi) = xi^alpha_k - psi_bar_k for the hierarchical monomial basis.
-template <int DIM, int R, typename T>
-__device__ inline void basis_at(const T (&xi)[DIM], const T (&psb)[n_unknowns(DIM, R)],
-                                T (&phi)[n_unknowns(DIM, R)]) {
-  constexpr Exps<DIM, 1, R> E{};
-  constexpr int K = n_unknowns(DIM, R);
-  T pw[DIM][R + 1];
-#pragma unroll
-  for (int j = 0; j < DIM; ++j) {
-    pw[j][0] = (T)1;
-#pragma unroll
-    for (int p = 1; p <= R; ++p) pw[j][p] = pw[j][p - 1] * xi[j];
-  }
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    T m = pw[0][E.e[k][0]];
-#pragma unroll
-    for (int j = 1; j < DIM; ++j) m *= pw[j][E.e[k][j]];
-    phi[k] = m - psb[k];
-  }
-}
-
-// a[k][q] = sum_m P[k][m] (U_{s_m} - U_i)   (Section 2.1, a = A^+ b)
-template <int DIM, int R, int VPL, typename T>
-__device__ inline void lsq_coeffs(const HotArgs<T> &a, int cell, int v0, const T (&u0)[VPL],
-                                  T (&co)[n_unknowns(DIM, R)][VPL]) {
-  constexpr int K = n_unknowns(DIM, R), M = 2 * K;
-  const int N = a.N;
-#pragma unroll
-  for (int k = 0; k < K; ++k)
-#pragma unroll
-    for (int q = 0; q < VPL; ++q) co[k][q] = (T)0;
-#pragma unroll 2
-  for (int m = 0; m < M; ++m) {
-    const int j = a.t.sten[(long)m * N + cell];
-    T du[VPL];
-#pragma unroll
-    for (int q = 0; q < VPL; ++q) du[q] = a.U[(long)(v0 + q) * N + j] - u0[q];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const T p = a.t.P[((long)k * M + m) * N + cell];
-#pragma unroll
-      for (int q = 0; q < VPL; ++q) co[k][q] += p * du[q];
-    }
-  }
-}
-
-template <int NV, typename T>
-__device__ inline void store(const HotArgs<T> &a, int dst, int v, T val) {
-  const long d = dst & ~(1 << 30);
-  a.fs[d + (long)v * a.NGPT] = val;
-  if (dst & (1 << 30)) a.fs[d + (long)(NV + v) * a.NGPT] = val;  // boundary: transmissive ghost
-}
 
 // ---------------------------------------------------------------------------
 // K1: linear candidate, face states, NAD own class, Harten flag.
@@ -265,7 +125,9 @@ __global__ __launch_bounds__(CLASSIFY_BLOCK) void k_classify(HotArgs<T> a, int n
   const int cell = blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = cell < a.N;
   int c = 0;
-  if (valid) {
+  if (valid && a.frozen) {
+    c = a.cls_in[cell];
+  } else if (valid) {
     const int o = a.own[cell];
     c = o & 3;
     if (a.mode == HFV_HYBRID) {
@@ -464,7 +326,7 @@ __global__ __launch_bounds__(256) void k_cwenoz(HotArgs<T> a, int direct) {
       }
       T all[NV];
       group_state<NV, G, T>(val, all, L.base);
-      hok = hok && harten_point<NV, T>(all, rho_b, p_b, a);
+      hok = a.frozen || (hok && harten_point<NV, T>(all, rho_b, p_b, a));
       const int dst = a.t.gpdst[(long)g * N + cell];
 #pragma unroll
       for (int q = 0; q < VPL; ++q) store<NV, T>(a, dst, v0 + q, hok ? val[q] : u0[q]);
@@ -478,7 +340,7 @@ __global__ __launch_bounds__(256) void k_cwenoz(HotArgs<T> a, int direct) {
         break;
       }
     }
-    if (L.sub == 0) a.cls[cell] = hok ? HFV_CLASS_CWENOZ : HFV_CLASS_FIRST_ORDER;
+    if (L.sub == 0 && !a.frozen) a.cls[cell] = hok ? HFV_CLASS_CWENOZ : HFV_CLASS_FIRST_ORDER;
   }
 }
 
@@ -579,7 +441,7 @@ __global__ __launch_bounds__(256) void k_muscl(HotArgs<T> a, int direct) {
       }
       T all[NV];
       group_state<NV, G, T>(val, all, L.base);
-      hok = harten_point<NV, T>(all, rho_b, p_b, a);
+      hok = a.frozen || harten_point<NV, T>(all, rho_b, p_b, a);
     }
     for (int g = 0; g < ng; ++g) {
       T phi[DIM];
@@ -594,7 +456,7 @@ __global__ __launch_bounds__(256) void k_muscl(HotArgs<T> a, int direct) {
         store<NV, T>(a, dst, v0 + q, hok ? u0[q] + th[q] * d : u0[q]);
       }
     }
-    if (L.sub == 0) a.cls[cell] = hok ? HFV_CLASS_MUSCL : HFV_CLASS_FIRST_ORDER;
+    if (L.sub == 0 && !a.frozen) a.cls[cell] = hok ? HFV_CLASS_MUSCL : HFV_CLASS_FIRST_ORDER;
   }
 }
 
@@ -611,74 +473,6 @@ __global__ __launch_bounds__(256) void k_first(HotArgs<T> a) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) store<NV, T>(a, dst, v, a.U[(long)v * a.N + cell]);
     }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Riemann fluxes (Section 2.4): HLLC and HLL with Davis wave-speed estimates.
-template <int DIM, typename T>
-__device__ inline void euler_flux(const T (&q)[DIM + 2], const T (&n)[DIM], T p, T un, T (&F)[DIM + 2]) {
-  F[0] = q[0] * un;
-#pragma unroll
-  for (int j = 0; j < DIM; ++j) F[1 + j] = q[1 + j] * un + p * n[j];
-  F[DIM + 1] = un * (q[DIM + 1] + p);
-}
-
-template <int DIM, typename T>
-__device__ inline void riemann(const T (&qL)[DIM + 2], const T (&qR)[DIM + 2], const T (&n)[DIM], T gamma,
-                               int hllc, T (&F)[DIM + 2]) {
-  constexpr int NV = DIM + 2;
-  const T rL = qL[0], rR = qR[0];
-  T vL[DIM], vR[DIM], unL = 0, unR = 0, kL = 0, kR = 0;
-#pragma unroll
-  for (int j = 0; j < DIM; ++j) {
-    vL[j] = qL[1 + j] / rL;
-    vR[j] = qR[1 + j] / rR;
-    unL += vL[j] * n[j];
-    unR += vR[j] * n[j];
-    kL += vL[j] * vL[j];
-    kR += vR[j] * vR[j];
-  }
-  const T pL = (gamma - 1) * (qL[NV - 1] - (T)0.5 * rL * kL);
-  const T pR = (gamma - 1) * (qR[NV - 1] - (T)0.5 * rR * kR);
-  const T cL = sqrt(gamma * pL / rL), cR = sqrt(gamma * pR / rR);
-  const T SL = fmin(unL - cL, unR - cR), SR = fmax(unL + cL, unR + cR);
-  T FL[NV], FR[NV];
-  euler_flux<DIM, T>(qL, n, pL, unL, FL);
-  euler_flux<DIM, T>(qR, n, pR, unR, FR);
-  if (SL >= 0) {
-#pragma unroll
-    for (int v = 0; v < NV; ++v) F[v] = FL[v];
-    return;
-  }
-  if (!hllc) {
-    if (SR <= 0) {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) F[v] = FR[v];
-      return;
-    }
-#pragma unroll
-    for (int v = 0; v < NV; ++v) F[v] = (SR * FL[v] - SL * FR[v] + SL * SR * (qR[v] - qL[v])) / (SR - SL);
-    return;
-  }
-  const T Ss = (pR - pL + rL * unL * (SL - unL) - rR * unR * (SR - unR)) / (rL * (SL - unL) - rR * (SR - unR));
-  if (Ss >= 0) {
-    const T fac = rL * (SL - unL) / (SL - Ss);
-    F[0] = FL[0] + SL * (fac - qL[0]);
-#pragma unroll
-    for (int j = 0; j < DIM; ++j) F[1 + j] = FL[1 + j] + SL * (fac * (vL[j] + (Ss - unL) * n[j]) - qL[1 + j]);
-    F[NV - 1] = FL[NV - 1] + SL * (fac * (qL[NV - 1] / rL + (Ss - unL) * (Ss + pL / (rL * (SL - unL)))) -
-                                   qL[NV - 1]);
-  } else if (SR > 0) {
-    const T fac = rR * (SR - unR) / (SR - Ss);
-    F[0] = FR[0] + SR * (fac - qR[0]);
-#pragma unroll
-    for (int j = 0; j < DIM; ++j) F[1 + j] = FR[1 + j] + SR * (fac * (vR[j] + (Ss - unR) * n[j]) - qR[1 + j]);
-    F[NV - 1] = FR[NV - 1] + SR * (fac * (qR[NV - 1] / rR + (Ss - unR) * (Ss + pR / (rR * (SR - unR)))) -
-                                   qR[NV - 1]);
-  } else {
-#pragma unroll
-    for (int v = 0; v < NV; ++v) F[v] = FR[v];
   }
 }
 
@@ -700,7 +494,7 @@ __global__ __launch_bounds__(256) void k_flux(int NF, int NGPT, const T *fs, con
       qR[v] = fs[(long)(NV + v) * NGPT + g];
     }
     T F[NV];
-    riemann<DIM, T>(qL, qR, n, gamma, hllc, F);
+    riemann<DIM, T, T>(qL, qR, n, gamma, hllc, F);
     const T w = gpw[g];
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] += w * F[v];
@@ -737,6 +531,8 @@ static HotArgs<T> make_args(hfv_ctx *ctx, Tables<T> &t, const void *U, void *fs,
   a.NGPT = ctx->NGPT;
   a.mode = ctx->p.mode;
   a.form = ctx->p.form;
+  a.frozen = 0;
+  a.cls_in = nullptr;
   a.U = (const T *)U;
   a.fs = (T *)fs;
   a.own = ctx->own;
@@ -787,6 +583,50 @@ static hfv_status recon_impl(hfv_ctx *ctx, Tables<T> &t, const void *U, void *fs
   }
   HFV_HIP(hipGetLastError());
   return HFV_OK;
+}
+
+// Face states for given (frozen) classes: the linear candidate everywhere,
+// then CWENOZ / MUSCL / first-order states on the given class lists, with no
+// NAD and no Harten re-check.
+template <int DIM, int R, typename T, int G>
+static hfv_status frozen_impl(hfv_ctx *ctx, Tables<T> &t, const void *U, void *fs, const uint8_t *cls,
+                              hipStream_t s) {
+  HotArgs<T> a = make_args<T>(ctx, t, U, fs, nullptr);
+  a.frozen = 1;
+  a.cls_in = cls;
+  a.mode = HFV_ALL_LINEAR;
+  const int B = ctx->block;
+  const long waves = ((long)ctx->N + 64 / G - 1) / (64 / G);
+  const unsigned grid_cells = nblk(waves * 64, B);
+  const unsigned grid_list = std::min<unsigned>(grid_cells, (unsigned)ctx->list_blocks);
+  k_linear<DIM, R, T, G><<<grid_cells, B, 0, s>>>(a);
+  k_classify<T><<<nblk(ctx->N, CLASSIFY_BLOCK), CLASSIFY_BLOCK, 0, s>>>(a, ctx->NFM);
+  k_cwenoz<DIM, R, T, G><<<grid_list, B, 0, s>>>(a, 0);
+  k_muscl<DIM, R, T, G><<<grid_list, B, 0, s>>>(a, 0);
+  k_first<DIM + 2, T><<<std::min<unsigned>(nblk(ctx->N, 256), 1024), 256, 0, s>>>(a);
+  HFV_HIP(hipGetLastError());
+  return HFV_OK;
+}
+
+template <typename T>
+static hfv_status frozen_t(hfv_ctx *ctx, Tables<T> &t, const void *U, void *fs, const uint8_t *cls, hipStream_t s) {
+  switch (ctx->dim * 10 + ctx->r) {
+    case 21: return frozen_impl<2, 1, T, 4>(ctx, t, U, fs, cls, s);
+    case 22: return frozen_impl<2, 2, T, 4>(ctx, t, U, fs, cls, s);
+    case 23: return frozen_impl<2, 3, T, 4>(ctx, t, U, fs, cls, s);
+    case 24: return frozen_impl<2, 4, T, 4>(ctx, t, U, fs, cls, s);
+    case 31: return frozen_impl<3, 1, T, 5>(ctx, t, U, fs, cls, s);
+    case 32: return frozen_impl<3, 2, T, 5>(ctx, t, U, fs, cls, s);
+    case 33: return frozen_impl<3, 3, T, 5>(ctx, t, U, fs, cls, s);
+    case 34: return frozen_impl<3, 4, T, 5>(ctx, t, U, fs, cls, s);
+  }
+  ctx->err = "unsupported (dim, order_r)";
+  return HFV_ERR_PARAM;
+}
+
+hfv_status run_reconstruct_frozen(hfv_ctx *ctx, const void *U, void *fs, const uint8_t *cls, hipStream_t s) {
+  return ctx->prec == 64 ? frozen_t<double>(ctx, ctx->t64, U, fs, cls, s)
+                         : frozen_t<float>(ctx, ctx->t32, U, fs, cls, s);
 }
 
 template <int DIM, int R, typename T>

@@ -79,6 +79,12 @@ struct Tables {
   int *cf_off = nullptr;   // [N+1]
   int *cf = nullptr;       // [..] face | (side << 31)
   T *ivol = nullptr;       // [N]
+  // adjoint: positions inside the central stencil and its transpose
+  uint8_t *dpos = nullptr;  // [NFM][Md][N] directional member -> central slot
+  uint8_t *mpos = nullptr;  // [NFM][N]     MUSCL member -> central slot
+  uint8_t *nbpos = nullptr; // [NFM][N]     face neighbour -> central slot (255: none)
+  int *inv_off = nullptr;   // [N+1]  cells whose central stencil holds cell j
+  int *inv_idx = nullptr;   // [N*M]  m * N + i, ordered by (i, m)
 };
 
 struct Params {
@@ -102,7 +108,11 @@ struct hfv_ctx {
   int *counts = nullptr;       // [4]
   void *fs_ws = nullptr;       // [2][nvar][NGPT]
   void *fflux = nullptr;       // [nvar][NF]
-  void *vjp_ws = nullptr;      // adjoint workspace
+  void *vjp_C = nullptr;       // adjoint: per stencil slot contributions [M][nvar][N]
+  void *vjp_S = nullptr;       // adjoint: self contributions [nvar][N]
+  void *vjp_gfs = nullptr;     // adjoint: face-state cotangents [2][nvar][NGPT]
+  bool vjp_ok = false;
+  std::string vjp_why;
   size_t table_bytes = 0;
   // launch configuration
   int lanes = 1, block = 256, list_blocks = 2048;
@@ -122,6 +132,7 @@ namespace hfv {
 
 hfv_status setup_tables(hfv_ctx *ctx, const hfv_mesh *mesh, const hfv_stencils *st, hipStream_t s);
 hfv_status run_reconstruct(hfv_ctx *ctx, const void *U, void *fs, uint8_t *cls, hipStream_t s);
+hfv_status run_reconstruct_frozen(hfv_ctx *ctx, const void *U, void *fs, const uint8_t *cls, hipStream_t s);
 hfv_status run_residual_tail(hfv_ctx *ctx, const void *fs, void *R, hipStream_t s);
 hfv_status run_vjp(hfv_ctx *ctx, const void *U, const uint8_t *cls, const void *gR, void *gU, hipStream_t s);
 hfv_status dev_alloc(hfv_ctx *ctx, void **p, size_t bytes);

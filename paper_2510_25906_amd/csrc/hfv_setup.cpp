@@ -881,6 +881,9 @@ static hfv_status setup_dr(hfv_ctx *ctx, const hfv_mesh *mesh, const hfv_stencil
   return HFV_OK;
 }
 
+static hfv_status build_vjp_tables(hfv_ctx *ctx, const hfv_mesh *mesh, const hfv_stencils *st,
+                                   const std::vector<int> &cf_off, const std::vector<int> &cf, hipStream_t s);
+
 hfv_status setup_tables(hfv_ctx *ctx, const hfv_mesh *mesh, const hfv_stencils *st, hipStream_t s) {
   const int N = ctx->N, NF = ctx->NF, DIM = ctx->dim, NFM = ctx->NFM, r = ctx->r;
   Rules RU{};
@@ -980,6 +983,83 @@ hfv_status setup_tables(hfv_ctx *ctx, const hfv_mesh *mesh, const hfv_stencils *
   };
   e = ctx->prec == 64 ? put(ctx->t64) : put(ctx->t32);
   if (e != HFV_OK) return e;
+  HFV_HIP(hipStreamSynchronize(s));
+  return build_vjp_tables(ctx, mesh, st, cf_off, cf, s);
+}
+
+// Adjoint tables: where the directional, MUSCL and face-neighbour members sit
+// inside each central stencil, and the transpose of the central stencil.
+static hfv_status build_vjp_tables(hfv_ctx *ctx, const hfv_mesh *mesh, const hfv_stencils *st,
+                                   const std::vector<int> &cf_off, const std::vector<int> &cf, hipStream_t s) {
+  const int N = ctx->N, M = ctx->M, NFM = ctx->NFM, Md = ctx->Md, D = ctx->dim;
+  std::vector<uint8_t> dpos((size_t)NFM * Md * N, 0), mpos((size_t)NFM * N, 0), nbpos((size_t)NFM * N, 255);
+  ctx->vjp_ok = true;
+  auto find = [&](int c, int id, const int8_t *sh) -> int {
+    for (int m = 0; m < M; ++m) {
+      if (st->central[(size_t)c * M + m] != id) continue;
+      bool eq = true;
+      for (int j = 0; j < D; ++j) {
+        int a = st->central_shift ? st->central_shift[((size_t)c * M + m) * D + j] : 0;
+        int b = sh ? sh[j] : 0;
+        eq = eq && a == b;
+      }
+      if (eq) return m;
+    }
+    return -1;
+  };
+  auto fail = [&](const std::string &why) {
+    if (ctx->vjp_ok) ctx->vjp_why = why;
+    ctx->vjp_ok = false;
+  };
+  for (int c = 0; c < N && ctx->vjp_ok; ++c) {
+    for (int sd = 0; sd < st->n_dir[c]; ++sd)
+      for (int q = 0; q < Md; ++q) {
+        size_t e = ((size_t)c * NFM + sd) * Md + q;
+        int m = find(c, st->dir[e], st->dir_shift ? st->dir_shift + e * D : nullptr);
+        if (m < 0) fail("directional member outside the central stencil at cell " + std::to_string(c));
+        dpos[((size_t)sd * Md + q) * N + c] = (uint8_t)std::max(m, 0);
+      }
+    for (int q = 0; q < st->n_muscl[c]; ++q) {
+      size_t e = (size_t)c * NFM + q;
+      int m = find(c, st->muscl[e], st->muscl_shift ? st->muscl_shift + e * D : nullptr);
+      if (m < 0) fail("MUSCL member outside the central stencil at cell " + std::to_string(c));
+      mpos[(size_t)q * N + c] = (uint8_t)std::max(m, 0);
+    }
+    int k = 0;
+    for (int e = cf_off[c]; e < cf_off[c + 1]; ++e, ++k) {
+      int f = cf[e] & 0x7fffffff;
+      int side = (cf[e] >> 31) & 1;
+      int nb = side ? mesh->face_cells[2 * f] : mesh->face_cells[2 * f + 1];
+      if (nb < 0) continue;
+      int8_t sh[3] = {0, 0, 0};
+      if (mesh->face_shift)
+        for (int j = 0; j < D; ++j) sh[j] = (int8_t)(side ? -mesh->face_shift[(size_t)f * D + j] : mesh->face_shift[(size_t)f * D + j]);
+      int m = find(c, nb, sh);
+      if (m < 0) fail("face neighbour outside the central stencil at cell " + std::to_string(c));
+      nbpos[(size_t)k * N + c] = (uint8_t)std::max(m, 0);
+    }
+  }
+  std::vector<int> inv_off(N + 1, 0), inv_idx((size_t)N * M);
+  for (size_t e = 0; e < (size_t)N * M; ++e) inv_off[st->central[e] + 1]++;
+  for (int j = 0; j < N; ++j) inv_off[j + 1] += inv_off[j];
+  std::vector<int> fill(inv_off.begin(), inv_off.end() - 1);
+  for (int i = 0; i < N; ++i)
+    for (int m = 0; m < M; ++m) inv_idx[fill[st->central[(size_t)i * M + m]]++] = m * N + i;
+  auto put = [&](auto &tabs) -> hfv_status {
+    hfv_status e2;
+    if ((e2 = upload(ctx, &tabs.dpos, dpos.data(), dpos.size(), s))) return e2;
+    if ((e2 = upload(ctx, &tabs.mpos, mpos.data(), mpos.size(), s))) return e2;
+    if ((e2 = upload(ctx, &tabs.nbpos, nbpos.data(), nbpos.size(), s))) return e2;
+    if ((e2 = upload(ctx, &tabs.inv_off, inv_off.data(), inv_off.size(), s))) return e2;
+    if ((e2 = upload(ctx, &tabs.inv_idx, inv_idx.data(), inv_idx.size(), s))) return e2;
+    return HFV_OK;
+  };
+  hfv_status e = ctx->prec == 64 ? put(ctx->t64) : put(ctx->t32);
+  if (e != HFV_OK) return e;
+  const size_t ts = ctx->prec == 64 ? 8 : 4;
+  if ((e = dev_alloc(ctx, &ctx->vjp_C, ts * (size_t)M * ctx->nvar * N))) return e;
+  if ((e = dev_alloc(ctx, &ctx->vjp_S, ts * (size_t)ctx->nvar * N))) return e;
+  if ((e = dev_alloc(ctx, &ctx->vjp_gfs, ts * 2 * (size_t)ctx->nvar * ctx->NGPT))) return e;
   HFV_HIP(hipStreamSynchronize(s));
   return HFV_OK;
 }

@@ -1,11 +1,515 @@
-// Vector-Jacobian product of the residual with frozen switches.
-#include "hfv_internal.hpp"
+// Vector-Jacobian product of the residual with the cell classes frozen.
+//
+// R(U) composes three maps: cell averages -> face Gauss-point states (the
+// reconstruction of each cell's class), face states -> integrated face
+// fluxes, face fluxes -> residual (Eq. EulerEquationsDetails).  The adjoint
+// runs them backwards:
+//   k_flux_vjp    dJ/dF from dJ/dR, then through the Riemann solver at every
+//                 Gauss point; its Jacobian columns come from forward-mode dual
+//                 numbers, branches (wave-speed choices, HLLC region) held at
+//                 the primal values
+//   k_recon_vjp   per cell and variable, back through the cell's frozen class:
+//                 linear (Section 2.1), CWENOZ including its nonlinear weights
+//                 (Section 2.3), Barth-Jespersen MUSCL with the limiting point
+//                 and bound frozen (Section 2.2), or first order; contributions
+//                 to each central-stencil slot are stored, not scattered
+//   k_gather_vjp  each cell sums the slot contributions that refer to it
+//                 through the transposed stencil, in a fixed order
+// No floating-point atomics are used, so the result is deterministic.
+#include "hfv_device.hpp"
 
 namespace hfv {
 
-hfv_status run_vjp(hfv_ctx *ctx, const void *, const uint8_t *, const void *, void *, hipStream_t) {
-  ctx->err = "residual VJP is not available in this build";
-  return HFV_ERR_STATE;
+template <typename T>
+struct VjpArgs {
+  int N, NGPT, form;
+  const T *U;
+  const uint8_t *cls;
+  const T *gfs;
+  T *C;
+  T *S;
+  Tables<T> t;
+  T lam1p, eps_w, b_w;
+};
+
+template <int DIM, typename T>
+__global__ __launch_bounds__(256) void k_flux_vjp(int NF, int N, int NGPT, const T *fs, const int *gp_off,
+                                                  const T *fn, const T *gpw, const int *fc, const T *ivol,
+                                                  const T *gR, T gamma, int hllc, T *gfs) {
+  constexpr int NV = DIM + 2;
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= NF) return;
+  const int L = fc[f], Rc = fc[NF + f];
+  T n[DIM];
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) n[j] = fn[(long)j * NF + f];
+  T gF[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+    gF[v] = -gR[(long)v * N + L] * ivol[L] + (Rc >= 0 ? gR[(long)v * N + Rc] * ivol[Rc] : (T)0);
+  for (int g = gp_off[f]; g < gp_off[f + 1]; ++g) {
+    T qL[NV], qR[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      qL[v] = fs[(long)v * NGPT + g];
+      qR[v] = fs[(long)(NV + v) * NGPT + g];
+    }
+    const T w = gpw[g];
+    T gl[NV], gr[NV];
+#pragma unroll
+    for (int tg = 0; tg < 2 * NV; ++tg) {
+      Dual<T> dL[NV], dR[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        dL[v] = Dual<T>(qL[v], tg == v ? (T)1 : (T)0);
+        dR[v] = Dual<T>(qR[v], tg == NV + v ? (T)1 : (T)0);
+      }
+      Dual<T> F[NV];
+      riemann<DIM, Dual<T>, T>(dL, dR, n, gamma, hllc, F);
+      T acc = 0;
+#pragma unroll
+      for (int u = 0; u < NV; ++u) acc += gF[u] * F[u].d;
+      if (tg < NV)
+        gl[tg] = w * acc;
+      else
+        gr[tg - NV] = w * acc;
+    }
+    if (Rc < 0) {  // transmissive ghost: the right state is a copy of the left one
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        gl[v] += gr[v];
+        gr[v] = 0;
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      gfs[(long)v * NGPT + g] = gl[v];
+      gfs[(long)(NV + v) * NGPT + g] = gr[v];
+    }
+  }
+}
+
+__device__ inline double pow_safe(double x, double e) { return (x == 0.0 && e > 0.0) ? 0.0 : pow(x, e); }
+
+template <int DIM, int R, typename T>
+__global__ __launch_bounds__(256) void k_recon_vjp(VjpArgs<T> a) {
+  constexpr int NV = DIM + 2, K = n_unknowns(DIM, R), M = 2 * K, NFM = nf_max(DIM), MD = 2 * DIM;
+  Lane<NV> L;
+  if (!L.ok || L.item >= a.N) return;
+  const int cell = L.item, v = L.sub, N = a.N;
+  const Tables<T> &t = a.t;
+  const int cls = a.cls[cell];
+  const int ng = t.ngp[cell];
+  const long MS = (long)NV * N;
+  T *C = a.C + (long)v * N + cell;  // slot m lives at C[m * MS]
+  auto gq_at = [&](int g) -> T {
+    const long d = t.gpdst[(long)g * N + cell] & ~(1 << 30);
+    return a.gfs[d + (long)v * a.NGPT];
+  };
+  T gsum = 0;
+  if (cls == HFV_CLASS_FIRST_ORDER) {
+    for (int g = 0; g < ng; ++g) gsum += gq_at(g);
+    for (int m = 0; m < M; ++m) C[m * MS] = 0;
+    a.S[(long)v * N + cell] = gsum;
+    return;
+  }
+  const T u0 = a.U[(long)v * N + cell];
+  T psb[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) psb[k] = t.psibar[(long)k * N + cell];
+  auto xi_at = [&](int g, T(&xi)[DIM]) {
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) xi[j] = t.gpxi[((long)g * DIM + j) * N + cell];
+  };
+
+  if (cls == HFV_CLASS_LINEAR) {
+    T b[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) b[k] = 0;
+    for (int g = 0; g < ng; ++g) {
+      const T gq = gq_at(g);
+      gsum += gq;
+      T xi[DIM], phi[K];
+      xi_at(g, xi);
+      basis_at<DIM, R, T>(xi, psb, phi);
+#pragma unroll
+      for (int k = 0; k < K; ++k) b[k] += phi[k] * gq;
+    }
+    T self = gsum;
+    for (int m = 0; m < M; ++m) {
+      T c = 0;
+#pragma unroll
+      for (int k = 0; k < K; ++k) c += t.P[((long)k * M + m) * N + cell] * b[k];
+      C[m * MS] = c;
+      self -= c;
+    }
+    a.S[(long)v * N + cell] = self;
+    return;
+  }
+
+  if (cls == HFV_CLASS_CWENOZ) {
+    // ---- forward recompute (Section 2.3)
+    T co[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) co[k] = 0;
+    for (int m = 0; m < M; ++m) {
+      const T du = a.U[(long)v * N + t.sten[(long)m * N + cell]] - u0;
+#pragma unroll
+      for (int k = 0; k < K; ++k) co[k] += t.P[((long)k * M + m) * N + cell] * du;
+    }
+    const int nd = t.ndir[cell];
+    T ad[NFM][DIM];
+#pragma unroll
+    for (int s = 0; s < NFM; ++s) {
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) ad[s][j] = 0;
+      if (s < nd) {
+        for (int q = 0; q < MD; ++q) {
+          const T du = a.U[(long)v * N + t.dsten[((long)s * MD + q) * N + cell]] - u0;
+#pragma unroll
+          for (int j = 0; j < DIM; ++j) ad[s][j] += t.Pdir[(((long)s * DIM + j) * MD + q) * N + cell] * du;
+        }
+      }
+    }
+    const T lam1 = (T)1 - (T)1 / a.lam1p;
+    const T lams = ((T)1 - lam1) / (T)nd;
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) {
+      T sdir = 0;
+#pragma unroll
+      for (int s = 0; s < NFM; ++s) sdir += ad[s][j];
+      co[j] = co[j] - lams * sdir;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) co[k] /= lam1;  // co now holds p_1's coefficients
+    double si1 = 0, sis[NFM];
+#pragma unroll
+    for (int s = 0; s < NFM; ++s) sis[s] = 0;
+    {
+      int p = 0;
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int q = k; q < K; ++q, ++p) {
+          const double o = (double)t.OI[(long)p * N + cell] * (q == k ? 1.0 : 2.0);
+          si1 += o * (double)co[k] * (double)co[q];
+          if (q < DIM) {
+#pragma unroll
+            for (int s = 0; s < NFM; ++s) sis[s] += o * (double)ad[s][k] * (double)ad[s][q];
+          }
+        }
+    }
+    double tau = 0;
+#pragma unroll
+    for (int s = 0; s < NFM; ++s)
+      if (s < nd) tau += fabs(sis[s] - si1);
+    tau /= (double)nd;
+    const double eps = (double)a.eps_w, b = (double)a.b_w, l1 = (double)lam1, ls = (double)lams;
+    const bool zform = a.form == HFV_WENOZ_POW;
+    double w1, ws[NFM], W;
+    if (zform)
+      w1 = l1 * (1.0 + pow_safe(tau / (eps + si1), b));
+    else
+      w1 = l1 * (1.0 + pow_safe(tau, b) / (eps + si1));
+    W = w1;
+#pragma unroll
+    for (int s = 0; s < NFM; ++s) {
+      ws[s] = 0;
+      if (s < nd)
+        ws[s] = zform ? ls * (1.0 + pow_safe(tau / (eps + sis[s]), b)) : ls * (1.0 + pow_safe(tau, b) / (eps + sis[s]));
+      W += ws[s];
+    }
+    const double om1 = w1 / W;
+    double oms[NFM];
+#pragma unroll
+    for (int s = 0; s < NFM; ++s) oms[s] = ws[s] / W;
+    // ---- backward
+    T gb[K];  // d J / d (CWENOZ coefficients)
+#pragma unroll
+    for (int k = 0; k < K; ++k) gb[k] = 0;
+    for (int g = 0; g < ng; ++g) {
+      const T gq = gq_at(g);
+      gsum += gq;
+      T xi[DIM], phi[K];
+      xi_at(g, xi);
+      basis_at<DIM, R, T>(xi, psb, phi);
+#pragma unroll
+      for (int k = 0; k < K; ++k) gb[k] += phi[k] * gq;
+    }
+    double g_om1 = 0, g_oms[NFM];
+#pragma unroll
+    for (int k = 0; k < K; ++k) g_om1 += (double)gb[k] * (double)co[k];
+    T gad[NFM][DIM];
+#pragma unroll
+    for (int s = 0; s < NFM; ++s) {
+      g_oms[s] = 0;
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) {
+        g_oms[s] += (double)gb[j] * (double)ad[s][j];
+        gad[s][j] = (T)oms[s] * gb[j];
+      }
+    }
+    // gb becomes d J / d a_1
+#pragma unroll
+    for (int k = 0; k < K; ++k) gb[k] = (T)om1 * gb[k];
+    double dot = g_om1 * om1;
+#pragma unroll
+    for (int s = 0; s < NFM; ++s) dot += g_oms[s] * oms[s];
+    const double gw1 = (g_om1 - dot) / W;
+    double gtau = 0, gsi1 = 0, gsis[NFM];
+    {
+      const double d1 = eps + si1;
+      if (zform) {
+        const double r1 = tau / d1;
+        gtau += gw1 * l1 * b * pow_safe(r1, b - 1.0) / d1;
+        gsi1 += -gw1 * l1 * b * pow_safe(r1, b) / d1;
+      } else {
+        gtau += gw1 * l1 * b * pow_safe(tau, b - 1.0) / d1;
+        gsi1 += -gw1 * l1 * pow_safe(tau, b) / (d1 * d1);
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < NFM; ++s) {
+      gsis[s] = 0;
+      if (s < nd) {
+        const double gws = (g_oms[s] - dot) / W;
+        const double ds = eps + sis[s];
+        if (zform) {
+          const double rs = tau / ds;
+          gtau += gws * ls * b * pow_safe(rs, b - 1.0) / ds;
+          gsis[s] = -gws * ls * b * pow_safe(rs, b) / ds;
+        } else {
+          gtau += gws * ls * b * pow_safe(tau, b - 1.0) / ds;
+          gsis[s] = -gws * ls * pow_safe(tau, b) / (ds * ds);
+        }
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < NFM; ++s) {
+      if (s < nd) {
+        const double sg = (double)((sis[s] > si1) - (sis[s] < si1));
+        gsis[s] += gtau * sg / (double)nd;
+        gsi1 -= gtau * sg / (double)nd;
+      }
+    }
+    // SI = a^T OI a  ->  d SI / d a = 2 OI a
+    {
+      int p = 0;
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int q = k; q < K; ++q, ++p) {
+          const T o = t.OI[(long)p * N + cell];
+          const T c1 = (T)(2.0 * gsi1) * o;
+          gb[k] += c1 * co[q];
+          if (q != k) gb[q] += c1 * co[k];
+          if (q < DIM) {
+#pragma unroll
+            for (int s = 0; s < NFM; ++s) {
+              const T cs = (T)(2.0 * gsis[s]) * o;
+              gad[s][k] += cs * ad[s][q];
+              if (q != k) gad[s][q] += cs * ad[s][k];
+            }
+          }
+        }
+    }
+    // a_1 = (a_opt - lambda_s sum_s a_s) / lambda_1
+#pragma unroll
+    for (int k = 0; k < K; ++k) gb[k] /= lam1;  // now d J / d a_opt
+#pragma unroll
+    for (int s = 0; s < NFM; ++s)
+      if (s < nd) {
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) gad[s][j] -= lams * gb[j];
+      }
+    T self = gsum;
+    for (int m = 0; m < M; ++m) {
+      T c = 0;
+#pragma unroll
+      for (int k = 0; k < K; ++k) c += t.P[((long)k * M + m) * N + cell] * gb[k];
+      C[m * MS] = c;
+      self -= c;
+    }
+#pragma unroll
+    for (int s = 0; s < NFM; ++s) {
+      if (s < nd) {
+        for (int q = 0; q < MD; ++q) {
+          T x = 0;
+#pragma unroll
+          for (int j = 0; j < DIM; ++j) x += t.Pdir[(((long)s * DIM + j) * MD + q) * N + cell] * gad[s][j];
+          C[(long)t.dpos[((long)s * MD + q) * N + cell] * MS] += x;
+          self -= x;
+        }
+      }
+    }
+    a.S[(long)v * N + cell] = self;
+    return;
+  }
+
+  // ---- MUSCL with the Barth-Jespersen limiter (Section 2.2)
+  for (int m = 0; m < M; ++m) C[m * MS] = 0;
+  const int nm = t.nmus[cell];
+  T gr[DIM];
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) gr[j] = 0;
+  for (int q = 0; q < nm; ++q) {
+    const T du = a.U[(long)v * N + t.msten[(long)q * N + cell]] - u0;
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) gr[j] += t.Pmus[((long)j * NFM + q) * N + cell] * du;
+  }
+  T mn = u0, mx = u0;
+  int imn = -1, imx = -1;
+  const int nf = t.nfc[cell];
+  for (int f = 0; f < nf; ++f) {
+    const int j = t.nbr[(long)f * N + cell];
+    if (j >= 0) {
+      const T u = a.U[(long)v * N + j];
+      if (u < mn) {
+        mn = u;
+        imn = f;
+      }
+      if (u > mx) {
+        mx = u;
+        imx = f;
+      }
+    }
+  }
+  T th = 1, dstar = 0;
+  int gstar = -1;
+  for (int g = 0; g < ng; ++g) {
+    T xi[DIM];
+    xi_at(g, xi);
+    T d = 0;
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) d += gr[j] * (xi[j] - psb[j]);
+    T ratio = 1;
+    if (d > 0)
+      ratio = fmin((T)1, (mx - u0) / d);
+    else if (d < 0)
+      ratio = fmin((T)1, (mn - u0) / d);
+    if (ratio < th) {
+      th = ratio;
+      gstar = g;
+      dstar = d;
+    }
+  }
+  T gth = 0, gg[DIM];
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) gg[j] = 0;
+  for (int g = 0; g < ng; ++g) {
+    const T gq = gq_at(g);
+    gsum += gq;
+    T xi[DIM];
+    xi_at(g, xi);
+    T d = 0;
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) d += gr[j] * (xi[j] - psb[j]);
+    gth += gq * d;
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) gg[j] += th * gq * (xi[j] - psb[j]);
+  }
+  T self = gsum;
+  if (gstar >= 0) {  // theta = (bound - U_i) / Delta at the limiting point
+    const T ginv = gth / dstar;
+    self -= ginv;
+    const int ib = dstar > 0 ? imx : imn;
+    if (ib < 0)
+      self += ginv;
+    else
+      C[(long)t.nbpos[(long)ib * N + cell] * MS] += ginv;
+    T xi[DIM];
+    xi_at(gstar, xi);
+    const T gd = -gth * th / dstar;
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) gg[j] += gd * (xi[j] - psb[j]);
+  }
+  for (int q = 0; q < nm; ++q) {
+    T x = 0;
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) x += t.Pmus[((long)j * NFM + q) * N + cell] * gg[j];
+    C[(long)t.mpos[(long)q * N + cell] * MS] += x;
+    self -= x;
+  }
+  a.S[(long)v * N + cell] = self;
+}
+
+template <int NV, typename T>
+__global__ __launch_bounds__(256) void k_gather_vjp(int N, const int *inv_off, const int *inv_idx, const T *C,
+                                                    const T *S, T *gU) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  T acc[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc[v] = S[(long)v * N + j];
+  for (int e = inv_off[j]; e < inv_off[j + 1]; ++e) {
+    const int code = inv_idx[e];
+    const int m = code / N, i = code - m * N;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] += C[((long)m * NV + v) * N + i];
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) gU[(long)v * N + j] = acc[v];
+}
+
+static inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
+
+template <int DIM, int R, typename T>
+static hfv_status vjp_impl(hfv_ctx *ctx, Tables<T> &t, const void *U, const uint8_t *cls, const void *gR, void *gU,
+                           hipStream_t s) {
+  constexpr int NV = DIM + 2;
+  hfv_status e = run_reconstruct_frozen(ctx, U, ctx->fs_ws, cls, s);
+  if (e != HFV_OK) return e;
+  ProfScope ps(ctx, HFV_SLOT_VJP, s);
+  k_flux_vjp<DIM, T><<<nblk(ctx->NF, 256), 256, 0, s>>>(ctx->NF, ctx->N, ctx->NGPT, (const T *)ctx->fs_ws, t.gp_off,
+                                                         t.fnormal, t.gpw, t.face_cells, t.ivol, (const T *)gR,
+                                                         (T)ctx->p.gamma, ctx->p.riemann == HFV_HLLC,
+                                                         (T *)ctx->vjp_gfs);
+  VjpArgs<T> a;
+  a.N = ctx->N;
+  a.NGPT = ctx->NGPT;
+  a.form = ctx->p.form;
+  a.U = (const T *)U;
+  a.cls = cls;
+  a.gfs = (const T *)ctx->vjp_gfs;
+  a.C = (T *)ctx->vjp_C;
+  a.S = (T *)ctx->vjp_S;
+  a.t = t;
+  a.lam1p = (T)ctx->p.lam1p;
+  a.eps_w = (T)ctx->p.eps_w;
+  a.b_w = (T)ctx->p.b_w;
+  constexpr int CPW = 64 / NV;
+  const long waves = ((long)ctx->N + CPW - 1) / CPW;
+  k_recon_vjp<DIM, R, T><<<nblk(waves * 64, 256), 256, 0, s>>>(a);
+  k_gather_vjp<NV, T><<<nblk(ctx->N, 256), 256, 0, s>>>(ctx->N, t.inv_off, t.inv_idx, (const T *)ctx->vjp_C,
+                                                       (const T *)ctx->vjp_S, (T *)gU);
+  HFV_HIP(hipGetLastError());
+  return HFV_OK;
+}
+
+template <typename T>
+static hfv_status vjp_t(hfv_ctx *ctx, Tables<T> &t, const void *U, const uint8_t *cls, const void *gR, void *gU,
+                        hipStream_t s) {
+  switch (ctx->dim * 10 + ctx->r) {
+    case 21: return vjp_impl<2, 1, T>(ctx, t, U, cls, gR, gU, s);
+    case 22: return vjp_impl<2, 2, T>(ctx, t, U, cls, gR, gU, s);
+    case 23: return vjp_impl<2, 3, T>(ctx, t, U, cls, gR, gU, s);
+    case 24: return vjp_impl<2, 4, T>(ctx, t, U, cls, gR, gU, s);
+    case 31: return vjp_impl<3, 1, T>(ctx, t, U, cls, gR, gU, s);
+    case 32: return vjp_impl<3, 2, T>(ctx, t, U, cls, gR, gU, s);
+    case 33: return vjp_impl<3, 3, T>(ctx, t, U, cls, gR, gU, s);
+    case 34: return vjp_impl<3, 4, T>(ctx, t, U, cls, gR, gU, s);
+  }
+  ctx->err = "unsupported (dim, order_r)";
+  return HFV_ERR_PARAM;
+}
+
+hfv_status run_vjp(hfv_ctx *ctx, const void *U, const uint8_t *cls, const void *gR, void *gU, hipStream_t s) {
+  if (!ctx->vjp_ok) {
+    ctx->err = "residual VJP unavailable for these stencils: " + ctx->vjp_why;
+    return HFV_ERR_STATE;
+  }
+  return ctx->prec == 64 ? vjp_t<double>(ctx, ctx->t64, U, cls, gR, gU, s)
+                         : vjp_t<float>(ctx, ctx->t32, U, cls, gR, gU, s);
 }
 
 }  // namespace hfv

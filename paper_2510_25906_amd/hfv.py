@@ -67,6 +67,7 @@ def load():
     lib.hfv_reconstruct.argtypes = [_p, _p, _p, _p, _p]
     lib.hfv_residual.argtypes = [_p, _p, _p, _p, _p, _p]
     lib.hfv_residual_vjp.argtypes = [_p, _p, _p, _p, _p, _p]
+    lib.hfv_residual_frozen.argtypes = [_p, _p, _p, _p, _p]
     lib.hfv_query.argtypes = [_p, C.c_int32, C.POINTER(C.c_int64)]
     lib.hfv_copy_table.argtypes = [_p, C.c_int32, _p, C.c_int64]
     lib.hfv_set_launch.argtypes = [_p, C.c_int32, C.c_int32, C.c_int32]
@@ -77,6 +78,7 @@ def load():
     lib.hfv_destroy.argtypes = [_p]
     lib.hfv_destroy.restype = None
     for name in ("hfv_create", "hfv_set_params", "hfv_reconstruct", "hfv_residual", "hfv_residual_vjp",
+                 "hfv_residual_frozen",
                  "hfv_query", "hfv_copy_table", "hfv_set_launch", "hfv_profile_enable", "hfv_profile_read"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
@@ -252,3 +254,47 @@ class Context:
                                               C.c_void_p(gR.data_ptr()), C.c_void_p(gU.data_ptr()),
                                               _stream_handle(stream)))
         return gU
+
+    def residual_frozen(self, U, cell_class, R=None, stream=None):
+        """Residual with the given classes held fixed (what the VJP linearises)."""
+        import torch
+        self._chk_u(U)
+        R = R if R is not None else torch.empty_like(U)
+        self._check(self.lib.hfv_residual_frozen(self.h, C.c_void_p(U.data_ptr()),
+                                                 C.c_void_p(cell_class.data_ptr()), C.c_void_p(R.data_ptr()),
+                                                 _stream_handle(stream)))
+        return R
+
+    def residual_autograd(self, U):
+        """R(U) as a differentiable torch op; backward is the library's VJP with
+        the classes of this forward evaluation frozen."""
+        return _residual_function().apply(U, self)
+
+
+_RF = None
+
+
+def _residual_function():
+    global _RF
+    if _RF is not None:
+        return _RF
+    import torch
+
+    class Residual(torch.autograd.Function):
+        @staticmethod
+        def forward(fctx, U, hctx):
+            U = U.contiguous()
+            cls = torch.empty(hctx.n_cells, dtype=torch.uint8, device=U.device)
+            R = hctx.residual(U, cell_class=cls)
+            fctx.save_for_backward(U, cls)
+            fctx.hctx = hctx
+            return R
+
+        @staticmethod
+        def backward(fctx, gR):
+            U, cls = fctx.saved_tensors
+            gU = fctx.hctx.residual_vjp(U, cls, gR.contiguous())
+            return gU, None
+
+    _RF = Residual
+    return _RF
