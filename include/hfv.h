@@ -187,10 +187,15 @@ hfv_status hfv_query(const hfv_ctx *ctx, int32_t what, int64_t *out);
 enum { HFV_T_PINV = 0, HFV_T_OI = 1, HFV_T_PSIBAR = 2, HFV_T_GEOM = 3, HFV_T_PDIR = 4, HFV_T_PMUS = 5 };
 hfv_status hfv_copy_table(const hfv_ctx *ctx, int32_t which, void *host_dst, int64_t bytes);
 
-/* Tuning: lanes per cell (1, 2 or 4 in 2D; 1 or 5 in 3D), threads per block
- * and the cap on resident blocks of the class-list kernels.  0 keeps the
- * current value. */
-hfv_status hfv_set_launch(hfv_ctx *ctx, int32_t lanes_per_cell, int32_t block, int32_t list_blocks);
+/* Tuning.  lanes_per_cell: lanes of a wave sharing one cell in the
+ * variable-split kernels (1, 2 or 4 in 2D; 1 or 5 in 3D); block: threads per
+ * block (64..256, multiple of 64); list_blocks: cap on resident blocks of the
+ * class-list kernels; linear_split: mapping of the linear + NAD kernel, 0 =
+ * lanes split the conserved variables (lanes_per_cell lanes), 1 = lanes split
+ * the stencil members and Gauss points (linear_lanes = 2, 4 or 8 lanes).
+ * 0 keeps the current value of lanes_per_cell, block and list_blocks. */
+hfv_status hfv_set_launch(hfv_ctx *ctx, int32_t lanes_per_cell, int32_t block, int32_t list_blocks,
+                          int32_t linear_split, int32_t linear_lanes);
 
 /* Kernel timing with HIP events recorded on the launch stream.
  * hfv_profile_enable arms up to `capacity` timed launches of the kernels

@@ -191,7 +191,8 @@ hfv_status hfv_set_params(hfv_ctx *ctx, const hfv_params *p) {
   return HFV_OK;
 }
 
-hfv_status hfv_set_launch(hfv_ctx *ctx, int32_t lanes, int32_t block, int32_t list_blocks) {
+hfv_status hfv_set_launch(hfv_ctx *ctx, int32_t lanes, int32_t block, int32_t list_blocks, int32_t linear_split,
+                          int32_t linear_lanes) {
   if (!ctx) return HFV_ERR_PARAM;
   if (lanes) {
     bool ok = lanes == 1 || lanes == ctx->nvar || (ctx->dim == 2 && lanes == 2);
@@ -206,6 +207,13 @@ hfv_status hfv_set_launch(hfv_ctx *ctx, int32_t lanes, int32_t block, int32_t li
     if (list_blocks < 1) return ctx->err = "list_blocks must be positive", HFV_ERR_PARAM;
     ctx->list_blocks = list_blocks;
   }
+  if (linear_split < 0 || linear_split > 1) return ctx->err = "linear_split must be 0 or 1", HFV_ERR_PARAM;
+  if (linear_split == 1) {
+    if (linear_lanes != 2 && linear_lanes != 4 && linear_lanes != 8)
+      return ctx->err = "linear_lanes must be 2, 4 or 8 with the member split", HFV_ERR_PARAM;
+    ctx->lin_lanes = linear_lanes;
+  }
+  ctx->lin_split = linear_split;
   return HFV_OK;
 }
 

@@ -118,6 +118,158 @@ __global__ __launch_bounds__(256) void k_linear(HotArgs<T> a) {
   if (L.sub == 0) a.own[cell] = (uint8_t)(c | (hok ? 0 : 4));
 }
 
+// K1, member-split mapping: the G lanes of a cell's group each take every G-th
+// stencil member (all variables), so one load instruction fetches G distinct
+// rows of the cell's pseudo-inverse; a butterfly sum gives every lane the
+// full coefficients.  The lanes then split the face neighbours and the Gauss
+// points, and combine the NAD excursions and Harten flags.  Same results as
+// k_linear up to the order of the sums.
+template <int G, typename V>
+__device__ inline V xor_sum(V x) {
+#pragma unroll
+  for (int off = 1; off < G; off <<= 1) x += __shfl_xor(x, off);
+  return x;
+}
+template <int G, typename V>
+__device__ inline V xor_max(V x) {
+#pragma unroll
+  for (int off = 1; off < G; off <<= 1) x = fmax(x, __shfl_xor(x, off));
+  return x;
+}
+template <int G, typename V>
+__device__ inline V xor_min(V x) {
+#pragma unroll
+  for (int off = 1; off < G; off <<= 1) x = fmin(x, __shfl_xor(x, off));
+  return x;
+}
+
+template <int DIM, int R, typename T, int G>
+__global__ __launch_bounds__(256) void k_linear_ms(HotArgs<T> a) {
+  constexpr int NV = DIM + 2, K = n_unknowns(DIM, R), M = 2 * K, NFM = nf_max(DIM);
+  constexpr int MPL = (M + G - 1) / G;
+  static_assert((G & (G - 1)) == 0 && 64 % G == 0, "group size must be a power of two");
+  if (blockIdx.x == 0 && threadIdx.x < 4) a.counts[threadIdx.x] = 0;
+  Lane<G> L;
+  const int cell = L.item;
+  if (!L.ok || cell >= a.N) return;  // whole groups leave together
+  const int N = a.N, q = L.sub;
+  T u0[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) u0[v] = a.U[(long)v * N + cell];
+  T co[K][NV];
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) co[k][v] = (T)0;
+#pragma unroll
+  for (int t = 0; t < MPL; ++t) {
+    const int m = q + t * G;
+    if (m < M) {
+      const int j = a.t.sten[(long)m * N + cell];
+      T du[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) du[v] = a.U[(long)v * N + j] - u0[v];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const T p = a.t.P[((long)k * M + m) * N + cell];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) co[k][v] += p * du[v];
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) co[k][v] = xor_sum<G>(co[k][v]);
+
+  T mn[NV], mx[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) mn[v] = mx[v] = u0[v];
+  T dmax = -INFINITY, dmin = INFINITY;
+  const int nf = a.t.nfc[cell];
+#pragma unroll
+  for (int f0 = 0; f0 < NFM; f0 += G) {
+    const int f = f0 + q;
+    if (f < nf) {
+      const int j = a.t.nbr[(long)f * N + cell];
+      if (j >= 0) {
+        T s2 = 0;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          const T u = a.U[(long)v * N + j];
+          mn[v] = fmin(mn[v], u);
+          mx[v] = fmax(mx[v], u);
+          s2 += (u - u0[v]) * (u - u0[v]);
+        }
+        const T nrm = sqrt(s2);
+        dmax = fmax(dmax, nrm);
+        dmin = fmin(dmin, nrm);
+      }
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    mn[v] = xor_min<G>(mn[v]);
+    mx[v] = xor_max<G>(mx[v]);
+  }
+  dmax = xor_max<G>(dmax);
+  dmin = xor_min<G>(dmin);
+  const bool has_nb = dmax >= (T)0;
+  const T rho_b = u0[0];
+  const T p_b = pressure<NV, T>(u0, a.gamma);
+  T psb[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) psb[k] = a.t.psibar[(long)k * N + cell];
+  T exc[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) exc[v] = -INFINITY;
+  bool hok = true;
+  const int ng = a.t.ngp[cell];
+  for (int g = q; g < ng; g += G) {
+    T xi[DIM];
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) xi[j] = a.t.gpxi[((long)g * DIM + j) * N + cell];
+    T phi[K];
+    basis_at<DIM, R, T>(xi, psb, phi);
+    T val[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      T s = 0;
+#pragma unroll
+      for (int k = 0; k < K; ++k) s += co[k][v] * phi[k];
+      val[v] = u0[v] + s;
+      exc[v] = fmax(exc[v], fmax(mn[v] - val[v], val[v] - mx[v]));
+    }
+    hok = hok && harten_point<NV, T>(val, rho_b, p_b, a);
+    const int dst = a.t.gpdst[(long)g * N + cell];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) store<NV, T>(a, dst, v, val[v]);
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) exc[v] = xor_max<G>(exc[v]);
+  {
+    int hv = hok ? 1 : 0;
+#pragma unroll
+    for (int off = 1; off < G; off <<= 1) hv &= __shfl_xor(hv, off);
+    hok = hv != 0;
+  }
+  int c = 0;
+  if (a.mode == HFV_HYBRID) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const T Rg = mx[v] - mn[v];
+      const T dm = fmax(a.alpha_m, a.beta_m * Rg);
+      const T sgn = (T)((a.beta_w > 0) - (a.beta_w < 0));
+      const T dw = sgn * fmax(a.alpha_w, fabs(a.beta_w * Rg));
+      const int cv = exc[v] <= dw ? HFV_CLASS_LINEAR : (exc[v] >= dm ? HFV_CLASS_MUSCL : HFV_CLASS_CWENOZ);
+      c = max(c, cv);
+    }
+    const T dU = has_nb ? dmax - dmin : (T)0;
+    if (dU < a.t.thr[cell]) c = HFV_CLASS_LINEAR;
+  }
+  if (q == 0) a.own[cell] = (uint8_t)(c | (hok ? 0 : 4));
+}
+
 // K2: final class (dilation over face neighbours) and per-class lists.
 constexpr int CLASSIFY_BLOCK = 1024;
 template <typename T>
@@ -573,7 +725,22 @@ static hfv_status recon_impl(hfv_ctx *ctx, Tables<T> &t, const void *U, void *fs
     k_zero4<<<1, 64, 0, s>>>(ctx->counts);
     { ProfScope ps(ctx, HFV_SLOT_MUSCL, s); k_muscl<DIM, R, T, G><<<grid_list, B, 0, s>>>(a, 1); }
   } else {
-    { ProfScope ps(ctx, HFV_SLOT_LINEAR, s); k_linear<DIM, R, T, G><<<grid_cells, B, 0, s>>>(a); }
+    {
+      ProfScope ps(ctx, HFV_SLOT_LINEAR, s);
+      if (ctx->lin_split == 1) {
+        const int GL = ctx->lin_lanes;
+        const long wl = ((long)ctx->N + 64 / GL - 1) / (64 / GL);
+        const unsigned gl = nblk(wl * 64, B);
+        if (GL == 4)
+          k_linear_ms<DIM, R, T, 4><<<gl, B, 0, s>>>(a);
+        else if (GL == 8)
+          k_linear_ms<DIM, R, T, 8><<<gl, B, 0, s>>>(a);
+        else
+          k_linear_ms<DIM, R, T, 2><<<gl, B, 0, s>>>(a);
+      } else {
+        k_linear<DIM, R, T, G><<<grid_cells, B, 0, s>>>(a);
+      }
+    }
     { ProfScope ps(ctx, HFV_SLOT_CLASSIFY, s); k_classify<T><<<nblk(ctx->N, CLASSIFY_BLOCK), CLASSIFY_BLOCK, 0, s>>>(a, ctx->NFM); }
     if (mode == HFV_HYBRID) {
       { ProfScope ps(ctx, HFV_SLOT_CWENOZ, s); k_cwenoz<DIM, R, T, G><<<grid_list, B, 0, s>>>(a, 0); }

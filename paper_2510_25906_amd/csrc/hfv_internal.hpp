@@ -116,6 +116,7 @@ struct hfv_ctx {
   size_t table_bytes = 0;
   // launch configuration
   int lanes = 1, block = 256, list_blocks = 2048;
+  int lin_split = 0, lin_lanes = 4;  // linear kernel: 0 variables per lane, 1 stencil members per lane
   int device = 0, n_cu = 256;
   // kernel timing (hfv_profile_*)
   struct ProfEv {

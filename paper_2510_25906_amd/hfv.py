@@ -70,7 +70,7 @@ def load():
     lib.hfv_residual_frozen.argtypes = [_p, _p, _p, _p, _p]
     lib.hfv_query.argtypes = [_p, C.c_int32, C.POINTER(C.c_int64)]
     lib.hfv_copy_table.argtypes = [_p, C.c_int32, _p, C.c_int64]
-    lib.hfv_set_launch.argtypes = [_p, C.c_int32, C.c_int32, C.c_int32]
+    lib.hfv_set_launch.argtypes = [_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
     lib.hfv_profile_enable.argtypes = [_p, C.c_int32, C.c_int32]
     lib.hfv_profile_read.argtypes = [_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     lib.hfv_last_error.argtypes = [_p]
@@ -164,6 +164,7 @@ class Context:
         self.K = self.query("K")
         self.M = self.query("M")
         self.dim = d
+        self._lin = (0, 4)
 
     def _check(self, rc):
         if rc != HFV_OK:
@@ -190,8 +191,12 @@ class Context:
         self._p = params_struct(params, self.precision)
         self._check(self.lib.hfv_set_params(self.h, C.byref(self._p)))
 
-    def set_launch(self, lanes=0, block=0, list_blocks=0):
-        self._check(self.lib.hfv_set_launch(self.h, lanes, block, list_blocks))
+    def set_launch(self, lanes=0, block=0, list_blocks=0, linear_split=None, linear_lanes=4):
+        """Launch shape; ``linear_split`` None keeps the linear kernel's current mapping."""
+        if linear_split is None:
+            linear_split, linear_lanes = self._lin
+        self._lin = (linear_split, linear_lanes)
+        self._check(self.lib.hfv_set_launch(self.h, lanes, block, list_blocks, linear_split, linear_lanes))
 
     def profile_enable(self, capacity: int, slots=None):
         mask = 0xff if slots is None else sum(1 << SLOTS[k] for k in slots)

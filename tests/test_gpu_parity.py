@@ -94,17 +94,19 @@ def test_c1_tables_match_oracle(hfv, c1):
     ctx.close()
 
 
-@pytest.mark.parametrize("lanes", [1, 2, 4])
-def test_c1_launch_shapes_agree(hfv, c1, lanes):
-    w, _ = c1
+@pytest.mark.parametrize("lanes,split,lin_lanes", [(1, 0, 4), (2, 0, 4), (4, 0, 4), (4, 1, 2), (4, 1, 4),
+                                                    (2, 1, 8)])
+def test_c1_launch_shapes_agree(hfv, c1, lanes, split, lin_lanes):
+    """Every work mapping gives the oracle's classes and states."""
+    w, om = c1
+    fs_o, cls_o = om.reconstruct(w.U)
     ctx = hfv.Context(w.mesh, w.stencils, w.params, 64)
-    Ud = to_dev(w.U, torch.float64)
-    fs0, c0 = ctx.reconstruct(Ud)
-    ctx.set_launch(lanes=lanes, block=128, list_blocks=3)
-    fs1, c1_ = ctx.reconstruct(Ud)
+    ctx.set_launch(lanes=lanes, block=128, list_blocks=3, linear_split=split, linear_lanes=lin_lanes)
+    fs, cls = ctx.reconstruct(to_dev(w.U, torch.float64))
     torch.cuda.synchronize()
-    assert torch.equal(c0, c1_)
-    assert torch.allclose(fs0, fs1, rtol=1e-13, atol=1e-13)
+    assert np.array_equal(cls.cpu().numpy(), cls_o)
+    S = state_scale(w.U)
+    assert rel_err(fs.cpu().numpy(), fs_o, S[None, :, None]) <= 1e-12
     ctx.close()
 
 
@@ -144,6 +146,8 @@ def test_c2_sampled_full_size(hfv):
             flags = dilated_flags(om, near_threshold(om, w.U, cells, 1e-12 if prec == 64 else 1e-6), cells)
             print(f"c2 prec={prec} mode={mode} sampled={cells.size} flagged={flags.sum()}", flush=True)
             ctx = hfv.Context(w.mesh, w.stencils, p, prec)
+            if mode == HYBRID and prec == 64:
+                ctx.set_launch(linear_split=1, linear_lanes=4)
             Ud = to_dev(w.U, torch.float64 if prec == 64 else torch.float32)
             fs, cls = ctx.reconstruct(Ud)
             torch.cuda.synchronize()

@@ -66,17 +66,19 @@ def test_3d_fp64_hybrid_residual(hfv, name):
     R_o, fs_o, cls_o = flux.residual(om, U)
     print(f"{name}: N={mesh.n_cells} classes={np.bincount(cls_o, minlength=4)}", flush=True)
     assert not near_threshold(om, U, np.arange(mesh.n_cells), 1e-12).any()
-    ctx = hfv.Context(mesh, st, p, 64)
-    fs = ctx.new_face_states()
-    cls = torch.empty(mesh.n_cells, dtype=torch.uint8, device="cuda")
-    R = ctx.residual(to_dev(U, torch.float64), face_states=fs, cell_class=cls)
-    torch.cuda.synchronize()
-    cls_g = cls.cpu().numpy()
-    assert np.array_equal(cls_g, cls_o), np.nonzero(cls_g != cls_o)[0][:20]
-    S = state_scale(U)
-    assert rel_err(fs.cpu().numpy(), fs_o, S[None, :, None]) <= 1e-12
-    assert rel_err(R.cpu().numpy(), R_o, np.abs(R_o).max(1)[:, None]) <= 1e-11
-    ctx.close()
+    for split in (0, 1):
+        ctx = hfv.Context(mesh, st, p, 64)
+        ctx.set_launch(linear_split=split, linear_lanes=4)
+        fs = ctx.new_face_states()
+        cls = torch.empty(mesh.n_cells, dtype=torch.uint8, device="cuda")
+        R = ctx.residual(to_dev(U, torch.float64), face_states=fs, cell_class=cls)
+        torch.cuda.synchronize()
+        cls_g = cls.cpu().numpy()
+        assert np.array_equal(cls_g, cls_o), np.nonzero(cls_g != cls_o)[0][:20]
+        S = state_scale(U)
+        assert rel_err(fs.cpu().numpy(), fs_o, S[None, :, None]) <= 1e-12
+        assert rel_err(R.cpu().numpy(), R_o, np.abs(R_o).max(1)[:, None]) <= 1e-11
+        ctx.close()
 
 
 @pytest.mark.parametrize("name,mode", [("tet4_r3", ALL_CWENOZ), ("tet4_r3", ALL_MUSCL), ("tgv10_r4", ALL_CWENOZ),
@@ -98,15 +100,15 @@ def test_3d_fp64_forced_modes(hfv, name, mode):
     ctx.close()
 
 
-@pytest.mark.parametrize("lanes", [1, 5])
-def test_3d_fp32_and_lane_shapes(hfv, lanes):
+@pytest.mark.parametrize("lanes,split,lin_lanes", [(1, 0, 4), (5, 0, 4), (5, 1, 4), (5, 1, 8)])
+def test_3d_fp32_and_lane_shapes(hfv, lanes, split, lin_lanes):
     mesh, st, U, p = case("tgv10_r4")
     om = OracleModel(mesh, st, p)
     R_o, fs_o, cls_o = flux.residual(om, U)
     cells = np.arange(mesh.n_cells)
     flags = near_threshold(om, U, cells, 1e-6)
     ctx = hfv.Context(mesh, st, p, 32)
-    ctx.set_launch(lanes=lanes)
+    ctx.set_launch(lanes=lanes, linear_split=split, linear_lanes=lin_lanes)
     fs, cls = ctx.reconstruct(to_dev(U, torch.float32))
     torch.cuda.synchronize()
     cls_g = cls.cpu().numpy()
