@@ -33,14 +33,14 @@ def kernel_bytes_linear(ctx, geo_ngp, geo_nf, prec):
 
     Per cell: the pseudo-inverse (K M s), stencil ids (4 M), the cell's own
     averages (nvar s), basis means (K s), Gauss-point coordinates (d s per
-    point) and slots (4 per point), the face-state writes (nvar s per point),
-    face-neighbour ids (4 per face), counts and threshold (2 + s) and the class
-    byte.  Neighbour averages are taken as cache hits (read once overall).
+    point), the Gauss-point state writes (nvar s per point), face-neighbour ids
+    (4 per face), counts and threshold (2 + s) and the class byte.  Neighbour
+    averages are taken as cache hits (read once overall).
     """
     s = 8 if prec == 64 else 4
     K, M, nvar, d = ctx.K, ctx.M, ctx.nvar, ctx.dim
     per_cell = s * K * M + 4 * M + s * nvar + s * K + 2 + s + 1
-    per_gp = s * d + 4 + s * nvar
+    per_gp = s * d + s * nvar
     return int(ctx.n_cells * per_cell + geo_ngp.sum() * per_gp + 4 * geo_nf.sum())
 
 

@@ -28,10 +28,15 @@
  *     conserved variables, states and residuals is double or float to match.
  *   - Conserved variables are structure-of-arrays [nvar][n_cells] with
  *     nvar = dim + 2: (rho, rho u, rho v[, rho w], E).
- *   - Face states are [2][nvar][n_gp]: side 0 is the face's left cell
- *     (face_cells[f][0]), side 1 its right cell; Gauss points are numbered
- *     face by face in face order.  At boundary faces side 1 holds the
- *     transmissive ghost state (a copy of side 0).
+ *   - Face Gauss-point states are cell-major, [ngp_cell_max][nvar][n_cells]
+ *     (ngp_cell_max = HFV_Q_NGP_CELL_MAX): slot g of cell c is the g-th
+ *     Gauss point on the faces of c, its faces taken in increasing face id
+ *     and each face's points in that face's quadrature order (the same order
+ *     for both cells of a face).  Slots beyond a cell's own count are left
+ *     untouched.  Face f's points start at slot (t & 255) of face_cells[f][0]
+ *     and at slot ((t >> 8) & 255) of face_cells[f][1], t = the f-th entry of
+ *     table HFV_T_FACE_SLOTS; a boundary face has no right state of its own
+ *     (its transmissive ghost is the left state).
  *   - A context is not thread-safe; calls that overlap on one context race.
  */
 #ifndef HFV_H
@@ -138,7 +143,7 @@ hfv_status hfv_set_params(hfv_ctx *ctx, const hfv_params *p);
  * cell, tagging of the von Neumann neighbourhood, CWENOZ / MUSCL on the
  * tagged cells through per-class work lists, Harten check on every cell.
  *   U            device [nvar][n_cells] cell averages
- *   face_states  device [2][nvar][n_gp] output
+ *   face_states  device [ngp_cell_max][nvar][n_cells] output (layout above)
  *   cell_class   device [n_cells] uint8 output (HFV_CLASS_*)
  * Asynchronous on `stream`. */
 hfv_status hfv_reconstruct(hfv_ctx *ctx, const void *U, void *face_states, uint8_t *cell_class, void *stream);
@@ -146,7 +151,7 @@ hfv_status hfv_reconstruct(hfv_ctx *ctx, const void *U, void *face_states, uint8
 /* Residual R_i = -(1/|V_i|) sum_f sum_alpha F(U_L, U_R) w_alpha |S_f| of
  * Eq. EulerEquationsDetails (F_v = 0) with HLLC or HLL fluxes (Section 2.4).
  *   R            device [nvar][n_cells] output
- *   face_states  device [2][nvar][n_gp] output, or NULL to use internal storage
+ *   face_states  device [ngp_cell_max][nvar][n_cells] output, or NULL to use internal storage
  *   cell_class   device [n_cells] output, or NULL to use internal storage
  * Deterministic: no floating-point atomics. */
 hfv_status hfv_residual(hfv_ctx *ctx, const void *U, void *R, void *face_states, uint8_t *cell_class,
@@ -183,8 +188,11 @@ hfv_status hfv_query(const hfv_ctx *ctx, int32_t what, int64_t *out);
  *   HFV_T_GEOM   [dim+2][n_cells]  double: centroid, volume, h_c
  *   HFV_T_PDIR   [nf_max][dim][Md][n_cells] directional pseudo-inverses
  *   HFV_T_PMUS   [dim][nf_max][n_cells] MUSCL pseudo-inverses
+ *   HFV_T_FACE_SLOTS [n_faces] int32: first Gauss-point slot of each face in
+ *                its left (bits 0-7) and right (bits 8-15) cell
  * `bytes` must equal the table size. */
-enum { HFV_T_PINV = 0, HFV_T_OI = 1, HFV_T_PSIBAR = 2, HFV_T_GEOM = 3, HFV_T_PDIR = 4, HFV_T_PMUS = 5 };
+enum { HFV_T_PINV = 0, HFV_T_OI = 1, HFV_T_PSIBAR = 2, HFV_T_GEOM = 3, HFV_T_PDIR = 4, HFV_T_PMUS = 5,
+       HFV_T_FACE_SLOTS = 6 };
 hfv_status hfv_copy_table(const hfv_ctx *ctx, int32_t which, void *host_dst, int64_t bytes);
 
 /* Tuning.  lanes_per_cell: lanes of a wave sharing one cell in the

@@ -155,7 +155,7 @@ hfv_status hfv_create(const hfv_mesh *mesh, const hfv_stencils *st, const hfv_pa
         (e = dev_alloc(ctx, (void **)&ctx->cls_ws, N)) == HFV_OK &&
         (e = dev_alloc(ctx, (void **)&ctx->lists, sizeof(int) * 3 * (size_t)N)) == HFV_OK &&
         (e = dev_alloc(ctx, (void **)&ctx->counts, sizeof(int) * 4)) == HFV_OK &&
-        (e = dev_alloc(ctx, &ctx->fs_ws, ts * 2 * ctx->nvar * (size_t)ctx->NGPT)) == HFV_OK &&
+        (e = dev_alloc(ctx, &ctx->fs_ws, ts * ctx->nvar * (size_t)ctx->NGPC * ctx->N)) == HFV_OK &&
         (e = dev_alloc(ctx, &ctx->fflux, ts * ctx->nvar * (size_t)ctx->NF)) == HFV_OK) {
       if (hipMemsetAsync(ctx->counts, 0, sizeof(int) * 4, s) != hipSuccess ||
           hipStreamSynchronize(s) != hipSuccess) {
@@ -289,6 +289,7 @@ hfv_status hfv_copy_table(const hfv_ctx *ctx, int32_t which, void *dst, int64_t 
     case HFV_T_GEOM: src = ctx->geom; n = 8 * (ctx->dim + 2) * N; break;
     case HFV_T_PDIR: src = d64 ? (const void *)ctx->t64.Pdir : ctx->t32.Pdir; n = ts * ctx->NFM * ctx->dim * ctx->Md * N; break;
     case HFV_T_PMUS: src = d64 ? (const void *)ctx->t64.Pmus : ctx->t32.Pmus; n = ts * ctx->dim * ctx->NFM * N; break;
+    case HFV_T_FACE_SLOTS: src = d64 ? ctx->t64.fgb : ctx->t32.fgb; n = sizeof(int) * (size_t)ctx->NF; break;
     default: return HFV_ERR_PARAM;
   }
   if ((int64_t)n != bytes) return HFV_ERR_PARAM;

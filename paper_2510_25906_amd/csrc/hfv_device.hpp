@@ -8,7 +8,7 @@ namespace hfv {
 
 template <typename T>
 struct HotArgs {
-  int N, NGPT, mode, form;
+  int N, mode, form;
   int frozen;              // adjoint recompute: classes given, no NAD or Harten re-check
   const uint8_t *cls_in;   // given classes when frozen
   const T *U;
@@ -141,11 +141,12 @@ __device__ inline void lsq_coeffs(const HotArgs<T> &a, int cell, int v0, const T
   }
 }
 
+// Gauss-point states are cell-major, [NGPC][NV][N]: slot g of a cell is its
+// g-th face Gauss point in the cell's face order, so a wave's stores of one
+// (slot, variable) pair are contiguous across its cells.
 template <int NV, typename T>
-__device__ inline void store(const HotArgs<T> &a, int dst, int v, T val) {
-  const long d = dst & ~(1 << 30);
-  a.fs[d + (long)v * a.NGPT] = val;
-  if (dst & (1 << 30)) a.fs[d + (long)(NV + v) * a.NGPT] = val;  // boundary: transmissive ghost
+__device__ inline void store(const HotArgs<T> &a, int g, int cell, int v, T val) {
+  a.fs[((long)g * NV + v) * a.N + cell] = val;
 }
 
 // ---------------------------------------------------------------------------

@@ -96,9 +96,8 @@ __global__ __launch_bounds__(256) void k_linear(HotArgs<T> a) {
     T all[NV];
     group_state<NV, G, T>(val, all, L.base);
     hok = hok && harten_point<NV, T>(all, rho_b, p_b, a);
-    const int dst = a.t.gpdst[(long)g * N + cell];
 #pragma unroll
-    for (int q = 0; q < VPL; ++q) store<NV, T>(a, dst, v0 + q, val[q]);
+    for (int q = 0; q < VPL; ++q) store<NV, T>(a, g, cell, v0 + q, val[q]);
   }
   int c = 0;
   if (a.mode == HFV_HYBRID) {
@@ -241,9 +240,8 @@ __global__ __launch_bounds__(256) void k_linear_ms(HotArgs<T> a) {
       exc[v] = fmax(exc[v], fmax(mn[v] - val[v], val[v] - mx[v]));
     }
     hok = hok && harten_point<NV, T>(val, rho_b, p_b, a);
-    const int dst = a.t.gpdst[(long)g * N + cell];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) store<NV, T>(a, dst, v, val[v]);
+    for (int v = 0; v < NV; ++v) store<NV, T>(a, g, cell, v, val[v]);
   }
 #pragma unroll
   for (int v = 0; v < NV; ++v) exc[v] = xor_max<G>(exc[v]);
@@ -479,15 +477,13 @@ __global__ __launch_bounds__(256) void k_cwenoz(HotArgs<T> a, int direct) {
       T all[NV];
       group_state<NV, G, T>(val, all, L.base);
       hok = a.frozen || (hok && harten_point<NV, T>(all, rho_b, p_b, a));
-      const int dst = a.t.gpdst[(long)g * N + cell];
 #pragma unroll
-      for (int q = 0; q < VPL; ++q) store<NV, T>(a, dst, v0 + q, hok ? val[q] : u0[q]);
+      for (int q = 0; q < VPL; ++q) store<NV, T>(a, g, cell, v0 + q, hok ? val[q] : u0[q]);
       if (!hok) {
         // first-order fallback: overwrite every point of the cell with U_i
         for (int g2 = 0; g2 < ng; ++g2) {
-          const int d2 = a.t.gpdst[(long)g2 * N + cell];
 #pragma unroll
-          for (int q = 0; q < VPL; ++q) store<NV, T>(a, d2, v0 + q, u0[q]);
+          for (int q = 0; q < VPL; ++q) store<NV, T>(a, g2, cell, v0 + q, u0[q]);
         }
         break;
       }
@@ -599,13 +595,12 @@ __global__ __launch_bounds__(256) void k_muscl(HotArgs<T> a, int direct) {
       T phi[DIM];
 #pragma unroll
       for (int j = 0; j < DIM; ++j) phi[j] = a.t.gpxi[((long)g * DIM + j) * N + cell] - psb[j];
-      const int dst = a.t.gpdst[(long)g * N + cell];
 #pragma unroll
       for (int q = 0; q < VPL; ++q) {
         T d = 0;
 #pragma unroll
         for (int j = 0; j < DIM; ++j) d += gr[j][q] * phi[j];
-        store<NV, T>(a, dst, v0 + q, hok ? u0[q] + th[q] * d : u0[q]);
+        store<NV, T>(a, g, cell, v0 + q, hok ? u0[q] + th[q] * d : u0[q]);
       }
     }
     if (L.sub == 0 && !a.frozen) a.cls[cell] = hok ? HFV_CLASS_MUSCL : HFV_CLASS_FIRST_ORDER;
@@ -620,30 +615,40 @@ __global__ __launch_bounds__(256) void k_first(HotArgs<T> a) {
        item += (long)gridDim.x * blockDim.x) {
     const int cell = a.lists[2L * a.N + item];
     const int ng = a.t.ngp[cell];
-    for (int g = 0; g < ng; ++g) {
-      const int dst = a.t.gpdst[(long)g * a.N + cell];
+    T u0[NV];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) store<NV, T>(a, dst, v, a.U[(long)v * a.N + cell]);
+    for (int v = 0; v < NV; ++v) u0[v] = a.U[(long)v * a.N + cell];
+    for (int g = 0; g < ng; ++g) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) store<NV, T>(a, g, cell, v, u0[v]);
     }
   }
 }
 
+// K6: the two sides of face f at its i-th Gauss point are slot gl + i of the
+// owner and slot gr + i of the neighbour (the owner again at a boundary face:
+// transmissive ghost).
 template <int DIM, typename T>
-__global__ __launch_bounds__(256) void k_flux(int NF, int NGPT, const T *fs, const int *gp_off, const T *fn,
-                                              const T *gpw, T gamma, int hllc, T *Ff) {
+__global__ __launch_bounds__(256) void k_flux(int NF, int N, const T *fs, const int *gp_off, const int *fc,
+                                              const int *fgb, const T *fn, const T *gpw, T gamma, int hllc,
+                                              T *Ff) {
   constexpr int NV = DIM + 2;
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= NF) return;
   T n[DIM];
 #pragma unroll
   for (int j = 0; j < DIM; ++j) n[j] = fn[(long)j * NF + f];
+  const int cL = fc[f], cR0 = fc[NF + f], cR = cR0 >= 0 ? cR0 : cL;
+  const int code = fgb[f];
+  const T *pL = fs + (long)(code & 255) * NV * N + cL;
+  const T *pR = fs + (long)((code >> 8) & 255) * NV * N + cR;
   T acc[NV] = {};
-  for (int g = gp_off[f]; g < gp_off[f + 1]; ++g) {
+  for (int g = gp_off[f], i = 0; g < gp_off[f + 1]; ++g, ++i) {
     T qL[NV], qR[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      qL[v] = fs[(long)v * NGPT + g];
-      qR[v] = fs[(long)(NV + v) * NGPT + g];
+      qL[v] = pL[((long)i * NV + v) * N];
+      qR[v] = pR[((long)i * NV + v) * N];
     }
     T F[NV];
     riemann<DIM, T, T>(qL, qR, n, gamma, hllc, F);
@@ -680,7 +685,6 @@ template <typename T>
 static HotArgs<T> make_args(hfv_ctx *ctx, Tables<T> &t, const void *U, void *fs, uint8_t *cls) {
   HotArgs<T> a;
   a.N = ctx->N;
-  a.NGPT = ctx->NGPT;
   a.mode = ctx->p.mode;
   a.form = ctx->p.form;
   a.frozen = 0;
@@ -838,14 +842,14 @@ static hfv_status tail_t(hfv_ctx *ctx, Tables<T> &t, const void *fs, void *R, hi
   const unsigned gf = nblk(ctx->NF, 256), gc = nblk(ctx->N, 256);
   if (ctx->dim == 2) {
     { ProfScope ps(ctx, HFV_SLOT_FLUX, s);
-      k_flux<2, T><<<gf, 256, 0, s>>>(ctx->NF, ctx->NGPT, (const T *)fs, t.gp_off, t.fnormal, t.gpw,
-                                       (T)ctx->p.gamma, hllc, Ff); }
+      k_flux<2, T><<<gf, 256, 0, s>>>(ctx->NF, ctx->N, (const T *)fs, t.gp_off, t.face_cells, t.fgb, t.fnormal,
+                                       t.gpw, (T)ctx->p.gamma, hllc, Ff); }
     { ProfScope ps(ctx, HFV_SLOT_GATHER, s);
       k_gather<4, T><<<gc, 256, 0, s>>>(ctx->N, ctx->NF, t.cf_off, t.cf, Ff, t.ivol, (T *)R); }
   } else {
     { ProfScope ps(ctx, HFV_SLOT_FLUX, s);
-      k_flux<3, T><<<gf, 256, 0, s>>>(ctx->NF, ctx->NGPT, (const T *)fs, t.gp_off, t.fnormal, t.gpw,
-                                       (T)ctx->p.gamma, hllc, Ff); }
+      k_flux<3, T><<<gf, 256, 0, s>>>(ctx->NF, ctx->N, (const T *)fs, t.gp_off, t.face_cells, t.fgb, t.fnormal,
+                                       t.gpw, (T)ctx->p.gamma, hllc, Ff); }
     { ProfScope ps(ctx, HFV_SLOT_GATHER, s);
       k_gather<5, T><<<gc, 256, 0, s>>>(ctx->N, ctx->NF, t.cf_off, t.cf, Ff, t.ivol, (T *)R); }
   }

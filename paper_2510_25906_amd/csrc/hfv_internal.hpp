@@ -59,7 +59,6 @@ struct Tables {
   T *P = nullptr;          // [K][M][N]   pseudo-inverse times |V_m'|
   T *psibar = nullptr;     // [K][N]
   T *gpxi = nullptr;       // [NGPC][DIM][N] Gauss points in the cell frame
-  int *gpdst = nullptr;    // [NGPC][N]  side*nvar*NGPT + g, bit 30: boundary ghost
   uint8_t *ngp = nullptr;  // [N]
   int *nbr = nullptr;      // [NFM][N]   face neighbours, -1 at boundaries
   uint8_t *nfc = nullptr;  // [N]
@@ -76,6 +75,8 @@ struct Tables {
   int *gp_off = nullptr;   // [NF+1]
   T *gpw = nullptr;        // [NGPT] weight x surface Jacobian
   int *face_cells = nullptr; // [2][NF]
+  int *fgb = nullptr;      // [NF] first local Gauss-point slot of the face in its owner (bits 0-7) and
+                           //      neighbour (bits 8-15) cell; the owner's slot again at boundaries
   int *cf_off = nullptr;   // [N+1]
   int *cf = nullptr;       // [..] face | (side << 31)
   T *ivol = nullptr;       // [N]
@@ -106,11 +107,11 @@ struct hfv_ctx {
   uint8_t *cls_ws = nullptr;   // [N]
   int *lists = nullptr;        // [3][N]
   int *counts = nullptr;       // [4]
-  void *fs_ws = nullptr;       // [2][nvar][NGPT]
+  void *fs_ws = nullptr;       // [NGPC][nvar][N] Gauss-point states, cell-major
   void *fflux = nullptr;       // [nvar][NF]
   void *vjp_C = nullptr;       // adjoint: per stencil slot contributions [M][nvar][N]
   void *vjp_S = nullptr;       // adjoint: self contributions [nvar][N]
-  void *vjp_gfs = nullptr;     // adjoint: face-state cotangents [2][nvar][NGPT]
+  void *vjp_gfs = nullptr;     // adjoint: Gauss-point state cotangents [NGPC][nvar][N]
   bool vjp_ok = false;
   std::string vjp_why;
   size_t table_bytes = 0;

@@ -583,12 +583,12 @@ __global__ void k_face_geom(int NF, const double *vtx, const int *fvo, const int
   }
 }
 
-// Gauss points of every cell in its own frame, and their face-state slots.
+// Gauss points of every cell in its own frame, listed face by face in the
+// cell's face order (increasing face id), quadrature index fastest.
 template <int DIM>
-__global__ void k_cell_gp(int N, int NGPT, int NGPC, int nvar, const int *cf_off, const int *cf,
-                          const int *face_cells, int NF, const int *gp_off, const double *gpx,
-                          const int8_t *fshift, const double *period, const double *geom, double *gpxi,
-                          int *gpdst, uint8_t *ngp) {
+__global__ void k_cell_gp(int N, int NGPT, int NGPC, const int *cf_off, const int *cf, const int *gp_off,
+                          const double *gpx, const int8_t *fshift, const double *period, const double *geom,
+                          double *gpxi, uint8_t *ngp) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= N) return;
   double xc[DIM];
@@ -599,20 +599,17 @@ __global__ void k_cell_gp(int N, int NGPT, int NGPC, int nvar, const int *cf_off
     int code = cf[e];
     int f = code & 0x7fffffff;
     int side = (code >> 31) & 1;
-    bool bnd = face_cells[NF + f] < 0;
     for (int g = gp_off[f]; g < gp_off[f + 1]; ++g, ++slot) {
       for (int j = 0; j < DIM; ++j) {
         double x = gpx[j * NGPT + g];
         if (side && fshift) x -= fshift[(long)f * DIM + j] * period[j];
         gpxi[((long)slot * DIM + j) * N + c] = (x - xc[j]) / h;
       }
-      gpdst[(long)slot * N + c] = (side * nvar * NGPT + g) | (bnd ? (1 << 30) : 0);
     }
   }
   ngp[c] = (uint8_t)slot;
   for (; slot < NGPC; ++slot) {
     for (int j = 0; j < DIM; ++j) gpxi[((long)slot * DIM + j) * N + c] = 0.0;
-    gpdst[(long)slot * N + c] = 0;
   }
 }
 
@@ -751,7 +748,7 @@ static hfv_status setup_dr(hfv_ctx *ctx, const hfv_mesh *mesh, const hfv_stencil
   ctx->geom = geom;
   using MC = MomCfg<DIM, R>;
   double *mom, *psibar, *OI, *A, *wv, *rdiag, *vn2, *y, *P, *Pdir, *Pmus, *gpx, *gpw, *fn, *gpxi;
-  int *gpdst, *bad;
+  int *bad;
   uint8_t *ngp;
   TMP_ALLOC(mom, (size_t)MC::NM * N);
   TMP_ALLOC(psibar, (size_t)K * N);
@@ -768,7 +765,6 @@ static hfv_status setup_dr(hfv_ctx *ctx, const hfv_mesh *mesh, const hfv_stencil
   TMP_ALLOC(gpw, (size_t)NGPT);
   TMP_ALLOC(fn, (size_t)DIM * NF);
   TMP_ALLOC(gpxi, (size_t)NGPC * DIM * N);
-  TMP_ALLOC(gpdst, (size_t)NGPC * N);
   TMP_ALLOC(bad, (size_t)N);
   TMP_ALLOC(ngp, (size_t)N);
   HFV_HIP(hipMemsetAsync(bad, 0, sizeof(int) * N, s));
@@ -832,8 +828,8 @@ static hfv_status setup_dr(hfv_ctx *ctx, const hfv_mesh *mesh, const hfv_stencil
   k_qr_pinv<<<nblk(N, 64), 64, 0, s>>>(N, K, M, A, wv, rdiag, vn2, y, P, bad);
   k_small_pinv<DIM><<<nblk((long)N * (NFM + 1), B), B, 0, s>>>(N, NFM, Md, dir, dshift, ndir, mus, mshift, nmus,
                                                                period, geom, psibar, Pdir, Pmus, bad);
-  k_cell_gp<DIM><<<nblk(N, B), B, 0, s>>>(N, NGPT, NGPC, nvar, cf_off, cf, fcells, NF, gp_off, gpx, fshift,
-                                          period, geom, gpxi, gpdst, ngp);
+  k_cell_gp<DIM><<<nblk(N, B), B, 0, s>>>(N, NGPT, NGPC, cf_off, cf, gp_off, gpx, fshift, period, geom, gpxi,
+                                          ngp);
   HFV_HIP(hipGetLastError());
   std::vector<int> h_bad(N);
   HFV_HIP(hipMemcpyAsync(h_bad.data(), bad, sizeof(int) * N, hipMemcpyDeviceToHost, s));
@@ -868,8 +864,6 @@ static hfv_status setup_dr(hfv_ctx *ctx, const hfv_mesh *mesh, const hfv_stencil
     if ((e = dev_alloc(ctx, (void **)&tabs.ivol, sizeof(T) * N))) return e;
     k_thresholds<T><<<nblk(N, 256), 256, 0, s>>>(N, DIM, geom, ctx->p.kappa, ctx->p.n_exp, tabs.thr, tabs.ivol);
     // integer tables (shared layout for both precisions)
-    if ((e = dev_alloc(ctx, (void **)&tabs.gpdst, sizeof(int) * NGPC * N))) return e;
-    HFV_HIP(hipMemcpyAsync(tabs.gpdst, gpdst, sizeof(int) * NGPC * N, hipMemcpyDeviceToDevice, s));
     if ((e = dev_alloc(ctx, (void **)&tabs.ngp, N))) return e;
     HFV_HIP(hipMemcpyAsync(tabs.ngp, ngp, N, hipMemcpyDeviceToDevice, s));
     HFV_HIP(hipGetLastError());
@@ -917,13 +911,22 @@ hfv_status setup_tables(hfv_ctx *ctx, const hfv_mesh *mesh, const hfv_stencils *
   int ngpc = 0;
   std::vector<int> nbr((size_t)NFM * N, -1);
   std::vector<uint8_t> nfc(N);
+  std::vector<int> fgb(NF, 0);  // local Gauss-point slot of each face in its two cells
   for (int c = 0; c < N; ++c) {
     int g = 0, k = 0;
     for (int e = cf_off[c]; e < cf_off[c + 1]; ++e, ++k) {
       int f = cf[e] & 0x7fffffff;
       int side = (cf[e] >> 31) & 1;
+      if (side)
+        fgb[f] |= g << 8;
+      else
+        fgb[f] |= g | (mesh->face_cells[2 * f + 1] < 0 ? g << 8 : 0);
       g += gp_off[f + 1] - gp_off[f];
       nbr[(size_t)k * N + c] = side ? mesh->face_cells[2 * f] : mesh->face_cells[2 * f + 1];
+    }
+    if (g > 255) {  // slots are stored in bytes
+      ctx->err = "more than 255 face Gauss points in cell " + std::to_string(c);
+      return HFV_ERR_MESH;
     }
     nfc[c] = (uint8_t)k;
     ngpc = std::max(ngpc, g);
@@ -976,6 +979,7 @@ hfv_status setup_tables(hfv_ctx *ctx, const hfv_mesh *mesh, const hfv_stencils *
     if ((e2 = upload(ctx, &tabs.nmus, nmus.data(), nmus.size(), s))) return e2;
     if ((e2 = upload(ctx, &tabs.gp_off, gp_off.data(), gp_off.size(), s))) return e2;
     if ((e2 = upload(ctx, &tabs.face_cells, fcells.data(), fcells.size(), s))) return e2;
+    if ((e2 = upload(ctx, &tabs.fgb, fgb.data(), fgb.size(), s))) return e2;
     if ((e2 = upload(ctx, &tabs.cf_off, cf_off.data(), cf_off.size(), s))) return e2;
     if ((e2 = upload(ctx, &tabs.cf, cf.data(), cf.size(), s))) return e2;
     ctx->table_bytes += sizeof(int) * (sten.size() + nbr.size() + dsten.size() + msten.size());
@@ -1059,7 +1063,7 @@ static hfv_status build_vjp_tables(hfv_ctx *ctx, const hfv_mesh *mesh, const hfv
   const size_t ts = ctx->prec == 64 ? 8 : 4;
   if ((e = dev_alloc(ctx, &ctx->vjp_C, ts * (size_t)M * ctx->nvar * N))) return e;
   if ((e = dev_alloc(ctx, &ctx->vjp_S, ts * (size_t)ctx->nvar * N))) return e;
-  if ((e = dev_alloc(ctx, &ctx->vjp_gfs, ts * 2 * (size_t)ctx->nvar * ctx->NGPT))) return e;
+  if ((e = dev_alloc(ctx, &ctx->vjp_gfs, ts * (size_t)ctx->NGPC * ctx->nvar * ctx->N))) return e;
   HFV_HIP(hipStreamSynchronize(s));
   return HFV_OK;
 }

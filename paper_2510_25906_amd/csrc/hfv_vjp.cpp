@@ -22,7 +22,7 @@ namespace hfv {
 
 template <typename T>
 struct VjpArgs {
-  int N, NGPT, form;
+  int N, form;
   const T *U;
   const uint8_t *cls;
   const T *gfs;
@@ -33,13 +33,16 @@ struct VjpArgs {
 };
 
 template <int DIM, typename T>
-__global__ __launch_bounds__(256) void k_flux_vjp(int NF, int N, int NGPT, const T *fs, const int *gp_off,
+__global__ __launch_bounds__(256) void k_flux_vjp(int NF, int N, const T *fs, const int *gp_off, const int *fgb,
                                                   const T *fn, const T *gpw, const int *fc, const T *ivol,
                                                   const T *gR, T gamma, int hllc, T *gfs) {
   constexpr int NV = DIM + 2;
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= NF) return;
   const int L = fc[f], Rc = fc[NF + f];
+  const int code = fgb[f];
+  const long oL = (long)(code & 255) * NV * N + L;
+  const long oR = (long)((code >> 8) & 255) * NV * N + (Rc >= 0 ? Rc : L);
   T n[DIM];
 #pragma unroll
   for (int j = 0; j < DIM; ++j) n[j] = fn[(long)j * NF + f];
@@ -47,12 +50,12 @@ __global__ __launch_bounds__(256) void k_flux_vjp(int NF, int N, int NGPT, const
 #pragma unroll
   for (int v = 0; v < NV; ++v)
     gF[v] = -gR[(long)v * N + L] * ivol[L] + (Rc >= 0 ? gR[(long)v * N + Rc] * ivol[Rc] : (T)0);
-  for (int g = gp_off[f]; g < gp_off[f + 1]; ++g) {
+  for (int g = gp_off[f], i = 0; g < gp_off[f + 1]; ++g, ++i) {
     T qL[NV], qR[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      qL[v] = fs[(long)v * NGPT + g];
-      qR[v] = fs[(long)(NV + v) * NGPT + g];
+      qL[v] = fs[oL + ((long)i * NV + v) * N];
+      qR[v] = fs[oR + ((long)i * NV + v) * N];
     }
     const T w = gpw[g];
     T gl[NV], gr[NV];
@@ -74,17 +77,15 @@ __global__ __launch_bounds__(256) void k_flux_vjp(int NF, int N, int NGPT, const
       else
         gr[tg - NV] = w * acc;
     }
-    if (Rc < 0) {  // transmissive ghost: the right state is a copy of the left one
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        gl[v] += gr[v];
-        gr[v] = 0;
-      }
-    }
+    // every cell slot belongs to exactly one face side, so each is written once
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      gfs[(long)v * NGPT + g] = gl[v];
-      gfs[(long)(NV + v) * NGPT + g] = gr[v];
+      if (Rc < 0) {  // transmissive ghost: the right state is a copy of the left one
+        gfs[oL + ((long)i * NV + v) * N] = gl[v] + gr[v];
+      } else {
+        gfs[oL + ((long)i * NV + v) * N] = gl[v];
+        gfs[oR + ((long)i * NV + v) * N] = gr[v];
+      }
     }
   }
 }
@@ -102,10 +103,7 @@ __global__ __launch_bounds__(256) void k_recon_vjp(VjpArgs<T> a) {
   const int ng = t.ngp[cell];
   const long MS = (long)NV * N;
   T *C = a.C + (long)v * N + cell;  // slot m lives at C[m * MS]
-  auto gq_at = [&](int g) -> T {
-    const long d = t.gpdst[(long)g * N + cell] & ~(1 << 30);
-    return a.gfs[d + (long)v * a.NGPT];
-  };
+  auto gq_at = [&](int g) -> T { return a.gfs[((long)g * NV + v) * N + cell]; };
   T gsum = 0;
   if (cls == HFV_CLASS_FIRST_ORDER) {
     for (int g = 0; g < ng; ++g) gsum += gq_at(g);
@@ -460,13 +458,12 @@ static hfv_status vjp_impl(hfv_ctx *ctx, Tables<T> &t, const void *U, const uint
   hfv_status e = run_reconstruct_frozen(ctx, U, ctx->fs_ws, cls, s);
   if (e != HFV_OK) return e;
   ProfScope ps(ctx, HFV_SLOT_VJP, s);
-  k_flux_vjp<DIM, T><<<nblk(ctx->NF, 256), 256, 0, s>>>(ctx->NF, ctx->N, ctx->NGPT, (const T *)ctx->fs_ws, t.gp_off,
+  k_flux_vjp<DIM, T><<<nblk(ctx->NF, 256), 256, 0, s>>>(ctx->NF, ctx->N, (const T *)ctx->fs_ws, t.gp_off, t.fgb,
                                                          t.fnormal, t.gpw, t.face_cells, t.ivol, (const T *)gR,
                                                          (T)ctx->p.gamma, ctx->p.riemann == HFV_HLLC,
                                                          (T *)ctx->vjp_gfs);
   VjpArgs<T> a;
   a.N = ctx->N;
-  a.NGPT = ctx->NGPT;
   a.form = ctx->p.form;
   a.U = (const T *)U;
   a.cls = cls;

@@ -23,7 +23,7 @@ ERRORS = {-1: "HFV_ERR_PARAM", -2: "HFV_ERR_MESH", -3: "HFV_ERR_RANK", -4: "HFV_
 Q = dict(N_CELLS=0, N_FACES=1, N_GP=2, NVAR=3, K=4, M=5, PRECISION=6, DIM=7, TABLE_BYTES=8,
          COUNT_CWENOZ=9, COUNT_MUSCL=10, COUNT_FIRST=11, NGP_CELL_MAX=12)
 SLOTS = dict(linear=0, classify=1, cwenoz=2, muscl=3, first=4, flux=5, gather=6, vjp=7)
-TABLES = dict(PINV=0, OI=1, PSIBAR=2, GEOM=3, PDIR=4, PMUS=5)
+TABLES = dict(PINV=0, OI=1, PSIBAR=2, GEOM=3, PDIR=4, PMUS=5, FACE_SLOTS=6)
 
 _p = C.c_void_p
 _i32p = C.POINTER(C.c_int32)
@@ -160,6 +160,7 @@ class Context:
         self.n_cells = self.query("N_CELLS")
         self.n_faces = self.query("N_FACES")
         self.n_gp = self.query("N_GP")
+        self.ngp_cell = self.query("NGP_CELL_MAX")
         self.nvar = self.query("NVAR")
         self.K = self.query("K")
         self.M = self.query("M")
@@ -213,8 +214,11 @@ class Context:
         N, K, M, d = self.n_cells, self.K, self.M, self.dim
         nfm = 4 if d == 2 else 6
         shapes = dict(PINV=(K, M, N), OI=(K * (K + 1) // 2, N), PSIBAR=(K, N), GEOM=(d + 2, N),
-                      PDIR=(nfm, d, 2 * d, N), PMUS=(d, nfm, N))
-        dt = np.float64 if (name == "GEOM" or self.precision == 64) else np.float32
+                      PDIR=(nfm, d, 2 * d, N), PMUS=(d, nfm, N), FACE_SLOTS=(self.n_faces,))
+        if name == "FACE_SLOTS":
+            dt = np.int32
+        else:
+            dt = np.float64 if (name == "GEOM" or self.precision == 64) else np.float32
         out = np.empty(shapes[name], dt)
         self._check(self.lib.hfv_copy_table(self.h, TABLES[name], out.ctypes.data_as(C.c_void_p), out.nbytes))
         return out
@@ -229,7 +233,7 @@ class Context:
 
     def new_face_states(self):
         import torch
-        return torch.empty((2, self.nvar, self.n_gp), dtype=self.dtype, device="cuda")
+        return torch.empty((self.ngp_cell, self.nvar, self.n_cells), dtype=self.dtype, device="cuda")
 
     def reconstruct(self, U, face_states=None, cell_class=None, stream=None):
         import torch

@@ -15,13 +15,36 @@ def rel_err(x, ref, scale_b):
     return float(np.nanmax(np.abs(x - ref) / den))
 
 
-def cell_face_values(fs, geo, cells):
-    """Per-cell Gauss-point values [n, NGPC, nvar] gathered from face states [2, nvar, NGPT]."""
-    out = np.full((len(cells), geo.c_gidx.shape[1], fs.shape[1]), np.nan)
-    for i, c in enumerate(cells):
-        k = geo.c_ngp[c]
-        out[i, :k] = fs[geo.c_side[c, :k], :, geo.c_gidx[c, :k]]
-    return out
+def _mask(out, geo, cells):
+    valid = np.arange(out.shape[1])[None, :] < geo.c_ngp[cells][:, None]
+    return np.where(valid[..., None], out, np.nan)
+
+
+def oracle_cell_values(fs, geo, cells):
+    """Per-cell Gauss-point values [n, NGPC, nvar] (NaN past a cell's count)
+    gathered from the oracle's face states [2, nvar, NGPT]."""
+    cells = np.asarray(cells)
+    out = fs[geo.c_side[cells], :, np.maximum(geo.c_gidx[cells], 0)]
+    return _mask(out, geo, cells)
+
+
+def gpu_cell_values(fs, geo, cells):
+    """Per-cell Gauss-point values [n, NGPC, nvar] (NaN past a cell's count)
+    from the library's cell-major states [NGPC, nvar, N]."""
+    cells = np.asarray(cells)
+    assert fs.shape[0] == geo.c_gidx.shape[1]
+    out = np.moveaxis(fs[:, :, cells], 2, 0)
+    valid = np.arange(out.shape[1])[None, :] < geo.c_ngp[cells][:, None]
+    # slots past a cell's count are never written: drop them before widening
+    return np.where(valid[..., None], np.where(valid[..., None], out, 0).astype(np.float64), np.nan)
+
+
+def states_err(fs_gpu, fs_o, geo, S, cells=None):
+    """rel_err of the library's Gauss-point states against the oracle's, all
+    (or the given) cells, scaled per variable by S."""
+    fs_gpu = fs_gpu.cpu().numpy() if hasattr(fs_gpu, "cpu") else fs_gpu
+    cells = np.arange(fs_gpu.shape[2]) if cells is None else cells
+    return rel_err(gpu_cell_values(fs_gpu, geo, cells), oracle_cell_values(fs_o, geo, cells), S[None, None, :])
 
 
 def near_threshold(om, U, cells, tol):

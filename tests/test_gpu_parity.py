@@ -8,7 +8,7 @@ FP32: states within 1e-5 relative, class flips only in cells flagged within
 import numpy as np
 import pytest
 
-from helpers import state_scale, rel_err, cell_face_values, near_threshold
+from helpers import state_scale, rel_err, near_threshold, gpu_cell_values, oracle_cell_values, states_err
 from oracle import OracleModel, flux
 from paper_2510_25906_amd.inputs import configs, fields
 from paper_2510_25906_amd.inputs.params import HYBRID, ALL_LINEAR, ALL_CWENOZ, ALL_MUSCL, preset
@@ -66,8 +66,28 @@ def test_c1_fp64_reconstruct_and_residual(hfv, c1, mode):
     cls_g = cls.cpu().numpy()
     assert np.array_equal(cls_g, cls_o), np.nonzero(cls_g != cls_o)[0][:20]
     S = state_scale(w.U)
-    assert rel_err(fs.cpu().numpy(), fs_o, S[None, :, None]) <= 1e-12
+    assert states_err(fs, fs_o, om.geo, S) <= 1e-12
     assert rel_err(R.cpu().numpy(), R_o, np.abs(R_o).max(1)[:, None]) <= 1e-11
+    ctx.close()
+
+
+def test_face_slot_table(hfv, c1):
+    """Each face's first Gauss point sits at the published slot of both of its
+    cells in the oracle's per-cell Gauss-point lists (faces in increasing id)."""
+    w, om = c1
+    ctx = hfv.Context(w.mesh, w.stencils, w.params, 64)
+    t = ctx.table("FACE_SLOTS")
+    geo = om.geo
+    fc = w.mesh.face_cells
+    for f in range(w.mesh.n_faces):
+        g0 = geo.gp_off[f]
+        for side in (0, 1):
+            c = fc[f, side]
+            if c < 0:
+                assert (t[f] >> 8) & 255 == t[f] & 255
+                continue
+            slot = (t[f] >> (8 * side)) & 255
+            assert geo.c_gidx[c, slot] == g0 and geo.c_side[c, slot] == side
     ctx.close()
 
 
@@ -106,7 +126,7 @@ def test_c1_launch_shapes_agree(hfv, c1, lanes, split, lin_lanes):
     torch.cuda.synchronize()
     assert np.array_equal(cls.cpu().numpy(), cls_o)
     S = state_scale(w.U)
-    assert rel_err(fs.cpu().numpy(), fs_o, S[None, :, None]) <= 1e-12
+    assert states_err(fs, fs_o, om.geo, S) <= 1e-12
     ctx.close()
 
 
@@ -126,8 +146,8 @@ def test_c1_fp32(hfv, c1):
     assert not np.any(flip & ~flags), np.nonzero(flip & ~flags)[0][:10]
     ok = ~flip
     S = state_scale(w.U)
-    fv_g = cell_face_values(fs.cpu().numpy().astype(np.float64), om.geo, cells)
-    fv_o = cell_face_values(fs_o, om.geo, cells)
+    fv_g = gpu_cell_values(fs.cpu().numpy(), om.geo, cells)
+    fv_o = oracle_cell_values(fs_o, om.geo, cells)
     assert rel_err(fv_g[ok], fv_o[ok], S[None, None, :]) <= 1e-5
     ctx.close()
 
@@ -157,7 +177,7 @@ def test_c2_sampled_full_size(hfv):
                 assert not flip.any(), cells[flip][:10]
             else:
                 assert not np.any(flip & ~flags)
-            fv_g = cell_face_values(fs.cpu().numpy().astype(np.float64), om.geo, cells)
+            fv_g = gpu_cell_values(fs.cpu().numpy(), om.geo, cells)
             S = state_scale(w.U)
             ok = ~flip
             assert rel_err(fv_g[ok], fv_o[ok], S[None, None, :]) <= tol

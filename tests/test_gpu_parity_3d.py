@@ -4,7 +4,7 @@ and sampled cells of the 262,144-cell periodic hexahedral workloads."""
 import numpy as np
 import pytest
 
-from helpers import state_scale, rel_err, cell_face_values, near_threshold
+from helpers import state_scale, rel_err, near_threshold, gpu_cell_values, oracle_cell_values, states_err
 from oracle import OracleModel, flux
 from paper_2510_25906_amd.inputs import configs, fields
 from paper_2510_25906_amd.inputs.mesh import hex_3d, tet_box
@@ -76,7 +76,7 @@ def test_3d_fp64_hybrid_residual(hfv, name):
         cls_g = cls.cpu().numpy()
         assert np.array_equal(cls_g, cls_o), np.nonzero(cls_g != cls_o)[0][:20]
         S = state_scale(U)
-        assert rel_err(fs.cpu().numpy(), fs_o, S[None, :, None]) <= 1e-12
+        assert states_err(fs, fs_o, om.geo, S) <= 1e-12
         assert rel_err(R.cpu().numpy(), R_o, np.abs(R_o).max(1)[:, None]) <= 1e-11
         ctx.close()
 
@@ -95,7 +95,7 @@ def test_3d_fp64_forced_modes(hfv, name, mode):
     torch.cuda.synchronize()
     assert np.array_equal(cls.cpu().numpy(), cls_o)
     S = state_scale(U)
-    assert rel_err(fs.cpu().numpy(), fs_o, S[None, :, None]) <= 1e-12
+    assert states_err(fs, fs_o, om.geo, S) <= 1e-12
     assert rel_err(R.cpu().numpy(), R_o, np.abs(R_o).max(1)[:, None]) <= 1e-11
     ctx.close()
 
@@ -116,8 +116,8 @@ def test_3d_fp32_and_lane_shapes(hfv, lanes, split, lin_lanes):
     nb = om.nbr
     near = flags | np.array([flags[nb[c][nb[c] >= 0]].any() for c in cells])
     assert not np.any(flip & ~near)
-    fv_g = cell_face_values(fs.cpu().numpy().astype(np.float64), om.geo, cells)
-    fv_o = cell_face_values(fs_o, om.geo, cells)
+    fv_g = gpu_cell_values(fs.cpu().numpy(), om.geo, cells)
+    fv_o = oracle_cell_values(fs_o, om.geo, cells)
     S = state_scale(U)
     assert rel_err(fv_g[~flip], fv_o[~flip], S[None, None, :]) <= 1e-5
     ctx.close()
@@ -144,7 +144,7 @@ def test_tgv64_sampled_full_size(hfv, r, precs):
             assert not flip.any()
         else:
             assert not np.any(flip & ~flags)
-        fv_g = cell_face_values(fs.cpu().numpy().astype(np.float64), om.geo, cells)
+        fv_g = gpu_cell_values(fs.cpu().numpy(), om.geo, cells)
         S = state_scale(U)
         assert rel_err(fv_g[~flip], fv_o[~flip], S[None, None, :]) <= (1e-12 if prec == 64 else 1e-5)
         ctx.close()
