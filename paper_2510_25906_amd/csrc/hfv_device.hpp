@@ -19,7 +19,18 @@ struct HotArgs {
   int *counts;
   Tables<T> t;
   T gamma, alpha_m, beta_m, alpha_w, beta_w, lam1p, eps_w, b_w, theta, tvd_eps;
+  int ib_w;  // b_w when it is an integer in [1, 8] (powers by multiplication), else 0
 };
+
+// x^b for x >= 0: repeated products when b is a small integer, pow otherwise.
+__device__ inline double powb(double x, double b, int ib) {
+  if (ib > 0) {
+    double r = x;
+    for (int i = 1; i < ib; ++i) r *= x;
+    return r;
+  }
+  return pow(x, b);
+}
 
 template <int G>
 struct Lane {

@@ -382,74 +382,59 @@ __global__ __launch_bounds__(256) void k_cwenoz(HotArgs<T> a, int direct) {
     for (int k = 0; k < K; ++k)
 #pragma unroll
       for (int q = 0; q < VPL; ++q) co[k][q] /= lam1;
-    // smoothness indicators SI = a^T OI a, accumulated in double
-    double si1[VPL], sis[NFM][VPL];
+    // smoothness indicators SI = a^T OI a, accumulated in double, then the
+    // nonlinear weights and the CWENOZ coefficients omega_1 p_1 + sum_s
+    // omega_s p_s; one variable at a time keeps few doubles live
+    const double eps = (double)a.eps_w, b = (double)a.b_w;
 #pragma unroll
     for (int q = 0; q < VPL; ++q) {
-      si1[q] = 0;
+      double si1 = 0, sis[NFM];
 #pragma unroll
-      for (int s = 0; s < NFM; ++s) sis[s][q] = 0;
-    }
-    {
+      for (int s = 0; s < NFM; ++s) sis[s] = 0;
       int pidx = 0;
 #pragma unroll
-      for (int k = 0; k < K; ++k)
+      for (int k = 0; k < K; ++k) {
+        const double ck = (double)co[k][q];
+        double row = 0;
 #pragma unroll
         for (int kq = k; kq < K; ++kq, ++pidx) {
-          const double o = (double)a.t.OI[(long)pidx * N + cell] * (kq == k ? 1.0 : 2.0);
-#pragma unroll
-          for (int q = 0; q < VPL; ++q) si1[q] += o * (double)co[k][q] * (double)co[kq][q];
+          const double o = (double)a.t.OI[(long)pidx * N + cell];
+          row += (kq == k ? o : 2.0 * o) * (double)co[kq][q];
           if (kq < DIM) {
 #pragma unroll
             for (int s = 0; s < NFM; ++s)
-#pragma unroll
-              for (int q = 0; q < VPL; ++q) sis[s][q] += o * (double)ad[s][k][q] * (double)ad[s][kq][q];
+              sis[s] += (kq == k ? o : 2.0 * o) * (double)ad[s][k][q] * (double)ad[s][kq][q];
           }
         }
-    }
-    // nonlinear weights
-    double om1[VPL], oms[NFM][VPL];
-#pragma unroll
-    for (int q = 0; q < VPL; ++q) {
+        si1 += ck * row;
+      }
       double tau = 0;
 #pragma unroll
       for (int s = 0; s < NFM; ++s)
-        if (s < nd) tau += fabs(sis[s][q] - si1[q]);
+        if (s < nd) tau += fabs(sis[s] - si1);
       tau /= (double)nd;
-      const double eps = (double)a.eps_w, b = (double)a.b_w;
-      double w1, tot;
-      if (a.form == HFV_WENOZ_POW) {
-        w1 = (double)lam1 * (1.0 + pow(tau / (eps + si1[q]), b));
-      } else {
-        w1 = (double)lam1 * (1.0 + pow(tau, b) / (eps + si1[q]));
-      }
-      tot = w1;
+      const bool zform = a.form == HFV_WENOZ_POW;
+      const double taub = zform ? 0.0 : powb(tau, b, a.ib_w);
+      const double w1 = (double)lam1 * (1.0 + (zform ? powb(tau / (eps + si1), b, a.ib_w) : taub / (eps + si1)));
+      double tot = w1, ws[NFM];
 #pragma unroll
       for (int s = 0; s < NFM; ++s) {
-        double ws = 0;
-        if (s < nd) {
-          ws = a.form == HFV_WENOZ_POW ? (double)lams * (1.0 + pow(tau / (eps + sis[s][q]), b))
-                                       : (double)lams * (1.0 + pow(tau, b) / (eps + sis[s][q]));
-        }
-        oms[s][q] = ws;
-        tot += ws;
+        ws[s] = 0;
+        if (s < nd)
+          ws[s] = (double)lams * (1.0 + (zform ? powb(tau / (eps + sis[s]), b, a.ib_w) : taub / (eps + sis[s])));
+        tot += ws[s];
       }
-      om1[q] = w1 / tot;
+      const double it = 1.0 / tot;
 #pragma unroll
-      for (int s = 0; s < NFM; ++s) oms[s][q] /= tot;
-    }
-    // CWENOZ coefficients: omega_1 a_1 + sum_s omega_s a_s
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-#pragma unroll
-      for (int q = 0; q < VPL; ++q) {
-        T v = (T)om1[q] * co[k][q];
+      for (int k = 0; k < K; ++k) {
+        double v = w1 * it * (double)co[k][q];
         if (k < DIM) {
 #pragma unroll
-          for (int s = 0; s < NFM; ++s) v += (T)oms[s][q] * ad[s][k][q];
+          for (int s = 0; s < NFM; ++s) v += ws[s] * it * (double)ad[s][k][q];
         }
-        co[k][q] = v;
+        co[k][q] = (T)v;
       }
+    }
     // face states, Harten check
     T all0[NV];
     group_state<NV, G, T>(u0, all0, L.base);
@@ -706,6 +691,8 @@ static HotArgs<T> make_args(hfv_ctx *ctx, Tables<T> &t, const void *U, void *fs,
   a.b_w = (T)ctx->p.b_w;
   a.theta = (T)ctx->p.theta;
   a.tvd_eps = (T)ctx->p.tvd_eps;
+  const double bw = ctx->p.b_w;
+  a.ib_w = (bw >= 1.0 && bw <= 8.0 && bw == (double)(int)bw) ? (int)bw : 0;
   return a;
 }
 
