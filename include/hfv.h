@@ -195,24 +195,67 @@ enum { HFV_T_PINV = 0, HFV_T_OI = 1, HFV_T_PSIBAR = 2, HFV_T_GEOM = 3, HFV_T_PDI
        HFV_T_FACE_SLOTS = 6 };
 hfv_status hfv_copy_table(const hfv_ctx *ctx, int32_t which, void *host_dst, int64_t bytes);
 
-/* Tuning.  lanes_per_cell: lanes of a wave sharing one cell in the
- * variable-split kernels (1, 2 or 4 in 2D; 1 or 5 in 3D); block: threads per
- * block (64..256, multiple of 64); list_blocks: cap on resident blocks of the
- * class-list kernels; linear_split: mapping of the linear + NAD kernel, 0 =
- * lanes split the conserved variables (lanes_per_cell lanes), 1 = lanes split
- * the stencil members and Gauss points (linear_lanes = 2, 4 or 8 lanes).
- * 0 keeps the current value of lanes_per_cell, block and list_blocks. */
-hfv_status hfv_set_launch(hfv_ctx *ctx, int32_t lanes_per_cell, int32_t block, int32_t list_blocks,
-                          int32_t linear_split, int32_t linear_lanes);
+/* Launch configuration of the hot path (results agree to rounding for every
+ * valid configuration; classes are identical in FP64).
+ *   lanes_per_cell  lanes of a wave sharing one cell in the class-list
+ *                   kernels (CWENOZ, MUSCL), which split the variables: 1, 2
+ *                   or 4 in 2D; 1 or 5 in 3D
+ *   block           threads per block: 64, 128, 192 or 256
+ *   list_blocks     cap on the resident blocks of the class-list kernels (>= 1)
+ *   linear_split    mapping of the linear + NAD kernel: 0 = lanes split the
+ *                   conserved variables, 1 = lanes split the stencil members
+ *                   and Gauss points, 2 = lanes split the polynomial's
+ *                   unknowns (rows of the pseudo-inverse) and reduce-scatter
+ *                   the Gauss-point sums
+ *   linear_lanes    lanes per cell of the linear kernel: as lanes_per_cell
+ *                   for linear_split 0; 2, 4 or 8 for 1 and 2
+ *   cwenoz_reuse    1: in hybrid mode the linear pass keeps every cell's
+ *                   central fit and the CWENOZ pass starts from it (the same
+ *                   polynomial, Section 2.3): pays off when CWENOZ cells are
+ *                   most of the mesh; 0: the CWENOZ pass refits it
+ *   fused_residual  1: one kernel per cell evaluates the Riemann fluxes of the
+ *                   cell's faces and sums them (each interior face's flux is
+ *                   evaluated by both of its cells, with identical operands, so
+ *                   conservation stays exact); 0: face fluxes, then a gather
+ * hfv_set_launch validates every field (HFV_ERR_PARAM, nothing changed, on
+ * an invalid one); hfv_get_launch reads the current configuration. */
+typedef struct {
+  int32_t lanes_per_cell, block, list_blocks, linear_split, linear_lanes, cwenoz_reuse, fused_residual;
+} hfv_launch;
+hfv_status hfv_set_launch(hfv_ctx *ctx, const hfv_launch *cfg);
+hfv_status hfv_get_launch(const hfv_ctx *ctx, hfv_launch *cfg);
+
+/* Autotuner (a project addition, not in the paper): times hfv_residual on the
+ * caller's state U (device [nvar][n_cells]) under the current parameters for
+ * candidate launch configurations, searched one coordinate at a time (linear
+ * kernel mapping; class-list kernel lanes, block and resident-block cap;
+ * CWENOZ reuse in hybrid mode; fused or two-kernel residual), and keeps the
+ * fastest (median of `reps`
+ * timed calls after one untimed call, reps in [1, 1000]).  Synchronous; it
+ * allocates and frees one residual-sized buffer.  `best` (may be NULL)
+ * receives the chosen configuration, which is also applied; up to
+ * `max_records` (configuration, median ms) pairs go to `records` (may be NULL
+ * when max_records is 0) and the number of configurations timed to
+ * `*n_records` (may be NULL).  On failure the starting configuration is
+ * restored. */
+typedef struct {
+  hfv_launch cfg;
+  double ms;
+} hfv_tune_record;
+hfv_status hfv_autotune(hfv_ctx *ctx, const void *U, int32_t reps, hfv_launch *best, hfv_tune_record *records,
+                        int32_t max_records, int32_t *n_records, void *stream);
 
 /* Kernel timing with HIP events recorded on the launch stream.
  * hfv_profile_enable arms up to `capacity` timed launches of the kernels
  * selected by `slot_mask` (bit i = HFV_SLOT_i); capacity 0 disables.
  * hfv_profile_read synchronises on the recorded events, writes per-slot sums
  * of the launch durations in milliseconds and launch counts (arrays of
- * HFV_NSLOTS), and re-arms the buffer. */
+ * HFV_NSLOTS), and re-arms the buffer.  HFV_SLOT_MUSCL times the kernel that
+ * serves both the MUSCL and the first-order lists; HFV_SLOT_FLUX the fused
+ * residual kernel when fused_residual is 1 (HFV_SLOT_GATHER then records
+ * nothing); HFV_SLOT_RESERVED records nothing. */
 enum {
-  HFV_SLOT_LINEAR = 0, HFV_SLOT_CLASSIFY = 1, HFV_SLOT_CWENOZ = 2, HFV_SLOT_MUSCL = 3, HFV_SLOT_FIRST = 4,
+  HFV_SLOT_LINEAR = 0, HFV_SLOT_CLASSIFY = 1, HFV_SLOT_CWENOZ = 2, HFV_SLOT_MUSCL = 3, HFV_SLOT_RESERVED = 4,
   HFV_SLOT_FLUX = 5, HFV_SLOT_GATHER = 6, HFV_SLOT_VJP = 7, HFV_NSLOTS = 8
 };
 hfv_status hfv_profile_enable(hfv_ctx *ctx, int32_t capacity, int32_t slot_mask);

@@ -137,6 +137,7 @@ hfv_status hfv_create(const hfv_mesh *mesh, const hfv_stencils *st, const hfv_pa
   ctx->NFM = nf_max(d);
   ctx->nvar = d + 2;
   ctx->lanes = d + 2;
+  ctx->lin_lanes = d + 2;
   copy_params(ctx, p);
   hipStream_t s = (hipStream_t)stream;
   if (hipGetDevice(&ctx->device) != hipSuccess) {
@@ -154,10 +155,11 @@ hfv_status hfv_create(const hfv_mesh *mesh, const hfv_stencils *st, const hfv_pa
     if ((e = dev_alloc(ctx, (void **)&ctx->own, N)) == HFV_OK &&
         (e = dev_alloc(ctx, (void **)&ctx->cls_ws, N)) == HFV_OK &&
         (e = dev_alloc(ctx, (void **)&ctx->lists, sizeof(int) * 3 * (size_t)N)) == HFV_OK &&
-        (e = dev_alloc(ctx, (void **)&ctx->counts, sizeof(int) * 4)) == HFV_OK &&
+        (e = dev_alloc(ctx, (void **)&ctx->counts, sizeof(int) * 8)) == HFV_OK &&
+        (e = dev_alloc(ctx, &ctx->coef, ts * ctx->K * ctx->nvar * (size_t)N)) == HFV_OK &&
         (e = dev_alloc(ctx, &ctx->fs_ws, ts * ctx->nvar * (size_t)ctx->NGPC * ctx->N)) == HFV_OK &&
         (e = dev_alloc(ctx, &ctx->fflux, ts * ctx->nvar * (size_t)ctx->NF)) == HFV_OK) {
-      if (hipMemsetAsync(ctx->counts, 0, sizeof(int) * 4, s) != hipSuccess ||
+      if (hipMemsetAsync(ctx->counts, 0, sizeof(int) * 8, s) != hipSuccess ||
           hipStreamSynchronize(s) != hipSuccess) {
         ctx->err = "workspace initialisation failed";
         e = HFV_ERR_HIP;
@@ -191,29 +193,43 @@ hfv_status hfv_set_params(hfv_ctx *ctx, const hfv_params *p) {
   return HFV_OK;
 }
 
-hfv_status hfv_set_launch(hfv_ctx *ctx, int32_t lanes, int32_t block, int32_t list_blocks, int32_t linear_split,
-                          int32_t linear_lanes) {
+hfv_status hfv_set_launch(hfv_ctx *ctx, const hfv_launch *c) {
   if (!ctx) return HFV_ERR_PARAM;
-  if (lanes) {
-    bool ok = lanes == 1 || lanes == ctx->nvar || (ctx->dim == 2 && lanes == 2);
-    if (!ok) return ctx->err = "lanes per cell must be 1 or nvar (or 2 in 2D)", HFV_ERR_PARAM;
-    ctx->lanes = lanes;
-  }
-  if (block) {
-    if (block % 64 != 0 || block < 64 || block > 256) return ctx->err = "block must be 64, 128, 192 or 256", HFV_ERR_PARAM;
-    ctx->block = block;
-  }
-  if (list_blocks) {
-    if (list_blocks < 1) return ctx->err = "list_blocks must be positive", HFV_ERR_PARAM;
-    ctx->list_blocks = list_blocks;
-  }
-  if (linear_split < 0 || linear_split > 1) return ctx->err = "linear_split must be 0 or 1", HFV_ERR_PARAM;
-  if (linear_split == 1) {
-    if (linear_lanes != 2 && linear_lanes != 4 && linear_lanes != 8)
-      return ctx->err = "linear_lanes must be 2, 4 or 8 with the member split", HFV_ERR_PARAM;
-    ctx->lin_lanes = linear_lanes;
-  }
-  ctx->lin_split = linear_split;
+  if (!c) return ctx->err = "NULL launch configuration", HFV_ERR_PARAM;
+  const int lanes = c->lanes_per_cell;
+  if (!(lanes == 1 || lanes == ctx->nvar || (ctx->dim == 2 && lanes == 2)))
+    return ctx->err = "lanes_per_cell must be 1 or nvar (or 2 in 2D)", HFV_ERR_PARAM;
+  if (c->block % 64 != 0 || c->block < 64 || c->block > 256)
+    return ctx->err = "block must be 64, 128, 192 or 256", HFV_ERR_PARAM;
+  if (c->list_blocks < 1) return ctx->err = "list_blocks must be positive", HFV_ERR_PARAM;
+  if (c->linear_split < 0 || c->linear_split > 2) return ctx->err = "linear_split must be 0, 1 or 2", HFV_ERR_PARAM;
+  const int ll = c->linear_lanes;
+  if (c->linear_split == 0 && !(ll == 1 || ll == ctx->nvar || (ctx->dim == 2 && ll == 2)))
+    return ctx->err = "linear_lanes must be 1 or nvar (or 2 in 2D) with the variable split", HFV_ERR_PARAM;
+  if (c->linear_split != 0 && ll != 2 && ll != 4 && ll != 8)
+    return ctx->err = "linear_lanes must be 2, 4 or 8 with the member or unknown split", HFV_ERR_PARAM;
+  if (c->cwenoz_reuse != 0 && c->cwenoz_reuse != 1) return ctx->err = "cwenoz_reuse must be 0 or 1", HFV_ERR_PARAM;
+  if (c->fused_residual != 0 && c->fused_residual != 1)
+    return ctx->err = "fused_residual must be 0 or 1", HFV_ERR_PARAM;
+  ctx->lanes = lanes;
+  ctx->block = c->block;
+  ctx->list_blocks = c->list_blocks;
+  ctx->lin_split = c->linear_split;
+  ctx->lin_lanes = c->linear_lanes;
+  ctx->cw_reuse = c->cwenoz_reuse;
+  ctx->fused_residual = c->fused_residual;
+  return HFV_OK;
+}
+
+hfv_status hfv_get_launch(const hfv_ctx *ctx, hfv_launch *c) {
+  if (!ctx || !c) return HFV_ERR_PARAM;
+  c->lanes_per_cell = ctx->lanes;
+  c->block = ctx->block;
+  c->list_blocks = ctx->list_blocks;
+  c->linear_split = ctx->lin_split;
+  c->linear_lanes = ctx->lin_lanes;
+  c->cwenoz_reuse = ctx->cw_reuse;
+  c->fused_residual = ctx->fused_residual;
   return HFV_OK;
 }
 
@@ -266,7 +282,7 @@ hfv_status hfv_query(const hfv_ctx *ctx, int32_t what, int64_t *out) {
     case HFV_Q_COUNT_CWENOZ:
     case HFV_Q_COUNT_MUSCL:
     case HFV_Q_COUNT_FIRST: {
-      int c[4];
+      int c[8];
       if (hipMemcpy(c, ctx->counts, sizeof c, hipMemcpyDeviceToHost) != hipSuccess) return HFV_ERR_HIP;
       *out = c[1 + what - HFV_Q_COUNT_CWENOZ];
       return HFV_OK;

@@ -13,6 +13,7 @@ struct HotArgs {
   const uint8_t *cls_in;   // given classes when frozen
   const T *U;
   T *fs;
+  T *coef;                 // central fits kept for CWENOZ ([K][NV][N]), or null
   uint8_t *own;
   uint8_t *cls;
   int *lists;

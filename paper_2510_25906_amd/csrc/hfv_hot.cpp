@@ -9,7 +9,7 @@
 //                wave-ballot / prefix compaction into per-class work lists
 //   k_cwenoz     CWENOZ on the class-1 list (Section 2.3)
 //   k_muscl      Barth-Jespersen limited MUSCL on the class-2 list (Section 2.2)
-//   k_first      first-order states on cells that failed the Harten check
+//                and first-order states on the cells that failed the Harten check
 //   k_flux       HLLC / HLL flux integrated over each face's Gauss points
 //   k_gather     residual of Eq. EulerEquationsDetails, fixed-order sums
 //
@@ -22,11 +22,22 @@
 namespace hfv {
 
 // ---------------------------------------------------------------------------
+// Central fit of a cell kept for the CWENOZ pass (the linear polynomial is
+// CWENOZ's central candidate, Section 2.3).  Every cell's fit is kept so that
+// the CWENOZ list stays one dense list in cell order.
+template <int NV, typename T, int K, int VPL>
+__device__ inline void keep_fit(const HotArgs<T> &a, int cell, int v0, const T (&co)[K][VPL]) {
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int q = 0; q < VPL; ++q) a.coef[((long)k * NV + v0 + q) * a.N + cell] = co[k][q];
+}
+
 // K1: linear candidate, face states, NAD own class, Harten flag.
 template <int DIM, int R, typename T, int G>
 __global__ __launch_bounds__(256) void k_linear(HotArgs<T> a) {
   constexpr int NV = DIM + 2, K = n_unknowns(DIM, R), VPL = NV / G, NFM = nf_max(DIM);
-  if (blockIdx.x == 0 && threadIdx.x < 4) a.counts[threadIdx.x] = 0;
+  if (blockIdx.x == 0 && threadIdx.x < 8) a.counts[threadIdx.x] = 0;
   Lane<G> L;
   const int cell = L.item;
   if (!L.ok || cell >= a.N) return;
@@ -43,26 +54,25 @@ __global__ __launch_bounds__(256) void k_linear(HotArgs<T> a) {
   for (int q = 0; q < VPL; ++q) mn[q] = mx[q] = u0[q];
   T dmax = -INFINITY, dmin = INFINITY;
   bool has_nb = false;
-  const int nf = a.t.nfc[cell];
+  // rows past the cell's face count hold -1, as do boundary faces: every
+  // row is read without waiting for the count
 #pragma unroll
   for (int f = 0; f < NFM; ++f) {
-    if (f < nf) {
-      const int j = a.t.nbr[(long)f * N + cell];
-      if (j >= 0) {
-        T s2 = 0;
+    const int j = a.t.nbr[(long)f * N + cell];
+    if (j >= 0) {
+      T s2 = 0;
 #pragma unroll
-        for (int q = 0; q < VPL; ++q) {
-          const T u = a.U[(long)(v0 + q) * N + j];
-          mn[q] = fmin(mn[q], u);
-          mx[q] = fmax(mx[q], u);
-          s2 += (u - u0[q]) * (u - u0[q]);
-        }
-        s2 = group_sum<G>(s2, L.base);
-        const T nrm = sqrt(s2);
-        dmax = fmax(dmax, nrm);
-        dmin = fmin(dmin, nrm);
-        has_nb = true;
+      for (int q = 0; q < VPL; ++q) {
+        const T u = a.U[(long)(v0 + q) * N + j];
+        mn[q] = fmin(mn[q], u);
+        mx[q] = fmax(mx[q], u);
+        s2 += (u - u0[q]) * (u - u0[q]);
       }
+      s2 = group_sum<G>(s2, L.base);
+      const T nrm = sqrt(s2);
+      dmax = fmax(dmax, nrm);
+      dmin = fmin(dmin, nrm);
+      has_nb = true;
     }
   }
   T all0[NV];
@@ -114,6 +124,7 @@ __global__ __launch_bounds__(256) void k_linear(HotArgs<T> a) {
     const T dU = has_nb ? dmax - dmin : (T)0;
     if (dU < a.t.thr[cell]) c = HFV_CLASS_LINEAR;
   }
+  if (a.coef) keep_fit<NV>(a, cell, v0, co);
   if (L.sub == 0) a.own[cell] = (uint8_t)(c | (hok ? 0 : 4));
 }
 
@@ -147,7 +158,7 @@ __global__ __launch_bounds__(256) void k_linear_ms(HotArgs<T> a) {
   constexpr int NV = DIM + 2, K = n_unknowns(DIM, R), M = 2 * K, NFM = nf_max(DIM);
   constexpr int MPL = (M + G - 1) / G;
   static_assert((G & (G - 1)) == 0 && 64 % G == 0, "group size must be a power of two");
-  if (blockIdx.x == 0 && threadIdx.x < 4) a.counts[threadIdx.x] = 0;
+  if (blockIdx.x == 0 && threadIdx.x < 8) a.counts[threadIdx.x] = 0;
   Lane<G> L;
   const int cell = L.item;
   if (!L.ok || cell >= a.N) return;  // whole groups leave together
@@ -185,11 +196,10 @@ __global__ __launch_bounds__(256) void k_linear_ms(HotArgs<T> a) {
 #pragma unroll
   for (int v = 0; v < NV; ++v) mn[v] = mx[v] = u0[v];
   T dmax = -INFINITY, dmin = INFINITY;
-  const int nf = a.t.nfc[cell];
 #pragma unroll
   for (int f0 = 0; f0 < NFM; f0 += G) {
     const int f = f0 + q;
-    if (f < nf) {
+    if (f < NFM) {  // rows past the cell's face count hold -1
       const int j = a.t.nbr[(long)f * N + cell];
       if (j >= 0) {
         T s2 = 0;
@@ -265,6 +275,206 @@ __global__ __launch_bounds__(256) void k_linear_ms(HotArgs<T> a) {
     const T dU = has_nb ? dmax - dmin : (T)0;
     if (dU < a.t.thr[cell]) c = HFV_CLASS_LINEAR;
   }
+  if (a.coef) {  // every lane holds the full fit: split the stores
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        if ((k * NV + v) % G == q) a.coef[((long)k * NV + v) * N + cell] = co[k][v];
+  }
+  if (q == 0) a.own[cell] = (uint8_t)(c | (hok ? 0 : 4));
+}
+
+// K1, unknown-split mapping: lane q of a cell's group of G owns the unknowns
+// k = q, q + G, q + 2G, ... for every variable, so the group streams each row
+// of the cell's pseudo-inverse exactly once and a lane holds only K/G x NV
+// coefficients.  Face Gauss points are taken G at a time: each lane forms the
+// partial sums of its unknowns at the G points, and a butterfly
+// reduce-scatter over the group leaves lane q with the full state at point q
+// of the batch, which it checks (NAD excursion, Harten) and stores.
+template <int DIM, int R, typename T, int G>
+__global__ __launch_bounds__(256) void k_linear_ks(HotArgs<T> a) {
+  constexpr int NV = DIM + 2, K = n_unknowns(DIM, R), M = 2 * K, NFM = nf_max(DIM);
+  constexpr int KPL = (K + G - 1) / G;
+  constexpr Exps<DIM, 1, R> E{};
+  static_assert((G & (G - 1)) == 0 && G >= 2 && 64 % G == 0, "group size must be a power of two");
+  if (blockIdx.x == 0 && threadIdx.x < 8) a.counts[threadIdx.x] = 0;
+  Lane<G> L;
+  const int cell = L.item;
+  if (!L.ok || cell >= a.N) return;  // whole groups leave together
+  const int N = a.N, q = L.sub;
+  T u0[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) u0[v] = a.U[(long)v * N + cell];
+  T co[KPL][NV];
+#pragma unroll
+  for (int j = 0; j < KPL; ++j)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) co[j][v] = (T)0;
+#pragma unroll 2
+  for (int m = 0; m < M; ++m) {
+    const int jc = a.t.sten[(long)m * N + cell];
+    T du[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) du[v] = a.U[(long)v * N + jc] - u0[v];
+#pragma unroll
+    for (int j = 0; j < KPL; ++j) {
+      const int k = q + j * G;
+      if (j * G + G <= K || k < K) {
+        const T p = a.t.P[((long)k * M + m) * N + cell];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) co[j][v] += p * du[v];
+      }
+    }
+  }
+  // NAD bounds and deactivation norms over the face neighbours, split over the group
+  T mn[NV], mx[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) mn[v] = mx[v] = u0[v];
+  T dmax = -INFINITY, dmin = INFINITY;
+#pragma unroll
+  for (int f0 = 0; f0 < NFM; f0 += G) {
+    const int f = f0 + q;
+    if (f < NFM) {  // rows past the cell's face count hold -1
+      const int j = a.t.nbr[(long)f * N + cell];
+      if (j >= 0) {
+        T s2 = 0;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          const T u = a.U[(long)v * N + j];
+          mn[v] = fmin(mn[v], u);
+          mx[v] = fmax(mx[v], u);
+          s2 += (u - u0[v]) * (u - u0[v]);
+        }
+        const T nrm = sqrt(s2);
+        dmax = fmax(dmax, nrm);
+        dmin = fmin(dmin, nrm);
+      }
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    mn[v] = xor_min<G>(mn[v]);
+    mx[v] = xor_max<G>(mx[v]);
+  }
+  dmax = xor_max<G>(dmax);
+  dmin = xor_min<G>(dmin);
+  const bool has_nb = dmax >= (T)0;
+  const T rho_b = u0[0];
+  const T p_b = pressure<NV, T>(u0, a.gamma);
+  T psb[KPL];
+#pragma unroll
+  for (int j = 0; j < KPL; ++j) {
+    const int k = q + j * G;
+    psb[j] = (k < K) ? a.t.psibar[(long)k * N + cell] : (T)0;
+  }
+  T exc[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) exc[v] = -INFINITY;
+  bool hok = true;
+  const int ng = a.t.ngp[cell];
+  for (int g0 = 0; g0 < ng; g0 += G) {
+    T part[G][NV];
+#pragma unroll
+    for (int t = 0; t < G; ++t) {
+      const int g = min(g0 + t, ng - 1);  // a short last batch repeats the cell's last point
+      T pw[DIM][R + 1];
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) {
+        const T x = a.t.gpxi[((long)g * DIM + j) * N + cell];
+        pw[j][0] = (T)1;
+#pragma unroll
+        for (int p = 1; p <= R; ++p) pw[j][p] = pw[j][p - 1] * x;
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) part[t][v] = (T)0;
+#pragma unroll
+      for (int j = 0; j < KPL; ++j) {
+        // this lane's unknown k = q + j G: pick its monomial among the G candidates
+        T mono = (T)0;
+#pragma unroll
+        for (int s = 0; s < G; ++s) {
+          const int k = j * G + s;
+          if (k < K) {
+            T m = pw[0][E.e[k][0]];
+#pragma unroll
+            for (int d = 1; d < DIM; ++d) m *= pw[d][E.e[k][d]];
+            mono = (q == s) ? m : mono;
+          }
+        }
+        const T phi = mono - psb[j];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) part[t][v] += co[j][v] * phi;
+      }
+    }
+    // reduce-scatter: halve the batch at each step, keeping the half picked by this lane's bit
+    T full[NV];
+    {
+      T cur[G][NV];
+#pragma unroll
+      for (int t = 0; t < G; ++t)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) cur[t][v] = part[t][v];
+#pragma unroll
+      for (int H = G / 2; H >= 1; H /= 2) {
+        const bool hi = (q & H) != 0;
+#pragma unroll
+        for (int i = 0; i < H; ++i)
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            const T keep = hi ? cur[i + H][v] : cur[i][v];
+            const T send = hi ? cur[i][v] : cur[i + H][v];
+            cur[i][v] = keep + __shfl_xor(send, H);
+          }
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) full[v] = cur[0][v];
+    }
+    const int g = g0 + q;
+    if (g < ng) {
+      T val[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        val[v] = u0[v] + full[v];
+        exc[v] = fmax(exc[v], fmax(mn[v] - val[v], val[v] - mx[v]));
+      }
+      hok = hok && harten_point<NV, T>(val, rho_b, p_b, a);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) store<NV, T>(a, g, cell, v, val[v]);
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) exc[v] = xor_max<G>(exc[v]);
+  {
+    int hv = hok ? 1 : 0;
+#pragma unroll
+    for (int off = 1; off < G; off <<= 1) hv &= __shfl_xor(hv, off);
+    hok = hv != 0;
+  }
+  int c = 0;
+  if (a.mode == HFV_HYBRID) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const T Rg = mx[v] - mn[v];
+      const T dm = fmax(a.alpha_m, a.beta_m * Rg);
+      const T sgn = (T)((a.beta_w > 0) - (a.beta_w < 0));
+      const T dw = sgn * fmax(a.alpha_w, fabs(a.beta_w * Rg));
+      const int cv = exc[v] <= dw ? HFV_CLASS_LINEAR : (exc[v] >= dm ? HFV_CLASS_MUSCL : HFV_CLASS_CWENOZ);
+      c = max(c, cv);
+    }
+    const T dU = has_nb ? dmax - dmin : (T)0;
+    if (dU < a.t.thr[cell]) c = HFV_CLASS_LINEAR;
+  }
+  if (a.coef) {
+#pragma unroll
+    for (int j = 0; j < KPL; ++j) {
+      const int k = q + j * G;
+      if (k < K) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) a.coef[((long)k * NV + v) * N + cell] = co[j][v];
+      }
+    }
+  }
   if (q == 0) a.own[cell] = (uint8_t)(c | (hok ? 0 : 4));
 }
 
@@ -292,9 +502,11 @@ __global__ __launch_bounds__(CLASSIFY_BLOCK) void k_classify(HotArgs<T> a, int n
     if (c == HFV_CLASS_LINEAR && (o & 4)) c = HFV_CLASS_FIRST_ORDER;
     a.cls[cell] = (uint8_t)c;
   }
+  // List of the cell: CWENOZ (0), MUSCL (1), first order (2).
+  const int li = c - 1;
   // Compaction: wave ballots give each lane its rank inside the wave; the
   // waves of the block combine their counts in LDS and the block reserves its
-  // range of each list with one atomic per class.
+  // range of each list with one atomic per list.
   constexpr int NW = CLASSIFY_BLOCK / 64;
   __shared__ int wcount[3][NW];
   __shared__ int wbase[3][NW];
@@ -303,7 +515,7 @@ __global__ __launch_bounds__(CLASSIFY_BLOCK) void k_classify(HotArgs<T> a, int n
   unsigned long long masks[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    masks[k] = __ballot(valid && c == k + 1);
+    masks[k] = __ballot(valid && li == k);
     if (lane == 0) wcount[k][wave] = __popcll(masks[k]);
   }
   __syncthreads();
@@ -318,14 +530,12 @@ __global__ __launch_bounds__(CLASSIFY_BLOCK) void k_classify(HotArgs<T> a, int n
     for (int w = 0; w < NW; ++w) wbase[k][w] += start;
   }
   __syncthreads();
-  if (valid && c >= 1) {
-    const int k = c - 1;
-    a.lists[(long)k * a.N + wbase[k][wave] + __popcll(masks[k] & lt)] = cell;
-  }
+  if (valid && li >= 0) a.lists[(long)li * a.N + wbase[li][wave] + __popcll(masks[li] & lt)] = cell;
 }
 
-// K3: CWENOZ over list 1 (or every cell when lists == nullptr).
-template <int DIM, int R, typename T, int G>
+// K3: CWENOZ over the class-1 list (every cell when direct).  REUSE: the
+// central fit is read from the linear pass's copy instead of refitted.
+template <int DIM, int R, typename T, int G, bool REUSE>
 __global__ __launch_bounds__(256) void k_cwenoz(HotArgs<T> a, int direct) {
   constexpr int NV = DIM + 2, K = n_unknowns(DIM, R), VPL = NV / G, NFM = nf_max(DIM), MD = 2 * DIM;
   constexpr int CPW = 64 / G;
@@ -340,7 +550,14 @@ __global__ __launch_bounds__(256) void k_cwenoz(HotArgs<T> a, int direct) {
 #pragma unroll
     for (int q = 0; q < VPL; ++q) u0[q] = a.U[(long)(v0 + q) * N + cell];
     T co[K][VPL];
-    lsq_coeffs<DIM, R, VPL, T>(a, cell, v0, u0, co);
+    if constexpr (REUSE) {
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int q = 0; q < VPL; ++q) co[k][q] = a.coef[((long)k * NV + v0 + q) * N + cell];
+    } else {
+      lsq_coeffs<DIM, R, VPL, T>(a, cell, v0, u0, co);
+    }
     // directional degree-1 fits (Section 2.3)
     const int nd = a.t.ndir[cell];
     T ad[NFM][DIM][VPL];
@@ -350,19 +567,19 @@ __global__ __launch_bounds__(256) void k_cwenoz(HotArgs<T> a, int direct) {
       for (int j = 0; j < DIM; ++j)
 #pragma unroll
         for (int q = 0; q < VPL; ++q) ad[s][j][q] = (T)0;
-      if (s < nd) {
+      // stencils past the cell's count are padded with the cell itself and
+      // zero weights: they add exact zeros, so every row is read unguarded
 #pragma unroll
-        for (int m = 0; m < MD; ++m) {
-          const int jc = a.t.dsten[((long)s * MD + m) * N + cell];
-          T du[VPL];
+      for (int m = 0; m < MD; ++m) {
+        const int jc = a.t.dsten[((long)s * MD + m) * N + cell];
+        T du[VPL];
 #pragma unroll
-          for (int q = 0; q < VPL; ++q) du[q] = a.U[(long)(v0 + q) * N + jc] - u0[q];
+        for (int q = 0; q < VPL; ++q) du[q] = a.U[(long)(v0 + q) * N + jc] - u0[q];
 #pragma unroll
-          for (int j = 0; j < DIM; ++j) {
-            const T p = a.t.Pdir[(((long)s * DIM + j) * MD + m) * N + cell];
+        for (int j = 0; j < DIM; ++j) {
+          const T p = a.t.Pdir[(((long)s * DIM + j) * MD + m) * N + cell];
 #pragma unroll
-            for (int q = 0; q < VPL; ++q) ad[s][j][q] += p * du[q];
-          }
+          for (int q = 0; q < VPL; ++q) ad[s][j][q] += p * du[q];
         }
       }
     }
@@ -477,7 +694,8 @@ __global__ __launch_bounds__(256) void k_cwenoz(HotArgs<T> a, int direct) {
   }
 }
 
-// K4: MUSCL with the Barth-Jespersen limiter over list 2.
+// K4: MUSCL with the Barth-Jespersen limiter over list 2, then first-order
+// states over list 3.
 template <int DIM, int R, typename T, int G>
 __global__ __launch_bounds__(256) void k_muscl(HotArgs<T> a, int direct) {
   constexpr int NV = DIM + 2, VPL = NV / G, NFM = nf_max(DIM);
@@ -497,37 +715,33 @@ __global__ __launch_bounds__(256) void k_muscl(HotArgs<T> a, int direct) {
     for (int j = 0; j < DIM; ++j)
 #pragma unroll
       for (int q = 0; q < VPL; ++q) gr[j][q] = 0;
-    const int nm = a.t.nmus[cell];
+    // members past the cell's count are padded with the cell itself and zero
+    // weights (exact zeros), neighbour rows past its face count with -1
 #pragma unroll
     for (int m = 0; m < NFM; ++m) {
-      if (m < nm) {
-        const int jc = a.t.msten[(long)m * N + cell];
-        T du[VPL];
+      const int jc = a.t.msten[(long)m * N + cell];
+      T du[VPL];
 #pragma unroll
-        for (int q = 0; q < VPL; ++q) du[q] = a.U[(long)(v0 + q) * N + jc] - u0[q];
+      for (int q = 0; q < VPL; ++q) du[q] = a.U[(long)(v0 + q) * N + jc] - u0[q];
 #pragma unroll
-        for (int j = 0; j < DIM; ++j) {
-          const T p = a.t.Pmus[((long)j * NFM + m) * N + cell];
+      for (int j = 0; j < DIM; ++j) {
+        const T p = a.t.Pmus[((long)j * NFM + m) * N + cell];
 #pragma unroll
-          for (int q = 0; q < VPL; ++q) gr[j][q] += p * du[q];
-        }
+        for (int q = 0; q < VPL; ++q) gr[j][q] += p * du[q];
       }
     }
     T mn[VPL], mx[VPL];
 #pragma unroll
     for (int q = 0; q < VPL; ++q) mn[q] = mx[q] = u0[q];
-    const int nf = a.t.nfc[cell];
 #pragma unroll
     for (int f = 0; f < NFM; ++f) {
-      if (f < nf) {
-        const int j = a.t.nbr[(long)f * N + cell];
-        if (j >= 0) {
+      const int j = a.t.nbr[(long)f * N + cell];
+      if (j >= 0) {
 #pragma unroll
-          for (int q = 0; q < VPL; ++q) {
-            const T u = a.U[(long)(v0 + q) * N + j];
-            mn[q] = fmin(mn[q], u);
-            mx[q] = fmax(mx[q], u);
-          }
+        for (int q = 0; q < VPL; ++q) {
+          const T u = a.U[(long)(v0 + q) * N + j];
+          mn[q] = fmin(mn[q], u);
+          mx[q] = fmax(mx[q], u);
         }
       }
     }
@@ -538,6 +752,7 @@ __global__ __launch_bounds__(256) void k_muscl(HotArgs<T> a, int direct) {
     T th[VPL];
 #pragma unroll
     for (int q = 0; q < VPL; ++q) th[q] = (T)1;
+#pragma unroll 4
     for (int g = 0; g < ng; ++g) {
       T phi[DIM];
 #pragma unroll
@@ -559,8 +774,11 @@ __global__ __launch_bounds__(256) void k_muscl(HotArgs<T> a, int direct) {
     group_state<NV, G, T>(u0, all0, L.base);
     const T rho_b = all0[0];
     const T p_b = pressure<NV, T>(all0, a.gamma);
+    // limited states and their Harten check; the rare failure rewrites the
+    // cell's points with the first-order state afterwards
     bool hok = true;
-    for (int g = 0; g < ng && hok; ++g) {
+#pragma unroll 4
+    for (int g = 0; g < ng; ++g) {
       T phi[DIM];
 #pragma unroll
       for (int j = 0; j < DIM; ++j) phi[j] = a.t.gpxi[((long)g * DIM + j) * N + cell] - psb[j];
@@ -574,39 +792,30 @@ __global__ __launch_bounds__(256) void k_muscl(HotArgs<T> a, int direct) {
       }
       T all[NV];
       group_state<NV, G, T>(val, all, L.base);
-      hok = a.frozen || harten_point<NV, T>(all, rho_b, p_b, a);
+      hok = hok && (a.frozen || harten_point<NV, T>(all, rho_b, p_b, a));
+#pragma unroll
+      for (int q = 0; q < VPL; ++q) store<NV, T>(a, g, cell, v0 + q, val[q]);
     }
-    for (int g = 0; g < ng; ++g) {
-      T phi[DIM];
+    if (!hok) {
+      for (int g = 0; g < ng; ++g)
 #pragma unroll
-      for (int j = 0; j < DIM; ++j) phi[j] = a.t.gpxi[((long)g * DIM + j) * N + cell] - psb[j];
-#pragma unroll
-      for (int q = 0; q < VPL; ++q) {
-        T d = 0;
-#pragma unroll
-        for (int j = 0; j < DIM; ++j) d += gr[j][q] * phi[j];
-        store<NV, T>(a, g, cell, v0 + q, hok ? u0[q] + th[q] * d : u0[q]);
-      }
+        for (int q = 0; q < VPL; ++q) store<NV, T>(a, g, cell, v0 + q, u0[q]);
     }
     if (L.sub == 0 && !a.frozen) a.cls[cell] = hok ? HFV_CLASS_MUSCL : HFV_CLASS_FIRST_ORDER;
   }
-}
-
-// K5: first-order states (cell average at every Gauss point) over list 3.
-template <int NV, typename T>
-__global__ __launch_bounds__(256) void k_first(HotArgs<T> a) {
-  const int total = a.counts[3];
-  for (long item = (long)blockIdx.x * blockDim.x + threadIdx.x; item < total;
-       item += (long)gridDim.x * blockDim.x) {
+  // K5: first-order states (the cell average at every Gauss point) over list 3
+  const int total3 = direct ? 0 : a.counts[3];
+  for (long item = L.item; item < total3; item += stride) {
     const int cell = a.lists[2L * a.N + item];
+    const int N = a.N, v0 = L.sub * VPL;
+    T u0[VPL];
+#pragma unroll
+    for (int q = 0; q < VPL; ++q) u0[q] = a.U[(long)(v0 + q) * N + cell];
     const int ng = a.t.ngp[cell];
-    T u0[NV];
+#pragma unroll 4
+    for (int g = 0; g < ng; ++g)
 #pragma unroll
-    for (int v = 0; v < NV; ++v) u0[v] = a.U[(long)v * a.N + cell];
-    for (int g = 0; g < ng; ++g) {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) store<NV, T>(a, g, cell, v, u0[v]);
-    }
+      for (int q = 0; q < VPL; ++q) store<NV, T>(a, g, cell, v0 + q, u0[q]);
   }
 }
 
@@ -663,6 +872,53 @@ __global__ __launch_bounds__(256) void k_gather(int N, int NF, const int *cf_off
   for (int v = 0; v < NV; ++v) R[(long)v * N + c] = acc[v] * iv;
 }
 
+// K6+K7 fused, owner computes: each cell integrates the Riemann flux over its
+// faces' Gauss points and sums them with its orientation signs.  An interior
+// face's flux is evaluated by both of its cells from the same operands in the
+// same order (left state, right state, the face's own normal), so the two
+// values are bitwise equal and the residual conserves exactly; the sums match
+// k_flux followed by k_gather bit for bit.
+template <int DIM, typename T>
+__global__ __launch_bounds__(256) void k_residual(int N, int NF, const T *fs, const int *cf_off, const int *cf,
+                                                  const int *fc, const int *fgb, const int *gp_off, const T *fn,
+                                                  const T *gpw, const T *ivol, T gamma, int hllc, T *R) {
+  constexpr int NV = DIM + 2;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= N) return;
+  T acc[NV] = {};
+  for (int e = cf_off[c]; e < cf_off[c + 1]; ++e) {
+    const int code = cf[e];
+    const int f = code & 0x7fffffff;
+    const T sg = (code < 0) ? (T)1 : (T)-1;
+    const int cL = fc[f], cR0 = fc[NF + f], cR = cR0 >= 0 ? cR0 : cL;
+    const int t = fgb[f];
+    const T *pL = fs + (long)(t & 255) * NV * N + cL;
+    const T *pR = fs + (long)((t >> 8) & 255) * NV * N + cR;
+    T n[DIM];
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) n[j] = fn[(long)j * NF + f];
+    T af[NV] = {};
+    for (int g = gp_off[f], i = 0; g < gp_off[f + 1]; ++g, ++i) {
+      T qL[NV], qR[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        qL[v] = pL[((long)i * NV + v) * N];
+        qR[v] = pR[((long)i * NV + v) * N];
+      }
+      T F[NV];
+      riemann<DIM, T, T>(qL, qR, n, gamma, hllc, F);
+      const T w = gpw[g];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) af[v] += w * F[v];
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] += sg * af[v];
+  }
+  const T iv = ivol[c];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) R[(long)v * N + c] = acc[v] * iv;
+}
+
 // ---------------------------------------------------------------------------
 static inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
 
@@ -676,6 +932,7 @@ static HotArgs<T> make_args(hfv_ctx *ctx, Tables<T> &t, const void *U, void *fs,
   a.cls_in = nullptr;
   a.U = (const T *)U;
   a.fs = (T *)fs;
+  a.coef = (ctx->cw_reuse && ctx->p.mode == HFV_HYBRID) ? (T *)ctx->coef : nullptr;
   a.own = ctx->own;
   a.cls = cls;
   a.lists = ctx->lists;
@@ -696,8 +953,30 @@ static HotArgs<T> make_args(hfv_ctx *ctx, Tables<T> &t, const void *U, void *fs,
   return a;
 }
 
-__global__ void k_zero4(int *c) {
-  if (threadIdx.x < 4) c[threadIdx.x] = 0;
+__global__ void k_zero_counts(int *c) {
+  if (threadIdx.x < 8) c[threadIdx.x] = 0;
+}
+
+// The linear + NAD kernel in the configured mapping: variables (split 0),
+// stencil members (1) or unknowns (2) per lane, lin_lanes lanes per cell.
+template <int DIM, int R, typename T>
+static void launch_linear(const hfv_ctx *ctx, const HotArgs<T> &a, hipStream_t s) {
+  const int B = ctx->block, GL = ctx->lin_lanes;
+  const long waves = ((long)ctx->N + 64 / GL - 1) / (64 / GL);
+  const unsigned grid = nblk(waves * 64, B);
+  switch (ctx->lin_split * 16 + GL) {
+    case 1: k_linear<DIM, R, T, 1><<<grid, B, 0, s>>>(a); break;
+    case 2:
+      if constexpr (DIM == 2) k_linear<DIM, R, T, 2><<<grid, B, 0, s>>>(a);
+      break;
+    case DIM + 2: k_linear<DIM, R, T, DIM + 2><<<grid, B, 0, s>>>(a); break;
+    case 16 + 2: k_linear_ms<DIM, R, T, 2><<<grid, B, 0, s>>>(a); break;
+    case 16 + 4: k_linear_ms<DIM, R, T, 4><<<grid, B, 0, s>>>(a); break;
+    case 16 + 8: k_linear_ms<DIM, R, T, 8><<<grid, B, 0, s>>>(a); break;
+    case 32 + 2: k_linear_ks<DIM, R, T, 2><<<grid, B, 0, s>>>(a); break;
+    case 32 + 4: k_linear_ks<DIM, R, T, 4><<<grid, B, 0, s>>>(a); break;
+    case 32 + 8: k_linear_ks<DIM, R, T, 8><<<grid, B, 0, s>>>(a); break;
+  }
 }
 
 template <int DIM, int R, typename T, int G>
@@ -710,34 +989,23 @@ static hfv_status recon_impl(hfv_ctx *ctx, Tables<T> &t, const void *U, void *fs
   const unsigned grid_list = std::min<unsigned>(grid_cells, (unsigned)ctx->list_blocks);
   const int mode = ctx->p.mode;
   if (mode == HFV_ALL_CWENOZ) {
-    k_zero4<<<1, 64, 0, s>>>(ctx->counts);
-    { ProfScope ps(ctx, HFV_SLOT_CWENOZ, s); k_cwenoz<DIM, R, T, G><<<grid_list, B, 0, s>>>(a, 1); }
+    k_zero_counts<<<1, 64, 0, s>>>(ctx->counts);
+    { ProfScope ps(ctx, HFV_SLOT_CWENOZ, s); k_cwenoz<DIM, R, T, G, false><<<grid_list, B, 0, s>>>(a, 1); }
   } else if (mode == HFV_ALL_MUSCL) {
-    k_zero4<<<1, 64, 0, s>>>(ctx->counts);
+    k_zero_counts<<<1, 64, 0, s>>>(ctx->counts);
     { ProfScope ps(ctx, HFV_SLOT_MUSCL, s); k_muscl<DIM, R, T, G><<<grid_list, B, 0, s>>>(a, 1); }
   } else {
-    {
-      ProfScope ps(ctx, HFV_SLOT_LINEAR, s);
-      if (ctx->lin_split == 1) {
-        const int GL = ctx->lin_lanes;
-        const long wl = ((long)ctx->N + 64 / GL - 1) / (64 / GL);
-        const unsigned gl = nblk(wl * 64, B);
-        if (GL == 4)
-          k_linear_ms<DIM, R, T, 4><<<gl, B, 0, s>>>(a);
-        else if (GL == 8)
-          k_linear_ms<DIM, R, T, 8><<<gl, B, 0, s>>>(a);
-        else
-          k_linear_ms<DIM, R, T, 2><<<gl, B, 0, s>>>(a);
-      } else {
-        k_linear<DIM, R, T, G><<<grid_cells, B, 0, s>>>(a);
-      }
-    }
+    { ProfScope ps(ctx, HFV_SLOT_LINEAR, s); launch_linear<DIM, R, T>(ctx, a, s); }
     { ProfScope ps(ctx, HFV_SLOT_CLASSIFY, s); k_classify<T><<<nblk(ctx->N, CLASSIFY_BLOCK), CLASSIFY_BLOCK, 0, s>>>(a, ctx->NFM); }
     if (mode == HFV_HYBRID) {
-      { ProfScope ps(ctx, HFV_SLOT_CWENOZ, s); k_cwenoz<DIM, R, T, G><<<grid_list, B, 0, s>>>(a, 0); }
-      { ProfScope ps(ctx, HFV_SLOT_MUSCL, s); k_muscl<DIM, R, T, G><<<grid_list, B, 0, s>>>(a, 0); }
+      ProfScope ps(ctx, HFV_SLOT_CWENOZ, s);
+      if (a.coef)
+        k_cwenoz<DIM, R, T, G, true><<<grid_list, B, 0, s>>>(a, 0);
+      else
+        k_cwenoz<DIM, R, T, G, false><<<grid_list, B, 0, s>>>(a, 0);
     }
-    { ProfScope ps(ctx, HFV_SLOT_FIRST, s); k_first<DIM + 2, T><<<std::min<unsigned>(nblk(ctx->N, 256), 1024), 256, 0, s>>>(a); }
+    // MUSCL list (empty unless hybrid) and the first-order list
+    { ProfScope ps(ctx, HFV_SLOT_MUSCL, s); k_muscl<DIM, R, T, G><<<grid_list, B, 0, s>>>(a, 0); }
   }
   HFV_HIP(hipGetLastError());
   return HFV_OK;
@@ -753,15 +1021,15 @@ static hfv_status frozen_impl(hfv_ctx *ctx, Tables<T> &t, const void *U, void *f
   a.frozen = 1;
   a.cls_in = cls;
   a.mode = HFV_ALL_LINEAR;
+  a.coef = nullptr;
   const int B = ctx->block;
   const long waves = ((long)ctx->N + 64 / G - 1) / (64 / G);
   const unsigned grid_cells = nblk(waves * 64, B);
   const unsigned grid_list = std::min<unsigned>(grid_cells, (unsigned)ctx->list_blocks);
-  k_linear<DIM, R, T, G><<<grid_cells, B, 0, s>>>(a);
+  launch_linear<DIM, R, T>(ctx, a, s);
   k_classify<T><<<nblk(ctx->N, CLASSIFY_BLOCK), CLASSIFY_BLOCK, 0, s>>>(a, ctx->NFM);
-  k_cwenoz<DIM, R, T, G><<<grid_list, B, 0, s>>>(a, 0);
+  k_cwenoz<DIM, R, T, G, false><<<grid_list, B, 0, s>>>(a, 0);
   k_muscl<DIM, R, T, G><<<grid_list, B, 0, s>>>(a, 0);
-  k_first<DIM + 2, T><<<std::min<unsigned>(nblk(ctx->N, 256), 1024), 256, 0, s>>>(a);
   HFV_HIP(hipGetLastError());
   return HFV_OK;
 }
@@ -827,6 +1095,17 @@ static hfv_status tail_t(hfv_ctx *ctx, Tables<T> &t, const void *fs, void *R, hi
   const int hllc = ctx->p.riemann == HFV_HLLC;
   T *Ff = (T *)ctx->fflux;
   const unsigned gf = nblk(ctx->NF, 256), gc = nblk(ctx->N, 256);
+  if (ctx->fused_residual) {
+    ProfScope ps(ctx, HFV_SLOT_FLUX, s);
+    if (ctx->dim == 2)
+      k_residual<2, T><<<gc, 256, 0, s>>>(ctx->N, ctx->NF, (const T *)fs, t.cf_off, t.cf, t.face_cells, t.fgb,
+                                          t.gp_off, t.fnormal, t.gpw, t.ivol, (T)ctx->p.gamma, hllc, (T *)R);
+    else
+      k_residual<3, T><<<gc, 256, 0, s>>>(ctx->N, ctx->NF, (const T *)fs, t.cf_off, t.cf, t.face_cells, t.fgb,
+                                          t.gp_off, t.fnormal, t.gpw, t.ivol, (T)ctx->p.gamma, hllc, (T *)R);
+    HFV_HIP(hipGetLastError());
+    return HFV_OK;
+  }
   if (ctx->dim == 2) {
     { ProfScope ps(ctx, HFV_SLOT_FLUX, s);
       k_flux<2, T><<<gf, 256, 0, s>>>(ctx->NF, ctx->N, (const T *)fs, t.gp_off, t.face_cells, t.fgb, t.fnormal,

@@ -105,8 +105,9 @@ struct hfv_ctx {
   // workspace
   uint8_t *own = nullptr;      // [N]
   uint8_t *cls_ws = nullptr;   // [N]
-  int *lists = nullptr;        // [3][N]
-  int *counts = nullptr;       // [4]
+  int *lists = nullptr;        // [3][N] CWENOZ, MUSCL, first order
+  int *counts = nullptr;       // [8] list lengths at 1 + list index
+  void *coef = nullptr;        // [K][nvar][N] central fits kept by the linear pass for CWENOZ
   void *fs_ws = nullptr;       // [NGPC][nvar][N] Gauss-point states, cell-major
   void *fflux = nullptr;       // [nvar][NF]
   void *vjp_C = nullptr;       // adjoint: per stencil slot contributions [M][nvar][N]
@@ -117,7 +118,9 @@ struct hfv_ctx {
   size_t table_bytes = 0;
   // launch configuration
   int lanes = 1, block = 256, list_blocks = 2048;
-  int lin_split = 0, lin_lanes = 4;  // linear kernel: 0 variables per lane, 1 stencil members per lane
+  int lin_split = 0, lin_lanes = 4;  // linear kernel: 0 variables, 1 stencil members, 2 unknowns per lane
+  int cw_reuse = 0;                  // CWENOZ starts from the linear pass's central fit
+  int fused_residual = 0;            // one owner-computes residual kernel instead of flux + gather
   int device = 0, n_cu = 256;
   // kernel timing (hfv_profile_*)
   struct ProfEv {

@@ -1,0 +1,158 @@
+// Launch-configuration autotuner (a project addition, not part of the paper's
+// method): times the residual on the caller's own state for candidate launch
+// configurations and keeps the fastest.  Every configuration computes the
+// same states up to the order of floating-point sums, so tuning changes
+// speed only.
+//
+// Search, coordinate by coordinate (each phase keeps the best of the previous):
+//   1. the linear + NAD kernel's mapping: variables (1, 2 in 2D, nvar lanes),
+//      stencil members or unknowns (2, 4, 8 lanes) per cell;
+//   2. the class-list kernels: lanes per cell x block x resident-block cap
+//      (skipped when no cell can reach a class list's kernels in numbers,
+//      i.e. in all-linear mode, where only first-order cells use them);
+//   3. in hybrid mode, whether CWENOZ reuses the linear pass's central fits;
+//   4. the fused (owner-computes) residual kernel against face fluxes + gather.
+// Each candidate runs once untimed, then `reps` times with HIP events around
+// each call; its score is the median.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "hfv_internal.hpp"
+
+namespace {
+
+struct Tuner {
+  hfv_ctx *ctx;
+  const void *U;
+  void *R;
+  hipStream_t s;
+  int reps;
+  hipEvent_t ea, eb;
+  std::vector<hfv_tune_record> rec;
+
+  // median residual time of configuration c in ms; +inf when c is rejected
+  double time(const hfv_launch &c) {
+    if (hfv_set_launch(ctx, &c) != HFV_OK) return INFINITY;
+    if (hfv_residual(ctx, U, R, nullptr, nullptr, s) != HFV_OK) return INFINITY;
+    if (hipStreamSynchronize(s) != hipSuccess) return INFINITY;
+    std::vector<float> t;
+    for (int i = 0; i < reps; ++i) {
+      float ms = 0;
+      if (hipEventRecord(ea, s) != hipSuccess || hfv_residual(ctx, U, R, nullptr, nullptr, s) != HFV_OK ||
+          hipEventRecord(eb, s) != hipSuccess || hipEventSynchronize(eb) != hipSuccess ||
+          hipEventElapsedTime(&ms, ea, eb) != hipSuccess)
+        return INFINITY;
+      t.push_back(ms);
+    }
+    std::sort(t.begin(), t.end());
+    const double med = t[t.size() / 2];
+    rec.push_back(hfv_tune_record{c, med});
+    return med;
+  }
+
+  // best of the candidates (the earlier one on ties); `best` is updated in place
+  void pick(const std::vector<hfv_launch> &cands, hfv_launch &best, double &best_ms) {
+    for (const hfv_launch &c : cands) {
+      const double ms = time(c);
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = c;
+      }
+    }
+  }
+};
+
+}  // namespace
+
+extern "C" hfv_status hfv_autotune(hfv_ctx *ctx, const void *U, int32_t reps, hfv_launch *best_out,
+                                   hfv_tune_record *records, int32_t max_records, int32_t *n_records,
+                                   void *stream) {
+  if (!ctx) return HFV_ERR_PARAM;
+  if (!U) return ctx->err = "NULL device pointer", HFV_ERR_PARAM;
+  if (reps < 1 || reps > 1000) return ctx->err = "reps must be in [1, 1000]", HFV_ERR_PARAM;
+  if (max_records < 0 || (max_records > 0 && !records)) return ctx->err = "bad record buffer", HFV_ERR_PARAM;
+  hipStream_t s = (hipStream_t)stream;
+  hfv_launch start;
+  hfv_get_launch(ctx, &start);
+  const int prof_mask = ctx->prof_mask;
+  ctx->prof_mask = 0;  // tuning runs do not consume timing slots
+
+  Tuner tu{ctx, U, nullptr, s, reps, nullptr, nullptr, {}};
+  const size_t rbytes = (size_t)(ctx->prec == 64 ? 8 : 4) * ctx->nvar * ctx->N;
+  hfv_status st = HFV_OK;
+  if (hipMalloc(&tu.R, rbytes) != hipSuccess) {
+    ctx->err = "autotune: residual buffer allocation failed";
+    st = HFV_ERR_OOM;
+  } else if (hipEventCreate(&tu.ea) != hipSuccess || hipEventCreate(&tu.eb) != hipSuccess) {
+    ctx->err = "autotune: event creation failed";
+    st = HFV_ERR_HIP;
+  }
+  hfv_launch best = start;
+  double best_ms = INFINITY;
+  if (st == HFV_OK) {
+    best_ms = tu.time(start);
+    if (!std::isfinite(best_ms)) {
+      ctx->err = "autotune: the starting configuration failed";
+      st = HFV_ERR_HIP;
+    }
+  }
+  if (st == HFV_OK) {
+    std::vector<int> var_lanes = {1, ctx->nvar};
+    if (ctx->dim == 2) var_lanes.push_back(2);
+    // 1. linear kernel mapping
+    std::vector<hfv_launch> cands;
+    for (int l : var_lanes) {
+      hfv_launch c = best;
+      c.linear_split = 0;
+      c.linear_lanes = l;
+      cands.push_back(c);
+    }
+    for (int split = 1; split <= 2; ++split)
+      for (int l : {2, 4, 8}) {
+        hfv_launch c = best;
+        c.linear_split = split;
+        c.linear_lanes = l;
+        cands.push_back(c);
+      }
+    tu.pick(cands, best, best_ms);
+    // 2. class-list kernels and block size
+    if (ctx->p.mode != HFV_ALL_LINEAR) {
+      cands.clear();
+      for (int l : var_lanes)
+        for (int b : {128, 256})
+          for (int lb : {4, 8, 16}) {
+            hfv_launch c = best;
+            c.lanes_per_cell = l;
+            c.block = b;
+            c.list_blocks = lb * ctx->n_cu;
+            cands.push_back(c);
+          }
+      tu.pick(cands, best, best_ms);
+    }
+    // 3. CWENOZ reuse of the central fits
+    if (ctx->p.mode == HFV_HYBRID) {
+      hfv_launch c = best;
+      c.cwenoz_reuse = 1 - best.cwenoz_reuse;
+      tu.pick({c}, best, best_ms);
+    }
+    // 4. residual kernel(s)
+    {
+      hfv_launch c = best;
+      c.fused_residual = 1 - best.fused_residual;
+      tu.pick({c}, best, best_ms);
+    }
+    if (hfv_set_launch(ctx, &best) != HFV_OK) st = HFV_ERR_PARAM;
+  } else {
+    (void)hfv_set_launch(ctx, &start);
+  }
+  if (tu.ea) (void)hipEventDestroy(tu.ea);
+  if (tu.eb) (void)hipEventDestroy(tu.eb);
+  if (tu.R) (void)hipFree(tu.R);
+  ctx->prof_mask = prof_mask;
+  if (best_out) *best_out = best;
+  const int n = std::min<int>((int)tu.rec.size(), max_records);
+  for (int i = 0; i < n; ++i) records[i] = tu.rec[i];
+  if (n_records) *n_records = (int32_t)tu.rec.size();
+  return st;
+}

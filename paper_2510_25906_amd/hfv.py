@@ -22,7 +22,7 @@ ERRORS = {-1: "HFV_ERR_PARAM", -2: "HFV_ERR_MESH", -3: "HFV_ERR_RANK", -4: "HFV_
           -5: "HFV_ERR_HIP", -6: "HFV_ERR_OOM", -7: "HFV_ERR_STATE"}
 Q = dict(N_CELLS=0, N_FACES=1, N_GP=2, NVAR=3, K=4, M=5, PRECISION=6, DIM=7, TABLE_BYTES=8,
          COUNT_CWENOZ=9, COUNT_MUSCL=10, COUNT_FIRST=11, NGP_CELL_MAX=12)
-SLOTS = dict(linear=0, classify=1, cwenoz=2, muscl=3, first=4, flux=5, gather=6, vjp=7)
+SLOTS = dict(linear=0, classify=1, cwenoz=2, muscl=3, flux=5, gather=6, vjp=7)
 TABLES = dict(PINV=0, OI=1, PSIBAR=2, GEOM=3, PDIR=4, PMUS=5, FACE_SLOTS=6)
 
 _p = C.c_void_p
@@ -70,7 +70,10 @@ def load():
     lib.hfv_residual_frozen.argtypes = [_p, _p, _p, _p, _p]
     lib.hfv_query.argtypes = [_p, C.c_int32, C.POINTER(C.c_int64)]
     lib.hfv_copy_table.argtypes = [_p, C.c_int32, _p, C.c_int64]
-    lib.hfv_set_launch.argtypes = [_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
+    lib.hfv_set_launch.argtypes = [_p, C.POINTER(HfvLaunch)]
+    lib.hfv_get_launch.argtypes = [_p, C.POINTER(HfvLaunch)]
+    lib.hfv_autotune.argtypes = [_p, _p, C.c_int32, C.POINTER(HfvLaunch), C.POINTER(HfvTuneRecord), C.c_int32,
+                                 C.POINTER(C.c_int32), _p]
     lib.hfv_profile_enable.argtypes = [_p, C.c_int32, C.c_int32]
     lib.hfv_profile_read.argtypes = [_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     lib.hfv_last_error.argtypes = [_p]
@@ -79,10 +82,21 @@ def load():
     lib.hfv_destroy.restype = None
     for name in ("hfv_create", "hfv_set_params", "hfv_reconstruct", "hfv_residual", "hfv_residual_vjp",
                  "hfv_residual_frozen",
-                 "hfv_query", "hfv_copy_table", "hfv_set_launch", "hfv_profile_enable", "hfv_profile_read"):
+                 "hfv_query", "hfv_copy_table", "hfv_set_launch", "hfv_get_launch", "hfv_autotune",
+                 "hfv_profile_enable",
+                 "hfv_profile_read"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
+
+
+class HfvLaunch(C.Structure):
+    _fields_ = [(n, C.c_int32) for n in ("lanes_per_cell", "block", "list_blocks", "linear_split",
+                                         "linear_lanes", "cwenoz_reuse", "fused_residual")]
+
+
+class HfvTuneRecord(C.Structure):
+    _fields_ = [("cfg", HfvLaunch), ("ms", C.c_double)]
 
 
 class HfvError(RuntimeError):
@@ -165,7 +179,6 @@ class Context:
         self.K = self.query("K")
         self.M = self.query("M")
         self.dim = d
-        self._lin = (0, 4)
 
     def _check(self, rc):
         if rc != HFV_OK:
@@ -192,12 +205,31 @@ class Context:
         self._p = params_struct(params, self.precision)
         self._check(self.lib.hfv_set_params(self.h, C.byref(self._p)))
 
-    def set_launch(self, lanes=0, block=0, list_blocks=0, linear_split=None, linear_lanes=4):
-        """Launch shape; ``linear_split`` None keeps the linear kernel's current mapping."""
-        if linear_split is None:
-            linear_split, linear_lanes = self._lin
-        self._lin = (linear_split, linear_lanes)
-        self._check(self.lib.hfv_set_launch(self.h, lanes, block, list_blocks, linear_split, linear_lanes))
+    def get_launch(self) -> dict:
+        cfg = HfvLaunch()
+        self._check(self.lib.hfv_get_launch(self.h, C.byref(cfg)))
+        return {n: getattr(cfg, n) for n, _ in HfvLaunch._fields_}
+
+    def set_launch(self, lanes=None, block=None, list_blocks=None, linear_split=None, linear_lanes=None,
+                   cwenoz_reuse=None, fused_residual=None):
+        """Change the launch configuration; fields left None keep their current value."""
+        cur = self.get_launch()
+        new = dict(lanes_per_cell=lanes, block=block, list_blocks=list_blocks, linear_split=linear_split,
+                   linear_lanes=linear_lanes, cwenoz_reuse=cwenoz_reuse, fused_residual=fused_residual)
+        cur.update({k: int(v) for k, v in new.items() if v is not None})
+        self._check(self.lib.hfv_set_launch(self.h, C.byref(HfvLaunch(**cur))))
+
+    def autotune(self, U, reps: int = 5, max_records: int = 64):
+        """Pick the fastest launch configuration for this state and the current
+        parameters (applied); returns (chosen configuration, [(configuration, ms)])."""
+        self._chk_u(U)
+        best = HfvLaunch()
+        recs = (HfvTuneRecord * max_records)()
+        n = C.c_int32()
+        self._check(self.lib.hfv_autotune(self.h, C.c_void_p(U.data_ptr()), reps, C.byref(best), recs, max_records,
+                                          C.byref(n), None))
+        as_dict = lambda cfg: {k: getattr(cfg, k) for k, _ in HfvLaunch._fields_}
+        return as_dict(best), [(as_dict(r.cfg), r.ms) for r in recs[:min(n.value, max_records)]]
 
     def profile_enable(self, capacity: int, slots=None):
         mask = 0xff if slots is None else sum(1 << SLOTS[k] for k in slots)

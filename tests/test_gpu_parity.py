@@ -68,6 +68,12 @@ def test_c1_fp64_reconstruct_and_residual(hfv, c1, mode):
     S = state_scale(w.U)
     assert states_err(fs, fs_o, om.geo, S) <= 1e-12
     assert rel_err(R.cpu().numpy(), R_o, np.abs(R_o).max(1)[:, None]) <= 1e-11
+    # the two residual kernels (fused owner-computes, face fluxes + gather) agree bit for bit
+    fused = ctx.get_launch()["fused_residual"]
+    ctx.set_launch(fused_residual=1 - fused)
+    R2 = ctx.residual(Ud, face_states=fs, cell_class=cls)
+    torch.cuda.synchronize()
+    assert torch.equal(R, R2)
     ctx.close()
 
 
@@ -114,14 +120,21 @@ def test_c1_tables_match_oracle(hfv, c1):
     ctx.close()
 
 
-@pytest.mark.parametrize("lanes,split,lin_lanes", [(1, 0, 4), (2, 0, 4), (4, 0, 4), (4, 1, 2), (4, 1, 4),
-                                                    (2, 1, 8)])
-def test_c1_launch_shapes_agree(hfv, c1, lanes, split, lin_lanes):
-    """Every work mapping gives the oracle's classes and states."""
+@pytest.mark.parametrize("lanes,split,lin_lanes,reuse", [(1, 0, 1, 0), (2, 0, 2, 1), (4, 0, 4, 0), (4, 1, 2, 1),
+                                                          (4, 1, 4, 0), (2, 1, 8, 1), (2, 2, 2, 1), (2, 2, 4, 0),
+                                                          (1, 2, 8, 1)])
+def test_c1_launch_shapes_agree(hfv, c1, lanes, split, lin_lanes, reuse):
+    """Every work mapping, with and without the CWENOZ reuse of the linear
+    pass's central fits, gives the oracle's classes and states."""
     w, om = c1
     fs_o, cls_o = om.reconstruct(w.U)
     ctx = hfv.Context(w.mesh, w.stencils, w.params, 64)
-    ctx.set_launch(lanes=lanes, block=128, list_blocks=3, linear_split=split, linear_lanes=lin_lanes)
+    ctx.set_launch(lanes=lanes, block=128, list_blocks=3, linear_split=split, linear_lanes=lin_lanes,
+                   cwenoz_reuse=reuse)
+    assert ctx.get_launch()["cwenoz_reuse"] == reuse
+    fs, cls = ctx.reconstruct(to_dev(w.U, torch.float64))
+    torch.cuda.synchronize()
+    assert ctx.query("COUNT_CWENOZ") == int((cls_o == 1).sum()) > 0
     fs, cls = ctx.reconstruct(to_dev(w.U, torch.float64))
     torch.cuda.synchronize()
     assert np.array_equal(cls.cpu().numpy(), cls_o)
@@ -166,8 +179,8 @@ def test_c2_sampled_full_size(hfv):
             flags = dilated_flags(om, near_threshold(om, w.U, cells, 1e-12 if prec == 64 else 1e-6), cells)
             print(f"c2 prec={prec} mode={mode} sampled={cells.size} flagged={flags.sum()}", flush=True)
             ctx = hfv.Context(w.mesh, w.stencils, p, prec)
-            if mode == HYBRID and prec == 64:
-                ctx.set_launch(linear_split=1, linear_lanes=4)
+            if mode == HYBRID:
+                ctx.set_launch(linear_split=1 if prec == 64 else 2, linear_lanes=4, cwenoz_reuse=1)
             Ud = to_dev(w.U, torch.float64 if prec == 64 else torch.float32)
             fs, cls = ctx.reconstruct(Ud)
             torch.cuda.synchronize()
@@ -219,3 +232,21 @@ def test_rank_deficient_stencil_is_reported(hfv):
     with pytest.raises(hfv.HfvError) as ei:
         hfv.Context(w.mesh, st2, w.params, 64)
     assert "HFV_ERR_RANK" in str(ei.value) and "cell 5" in str(ei.value)
+
+
+def test_autotune_keeps_results(hfv, c1):
+    """The autotuner applies the fastest configuration it timed, and the
+    results under it are still the oracle's."""
+    w, om = c1
+    fs_o, cls_o = om.reconstruct(w.U)
+    ctx = hfv.Context(w.mesh, w.stencils, w.params, 64)
+    Ud = to_dev(w.U, torch.float64)
+    best, recs = ctx.autotune(Ud, reps=3)
+    assert ctx.get_launch() == best
+    assert len(recs) >= 10 and all(np.isfinite(ms) and ms > 0 for _, ms in recs)
+    assert min(ms for _, ms in recs) == min(ms for cfg, ms in recs if cfg == best)
+    fs, cls = ctx.reconstruct(Ud)
+    torch.cuda.synchronize()
+    assert np.array_equal(cls.cpu().numpy(), cls_o)
+    assert states_err(fs, fs_o, om.geo, state_scale(w.U)) <= 1e-12
+    ctx.close()

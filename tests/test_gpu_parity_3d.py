@@ -66,9 +66,10 @@ def test_3d_fp64_hybrid_residual(hfv, name):
     R_o, fs_o, cls_o = flux.residual(om, U)
     print(f"{name}: N={mesh.n_cells} classes={np.bincount(cls_o, minlength=4)}", flush=True)
     assert not near_threshold(om, U, np.arange(mesh.n_cells), 1e-12).any()
-    for split in (0, 1):
+    for split in (0, 1, 2):
         ctx = hfv.Context(mesh, st, p, 64)
-        ctx.set_launch(linear_split=split, linear_lanes=4)
+        ctx.set_launch(linear_split=split, linear_lanes=5 if split == 0 else 4, cwenoz_reuse=int(split > 0),
+                       fused_residual=int(split != 1))
         fs = ctx.new_face_states()
         cls = torch.empty(mesh.n_cells, dtype=torch.uint8, device="cuda")
         R = ctx.residual(to_dev(U, torch.float64), face_states=fs, cell_class=cls)
@@ -100,7 +101,8 @@ def test_3d_fp64_forced_modes(hfv, name, mode):
     ctx.close()
 
 
-@pytest.mark.parametrize("lanes,split,lin_lanes", [(1, 0, 4), (5, 0, 4), (5, 1, 4), (5, 1, 8)])
+@pytest.mark.parametrize("lanes,split,lin_lanes", [(1, 0, 1), (5, 0, 5), (5, 1, 4), (5, 1, 8), (5, 2, 2),
+                                                    (5, 2, 4), (1, 2, 8), (1, 0, 5)])
 def test_3d_fp32_and_lane_shapes(hfv, lanes, split, lin_lanes):
     mesh, st, U, p = case("tgv10_r4")
     om = OracleModel(mesh, st, p)
@@ -108,7 +110,7 @@ def test_3d_fp32_and_lane_shapes(hfv, lanes, split, lin_lanes):
     cells = np.arange(mesh.n_cells)
     flags = near_threshold(om, U, cells, 1e-6)
     ctx = hfv.Context(mesh, st, p, 32)
-    ctx.set_launch(lanes=lanes, linear_split=split, linear_lanes=lin_lanes)
+    ctx.set_launch(lanes=lanes, linear_split=split, linear_lanes=lin_lanes, cwenoz_reuse=int(split == 2))
     fs, cls = ctx.reconstruct(to_dev(U, torch.float32))
     torch.cuda.synchronize()
     cls_g = cls.cpu().numpy()
