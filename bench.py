@@ -217,7 +217,11 @@ def main():
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the library's default launch configuration")
+    ap.add_argument("--launch", default="",
+                    help="fixed launch configuration instead of tuning, e.g. lanes_per_cell=2,linear_split=1")
     ap.add_argument("--quick", action="store_true", help="hybrid FP64 only (for profiling runs)")
+    ap.add_argument("--spinup", type=float, default=1.0,
+                    help="seconds of untimed residual evaluations before each variant (steady clocks)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -266,11 +270,26 @@ def main():
             dl = dict(default_launch)
             ctx.set_launch(lanes=dl.pop("lanes_per_cell"), **dl)
             t_tune = 0.0
-            if not args.no_tune:
+            if args.launch:
+                fixed = dict(kv.split("=") for kv in args.launch.split(","))
+                fixed = {k: int(v) for k, v in fixed.items()}
+                if "lanes_per_cell" in fixed:
+                    fixed["lanes"] = fixed.pop("lanes_per_cell")
+                ctx.set_launch(**fixed)
+            elif not args.no_tune:
                 t0 = time.perf_counter()
                 ctx.autotune(U, reps=5)
                 t_tune = time.perf_counter() - t0
             launch = ctx.get_launch()
+            # spin-up: first launches load code objects, and the clocks settle
+            # under sustained load
+            t_end = time.perf_counter() + args.spinup
+            while True:
+                for _ in range(20):
+                    ctx.residual(U, R, fs, cls)
+                torch.cuda.synchronize()
+                if time.perf_counter() >= t_end:
+                    break
             # per-kernel times of this configuration (untimed pass, all slots)
             ctx.profile_enable(16 * 8)
             for _ in range(8):

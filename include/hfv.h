@@ -201,7 +201,9 @@ hfv_status hfv_copy_table(const hfv_ctx *ctx, int32_t which, void *host_dst, int
  *                   kernels (CWENOZ, MUSCL), which split the variables: 1, 2
  *                   or 4 in 2D; 1 or 5 in 3D
  *   block           threads per block: 64, 128, 192 or 256
- *   list_blocks     cap on the resident blocks of the class-list kernels (>= 1)
+ *   list_blocks     blocks of the class-list kernels, which stride over their
+ *                   list (>= 1), or 0 for one list entry per lane group and a
+ *                   grid that covers every cell
  *   linear_split    mapping of the linear + NAD kernel: 0 = lanes split the
  *                   conserved variables, 1 = lanes split the stencil members
  *                   and Gauss points, 2 = lanes split the polynomial's
@@ -228,7 +230,7 @@ hfv_status hfv_get_launch(const hfv_ctx *ctx, hfv_launch *cfg);
 /* Autotuner (a project addition, not in the paper): times hfv_residual on the
  * caller's state U (device [nvar][n_cells]) under the current parameters for
  * candidate launch configurations, searched one coordinate at a time (linear
- * kernel mapping; class-list kernel lanes, block and resident-block cap;
+ * kernel mapping; class-list kernel lanes, block and grid;
  * CWENOZ reuse in hybrid mode; fused or two-kernel residual), and keeps the
  * fastest (median of `reps`
  * timed calls after one untimed call, reps in [1, 1000]).  Synchronous; it

@@ -201,7 +201,7 @@ hfv_status hfv_set_launch(hfv_ctx *ctx, const hfv_launch *c) {
     return ctx->err = "lanes_per_cell must be 1 or nvar (or 2 in 2D)", HFV_ERR_PARAM;
   if (c->block % 64 != 0 || c->block < 64 || c->block > 256)
     return ctx->err = "block must be 64, 128, 192 or 256", HFV_ERR_PARAM;
-  if (c->list_blocks < 1) return ctx->err = "list_blocks must be positive", HFV_ERR_PARAM;
+  if (c->list_blocks < 0) return ctx->err = "list_blocks must be >= 0", HFV_ERR_PARAM;
   if (c->linear_split < 0 || c->linear_split > 2) return ctx->err = "linear_split must be 0, 1 or 2", HFV_ERR_PARAM;
   const int ll = c->linear_lanes;
   if (c->linear_split == 0 && !(ll == 1 || ll == ctx->nvar || (ctx->dim == 2 && ll == 2)))

@@ -567,19 +567,21 @@ __global__ __launch_bounds__(256) void k_cwenoz(HotArgs<T> a, int direct) {
       for (int j = 0; j < DIM; ++j)
 #pragma unroll
         for (int q = 0; q < VPL; ++q) ad[s][j][q] = (T)0;
-      // stencils past the cell's count are padded with the cell itself and
-      // zero weights: they add exact zeros, so every row is read unguarded
+      // the guard also keeps the compiler from hoisting every stencil's loads
+      // at once, which would cost occupancy
+      if (s < nd) {
 #pragma unroll
-      for (int m = 0; m < MD; ++m) {
-        const int jc = a.t.dsten[((long)s * MD + m) * N + cell];
-        T du[VPL];
+        for (int m = 0; m < MD; ++m) {
+          const int jc = a.t.dsten[((long)s * MD + m) * N + cell];
+          T du[VPL];
 #pragma unroll
-        for (int q = 0; q < VPL; ++q) du[q] = a.U[(long)(v0 + q) * N + jc] - u0[q];
+          for (int q = 0; q < VPL; ++q) du[q] = a.U[(long)(v0 + q) * N + jc] - u0[q];
 #pragma unroll
-        for (int j = 0; j < DIM; ++j) {
-          const T p = a.t.Pdir[(((long)s * DIM + j) * MD + m) * N + cell];
+          for (int j = 0; j < DIM; ++j) {
+            const T p = a.t.Pdir[(((long)s * DIM + j) * MD + m) * N + cell];
 #pragma unroll
-          for (int q = 0; q < VPL; ++q) ad[s][j][q] += p * du[q];
+            for (int q = 0; q < VPL; ++q) ad[s][j][q] += p * du[q];
+          }
         }
       }
     }
@@ -986,7 +988,8 @@ static hfv_status recon_impl(hfv_ctx *ctx, Tables<T> &t, const void *U, void *fs
   const long items = (long)ctx->N;
   const long waves = (items + 64 / G - 1) / (64 / G);
   const unsigned grid_cells = nblk(waves * 64, B);
-  const unsigned grid_list = std::min<unsigned>(grid_cells, (unsigned)ctx->list_blocks);
+  const unsigned grid_list =
+      ctx->list_blocks > 0 ? std::min<unsigned>(grid_cells, (unsigned)ctx->list_blocks) : grid_cells;
   const int mode = ctx->p.mode;
   if (mode == HFV_ALL_CWENOZ) {
     k_zero_counts<<<1, 64, 0, s>>>(ctx->counts);
@@ -1025,7 +1028,8 @@ static hfv_status frozen_impl(hfv_ctx *ctx, Tables<T> &t, const void *U, void *f
   const int B = ctx->block;
   const long waves = ((long)ctx->N + 64 / G - 1) / (64 / G);
   const unsigned grid_cells = nblk(waves * 64, B);
-  const unsigned grid_list = std::min<unsigned>(grid_cells, (unsigned)ctx->list_blocks);
+  const unsigned grid_list =
+      ctx->list_blocks > 0 ? std::min<unsigned>(grid_cells, (unsigned)ctx->list_blocks) : grid_cells;
   launch_linear<DIM, R, T>(ctx, a, s);
   k_classify<T><<<nblk(ctx->N, CLASSIFY_BLOCK), CLASSIFY_BLOCK, 0, s>>>(a, ctx->NFM);
   k_cwenoz<DIM, R, T, G, false><<<grid_list, B, 0, s>>>(a, 0);

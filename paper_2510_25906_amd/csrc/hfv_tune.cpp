@@ -7,7 +7,8 @@
 // Search, coordinate by coordinate (each phase keeps the best of the previous):
 //   1. the linear + NAD kernel's mapping: variables (1, 2 in 2D, nvar lanes),
 //      stencil members or unknowns (2, 4, 8 lanes) per cell;
-//   2. the class-list kernels: lanes per cell x block x resident-block cap
+//   2. the class-list kernels: lanes per cell x block x grid (capped and
+//      striding, or one list entry per lane group)
 //      (skipped when no cell can reach a class list's kernels in numbers,
 //      i.e. in all-linear mode, where only first-order cells use them);
 //   3. in hybrid mode, whether CWENOZ reuses the linear pass's central fits;
@@ -121,7 +122,7 @@ extern "C" hfv_status hfv_autotune(hfv_ctx *ctx, const void *U, int32_t reps, hf
       cands.clear();
       for (int l : var_lanes)
         for (int b : {128, 256})
-          for (int lb : {4, 8, 16}) {
+          for (int lb : {0, 4, 8, 16}) {
             hfv_launch c = best;
             c.lanes_per_cell = l;
             c.block = b;

@@ -129,7 +129,7 @@ def test_c1_launch_shapes_agree(hfv, c1, lanes, split, lin_lanes, reuse):
     w, om = c1
     fs_o, cls_o = om.reconstruct(w.U)
     ctx = hfv.Context(w.mesh, w.stencils, w.params, 64)
-    ctx.set_launch(lanes=lanes, block=128, list_blocks=3, linear_split=split, linear_lanes=lin_lanes,
+    ctx.set_launch(lanes=lanes, block=128, list_blocks=0 if reuse else 3, linear_split=split, linear_lanes=lin_lanes,
                    cwenoz_reuse=reuse)
     assert ctx.get_launch()["cwenoz_reuse"] == reuse
     fs, cls = ctx.reconstruct(to_dev(w.U, torch.float64))
