@@ -128,6 +128,47 @@ __device__ inline void basis_at(const T (&xi)[DIM], const T (&psb)[n_unknowns(DI
   }
 }
 
+// The polynomial U_i + sum_k a_k (xi^alpha_k - psi_bar_k) regrouped as
+// c0 + sum_k a_k xi^alpha_k with c0 = U_i - sum_k a_k psi_bar_k, so that the
+// Gauss-point loop needs neither the basis means nor their K registers.
+template <int DIM, int R, int VPL, typename T>
+__device__ inline void poly_offset(const HotArgs<T> &a, int cell, const T (&u0)[VPL],
+                                   const T (&co)[n_unknowns(DIM, R)][VPL], T (&c0)[VPL]) {
+  constexpr int K = n_unknowns(DIM, R);
+#pragma unroll
+  for (int q = 0; q < VPL; ++q) c0[q] = u0[q];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const T pb = a.t.psibar[(long)k * a.N + cell];
+#pragma unroll
+    for (int q = 0; q < VPL; ++q) c0[q] -= co[k][q] * pb;
+  }
+}
+
+template <int DIM, int R, int VPL, typename T>
+__device__ inline void poly_at(const T (&xi)[DIM], const T (&co)[n_unknowns(DIM, R)][VPL], const T (&c0)[VPL],
+                               T (&val)[VPL]) {
+  constexpr Exps<DIM, 1, R> E{};
+  constexpr int K = n_unknowns(DIM, R);
+  T pw[DIM][R + 1];
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) {
+    pw[j][0] = (T)1;
+#pragma unroll
+    for (int p = 1; p <= R; ++p) pw[j][p] = pw[j][p - 1] * xi[j];
+  }
+#pragma unroll
+  for (int q = 0; q < VPL; ++q) val[q] = c0[q];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    T m = pw[0][E.e[k][0]];
+#pragma unroll
+    for (int j = 1; j < DIM; ++j) m *= pw[j][E.e[k][j]];
+#pragma unroll
+    for (int q = 0; q < VPL; ++q) val[q] += co[k][q] * m;
+  }
+}
+
 // a[k][q] = sum_m P[k][m] (U_{s_m} - U_i)   (Section 2.1, a = A^+ b)
 template <int DIM, int R, int VPL, typename T>
 __device__ inline void lsq_coeffs(const HotArgs<T> &a, int cell, int v0, const T (&u0)[VPL],
@@ -138,8 +179,7 @@ __device__ inline void lsq_coeffs(const HotArgs<T> &a, int cell, int v0, const T
   for (int k = 0; k < K; ++k)
 #pragma unroll
     for (int q = 0; q < VPL; ++q) co[k][q] = (T)0;
-#pragma unroll 2
-  for (int m = 0; m < M; ++m) {
+  auto member = [&](int m) {
     const int j = a.t.sten[(long)m * N + cell];
     T du[VPL];
 #pragma unroll
@@ -150,6 +190,15 @@ __device__ inline void lsq_coeffs(const HotArgs<T> &a, int cell, int v0, const T
 #pragma unroll
       for (int q = 0; q < VPL; ++q) co[k][q] += p * du[q];
     }
+  };
+  // two members in flight for small K; one for large K, whose K loads per
+  // member would otherwise exhaust the registers
+  if constexpr (K > 20) {
+#pragma unroll 1
+    for (int m = 0; m < M; ++m) member(m);
+  } else {
+#pragma unroll 2
+    for (int m = 0; m < M; ++m) member(m);
   }
 }
 

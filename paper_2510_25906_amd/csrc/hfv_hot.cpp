@@ -80,9 +80,8 @@ __global__ __launch_bounds__(256) void k_linear(HotArgs<T> a) {
   const T rho_b = all0[0];
   const T p_b = pressure<NV, T>(all0, a.gamma);
 
-  T psb[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) psb[k] = a.t.psibar[(long)k * N + cell];
+  T c0[VPL];
+  poly_offset<DIM, R, VPL, T>(a, cell, u0, co, c0);
   T exc[VPL];
 #pragma unroll
   for (int q = 0; q < VPL; ++q) exc[q] = -INFINITY;
@@ -92,17 +91,10 @@ __global__ __launch_bounds__(256) void k_linear(HotArgs<T> a) {
     T xi[DIM];
 #pragma unroll
     for (int j = 0; j < DIM; ++j) xi[j] = a.t.gpxi[((long)g * DIM + j) * N + cell];
-    T phi[K];
-    basis_at<DIM, R, T>(xi, psb, phi);
     T val[VPL];
+    poly_at<DIM, R, VPL, T>(xi, co, c0, val);
 #pragma unroll
-    for (int q = 0; q < VPL; ++q) {
-      T s = 0;
-#pragma unroll
-      for (int k = 0; k < K; ++k) s += co[k][q] * phi[k];
-      val[q] = u0[q] + s;
-      exc[q] = fmax(exc[q], fmax(mn[q] - val[q], val[q] - mx[q]));
-    }
+    for (int q = 0; q < VPL; ++q) exc[q] = fmax(exc[q], fmax(mn[q] - val[q], val[q] - mx[q]));
     T all[NV];
     group_state<NV, G, T>(val, all, L.base);
     hok = hok && harten_point<NV, T>(all, rho_b, p_b, a);
@@ -226,9 +218,8 @@ __global__ __launch_bounds__(256) void k_linear_ms(HotArgs<T> a) {
   const bool has_nb = dmax >= (T)0;
   const T rho_b = u0[0];
   const T p_b = pressure<NV, T>(u0, a.gamma);
-  T psb[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) psb[k] = a.t.psibar[(long)k * N + cell];
+  T c0[NV];
+  poly_offset<DIM, R, NV, T>(a, cell, u0, co, c0);
   T exc[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) exc[v] = -INFINITY;
@@ -238,15 +229,10 @@ __global__ __launch_bounds__(256) void k_linear_ms(HotArgs<T> a) {
     T xi[DIM];
 #pragma unroll
     for (int j = 0; j < DIM; ++j) xi[j] = a.t.gpxi[((long)g * DIM + j) * N + cell];
-    T phi[K];
-    basis_at<DIM, R, T>(xi, psb, phi);
     T val[NV];
+    poly_at<DIM, R, NV, T>(xi, co, c0, val);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      T s = 0;
-#pragma unroll
-      for (int k = 0; k < K; ++k) s += co[k][v] * phi[k];
-      val[v] = u0[v] + s;
       exc[v] = fmax(exc[v], fmax(mn[v] - val[v], val[v] - mx[v]));
     }
     hok = hok && harten_point<NV, T>(val, rho_b, p_b, a);
@@ -362,11 +348,23 @@ __global__ __launch_bounds__(256) void k_linear_ks(HotArgs<T> a) {
   const bool has_nb = dmax >= (T)0;
   const T rho_b = u0[0];
   const T p_b = pressure<NV, T>(u0, a.gamma);
-  T psb[KPL];
+  // In FP64 this lane's share of sum_k a_k psi_bar_k leaves the Gauss-point
+  // loop (raw monomials there, fewer live registers); in FP32 keeping the
+  // basis means measured faster.
+  constexpr bool FOLD = sizeof(T) == 8;
+  T off[NV], psb[KPL];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) off[v] = (T)0;
 #pragma unroll
   for (int j = 0; j < KPL; ++j) {
     const int k = q + j * G;
-    psb[j] = (k < K) ? a.t.psibar[(long)k * N + cell] : (T)0;
+    const T pb = (k < K) ? a.t.psibar[(long)k * N + cell] : (T)0;
+    if constexpr (FOLD) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) off[v] += co[j][v] * pb;
+    } else {
+      psb[j] = pb;
+    }
   }
   T exc[NV];
 #pragma unroll
@@ -387,7 +385,7 @@ __global__ __launch_bounds__(256) void k_linear_ks(HotArgs<T> a) {
         for (int p = 1; p <= R; ++p) pw[j][p] = pw[j][p - 1] * x;
       }
 #pragma unroll
-      for (int v = 0; v < NV; ++v) part[t][v] = (T)0;
+      for (int v = 0; v < NV; ++v) part[t][v] = FOLD ? -off[v] : (T)0;
 #pragma unroll
       for (int j = 0; j < KPL; ++j) {
         // this lane's unknown k = q + j G: pick its monomial among the G candidates
@@ -402,9 +400,9 @@ __global__ __launch_bounds__(256) void k_linear_ks(HotArgs<T> a) {
             mono = (q == s) ? m : mono;
           }
         }
-        const T phi = mono - psb[j];
+        if constexpr (!FOLD) mono -= psb[j];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) part[t][v] += co[j][v] * phi;
+        for (int v = 0; v < NV; ++v) part[t][v] += co[j][v] * mono;
       }
     }
     // reduce-scatter: halve the batch at each step, keeping the half picked by this lane's bit
@@ -626,6 +624,9 @@ __global__ __launch_bounds__(256) void k_cwenoz(HotArgs<T> a, int direct) {
           }
         }
         si1 += ck * row;
+        // large K in FP64: keep each row's loads from being hoisted over the
+        // others (measured: spills otherwise; FP32 is faster without)
+        if constexpr (K > 20 && sizeof(T) == 8) __builtin_amdgcn_sched_barrier(0);
       }
       double tau = 0;
 #pragma unroll

@@ -47,6 +47,39 @@ def states_err(fs_gpu, fs_o, geo, S, cells=None):
     return rel_err(gpu_cell_values(fs_gpu, geo, cells), oracle_cell_values(fs_o, geo, cells), S[None, None, :])
 
 
+def near_riemann_branch(om, fs_o, stencils, tol):
+    """Cells whose gradient can see a Riemann-solver branch point: the two cells
+    of every face with a Gauss point where |S_L|, |S_R| or (HLLC) |S*| is
+    within tol * max sound speed of zero, and every cell in their central
+    stencils.  The flux Jacobian jumps there, so a state rounding can switch
+    the branch the adjoint differentiates."""
+    g = om.p.gamma
+    geo = om.geo
+    nrm = np.repeat(geo.normal, np.diff(geo.gp_off), axis=0)
+
+    def prim(q):
+        r = q[:, 0]
+        v = q[:, 1:-1] / r[:, None]
+        return r, v, (g - 1) * (q[:, -1] - 0.5 * r * (v ** 2).sum(1))
+    rL, vL, pL = prim(fs_o[0].T)
+    rR, vR, pR = prim(fs_o[1].T)
+    unL, unR = (vL * nrm).sum(1), (vR * nrm).sum(1)
+    cL, cR = np.sqrt(g * pL / rL), np.sqrt(g * pR / rR)
+    SL, SR = np.minimum(unL - cL, unR - cR), np.maximum(unL + cL, unR + cR)
+    near = np.minimum(np.abs(SL), np.abs(SR))
+    if om.p.riemann == 0:  # HLLC contact speed
+        Ss = (pR - pL + rL * unL * (SL - unL) - rR * unR * (SR - unR)) / (rL * (SL - unL) - rR * (SR - unR))
+        near = np.minimum(near, np.abs(Ss))
+    thr = tol * max(cL.max(), cR.max())
+    faces = np.nonzero(np.minimum.reduceat(near, geo.gp_off[:-1]) <= thr)[0]
+    cells = np.unique(om.mesh.face_cells[faces].ravel())
+    cells = cells[cells >= 0]
+    out = np.zeros(om.mesh.n_cells, bool)
+    out[cells] = True
+    out[stencils.central[cells].ravel()] = True
+    return out
+
+
 def near_threshold(om, U, cells, tol):
     """Cells whose class decision lies within ``tol`` (relative) of a threshold.
 
