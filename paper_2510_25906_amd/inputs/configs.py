@@ -11,7 +11,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from .mesh import Mesh, quad_tri_2d, hex_3d
+from .mesh import Mesh, quad_tri_2d, hex_3d, mixed_box
 from .stencil import Stencils, build_stencils, build_stencils_periodic_hex
 from . import fields
 from .params import Params
@@ -58,12 +58,12 @@ def _load(path):
     return mesh, st
 
 
-def mesh_and_stencils(key, make_mesh, r):
+def mesh_and_stencils(key, make_mesh, r, workers=1):
     path = _cache_path(key)
     if path and os.path.exists(path):
         return _load(path)
     mesh = make_mesh()
-    st = build_stencils(mesh, r)
+    st = build_stencils(mesh, r, workers=workers)
     if path:
         _save(path, mesh, st)
     return mesh, st
@@ -126,3 +126,27 @@ CONFIGS = {
     "c3": lambda: tgv_hex(64, 4),
     "c5": lambda: tgv_hex(64, 2),
 }
+
+
+# Mixed-mesh sizes: (nx, ny, nz, core x-range, prism layers).  "full" is the
+# ~1M-cell shock-vortex workload; the smaller ones have the same layout.
+C4_SIZES = {"small": (24, 8, 8, (8, 16), 2), "medium": (60, 20, 20, (24, 36), 3),
+            "full": (160, 56, 56, (64, 96), 8)}
+
+
+def c4_mixed(size="small", r=3, workers=1) -> Workload:
+    """3D Euler on the mixed tetrahedron / prism / pyramid / hexahedron box of
+    ``mixed_box`` (tetrahedral core with a prism layer on the wall z = 0,
+    pyramid-and-tetrahedron transition columns, hexahedral far field): a
+    Mach-3 normal shock in the middle of the core and three Gaussian vortices,
+    HLLC, r = 3."""
+    nx, ny, nz, core, kb = C4_SIZES[size]
+    h = 1.0 / ny
+    length = nx * h
+    x_shock = 0.5 * (core[0] + core[1]) * h + 0.37 * h   # inside a cube layer, not on a lattice plane
+    mesh, st = mesh_and_stencils(f"c4_{size}_r{r}",
+                                 lambda: mixed_box(nx, ny, nz, core=core, prism_layers=kb, jitter=0.2, seed=0),
+                                 r, workers=workers)
+    U = fields.cell_average(mesh, lambda p: fields.prim_to_cons(fields.shock_vortices_prim(p, length, x_shock)),
+                            nq=4)
+    return Workload(f"c4_mixed_{size}_r{r}", mesh, st, U, Params(order_r=r, riemann=0))

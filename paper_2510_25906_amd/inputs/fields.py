@@ -219,6 +219,37 @@ def rankine_hugoniot(mach, gamma=GAMMA, rho1=1.0, p1=1.0):
     return rho2, u2, p2
 
 
+# Three smooth vortices (axis along z) for the shock-vortex workload: centre
+# (x, y) as fractions of the box, radius and peak speed in units of the
+# upstream sound speed.
+SHOCK_VORTICES = ((0.25, 0.35, 0.08, 0.3), (0.55, 0.60, 0.08, 0.3), (0.80, 0.40, 0.08, 0.3))
+
+
+def shock_vortices_prim(pts, length, x_shock, mach=3.0, gamma=GAMMA, vortices=SHOCK_VORTICES, ambient=0.1):
+    """A planar normal shock moving in +x at Mach ``mach`` into gas at rest
+    (rho = p = 1 ahead, x > x_shock; Rankine-Hugoniot state behind it) plus
+    Gaussian vortices u_theta = s (r/R) exp((1 - r^2/R^2)/2) around z-parallel
+    axes, on the box [0, length] x [0, 1] x [0, 1]; returns (rho, u, v, w, p).
+    ``ambient`` adds smooth waves uniform in x on both sides (density factor
+    1 + a sin 2pi y sin 2pi z, transverse velocities a sin 2pi z and a sin 2pi y)
+    so that no conserved variable is constant up to rounding anywhere."""
+    x, y, z = pts[..., 0], pts[..., 1], pts[..., 2]
+    rho2, u2, p2 = rankine_hugoniot(mach, gamma)
+    behind = x < x_shock
+    rho = np.where(behind, rho2, 1.0) * (1.0 + ambient * np.sin(2 * np.pi * y) * np.sin(2 * np.pi * z))
+    p = np.where(behind, p2, 1.0)
+    u = np.where(behind, u2, 0.0)
+    v = ambient * np.sin(2 * np.pi * z)
+    w = ambient * np.sin(2 * np.pi * y)
+    c1 = np.sqrt(gamma)
+    for fx, fy, R, s in vortices:
+        dx, dy = x - fx * length, y - fy
+        g = s * c1 / R * np.exp(0.5 * (1.0 - (dx * dx + dy * dy) / (R * R)))
+        u = u - g * dy
+        v = v + g * dx
+    return np.stack([rho, u, v, w, p], -1)
+
+
 def random_polynomial(d, r, nvar, seed, scale=1.0):
     """A seeded random polynomial of total degree <= r per variable.
 

@@ -330,3 +330,124 @@ def tet_box(nx, ny, nz, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), jitter=0.0, seed
     tets[neg, 1], tets[neg, 2] = tets[neg, 2].copy(), tets[neg, 1].copy()
     canon = np.arange(vertices.shape[0], dtype=np.int64)
     return _assemble(3, vertices, np.full(tets.shape[0], TET, np.int8), tets, canon, None, name)
+
+
+# Hex faces in CELL_FACES[HEX] order and the lattice offset of the cube across each.
+_HEX_FACE_NB = [(0, 0, -1), (0, 0, 1), (0, -1, 0), (1, 0, 0), (0, 1, 0), (-1, 0, 0)]
+_HEX_CORNER = np.array([(0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 1, 0), (0, 0, 1), (1, 0, 1), (1, 1, 1), (0, 1, 1)])
+CUBE_HEX, CUBE_PRISM, CUBE_TET, CUBE_TRANSITION = 0, 1, 2, 3
+
+
+def mixed_box(nx, ny, nz, core=None, prism_layers=2, jitter=0.2, seed=0, h=None, name=""):
+    """Conforming mixed tetrahedron / prism / pyramid / hexahedron mesh of a box.
+
+    A lattice of nx x ny x nz cubes of edge h (default 1/ny) is split by
+    region: in the core x-range ``core = (i1, i2)`` the bottom
+    ``prism_layers`` cube layers become two prisms each (a boundary layer on
+    the wall z = 0) and the cubes above them six Kuhn tetrahedra each, with the
+    interior core vertices jittered (seeded); the cube columns just outside
+    the core (i1 - 1 and i2), above the prism layers, are transition cubes:
+    split around an added centre vertex into a pyramid on every face shared
+    with a hexahedron (or on the boundary) and two tetrahedra on every other
+    face; every other cube is a hexahedron.  Every split quad face is cut along
+    the diagonal from its lowest to its highest lattice corner, which is the
+    cut the Kuhn tetrahedra and the prism caps make, so all faces match.
+    Cells are numbered cube by cube in lattice order (x fastest).
+    """
+    h = 1.0 / ny if h is None else h
+    i1, i2 = core if core is not None else (nx // 3, nx - nx // 3)
+    kb = prism_layers
+    if not (1 <= i1 < i2 <= nx - 1 and 0 <= kb < nz):
+        raise ValueError("core must leave a transition column on both sides")
+    nvl = (nx + 1) * (ny + 1) * (nz + 1)
+    vid = lambda i, j, k: (k * (ny + 1) + j) * (nx + 1) + i
+    Kv, Jv, Iv = np.meshgrid(np.arange(nz + 1), np.arange(ny + 1), np.arange(nx + 1), indexing="ij")
+    verts = np.stack([Iv.ravel(), Jv.ravel(), Kv.ravel()], 1).astype(np.float64) * h
+    if jitter > 0:
+        inner = ((Iv > i1) & (Iv < i2) & (Jv > 0) & (Jv < ny) & (Kv > kb) & (Kv < nz)).ravel()
+        rng = np.random.default_rng(seed)
+        verts[inner] += jitter * h * rng.uniform(-1, 1, size=(int(inner.sum()), 3))
+    K3, J3, I3 = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    kind = np.full((nz, ny, nx), CUBE_HEX, np.int8)
+    in_core = (I3 >= i1) & (I3 < i2)
+    kind[in_core & (K3 < kb)] = CUBE_PRISM
+    kind[in_core & (K3 >= kb)] = CUBE_TET
+    kind[((I3 == i1 - 1) | (I3 == i2)) & (K3 >= kb)] = CUBE_TRANSITION
+    flat_kind = kind.ravel()
+    I, J, Kk = I3.ravel(), J3.ravel(), K3.ravel()
+    cube = np.stack([vid(I + a, J + b, Kk + c) for a, b, c in _HEX_CORNER], 1)
+    cells, ctype, owner = [], [], []
+
+    def add(kind_mask, local, t):
+        idx = np.nonzero(kind_mask)[0]
+        for loc in local:
+            cells.append(cube[idx][:, list(loc)])
+            ctype.append(np.full(idx.size, t, np.int8))
+            owner.append(idx)
+
+    add(flat_kind == CUBE_HEX, [tuple(range(8))], HEX)
+    add(flat_kind == CUBE_PRISM, [(0, 1, 2, 4, 5, 6), (0, 2, 3, 4, 6, 7)], PRISM)
+    add(flat_kind == CUBE_TET, _KUHN, TET)
+    # transition cubes: centre vertex, pyramids toward hexahedra, tetrahedra elsewhere
+    tr = np.nonzero(flat_kind == CUBE_TRANSITION)[0]
+    centre = nvl + np.arange(tr.size)
+    verts = np.concatenate([verts, verts[cube[tr]].mean(1)], 0)
+    pyr, tet, pyr_own, tet_own = [], [], [], []
+    for n_, q in enumerate(tr):
+        i, j, k = int(I[q]), int(J[q]), int(Kk[q])
+        for fl, (di, dj, dk) in zip(CELL_FACES[HEX], _HEX_FACE_NB):
+            a, b, c = i + di, j + dj, k + dk
+            outside = not (0 <= a < nx and 0 <= b < ny and 0 <= c < nz)
+            quad = outside or kind[c, b, a] in (CUBE_HEX, CUBE_PRISM)
+            loop = [int(cube[q, v]) for v in fl]
+            if quad:
+                pyr.append(loop[::-1] + [int(centre[n_])])
+                pyr_own.append(q)
+            else:
+                corner = [tuple(_HEX_CORNER[v]) for v in fl]
+                lo_ = min(range(4), key=lambda t: sum(corner[t]))
+                la, lb, lc, ld = (loop[(lo_ + t) % 4] for t in range(4))
+                for tri in ((la, lb, lc), (la, lc, ld)):
+                    tet.append(list(tri) + [int(centre[n_])])
+                    tet_own.append(q)
+    if pyr:
+        cells.append(np.array(pyr, np.int64))
+        ctype.append(np.full(len(pyr), PYR, np.int8))
+        owner.append(np.array(pyr_own))
+    if tet:
+        cells.append(np.array(tet, np.int64))
+        ctype.append(np.full(len(tet), TET, np.int8))
+        owner.append(np.array(tet_own))
+    # positive orientation of every tetrahedron
+    for c_, t_ in zip(cells, ctype):
+        if t_.size and t_[0] == TET:
+            P = verts[c_]
+            neg = np.linalg.det(P[:, 1:] - P[:, :1]) < 0
+            c_[neg, 1], c_[neg, 2] = c_[neg, 2].copy(), c_[neg, 1].copy()
+    # cube-major order, cells padded to 8 vertices (-1) and then flattened
+    own = np.concatenate(owner)
+    order = np.argsort(own, kind="stable")
+    types = np.concatenate(ctype)[order]
+    padded = np.concatenate([np.pad(c_, ((0, 0), (0, 8 - c_.shape[1])), constant_values=-1) for c_ in cells])[order]
+    counts = (padded >= 0).sum(1)
+    off = np.zeros(types.size + 1, np.int64)
+    off[1:] = np.cumsum(counts)
+    flat = padded[padded >= 0].astype(np.int64)
+    canon = np.arange(verts.shape[0], dtype=np.int64)
+    fc, fo, fv, fs = _build_faces(3, verts, types, off, flat, canon, None)
+    m = Mesh(dim=3, vertices=np.ascontiguousarray(verts, np.float64), cell_type=types,
+             cell_vtx_off=off.astype(np.int32), cell_vtx=flat.astype(np.int32), face_cells=fc,
+             face_vtx_off=fo, face_vtx=fv, face_shift=fs, period=None,
+             name=name or f"mixed{nx}x{ny}x{nz}").finalize()
+    # every unmatched face must lie on the box boundary (conformity check)
+    bnd = np.nonzero(m.face_cells[:, 1] < 0)[0]
+    first = m.vertices[m.face_vtx[m.face_vtx_off[bnd]]]
+    third = m.vertices[m.face_vtx[m.face_vtx_off[bnd] + 2]]
+    ext = np.array([nx, ny, nz]) * h
+    tol = 1e-9 * h
+    # a boundary face has all its vertices on one box plane; testing two of them suffices here
+    on = np.any(((np.abs(first) < tol) & (np.abs(third) < tol)) |
+                ((np.abs(first - ext) < tol) & (np.abs(third - ext) < tol)), axis=1)
+    if not np.all(on):
+        raise AssertionError("non-conforming mixed mesh: interior faces left unmatched")
+    return m

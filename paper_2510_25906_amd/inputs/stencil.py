@@ -115,48 +115,92 @@ def _decode(k, d):
     return s, c, sh
 
 
-def _degenerate(take, s_all, off, h, d, r, N, M):
-    """Cells whose selected centroids cannot separate the degree-r monomials."""
-    exps = [e for e in np.ndindex(*([r + 1] * d)) if 1 <= sum(e) <= r]
-    o = off[take] / h[s_all[take]][:, None]
+def _central_moments(mesh, r, cen):
+    """Per cell, the means of (x - x_c)^beta over the cell for |beta| <= r
+    (quadrature exact for these degrees), in the order of ``_moment_exps``."""
+    from .fields import cell_quadrature
+    d = mesh.dim
+    bexps = _moment_exps(d, r)
+    mom = np.zeros((mesh.n_cells, len(bexps)))
+    for t in np.unique(mesh.cell_type):
+        cells = np.nonzero(mesh.cell_type == t)[0]
+        for a in range(0, cells.size, 65536):
+            cc = cells[a:a + 65536]
+            pts, w = cell_quadrature(mesh, cc, r + 1)
+            y = pts - cen[cc][:, None, :]
+            vol = w.sum(1)
+            for i, b in enumerate(bexps):
+                mom[cc, i] = (w * np.prod(y ** np.array(b), axis=2)).sum(1) / vol
+    return mom
+
+
+def _moment_exps(d, r):
+    return [e for e in np.ndindex(*([r + 1] * d)) if sum(e) <= r]
+
+
+def _member_rows(mom, src, mem, off, h, d, r):
+    """Rows of the least-squares system in the source cell's frame: the mean of
+    xi^alpha over each member minus its mean over the source cell, xi = (x -
+    x_src) / h_src, |alpha| = 1..r, from the members' central moments."""
+    bexps = _moment_exps(d, r)
+    bidx = {b: i for i, b in enumerate(bexps)}
+    exps = [e for e in bexps if sum(e) >= 1]
+    hs = h[src]
+    rows = np.zeros(src.shape + (len(exps),))
+    for k, a in enumerate(exps):
+        acc = np.zeros(src.shape)
+        for b in np.ndindex(*[x + 1 for x in a]):
+            coef = np.prod([comb(a[j], b[j]) for j in range(d)])
+            term = coef * mom[mem, bidx[b]]
+            for j in range(d):
+                if a[j] - b[j]:
+                    term = term * off[..., j] ** (a[j] - b[j])
+            acc += term
+        rows[..., k] = (acc - mom[src, bidx[a]]) / hs ** sum(a)
+    return rows
+
+
+# condition number of the least-squares rows above which a stencil is rebuilt
+COND_MAX = 1e3
+
+
+def _row_cond(V):
+    sv = np.linalg.svd(V, compute_uv=False)
+    return sv[..., 0] / np.maximum(sv[..., -1], 1e-300)
+
+
+def _degenerate(take, s_all, c_all, off, h, d, r, N, M, mom):
+    """Cells whose selected members separate the degree-r polynomials badly:
+    the least-squares rows (member means of the monomials, from quadrature
+    moments) are rank deficient or have a condition number above COND_MAX
+    (one-sided stencils at walls, thin cell layers)."""
     order = np.argsort(s_all[take], kind="stable")
-    o = o[order].reshape(N, M, d)
-    V = np.ones((N, M, len(exps)))
-    for k, e in enumerate(exps):
-        for j in range(d):
-            V[:, :, k] *= o[:, :, j] ** e[j]
-    bad = np.zeros(N, bool)
+    t = take[order]
+    V = _member_rows(mom, s_all[t].reshape(N, M), c_all[t].reshape(N, M), off[t].reshape(N, M, d), h, d, r)
+    cond = np.zeros(N)
     for a in range(0, N, 65536):
-        sv = np.linalg.svd(V[a:a + 65536], compute_uv=False)
-        bad[a:a + 65536] = sv[:, -1] < 1e-6 * sv[:, 0]
-    return bad
+        cond[a:a + 65536] = _row_cond(V[a:a + 65536])
+    return cond > COND_MAX, cond
 
 
-def build_stencils(mesh: Mesh, r: int) -> Stencils:
+def _central_stencils(mesh, r, lo, hi, cen, h, period, adj_off, adj_dst, adj_sh, mom):
+    """Central stencils (ids, periodic images) of the source cells lo..hi-1."""
     d = mesh.dim
     N = mesh.n_cells
-    if N >= (1 << 21):
-        raise ValueError("stencil builder supports fewer than 2^21 cells")
     K = n_unknowns(r, d)
     M = 2 * K
-    Md = 2 * d
-    NF = nf_max(d)
-    cen, vol = cell_centroids(mesh)
-    h = vol ** (1.0 / d)
-    period = mesh.period if mesh.period is not None else np.zeros(d)
-    adj_off, adj_dst, adj_sh = _adjacency(mesh)
     deg = np.diff(adj_off)
-
+    n = hi - lo
     # ---- breadth-first growth over (cell, image) pairs ----------------------
-    ids = np.arange(N, dtype=np.int64)
-    visited = _encode(ids, ids, np.zeros((N, d), np.int64), d)
+    ids = np.arange(lo, hi, dtype=np.int64)
+    visited = _encode(ids, ids, np.zeros((n, d), np.int64), d)
     layer_keys = [visited]
-    layer_ids = [np.zeros(N, np.int64)]
-    front_s, front_c, front_sh = ids, ids, np.zeros((N, d), np.int64)
-    count = np.ones(N, np.int64)
+    layer_ids = [np.zeros(n, np.int64)]
+    front_s, front_c, front_sh = ids, ids, np.zeros((n, d), np.int64)
+    count = np.ones(n, np.int64)
     target = 2 * M + 1
     for layer in range(1, 64):
-        need = count[front_s] < target
+        need = count[front_s - lo] < target
         fs, fcc, fsh = front_s[need], front_c[need], front_sh[need]
         if fs.size == 0:
             break
@@ -176,13 +220,13 @@ def build_stencils(mesh: Mesh, r: int) -> Stencils:
         layer_keys.append(keys)
         layer_ids.append(np.full(keys.size, layer, np.int64))
         front_s, front_c, front_sh = _decode(keys, d)
-        count = np.bincount(_decode(visited, d)[0], minlength=N)
+        count = np.bincount(_decode(visited, d)[0] - lo, minlength=n)
     all_keys = np.concatenate(layer_keys)
     all_layer = np.concatenate(layer_ids)
     s_all, c_all, sh_all = _decode(all_keys, d)
     self_mask = (s_all == c_all) & np.all(sh_all == 0, axis=1)
     s_all, c_all, sh_all, hop = s_all[~self_mask], c_all[~self_mask], sh_all[~self_mask], all_layer[~self_mask]
-    if np.any(np.bincount(s_all, minlength=N) < M):
+    if np.any(np.bincount(s_all - lo, minlength=n) < M):
         raise ValueError("mesh too small for a central stencil of %d cells" % M)
 
     off = cen[c_all] + sh_all * period - cen[s_all]
@@ -190,7 +234,9 @@ def build_stencils(mesh: Mesh, r: int) -> Stencils:
     qoff = np.rint(off / hs * 1e6).astype(np.int64)
     qd = np.rint((off ** 2).sum(1) / hs[:, 0] ** 2 * 1e8).astype(np.int64)
     # forced face neighbours
-    fn_key = _encode(np.repeat(ids, deg), adj_dst, adj_sh, d)
+    src = np.repeat(np.arange(N), deg)
+    fsel = (src >= lo) & (src < hi)
+    fn_key = _encode(src[fsel], adj_dst[fsel], adj_sh[fsel], d)
     forced = np.isin(_encode(s_all, c_all, sh_all, d), fn_key)
 
     def select(primary):
@@ -198,7 +244,7 @@ def build_stencils(mesh: Mesh, r: int) -> Stencils:
         order = np.lexsort(tuple(sort_keys))
         s_o = s_all[order]
         first = np.searchsorted(s_o, ids)
-        rank = np.arange(s_o.size) - first[s_o]
+        rank = np.arange(s_o.size) - first[s_o - lo]
         return order[rank < M]
 
     take = select(np.zeros_like(hop))
@@ -207,38 +253,45 @@ def build_stencils(mesh: Mesh, r: int) -> Stencils:
         # layers normal to a wall): rebuild those greedily, nearest first,
         # accepting a candidate only while it adds a new direction in the space
         # of degree-r monomials of the centroid offsets, then fill by distance
-        bad = np.nonzero(_degenerate(take, s_all, off, h, d, r, N, M))[0]
+        flag, cond0 = _degenerate(take, s_all, c_all, off, h, d, r, n, M, mom)
+        bad = lo + np.nonzero(flag)[0]
         if bad.size:
             order = np.lexsort(tuple([c_all] + [qoff[:, j] for j in range(d - 1, -1, -1)]
                                      + [qd, ~forced, s_all]))
             s_o = s_all[order]
             starts = np.searchsorted(s_o, bad)
             ends = np.searchsorted(s_o, bad, side="right")
-            exps = [e for e in np.ndindex(*([r + 1] * d)) if 1 <= sum(e) <= r]
             repl = {}
+            cur = {int(c): take[s_all[take] == c] for c in bad}
             for c, a, b in zip(bad, starts, ends):
                 cand = order[a:b]
-                o = off[cand] / h[c]
-                V = np.ones((cand.size, len(exps)))
-                for k, e in enumerate(exps):
-                    for j in range(d):
-                        V[:, k] *= o[:, j] ** e[j]
-                Qb = np.zeros((0, len(exps)))
-                chosen = []
-                for t in range(cand.size):
-                    if forced[cand[t]] or Qb.shape[0] < len(exps):
-                        v = V[t] - Qb.T @ (Qb @ V[t])
-                        nv = np.linalg.norm(v)
-                        if forced[cand[t]] or nv > 1e-6 * np.linalg.norm(V[t]):
+                V = _member_rows(mom, s_all[cand], c_all[cand], off[cand], h, d, r)
+                best, best_cond = cur[int(c)], cond0[c - lo]
+                # nearest first, a candidate joins while it adds a direction of at
+                # least tau of its own norm; larger tau spreads the members
+                for tau in (0.3, 0.1, 0.03, 1e-6):
+                    Qb = np.zeros((0, V.shape[1]))
+                    chosen = []
+                    for t in range(cand.size):
+                        if forced[cand[t]] or Qb.shape[0] < V.shape[1]:
+                            v = V[t] - Qb.T @ (Qb @ V[t])
+                            nv = np.linalg.norm(v)
+                            if forced[cand[t]] or nv > tau * np.linalg.norm(V[t]):
+                                chosen.append(t)
+                                if nv > tau * np.linalg.norm(V[t]) and Qb.shape[0] < V.shape[1]:
+                                    Qb = np.vstack([Qb, v / nv])
+                    if Qb.shape[0] < V.shape[1]:
+                        continue
+                    for t in range(cand.size):
+                        if len(chosen) >= M:
+                            break
+                        if t not in chosen:
                             chosen.append(t)
-                            if nv > 1e-6 * np.linalg.norm(V[t]) and Qb.shape[0] < len(exps):
-                                Qb = np.vstack([Qb, v / nv])
-                for t in range(cand.size):
-                    if len(chosen) >= M:
-                        break
-                    if t not in chosen:
-                        chosen.append(t)
-                repl[int(c)] = cand[np.array(sorted(chosen[:M]))]
+                    sel = np.array(sorted(chosen[:M]))
+                    cnd = _row_cond(V[sel])
+                    if cnd < best_cond:
+                        best, best_cond = cand[sel], cnd
+                repl[int(c)] = best
             keep = ~np.isin(s_all[take], bad)
             take = np.concatenate([take[keep]] + [repl[int(c)] for c in bad])
             take = take[np.argsort(s_all[take], kind="stable")]
@@ -247,8 +300,52 @@ def build_stencils(mesh: Mesh, r: int) -> Stencils:
     # final nearest-first order
     sort_keys = [sel_c] + [sel_qoff[:, j] for j in range(d - 1, -1, -1)] + [sel_qd, sel_s]
     o2 = np.lexsort(tuple(sort_keys))
-    central = sel_c[o2].reshape(N, M).astype(np.int32)
-    central_shift = sel_sh[o2].reshape(N, M, d).astype(np.int8)
+    central = sel_c[o2].reshape(n, M).astype(np.int32)
+    central_shift = sel_sh[o2].reshape(n, M, d).astype(np.int8)
+    return central, central_shift
+
+
+_POOL_ARGS = None
+
+
+def _central_chunk(lo_hi):
+    lo, hi = lo_hi
+    return _central_stencils(*_POOL_ARGS[:2], lo, hi, *_POOL_ARGS[2:])
+
+
+def build_stencils(mesh: Mesh, r: int, chunk: int = 131072, workers: int = 1) -> Stencils:
+    """Stencils of every cell.  ``workers`` > 1 builds the central stencils in a
+    pool of forked processes (use only in a process that has not initialised a
+    GPU)."""
+    d = mesh.dim
+    N = mesh.n_cells
+    if N >= (1 << 21):
+        raise ValueError("stencil builder supports fewer than 2^21 cells")
+    K = n_unknowns(r, d)
+    M = 2 * K
+    Md = 2 * d
+    NF = nf_max(d)
+    cen, vol = cell_centroids(mesh)
+    h = vol ** (1.0 / d)
+    period = mesh.period if mesh.period is not None else np.zeros(d)
+    adj_off, adj_dst, adj_sh = _adjacency(mesh)
+    # central stencils source cell by source cell, in chunks (each cell's
+    # selection depends only on its own neighbourhood)
+    ranges = [(lo, min(N, lo + chunk)) for lo in range(0, N, chunk)]
+    bounded = mesh.period is None or np.any(mesh.face_cells[:, 1] < 0)
+    mom = _central_moments(mesh, r, cen) if bounded else None
+    if workers > 1 and len(ranges) > 1:
+        import multiprocessing as mp
+        global _POOL_ARGS
+        _POOL_ARGS = (mesh, r, cen, h, period, adj_off, adj_dst, adj_sh, mom)
+        with mp.get_context("fork").Pool(min(workers, len(ranges))) as pool:
+            parts = pool.map(_central_chunk, ranges)
+        _POOL_ARGS = None
+    else:
+        parts = [_central_stencils(mesh, r, lo, hi, cen, h, period, adj_off, adj_dst, adj_sh, mom)
+                 for lo, hi in ranges]
+    central = np.concatenate([p_[0] for p_ in parts])
+    central_shift = np.concatenate([p_[1] for p_ in parts])
     coff = (cen[central] + central_shift * period - cen[:, None, :])  # [N, M, d]
 
     # ---- face data per cell (in cell_face order) -----------------------------
@@ -333,7 +430,30 @@ def build_stencils(mesh: Mesh, r: int) -> Stencils:
         pri = np.where(is_fn, 0, np.where(inside, 1, np.where(half, 2, 3)))
         key = pri * 10 ** 12 + np.rint(dist2[cells] / (h[cells, None] ** 2) * 1e8).astype(np.int64)
         # stable tie-break by stencil position (which is already nearest-first and deterministic)
-        o = np.argsort(key, axis=1, kind="stable")[:, :Md]
+        full = np.argsort(key, axis=1, kind="stable")
+        o = full[:, :Md]
+        # a degree-1 fit needs members spanning d directions; where the first Md
+        # do not (e.g. the wall face of a prism layer, whose nearest cells share
+        # one plane), take members in the same order, accepting one only while it
+        # adds a direction, then fill in that order
+        Po = np.take_along_axis(P, o[:, :, None], axis=1)
+        sv = np.linalg.svd(Po, compute_uv=False)
+        for i in np.nonzero(sv[:, -1] <= 1e-6 * sv[:, 0])[0]:
+            basis, chosen = [], []
+            for t in full[i]:
+                v = P[i, t].copy()
+                for b in basis:
+                    v -= (v @ b) * b
+                nv_ = np.linalg.norm(v)
+                if len(basis) < d and nv_ > 1e-6 * np.linalg.norm(P[i, t]):
+                    basis.append(v / nv_)
+                    chosen.append(t)
+            for t in full[i]:
+                if len(chosen) >= Md:
+                    break
+                if t not in chosen:
+                    chosen.append(t)
+            o[i] = np.array(sorted(chosen[:Md], key=lambda t: list(full[i]).index(t)))
         dir_pos[cells, k] = o
     rows = np.arange(N)[:, None, None]
     dir_ids = central[rows, dir_pos].astype(np.int32)

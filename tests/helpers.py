@@ -84,17 +84,30 @@ def near_threshold(om, U, cells, tol):
     """Cells whose class decision lies within ``tol`` (relative) of a threshold.
 
     NAD: |d - delta_w| or |d - delta_m| within tol * S with S = max(|m|, |M|, R)
-    for a variable whose stencil range is non-zero; deactivation:
-    |dU - (kappa h)^n| within tol * max(dU, (kappa h)^n); Harten: any point of
-    the linear candidate within tol of its bound.
+    for a variable whose stencil range is non-zero, when the higher of the two
+    classes at that tie exceeds the class the other variables give (the cell
+    takes the maximum over variables), in a cell that is not deactivated (a
+    deactivated cell is linear whatever the NAD says);
+    deactivation: |dU - (kappa h)^n| within tol * max(dU, (kappa h)^n); Harten:
+    any point of the linear candidate within tol of its bound.
     """
     own, info = om.own_class(cells, U)
     S = np.maximum(np.maximum(np.abs(info["m"]), np.abs(info["M"])), info["R"])
     live = info["R"] > 0
     dv = info["dv"]
-    nad = live & ((np.abs(dv - info["wmarg"]) <= tol * S) | (np.abs(dv - info["dmarg"]) <= tol * S))
-    flag = nad.any(1)
-    flag |= np.abs(info["dU"] - info["thr"]) <= tol * np.maximum(info["dU"], info["thr"])
+    wm, dm = info["wmarg"], info["dmarg"]
+    cv = np.where(~live | (dv <= wm), 0, np.where(dv >= dm, 2, 1))      # per-variable class
+    tie_w = live & (np.abs(dv - wm) <= tol * S)
+    tie_m = live & (np.abs(dv - dm) <= tol * S)
+    hi = np.where(tie_m, 2, np.where(dv >= dm, 2, 1))                    # higher class at the tie
+    nv = cv.shape[1]
+    others = np.stack([np.delete(cv, v, axis=1).max(1) if nv > 1 else np.zeros(len(cv), int)
+                       for v in range(nv)], 1)
+    nad = (tie_w | tie_m) & (others < hi)
+    deact_near = np.abs(info["dU"] - info["thr"]) <= tol * np.maximum(info["dU"], info["thr"])
+    deactivated = (info["dU"] < info["thr"]) & ~deact_near
+    flag = nad.any(1) & ~deactivated
+    flag |= deact_near
     _, fv, _ = om.linear(cells, U)
     g = om.p.gamma
     ngp = om.geo.c_ngp[cells]

@@ -1,0 +1,133 @@
+"""GPU path against the FP64 oracle on the mixed tetrahedron / prism / pyramid /
+hexahedron box with a Mach-3 shock and three vortices, r = 3: the 4,488-cell
+layout in full, with every launch mapping, and cells sampled from the
+51,772-cell layout of the same recipe."""
+import numpy as np
+import pytest
+
+from helpers import state_scale, rel_err, near_threshold, gpu_cell_values, states_err
+from oracle import OracleModel, flux
+from paper_2510_25906_amd.inputs import configs
+from paper_2510_25906_amd.inputs.mesh import TET, PYR, PRISM, HEX
+from paper_2510_25906_amd.inputs.params import HYBRID, ALL_CWENOZ, ALL_MUSCL
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def hfv():
+    from paper_2510_25906_amd import hfv as H
+    H.load()
+    assert torch.cuda.is_available()
+    return H
+
+
+@pytest.fixture(scope="module")
+def small():
+    w = configs.c4_mixed("small")
+    assert set(np.unique(w.mesh.cell_type)) == {TET, PYR, PRISM, HEX}
+    om = OracleModel(w.mesh, w.stencils, w.params)
+    return w, om
+
+
+def to_dev(U, dtype):
+    return torch.tensor(np.ascontiguousarray(U.T), dtype=dtype, device="cuda")
+
+
+def dilated(om, flags):
+    nb = om.nbr
+    return flags | np.array([flags[nb[c][nb[c] >= 0]].any() for c in range(len(flags))])
+
+
+@pytest.mark.parametrize("split,lanes,reuse", [(0, 5, 0), (0, 1, 1), (1, 4, 0), (2, 2, 1), (2, 4, 0)])
+def test_c4_small_fp64_hybrid(hfv, small, split, lanes, reuse):
+    w, om = small
+    R_o, fs_o, cls_o = flux.residual(om, w.U)
+    counts = np.bincount(cls_o, minlength=4)
+    print(f"c4 small: N={w.mesh.n_cells} classes={counts}", flush=True)
+    assert counts[1] > 0 and counts[2] > 0
+    assert not near_threshold(om, w.U, np.arange(w.mesh.n_cells), 1e-12).any()
+    ctx = hfv.Context(w.mesh, w.stencils, w.params, 64)
+    ctx.set_launch(linear_split=split, linear_lanes=lanes, cwenoz_reuse=reuse, list_blocks=0 if reuse else 64)
+    fs = ctx.new_face_states()
+    cls = torch.empty(w.mesh.n_cells, dtype=torch.uint8, device="cuda")
+    R = ctx.residual(to_dev(w.U, torch.float64), face_states=fs, cell_class=cls)
+    torch.cuda.synchronize()
+    cls_g = cls.cpu().numpy()
+    assert np.array_equal(cls_g, cls_o), np.nonzero(cls_g != cls_o)[0][:20]
+    S = state_scale(w.U)
+    es = states_err(fs, fs_o, om.geo, S)
+    er = rel_err(R.cpu().numpy(), R_o, np.abs(R_o).max(1)[:, None])
+    print(f"state error {es:.2e}, residual error {er:.2e}", flush=True)
+    assert es <= 1e-12 and er <= 1e-11
+    ctx.close()
+
+
+@pytest.mark.parametrize("mode", [ALL_CWENOZ, ALL_MUSCL])
+def test_c4_small_fp64_forced_modes(hfv, small, mode):
+    w, om0 = small
+    p = w.params.with_(scheme_mode=mode)
+    om = OracleModel(w.mesh, w.stencils, p)
+    om._tab = om0._tab
+    R_o, fs_o, cls_o = flux.residual(om, w.U)
+    ctx = hfv.Context(w.mesh, w.stencils, p, 64)
+    fs = ctx.new_face_states()
+    cls = torch.empty(w.mesh.n_cells, dtype=torch.uint8, device="cuda")
+    R = ctx.residual(to_dev(w.U, torch.float64), face_states=fs, cell_class=cls)
+    torch.cuda.synchronize()
+    assert np.array_equal(cls.cpu().numpy(), cls_o)
+    S = state_scale(w.U)
+    es = states_err(fs, fs_o, om.geo, S)
+    er = rel_err(R.cpu().numpy(), R_o, np.abs(R_o).max(1)[:, None])
+    print(f"state error {es:.2e}, residual error {er:.2e}", flush=True)
+    assert es <= 1e-12 and er <= 1e-11
+    ctx.close()
+
+
+def test_c4_small_fp32(hfv, small):
+    w, om = small
+    fs_o, cls_o = om.reconstruct(w.U)
+    cells = np.arange(w.mesh.n_cells)
+    flags = dilated(om, near_threshold(om, w.U, cells, 1e-6))
+    ctx = hfv.Context(w.mesh, w.stencils, w.params, 32)
+    fs, cls = ctx.reconstruct(to_dev(w.U, torch.float32))
+    torch.cuda.synchronize()
+    cls_g = cls.cpu().numpy()
+    flip = cls_g != cls_o
+    print(f"fp32 flips {flip.sum()} (flagged {flags.sum()})", flush=True)
+    assert not np.any(flip & ~flags), np.nonzero(flip & ~flags)[0][:10]
+    fv_g = gpu_cell_values(fs.cpu().numpy(), om.geo, cells)
+    from helpers import oracle_cell_values
+    fv_o = oracle_cell_values(fs_o, om.geo, cells)
+    e = rel_err(fv_g[~flip], fv_o[~flip], state_scale(w.U)[None, None, :])
+    print(f"fp32 state error {e:.2e}", flush=True)
+    assert e <= 1e-5
+    ctx.close()
+
+
+def test_c4_medium_sampled(hfv):
+    """The 51,772-cell layout: sampled cells of every element type against the oracle."""
+    w = configs.c4_mixed("medium")
+    om = OracleModel(w.mesh, w.stencils, w.params)
+    rng = np.random.default_rng(11)
+    cells = np.unique(np.concatenate([rng.choice(np.nonzero(w.mesh.cell_type == t)[0], 40, replace=False)
+                                      for t in (TET, PYR, PRISM, HEX)]))
+    fv_o, cls_o = om.reconstruct_cells(cells, w.U)
+    print(f"c4 medium: N={w.mesh.n_cells} sampled classes {np.bincount(cls_o, minlength=4)}", flush=True)
+    for prec in (64, 32):
+        flags = near_threshold(om, w.U, cells, 1e-12 if prec == 64 else 1e-6)
+        ctx = hfv.Context(w.mesh, w.stencils, w.params, prec)
+        fs, cls = ctx.reconstruct(to_dev(w.U, torch.float64 if prec == 64 else torch.float32))
+        torch.cuda.synchronize()
+        cls_g = cls.cpu().numpy()[cells]
+        flip = cls_g != cls_o
+        if prec == 64:
+            assert not flip.any(), cells[flip][:10]
+        else:
+            assert not np.any(flip & ~flags)
+        fv_g = gpu_cell_values(fs.cpu().numpy(), om.geo, cells)
+        e = rel_err(fv_g[~flip], fv_o[~flip], state_scale(w.U)[None, None, :])
+        print(f"fp{prec} sampled state error {e:.2e}", flush=True)
+        assert e <= (1e-12 if prec == 64 else 1e-5)
+        ctx.close()

@@ -5,7 +5,7 @@ import pytest
 from oracle import OracleModel, flux
 from oracle.reconstruction import monomials, LIN, CW, MU, FO
 from paper_2510_25906_amd.inputs import configs, fields
-from paper_2510_25906_amd.inputs.mesh import quad_tri_2d, hex_3d
+from paper_2510_25906_amd.inputs.mesh import quad_tri_2d, hex_3d, mixed_box, TET, PYR, PRISM, HEX
 from paper_2510_25906_amd.inputs.stencil import build_stencils
 from paper_2510_25906_amd.inputs.params import Params, preset, ALL_CWENOZ, ALL_MUSCL, ALL_LINEAR
 
@@ -23,12 +23,17 @@ def interior_cells(model, margin):
     return np.nonzero(np.all((c > lo + margin * span) & (c < hi - margin * span), axis=1))[0]
 
 
-@pytest.mark.parametrize("case", [("mixed2d", 2), ("mixed2d", 3), ("hex3d", 2), ("hex3d", 3)])
+@pytest.mark.parametrize("case", [("mixed2d", 2), ("mixed2d", 3), ("hex3d", 2), ("hex3d", 3), ("mixed3d", 2),
+                                  ("mixed3d", 3)])
 def test_polynomial_exactness(case):
-    """Cell averages of a degree-r polynomial reproduce it exactly at the face points."""
+    """Cell averages of a degree-r polynomial reproduce it exactly at the face points
+    (the mixed 3D box has tetrahedra, pyramids, prisms and hexahedra)."""
     kind, r = case
     if kind == "mixed2d":
         mesh = mixed_2d(12)
+    elif kind == "mixed3d":
+        mesh = mixed_box(10, 5, 5, core=(3, 7), prism_layers=2, jitter=0.2, seed=0)
+        assert set(np.unique(mesh.cell_type)) == {TET, PYR, PRISM, HEX}
     else:
         mesh = hex_3d(7, 7, 7, lo=(-1, -1, -1), hi=(1, 1, 1))
     st = build_stencils(mesh, r)
@@ -202,6 +207,18 @@ def test_free_stream_preservation():
     assert np.all(cls == LIN)
     assert np.allclose(fs, U[0][None, :, None], rtol=0, atol=1e-13)
     assert np.abs(R).max() < 1e-12
+
+
+def test_free_stream_on_mixed_3d_box():
+    """A uniform state gives zero residual on every element type: each cell's
+    face normals weighted by area close (including pyramid apex faces and
+    prism sides), and the transmissive boundary ghost equals the state."""
+    w = configs.c4_mixed("small")
+    U = np.tile(fields.prim_to_cons(np.array([1.3, 0.4, -0.2, 0.3, 2.0])), (w.mesh.n_cells, 1))
+    om = OracleModel(w.mesh, w.stencils, w.params)
+    R, fs, cls = flux.residual(om, U)
+    assert np.all(cls == LIN)
+    assert np.abs(R).max() < 1e-11
 
 
 def test_conservation_telescopes_on_periodic_mesh():
