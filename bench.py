@@ -9,12 +9,15 @@ face fluxes and residual.  Inputs are resident in HBM before the timed region.
 
 Before timing, each (precision, scheme mode) pair is autotuned on the same
 state (the library's hfv_autotune), and the chosen launch configuration is
-reported.  Prints one JSON line: `value` is the hybrid FP64 residual
-throughput in cells/s; `modes` holds cells reconstructed/s, residual
-evaluations/s, the fraction of the HBM roofline of the reconstruction and of
-the residual, and per-kernel times, for hybrid, all-CWENOZ and all-linear in
-FP64 and FP32.  `roofline` is the live measurement of the kernel that takes
-the most time in the hybrid FP64 residual.
+reported.  Prints one JSON line: `value` is the hybrid residual throughput
+in cells/s at the workload's headline precision (FP64 for the 2D mixed mesh
+and the r = 2 hexahedral case, FP32 for the r = 4 hexahedral case and the
+mixed tetrahedron / prism / hexahedron box, as their configurations state);
+`modes` holds cells reconstructed/s, residual evaluations/s, the fraction of
+the HBM roofline of the reconstruction and of the residual, and per-kernel
+times, for hybrid, all-CWENOZ and all-linear in FP64 and FP32.  `roofline` is
+the live measurement of the kernel that takes the most time in the headline
+hybrid residual.  Progress goes to stderr.
 """
 from __future__ import annotations
 
@@ -195,18 +198,26 @@ def cpu_baseline(w, cells_target=None):
 
 WORKLOADS = {
     "c2": ("2D Euler, 256x256 quads with seeded 30% split into triangles (85,197 cells), r=3 (4th order), "
-           "four-quadrant Riemann data + 1% noise, HLL; hybrid residual", "mixed2d_85k_r3"),
+           "four-quadrant Riemann data + 1% noise, HLL; hybrid residual", "mixed2d_85k_r3", 64),
     "c3": ("3D Euler, periodic 64^3 hexahedra (262,144 cells), r=4 (5th order), Taylor-Green vortex at "
-           "Mach 1.25 with seeded perturbation, HLLC; hybrid residual", "hex64_r4"),
+           "Mach 1.25 with seeded perturbation, HLLC; hybrid residual", "hex64_r4", 32),
+    "c4": ("3D Euler, mixed box of 569,024 tetrahedra, 5,792 pyramids, 28,672 prisms (wall layer) and "
+           "396,032 hexahedra (999,520 cells), r=3 (4th order), Mach-3 normal shock with Rankine-Hugoniot "
+           "states and three Gaussian vortices, HLLC; hybrid residual", "mixed3d_1m_r3", 32),
     "c5": ("3D Euler, periodic 64^3 hexahedra (262,144 cells), r=2, Taylor-Green vortex at Mach 1.25 with "
-           "seeded perturbation, HLLC; hybrid residual", "hex64_r2"),
+           "seeded perturbation, HLLC; hybrid residual", "hex64_r2", 64),
 }
 
 
-def make_workload(name):
+def make_workload(name, workers):
     from paper_2510_25906_amd.inputs import configs
     return {"c2": lambda: configs.c2_riemann(256, 3), "c3": lambda: configs.tgv_hex(64, 4),
+            "c4": lambda: configs.c4_mixed("full", workers=workers),
             "c5": lambda: configs.tgv_hex(64, 2)}[name]()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def main():
@@ -219,7 +230,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the library's default launch configuration")
     ap.add_argument("--launch", default="",
                     help="fixed launch configuration instead of tuning, e.g. lanes_per_cell=2,linear_split=1")
-    ap.add_argument("--quick", action="store_true", help="hybrid FP64 only (for profiling runs)")
+    ap.add_argument("--quick", action="store_true", help="headline hybrid variant only (for profiling runs)")
     ap.add_argument("--spinup", type=float, default=1.0,
                     help="seconds of untimed residual evaluations before each variant (steady clocks)")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -229,6 +240,13 @@ def main():
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU sharding of the mesh "
                                    "is described in the design notes but not built", "n_gpus": args.gpus}))
         sys.exit(2)
+
+    # inputs first: the mixed-mesh generator forks worker processes, which must
+    # happen before this process touches the GPU
+    t0 = time.perf_counter()
+    w = make_workload(args.workload, workers=max(1, min(16, os.cpu_count() or 1)))
+    wl_text, wl_tag, head_prec = WORKLOADS[args.workload]
+    log(f"workload {args.workload}: {w.mesh.n_cells} cells, built in {time.perf_counter() - t0:.1f} s")
 
     import torch
     from paper_2510_25906_amd import hfv
@@ -242,12 +260,10 @@ def main():
         y.copy_(x)
         torch.cuda.synchronize()
         del x, y
-    w = make_workload(args.workload)
-    wl_text, wl_tag = WORKLOADS[args.workload]
     mesh = w.mesh
     N = mesh.n_cells
     names = {HYBRID: "hybrid", ALL_CWENOZ: "cwenoz", ALL_LINEAR: "linear"}
-    variants = [(64, HYBRID)] if args.quick else [(p, m) for p in (64, 32) for m in (HYBRID, ALL_CWENOZ, ALL_LINEAR)]
+    variants = [(head_prec, HYBRID)] if args.quick else [(p, m) for p in (64, 32) for m in (HYBRID, ALL_CWENOZ, ALL_LINEAR)]
 
     modes, headline, roof, classes = {}, None, None, None
     for prec in sorted(set(p for p, _ in variants), reverse=True):
@@ -281,6 +297,7 @@ def main():
                 ctx.autotune(U, reps=5)
                 t_tune = time.perf_counter() - t0
             launch = ctx.get_launch()
+            log(f"FP{prec} {name}: setup {t_setup:.1f} s, tuned in {t_tune:.1f} s")
             # spin-up: first launches load code objects, and the clocks settle
             # under sustained load
             t_end = time.perf_counter() + args.spinup
@@ -299,7 +316,7 @@ def main():
             ctx.profile_enable(0)
             dominant = max(kern, key=kern.get)
             ms_rec = time_steps(lambda: ctx.reconstruct(U, fs, cls), args.steps, args.warmup, torch)
-            live = prec == 64 and mode == HYBRID
+            live = prec == head_prec and mode == HYBRID
             if live:  # the dominant kernel timed with HIP events on its stream, inside the timed region
                 ctx.profile_enable(args.steps * 2, slots=[dominant])
             ms_res = time_steps(lambda: ctx.residual(U, R, fs, cls), args.steps, 0 if live else args.warmup, torch)
@@ -354,9 +371,9 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": f"f{head_prec}",
         "data": "synthetic",
-        "config": {"workload": wl_text, "n_cells": N, "order_r": w.params.order_r, "precision": "fp64",
+        "config": {"workload": wl_text, "n_cells": N, "order_r": w.params.order_r, "precision": f"fp{head_prec}",
                    "class_fractions": [round(x / N, 4) for x in classes] if classes is not None else None},
         "roofline": roof,
         "modes": modes,

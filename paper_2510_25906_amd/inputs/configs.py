@@ -148,5 +148,5 @@ def c4_mixed(size="small", r=3, workers=1) -> Workload:
                                  lambda: mixed_box(nx, ny, nz, core=core, prism_layers=kb, jitter=0.2, seed=0),
                                  r, workers=workers)
     U = fields.cell_average(mesh, lambda p: fields.prim_to_cons(fields.shock_vortices_prim(p, length, x_shock)),
-                            nq=4)
+                            nq=4, workers=workers)
     return Workload(f"c4_mixed_{size}_r{r}", mesh, st, U, Params(order_r=r, riemann=0))

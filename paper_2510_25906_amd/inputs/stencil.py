@@ -29,6 +29,7 @@ from math import comb
 
 import numpy as np
 
+from . import pool
 from .mesh import Mesh, simplex_decomposition, TYPE_NVTX, CELL_FACES
 
 
@@ -115,22 +116,38 @@ def _decode(k, d):
     return s, c, sh
 
 
-def _central_moments(mesh, r, cen):
+def _moment_block(item):
+    from .fields import cell_quadrature
+    mesh, r, cen = pool.SHARED
+    cc = item
+    d = mesh.dim
+    pts, w = cell_quadrature(mesh, cc, r + 1)
+    y = pts - cen[cc][:, None, :]
+    vol = w.sum(1)
+    ypow = [[np.ones_like(y[..., j])] for j in range(d)]
+    for j in range(d):
+        for _ in range(r):
+            ypow[j].append(ypow[j][-1] * y[..., j])
+    out = np.zeros((cc.size, len(_moment_exps(d, r))))
+    for i, b in enumerate(_moment_exps(d, r)):
+        term = w * ypow[0][b[0]]
+        for j in range(1, d):
+            term = term * ypow[j][b[j]]
+        out[:, i] = term.sum(1) / vol
+    return out
+
+
+def _central_moments(mesh, r, cen, workers=1):
     """Per cell, the means of (x - x_c)^beta over the cell for |beta| <= r
     (quadrature exact for these degrees), in the order of ``_moment_exps``."""
-    from .fields import cell_quadrature
-    d = mesh.dim
-    bexps = _moment_exps(d, r)
-    mom = np.zeros((mesh.n_cells, len(bexps)))
+    blocks = []
     for t in np.unique(mesh.cell_type):
         cells = np.nonzero(mesh.cell_type == t)[0]
-        for a in range(0, cells.size, 65536):
-            cc = cells[a:a + 65536]
-            pts, w = cell_quadrature(mesh, cc, r + 1)
-            y = pts - cen[cc][:, None, :]
-            vol = w.sum(1)
-            for i, b in enumerate(bexps):
-                mom[cc, i] = (w * np.prod(y ** np.array(b), axis=2)).sum(1) / vol
+        blocks += [cells[a:a + 32768] for a in range(0, cells.size, 32768)]
+    parts = pool.pool_map(_moment_block, blocks, workers, (mesh, r, cen))
+    mom = np.zeros((mesh.n_cells, len(_moment_exps(mesh.dim, r))))
+    for cc, m in zip(blocks, parts):
+        mom[cc] = m
     return mom
 
 
@@ -260,38 +277,57 @@ def _central_stencils(mesh, r, lo, hi, cen, h, period, adj_off, adj_dst, adj_sh,
                                      + [qd, ~forced, s_all]))
             s_o = s_all[order]
             starts = np.searchsorted(s_o, bad)
-            ends = np.searchsorted(s_o, bad, side="right")
-            repl = {}
-            cur = {int(c): take[s_all[take] == c] for c in bad}
-            for c, a, b in zip(bad, starts, ends):
-                cand = order[a:b]
-                V = _member_rows(mom, s_all[cand], c_all[cand], off[cand], h, d, r)
-                best, best_cond = cur[int(c)], cond0[c - lo]
-                # nearest first, a candidate joins while it adds a direction of at
-                # least tau of its own norm; larger tau spreads the members
-                for tau in (0.3, 0.1, 0.03, 1e-6):
-                    Qb = np.zeros((0, V.shape[1]))
-                    chosen = []
-                    for t in range(cand.size):
-                        if forced[cand[t]] or Qb.shape[0] < V.shape[1]:
-                            v = V[t] - Qb.T @ (Qb @ V[t])
-                            nv = np.linalg.norm(v)
-                            if forced[cand[t]] or nv > tau * np.linalg.norm(V[t]):
-                                chosen.append(t)
-                                if nv > tau * np.linalg.norm(V[t]) and Qb.shape[0] < V.shape[1]:
-                                    Qb = np.vstack([Qb, v / nv])
-                    if Qb.shape[0] < V.shape[1]:
-                        continue
-                    for t in range(cand.size):
-                        if len(chosen) >= M:
-                            break
-                        if t not in chosen:
-                            chosen.append(t)
-                    sel = np.array(sorted(chosen[:M]))
-                    cnd = _row_cond(V[sel])
-                    if cnd < best_cond:
-                        best, best_cond = cand[sel], cnd
-                repl[int(c)] = best
+            ncand = np.searchsorted(s_o, bad, side="right") - starts
+            # candidates of every flagged cell side by side, nearest first,
+            # padded with the cell's first candidate (masked out)
+            L = int(ncand.max())
+            slot = np.arange(L)
+            valid = slot[None, :] < ncand[:, None]
+            cand = order[starts[:, None] + np.where(valid, slot[None, :], 0)]
+            fc = forced[cand] & valid
+            V = _member_rows(mom, s_all[cand], c_all[cand], off[cand], h, d, r)
+            V[~valid] = 0.0
+            nrm = np.linalg.norm(V, axis=2)
+            nb = bad.size
+            KK = V.shape[2]
+            # take is grouped by source cell, M members each
+            best = take.reshape(n, M)[bad - lo].copy()
+            best_cond = cond0[bad - lo].copy()
+            rows = np.arange(nb)
+            # nearest first, a candidate joins while it adds a direction of at
+            # least tau of its own norm (face neighbours always join); larger
+            # tau spreads the members; then fill by distance
+            for tau in (0.3, 0.1, 0.03, 1e-6):
+                Q = np.zeros((nb, KK, KK))
+                qn = np.zeros(nb, np.int64)
+                chosen = np.zeros((nb, L), bool)
+                for t in range(L):
+                    vt = V[:, t]
+                    v = vt - np.einsum("nki,nk->ni", Q, np.einsum("nki,ni->nk", Q, vt))
+                    nv = np.linalg.norm(v, axis=1)
+                    room = qn < KK
+                    new_dir = valid[:, t] & (nv > tau * nrm[:, t])
+                    chosen[:, t] = fc[:, t] | (room & new_dir)
+                    add = room & new_dir
+                    ia = rows[add]
+                    Q[ia, qn[ia]] = v[ia] / nv[ia, None]
+                    qn[ia] += 1
+                ok = qn == KK
+                n_ch = chosen.sum(1)
+                crank = np.cumsum(chosen, 1) - 1
+                urank = np.cumsum(valid & ~chosen, 1) - 1
+                sel = (chosen & (crank < M)) | (valid & ~chosen & (urank < (M - n_ch)[:, None]))
+                ok &= sel.sum(1) == M
+                if not ok.any():
+                    continue
+                io = rows[ok]
+                pick = np.nonzero(sel[io])[1].reshape(io.size, M)
+                cnd = _row_cond(V[io[:, None], pick])
+                better = cnd < best_cond[io]
+                ib = io[better]
+                best[ib] = cand[ib[:, None], pick[better]]
+                best_cond[ib] = cnd[better]
+            repl = {int(c): best[i] for i, c in enumerate(bad)}
             keep = ~np.isin(s_all[take], bad)
             take = np.concatenate([take[keep]] + [repl[int(c)] for c in bad])
             take = take[np.argsort(s_all[take], kind="stable")]
@@ -305,61 +341,38 @@ def _central_stencils(mesh, r, lo, hi, cen, h, period, adj_off, adj_dst, adj_sh,
     return central, central_shift
 
 
-_POOL_ARGS = None
-
-
-def _central_chunk(lo_hi):
+def _cell_stencils(lo_hi):
+    """Central, directional and MUSCL stencils of the source cells lo..hi-1."""
     lo, hi = lo_hi
-    return _central_stencils(*_POOL_ARGS[:2], lo, hi, *_POOL_ARGS[2:])
+    mesh, r, cen, h, period, adj_off, adj_dst, adj_sh, mom = pool.SHARED
+    central, central_shift = _central_stencils(mesh, r, lo, hi, cen, h, period, adj_off, adj_dst, adj_sh, mom)
+    return (central, central_shift) + _face_stencils(mesh, r, lo, hi, central, central_shift, cen, h, period)
 
 
-def build_stencils(mesh: Mesh, r: int, chunk: int = 131072, workers: int = 1) -> Stencils:
-    """Stencils of every cell.  ``workers`` > 1 builds the central stencils in a
-    pool of forked processes (use only in a process that has not initialised a
-    GPU)."""
+def _face_stencils(mesh, r, lo, hi, central, central_shift, cen, h, period):
+    """Directional and MUSCL stencils of the cells lo..hi-1, whose central
+    stencils (rows 0..hi-lo-1) are given."""
     d = mesh.dim
-    N = mesh.n_cells
-    if N >= (1 << 21):
-        raise ValueError("stencil builder supports fewer than 2^21 cells")
-    K = n_unknowns(r, d)
-    M = 2 * K
+    n = hi - lo
+    M = central.shape[1]
     Md = 2 * d
     NF = nf_max(d)
-    cen, vol = cell_centroids(mesh)
-    h = vol ** (1.0 / d)
-    period = mesh.period if mesh.period is not None else np.zeros(d)
-    adj_off, adj_dst, adj_sh = _adjacency(mesh)
-    # central stencils source cell by source cell, in chunks (each cell's
-    # selection depends only on its own neighbourhood)
-    ranges = [(lo, min(N, lo + chunk)) for lo in range(0, N, chunk)]
-    bounded = mesh.period is None or np.any(mesh.face_cells[:, 1] < 0)
-    mom = _central_moments(mesh, r, cen) if bounded else None
-    if workers > 1 and len(ranges) > 1:
-        import multiprocessing as mp
-        global _POOL_ARGS
-        _POOL_ARGS = (mesh, r, cen, h, period, adj_off, adj_dst, adj_sh, mom)
-        with mp.get_context("fork").Pool(min(workers, len(ranges))) as pool:
-            parts = pool.map(_central_chunk, ranges)
-        _POOL_ARGS = None
-    else:
-        parts = [_central_stencils(mesh, r, lo, hi, cen, h, period, adj_off, adj_dst, adj_sh, mom)
-                 for lo, hi in ranges]
-    central = np.concatenate([p_[0] for p_ in parts])
-    central_shift = np.concatenate([p_[1] for p_ in parts])
-    coff = (cen[central] + central_shift * period - cen[:, None, :])  # [N, M, d]
+    gid = np.arange(lo, hi)
+    coff = (cen[central] + central_shift * period - cen[gid][:, None, :])  # [n, M, d]
+    hl = h[lo:hi]
 
     # ---- face data per cell (in cell_face order) -----------------------------
-    nfc = np.diff(mesh.cell_face_off)
-    fverts_rel = np.zeros((N, NF, 4, d))   # face vertices relative to cell centroid
-    f_nverts = np.zeros((N, NF), np.int64)
-    f_valid = np.zeros((N, NF), bool)
-    f_nbr = np.full((N, NF), -1, np.int64)
-    f_nbr_sh = np.zeros((N, NF, d), np.int64)
+    nfc = np.diff(mesh.cell_face_off)[lo:hi]
+    fverts_rel = np.zeros((n, NF, 4, d))   # face vertices relative to cell centroid
+    f_nverts = np.zeros((n, NF), np.int64)
+    f_valid = np.zeros((n, NF), bool)
+    f_nbr = np.full((n, NF), -1, np.int64)
+    f_nbr_sh = np.zeros((n, NF, d), np.int64)
     for k in range(NF):
-        has = nfc > k
-        cells = np.nonzero(has)[0]
-        f = mesh.cell_face[mesh.cell_face_off[cells] + k]
-        side = mesh.cell_face_side[mesh.cell_face_off[cells] + k]
+        cells = np.nonzero(nfc > k)[0]      # local rows
+        gc = cells + lo
+        f = mesh.cell_face[mesh.cell_face_off[gc] + k]
+        side = mesh.cell_face_side[mesh.cell_face_off[gc] + k]
         f_valid[cells, k] = True
         nv = np.diff(mesh.face_vtx_off)[f]
         f_nverts[cells, k] = nv
@@ -369,7 +382,7 @@ def build_stencils(mesh: Mesh, r: int, chunk: int = 131072, workers: int = 1) ->
             pos = mesh.vertices[vv]
             # the right cell sees the face shifted back by its image
             pos = pos - (side[:, None] == 1) * mesh.face_shift[f].astype(np.float64) * period
-            fverts_rel[cells, k, j] = np.where(ok[:, None], pos - cen[cells], 0.0)
+            fverts_rel[cells, k, j] = np.where(ok[:, None], pos - cen[gc], 0.0)
         l, rr = mesh.face_cells[f, 0], mesh.face_cells[f, 1]
         nb = np.where(side == 0, rr, l)
         nsh = np.where((side == 0)[:, None], mesh.face_shift[f], -mesh.face_shift[f].astype(np.int64))
@@ -383,23 +396,23 @@ def build_stencils(mesh: Mesh, r: int, chunk: int = 131072, workers: int = 1) ->
                 fverts_rel[rc, k, :n_] = fverts_rel[rc, k, :n_][:, ::-1]
 
     # position of each face neighbour inside the central stencil
-    def member_pos(cell_ids, nb, nbsh):
-        eq = (central[cell_ids] == nb[:, None]) & np.all(central_shift[cell_ids] == nbsh[:, None, :], 2)
+    def member_pos(rows_, nb, nbsh):
+        eq = (central[rows_] == nb[:, None]) & np.all(central_shift[rows_] == nbsh[:, None, :], 2)
         pos = np.argmax(eq, 1)
         pos[~eq.any(1)] = -1
         return pos
 
     # ---- directional stencils ------------------------------------------------
-    dir_pos = np.zeros((N, NF, Md), np.int64)
+    dir_pos = np.zeros((n, NF, Md), np.int64)
     tol = 1e-9
-    dist2 = (coff ** 2).sum(2)  # [N, M]
+    dist2 = (coff ** 2).sum(2)  # [n, M]
     for k in range(NF):
         cells = np.nonzero(f_valid[:, k])[0]
         if cells.size == 0:
             continue
-        V = fverts_rel[cells, k]  # [n, 4, d]
+        V = fverts_rel[cells, k]  # [nc, 4, d]
         nv = f_nverts[cells, k]
-        P = coff[cells]           # [n, M, d]
+        P = coff[cells]           # [nc, M, d]
         inside = np.ones((cells.size, M), bool)
         if d == 2:
             a, b = V[:, 0], V[:, 1]
@@ -428,7 +441,7 @@ def build_stencils(mesh: Mesh, r: int, chunk: int = 131072, workers: int = 1) ->
         is_fn[np.nonzero(okf)[0], fpos[okf]] = True
         # priority: face neighbour, sector/cone, half-space, rest; then distance
         pri = np.where(is_fn, 0, np.where(inside, 1, np.where(half, 2, 3)))
-        key = pri * 10 ** 12 + np.rint(dist2[cells] / (h[cells, None] ** 2) * 1e8).astype(np.int64)
+        key = pri * 10 ** 12 + np.rint(dist2[cells] / (hl[cells, None] ** 2) * 1e8).astype(np.int64)
         # stable tie-break by stencil position (which is already nearest-first and deterministic)
         full = np.argsort(key, axis=1, kind="stable")
         o = full[:, :Md]
@@ -455,7 +468,7 @@ def build_stencils(mesh: Mesh, r: int, chunk: int = 131072, workers: int = 1) ->
                     chosen.append(t)
             o[i] = np.array(sorted(chosen[:Md], key=lambda t: list(full[i]).index(t)))
         dir_pos[cells, k] = o
-    rows = np.arange(N)[:, None, None]
+    rows = np.arange(n)[:, None, None]
     dir_ids = central[rows, dir_pos].astype(np.int32)
     dir_sh = central_shift[rows, dir_pos].astype(np.int8)
     n_dir = nfc.astype(np.int32)
@@ -464,9 +477,9 @@ def build_stencils(mesh: Mesh, r: int, chunk: int = 131072, workers: int = 1) ->
         dir_sh[~f_valid[:, k], k] = 0
 
     # ---- MUSCL stencils --------------------------------------------------------
-    muscl = np.full((N, NF), -1, np.int32)
-    muscl_sh = np.zeros((N, NF, d), np.int8)
-    n_muscl = np.zeros(N, np.int32)
+    muscl = np.full((n, NF), -1, np.int32)
+    muscl_sh = np.zeros((n, NF, d), np.int8)
+    n_muscl = np.zeros(n, np.int32)
     has_nb = (f_nbr >= 0) & f_valid
     # face neighbours first, in cell-face order
     rank = np.cumsum(has_nb, axis=1) - 1
@@ -486,9 +499,31 @@ def build_stencils(mesh: Mesh, r: int, chunk: int = 131072, workers: int = 1) ->
         for j, (cc, ss) in enumerate(lst):
             muscl[c, j] = cc
             muscl_sh[c, j] = ss
-    return Stencils(r=r, M=M, Md=Md, central=central, central_shift=central_shift,
-                    dir=dir_ids, dir_shift=dir_sh, n_dir=n_dir, muscl=muscl,
-                    muscl_shift=muscl_sh, n_muscl=n_muscl)
+    return dir_ids, dir_sh, n_dir, muscl, muscl_sh, n_muscl
+
+
+def build_stencils(mesh: Mesh, r: int, chunk: int = 65536, workers: int = 1) -> Stencils:
+    """Stencils of every cell, built in chunks of source cells (each cell's
+    stencils depend only on its own neighbourhood).  ``workers`` > 1 builds
+    the chunks in a pool of forked processes (use only in a process that has
+    not initialised a GPU)."""
+    d = mesh.dim
+    N = mesh.n_cells
+    if N >= (1 << 21):
+        raise ValueError("stencil builder supports fewer than 2^21 cells")
+    cen, vol = cell_centroids(mesh)
+    h = vol ** (1.0 / d)
+    period = mesh.period if mesh.period is not None else np.zeros(d)
+    adj_off, adj_dst, adj_sh = _adjacency(mesh)
+    ranges = [(lo, min(N, lo + chunk)) for lo in range(0, N, chunk)]
+    bounded = mesh.period is None or np.any(mesh.face_cells[:, 1] < 0)
+    mom = _central_moments(mesh, r, cen, workers) if bounded else None
+    parts = pool.pool_map(_cell_stencils, ranges, workers,
+                          (mesh, r, cen, h, period, adj_off, adj_dst, adj_sh, mom))
+    cat = [np.concatenate([p_[i] for p_ in parts]) for i in range(8)]
+    return Stencils(r=r, M=cat[0].shape[1], Md=2 * d, central=cat[0], central_shift=cat[1],
+                    dir=cat[2], dir_shift=cat[3], n_dir=cat[4], muscl=cat[5],
+                    muscl_shift=cat[6], n_muscl=cat[7])
 
 
 def build_stencils_periodic_hex(mesh: Mesh, dims, r: int, n_small: int = 12) -> Stencils:
