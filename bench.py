@@ -17,7 +17,14 @@ mixed tetrahedron / prism / hexahedron box, as their configurations state);
 the HBM roofline of the reconstruction and of the residual, and per-kernel
 times, for hybrid, all-CWENOZ and all-linear in FP64 and FP32.  `roofline` is
 the live measurement of the kernel that takes the most time in the headline
-hybrid residual.  Progress goes to stderr.
+hybrid residual, against the 8 TB/s peak and against the bandwidth a plain
+1 GiB device copy reaches in the same process.  Each mode also reports the
+median of single residuals started after a 1 GiB write that flushes the
+last-level cache (`ms_residual_cold`) and, on workloads whose field is
+smooth and known in closed form (the hexahedral Taylor-Green cases), the RMS
+error of its face states against the exact point values
+(`face_err_rms_rel`), the accuracy at which the modes are compared.
+Progress goes to stderr.
 """
 from __future__ import annotations
 
@@ -136,6 +143,69 @@ def time_steps(fn, steps, warmup, torch):
     return a.elapsed_time(b) / steps
 
 
+def time_cold(fn, reps, flush, torch):
+    """Median time of single steps, each started after a write over `flush`
+    (>= 1 GiB), so that none of its inputs is left in the 256 MB last-level
+    cache (MALL)."""
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    ts = []
+    for i in range(reps):
+        flush.fill_(float(i))
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    return float(np.median(ts))
+
+
+def probe_bandwidth(torch, mib=1024, reps=20):
+    """HBM bandwidth a plain device-to-device copy achieves: (read + written
+    bytes) / time, median over `reps` copies of `mib` MiB."""
+    n = mib * (1 << 20) // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    ts = []
+    for _ in range(reps):
+        a.record()
+        y.copy_(x)
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    del x, y
+    return 2.0 * n * 4 / (float(np.median(ts)) * 1e-3) / 1e9
+
+
+class FaceAccuracy:
+    """Face Gauss-point states against the exact point values of a smooth
+    workload: RMS error over every (Gauss point, cell) relative to the
+    variable's largest exact value, the largest over the variables."""
+
+    def __init__(self, ctx, w, ngp):
+        d, N = w.mesh.dim, w.mesh.n_cells
+        xi = ctx.table("GP_XI").astype(np.float64)        # [NGPC][d][N]
+        geom = ctx.table("GEOM")                          # centroid, volume, h_c
+        self.valid = np.arange(xi.shape[0])[:, None] < ngp[None, :].astype(np.int64)  # [NGPC][N]
+        ex = np.zeros((xi.shape[0], N, w.U.shape[1]))
+        for g in range(xi.shape[0]):
+            x = (geom[:d] + geom[d + 1][None, :] * xi[g]).T    # [N, d]
+            ex[g] = w.exact(x)
+        self.ex = ex.transpose(0, 2, 1)                   # [NGPC][nvar][N], like the states
+        self.scale = np.abs(self.ex).max(axis=(0, 2))
+
+    def error(self, fs):
+        f = fs.cpu().numpy().astype(np.float64)
+        m = self.valid[:, None, :]
+        e2 = np.where(m, (f - self.ex) ** 2, 0.0).sum(axis=(0, 2)) / m.sum()
+        return float((np.sqrt(e2) / self.scale).max())
+
+
 def source_hash():
     h = hashlib.sha256()
     for f in sorted(os.listdir(CSRC)):
@@ -157,12 +227,11 @@ def measured_traffic(kernel, workload):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(w, cells_target=None):
+def cpu_baseline(w, cells_target=None, min_seconds=10.0):
     """The FP64 oracle's residual on the host: tables precomputed (untimed), one
-    BLAS thread, the whole mesh (or ``cells_target`` cells) timed once."""
-    from threadpoolctl import threadpool_limits
+    BLAS thread, the whole mesh (or ``cells_target`` cells), repeated until at
+    least ``min_seconds`` of work have been timed."""
     from oracle import OracleModel
-    from oracle import flux as oflux
     om = OracleModel(w.mesh, w.stencils, w.params)
     N = w.mesh.n_cells
     n = N if cells_target is None else min(N, cells_target)
@@ -175,6 +244,19 @@ def cpu_baseline(w, cells_target=None):
     nb = om.nbr[closure].ravel()
     om.tables(np.unique(np.concatenate([closure, nb[nb >= 0]])))
     geo = om.geo
+    passes, dt = 0, 0.0
+    while dt < min_seconds:
+        dt += _oracle_pass(om, w, closure, fc, fmask, geo, n, N)
+        passes += 1
+    return dict(value=round(passes * n / dt, 1), unit="cells/s", cores=1, kind="oracle",
+                sample=f"FP64 NumPy oracle, hybrid residual of {n} of {N} cells (with their face-neighbour "
+                       f"closure), one BLAS thread, tables precomputed outside the timing, {passes} passes "
+                       f"in {dt:.1f} s")
+
+
+def _oracle_pass(om, w, closure, fc, fmask, geo, n, N):
+    from threadpoolctl import threadpool_limits
+    from oracle import flux as oflux
     with threadpool_limits(1):
         t0 = time.perf_counter()
         fv, cls = om.reconstruct_cells(closure, w.U)
@@ -189,11 +271,8 @@ def cpu_baseline(w, cells_target=None):
                 a, b = geo.gp_off[f], geo.gp_off[f + 1]
                 fs[1, :, a:b] = fs[0, :, a:b]
         Ff = oflux.face_fluxes(om, fs, w.params.riemann)
-        R = oflux.residual_from_face_fluxes(om, Ff)
-        dt = time.perf_counter() - t0
-    return dict(value=round(n / dt, 1), unit="cells/s", cores=1, kind="oracle",
-                sample=f"FP64 NumPy oracle, hybrid residual of {n} of {N} cells (with their face-neighbour "
-                       f"closure), one BLAS thread, tables precomputed outside the timing, {dt:.1f} s")
+        oflux.residual_from_face_fluxes(om, Ff)
+        return time.perf_counter() - t0
 
 
 WORKLOADS = {
@@ -233,6 +312,12 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline hybrid variant only (for profiling runs)")
     ap.add_argument("--spinup", type=float, default=1.0,
                     help="seconds of untimed residual evaluations before each variant (steady clocks)")
+    ap.add_argument("--workers", type=int, default=max(1, min(16, os.cpu_count() or 1)),
+                    help="processes for input generation (1 when a profiler has initialised the GPU "
+                         "before the program starts: the generator forks)")
+    ap.add_argument("--cold", type=int, default=10,
+                    help="also time this many single residuals, each after a 1 GiB cache-flushing write "
+                         "(0: skip)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -244,7 +329,7 @@ def main():
     # inputs first: the mixed-mesh generator forks worker processes, which must
     # happen before this process touches the GPU
     t0 = time.perf_counter()
-    w = make_workload(args.workload, workers=max(1, min(16, os.cpu_count() or 1)))
+    w = make_workload(args.workload, workers=args.workers)
     wl_text, wl_tag, head_prec = WORKLOADS[args.workload]
     log(f"workload {args.workload}: {w.mesh.n_cells} cells, built in {time.perf_counter() - t0:.1f} s")
 
@@ -260,6 +345,10 @@ def main():
         y.copy_(x)
         torch.cuda.synchronize()
         del x, y
+    probe = probe_bandwidth(torch)
+    log(f"copy probe {probe:.0f} GB/s")
+    flush = torch.empty(1 << 28, dtype=torch.float32, device="cuda") if args.cold else None
+    acc = None
     mesh = w.mesh
     N = mesh.n_cells
     names = {HYBRID: "hybrid", ALL_CWENOZ: "cwenoz", ALL_LINEAR: "linear"}
@@ -332,10 +421,17 @@ def main():
                 traffic = measured_traffic(kname, wl_tag)
                 roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
+                        "probe_copy_GBps": round(probe, 1), "frac_of_probe": round(ach / probe, 4),
                         "kernel": f"{kname} ({name}, FP{prec})",
                         "bytes_per_launch": byts[dominant], "avg_launch_ms": round(avg, 5)}
                 headline = ms_res
                 classes = np.bincount(cl_dev, minlength=4)
+            ms_cold = time_cold(lambda: ctx.residual(U, R, fs, cls), args.cold, flush, torch) if args.cold else None
+            face_err = None
+            if w.exact is not None:
+                if acc is None:
+                    acc = FaceAccuracy(ctx, w, bm.ngp)
+                face_err = acc.error(fs)
             cl = np.bincount(cl_dev, minlength=4)
             rec_b = sum(v for k, v in byts.items() if k not in ("flux", "gather"))
             modes[f"{name}_fp{prec}"] = {
@@ -351,6 +447,10 @@ def main():
                                     for k in kern if k in byts},
                 "launch": launch, "tune_s": round(t_tune, 2), "setup_s": round(t_setup, 3),
             }
+            if ms_cold is not None:
+                modes[f"{name}_fp{prec}"]["ms_residual_cold"] = round(ms_cold, 4)
+            if face_err is not None:
+                modes[f"{name}_fp{prec}"]["face_err_rms_rel"] = float(f"{face_err:.6g}")
         ctx.close()
         del U, fs, cls, R
         torch.cuda.empty_cache()

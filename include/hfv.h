@@ -190,9 +190,13 @@ hfv_status hfv_query(const hfv_ctx *ctx, int32_t what, int64_t *out);
  *   HFV_T_PMUS   [dim][nf_max][n_cells] MUSCL pseudo-inverses
  *   HFV_T_FACE_SLOTS [n_faces] int32: first Gauss-point slot of each face in
  *                its left (bits 0-7) and right (bits 8-15) cell
+ *   HFV_T_GP_XI  [ngp_cell_max][dim][n_cells] each cell's Gauss-point slots
+ *                in its own frame, xi = (x - x_c) / h_c (x_c, h_c from
+ *                HFV_T_GEOM; periodic images unwrapped), slot order as in the
+ *                face states; slots past the cell's Gauss points hold 0
  * `bytes` must equal the table size. */
 enum { HFV_T_PINV = 0, HFV_T_OI = 1, HFV_T_PSIBAR = 2, HFV_T_GEOM = 3, HFV_T_PDIR = 4, HFV_T_PMUS = 5,
-       HFV_T_FACE_SLOTS = 6 };
+       HFV_T_FACE_SLOTS = 6, HFV_T_GP_XI = 7 };
 hfv_status hfv_copy_table(const hfv_ctx *ctx, int32_t which, void *host_dst, int64_t bytes);
 
 /* Launch configuration of the hot path (results agree to rounding for every
@@ -219,10 +223,14 @@ hfv_status hfv_copy_table(const hfv_ctx *ctx, int32_t which, void *host_dst, int
  *                   cell's faces and sums them (each interior face's flux is
  *                   evaluated by both of its cells, with identical operands, so
  *                   conservation stays exact); 0: face fluxes, then a gather
+ *   xcd_remap       1: permute block ids so that the blocks the dispatcher
+ *                   places on one XCD (every eighth block) cover one
+ *                   contiguous range of cells, lists or faces, and neighbour
+ *                   gathers share that XCD's L2; 0: plain block order
  * hfv_set_launch validates every field (HFV_ERR_PARAM, nothing changed, on
  * an invalid one); hfv_get_launch reads the current configuration. */
 typedef struct {
-  int32_t lanes_per_cell, block, list_blocks, linear_split, linear_lanes, cwenoz_reuse, fused_residual;
+  int32_t lanes_per_cell, block, list_blocks, linear_split, linear_lanes, cwenoz_reuse, fused_residual, xcd_remap;
 } hfv_launch;
 hfv_status hfv_set_launch(hfv_ctx *ctx, const hfv_launch *cfg);
 hfv_status hfv_get_launch(const hfv_ctx *ctx, hfv_launch *cfg);
@@ -231,7 +239,8 @@ hfv_status hfv_get_launch(const hfv_ctx *ctx, hfv_launch *cfg);
  * caller's state U (device [nvar][n_cells]) under the current parameters for
  * candidate launch configurations, searched one coordinate at a time (linear
  * kernel mapping; class-list kernel lanes, block and grid;
- * CWENOZ reuse in hybrid mode; fused or two-kernel residual), and keeps the
+ * CWENOZ reuse in hybrid mode; fused or two-kernel residual; XCD block
+ * order), and keeps the
  * fastest (median of `reps`
  * timed calls after one untimed call, reps in [1, 1000]).  Synchronous; it
  * allocates and frees one residual-sized buffer.  `best` (may be NULL)

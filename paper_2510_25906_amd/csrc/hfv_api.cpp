@@ -211,6 +211,7 @@ hfv_status hfv_set_launch(hfv_ctx *ctx, const hfv_launch *c) {
   if (c->cwenoz_reuse != 0 && c->cwenoz_reuse != 1) return ctx->err = "cwenoz_reuse must be 0 or 1", HFV_ERR_PARAM;
   if (c->fused_residual != 0 && c->fused_residual != 1)
     return ctx->err = "fused_residual must be 0 or 1", HFV_ERR_PARAM;
+  if (c->xcd_remap != 0 && c->xcd_remap != 1) return ctx->err = "xcd_remap must be 0 or 1", HFV_ERR_PARAM;
   ctx->lanes = lanes;
   ctx->block = c->block;
   ctx->list_blocks = c->list_blocks;
@@ -218,6 +219,7 @@ hfv_status hfv_set_launch(hfv_ctx *ctx, const hfv_launch *c) {
   ctx->lin_lanes = c->linear_lanes;
   ctx->cw_reuse = c->cwenoz_reuse;
   ctx->fused_residual = c->fused_residual;
+  ctx->xcd_remap = c->xcd_remap;
   return HFV_OK;
 }
 
@@ -230,6 +232,7 @@ hfv_status hfv_get_launch(const hfv_ctx *ctx, hfv_launch *c) {
   c->linear_lanes = ctx->lin_lanes;
   c->cwenoz_reuse = ctx->cw_reuse;
   c->fused_residual = ctx->fused_residual;
+  c->xcd_remap = ctx->xcd_remap;
   return HFV_OK;
 }
 
@@ -306,6 +309,7 @@ hfv_status hfv_copy_table(const hfv_ctx *ctx, int32_t which, void *dst, int64_t 
     case HFV_T_PDIR: src = d64 ? (const void *)ctx->t64.Pdir : ctx->t32.Pdir; n = ts * ctx->NFM * ctx->dim * ctx->Md * N; break;
     case HFV_T_PMUS: src = d64 ? (const void *)ctx->t64.Pmus : ctx->t32.Pmus; n = ts * ctx->dim * ctx->NFM * N; break;
     case HFV_T_FACE_SLOTS: src = d64 ? ctx->t64.fgb : ctx->t32.fgb; n = sizeof(int) * (size_t)ctx->NF; break;
+    case HFV_T_GP_XI: src = d64 ? (const void *)ctx->t64.gpxi : ctx->t32.gpxi; n = ts * ctx->NGPC * ctx->dim * N; break;
     default: return HFV_ERR_PARAM;
   }
   if ((int64_t)n != bytes) return HFV_ERR_PARAM;

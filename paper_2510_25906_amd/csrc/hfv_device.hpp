@@ -21,7 +21,21 @@ struct HotArgs {
   Tables<T> t;
   T gamma, alpha_m, beta_m, alpha_w, beta_w, lam1p, eps_w, b_w, theta, tvd_eps;
   int ib_w;  // b_w when it is an integer in [1, 8] (powers by multiplication), else 0
+  int xcd;   // block ids remapped so each XCD takes one contiguous range (block_id)
 };
+
+// Block id, optionally permuted.  The dispatcher hands workgroups to the 8
+// XCDs in turn (block b to XCD b mod 8), and each XCD has its own L2.  With
+// the remap, the blocks running on one XCD cover one contiguous range of
+// items instead of every eighth block, so cells that gather the same
+// neighbour values (nearby ids) meet in the same L2.  A permutation of the
+// block ids: results do not change.
+__device__ inline long block_id(int xcd) {
+  const unsigned b = blockIdx.x, n = gridDim.x;
+  if (!xcd || n < 16) return b;
+  const unsigned x = b & 7u, k = b >> 3, per = n >> 3, rem = n & 7u;
+  return (long)x * per + min(x, rem) + k;
+}
 
 // x^b for x >= 0: repeated products when b is a small integer, pow otherwise.
 __device__ inline double powb(double x, double b, int ib) {
@@ -37,10 +51,10 @@ template <int G>
 struct Lane {
   int item, sub, base;
   bool ok;
-  __device__ Lane() {
+  __device__ explicit Lane(int xcd = 0) {
     constexpr int CPW = 64 / G;
     const int lane = threadIdx.x & 63;
-    const long wave = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const long wave = (block_id(xcd) * blockDim.x + threadIdx.x) >> 6;
     item = (int)(wave * CPW + lane / G);
     sub = lane % G;
     base = lane - sub;

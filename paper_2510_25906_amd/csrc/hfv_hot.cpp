@@ -38,7 +38,7 @@ template <int DIM, int R, typename T, int G>
 __global__ __launch_bounds__(256) void k_linear(HotArgs<T> a) {
   constexpr int NV = DIM + 2, K = n_unknowns(DIM, R), VPL = NV / G, NFM = nf_max(DIM);
   if (blockIdx.x == 0 && threadIdx.x < 8) a.counts[threadIdx.x] = 0;
-  Lane<G> L;
+  Lane<G> L(a.xcd);
   const int cell = L.item;
   if (!L.ok || cell >= a.N) return;
   const int N = a.N, v0 = L.sub * VPL;
@@ -151,7 +151,7 @@ __global__ __launch_bounds__(256) void k_linear_ms(HotArgs<T> a) {
   constexpr int MPL = (M + G - 1) / G;
   static_assert((G & (G - 1)) == 0 && 64 % G == 0, "group size must be a power of two");
   if (blockIdx.x == 0 && threadIdx.x < 8) a.counts[threadIdx.x] = 0;
-  Lane<G> L;
+  Lane<G> L(a.xcd);
   const int cell = L.item;
   if (!L.ok || cell >= a.N) return;  // whole groups leave together
   const int N = a.N, q = L.sub;
@@ -285,7 +285,7 @@ __global__ __launch_bounds__(256) void k_linear_ks(HotArgs<T> a) {
   constexpr Exps<DIM, 1, R> E{};
   static_assert((G & (G - 1)) == 0 && G >= 2 && 64 % G == 0, "group size must be a power of two");
   if (blockIdx.x == 0 && threadIdx.x < 8) a.counts[threadIdx.x] = 0;
-  Lane<G> L;
+  Lane<G> L(a.xcd);
   const int cell = L.item;
   if (!L.ok || cell >= a.N) return;  // whole groups leave together
   const int N = a.N, q = L.sub;
@@ -480,7 +480,7 @@ __global__ __launch_bounds__(256) void k_linear_ks(HotArgs<T> a) {
 constexpr int CLASSIFY_BLOCK = 1024;
 template <typename T>
 __global__ __launch_bounds__(CLASSIFY_BLOCK) void k_classify(HotArgs<T> a, int nfm) {
-  const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+  const int cell = (int)(block_id(a.xcd) * blockDim.x + threadIdx.x);
   const bool valid = cell < a.N;
   int c = 0;
   if (valid && a.frozen) {
@@ -538,7 +538,7 @@ __global__ __launch_bounds__(256) void k_cwenoz(HotArgs<T> a, int direct) {
   constexpr int NV = DIM + 2, K = n_unknowns(DIM, R), VPL = NV / G, NFM = nf_max(DIM), MD = 2 * DIM;
   constexpr int CPW = 64 / G;
   const int total = direct ? a.N : a.counts[1];
-  Lane<G> L;
+  Lane<G> L(a.xcd);
   if (!L.ok) return;
   const long stride = (long)gridDim.x * (blockDim.x / 64) * CPW;
   for (long item = L.item; item < total; item += stride) {
@@ -704,7 +704,7 @@ __global__ __launch_bounds__(256) void k_muscl(HotArgs<T> a, int direct) {
   constexpr int NV = DIM + 2, VPL = NV / G, NFM = nf_max(DIM);
   constexpr int CPW = 64 / G;
   const int total = direct ? a.N : a.counts[2];
-  Lane<G> L;
+  Lane<G> L(a.xcd);
   if (!L.ok) return;
   const long stride = (long)gridDim.x * (blockDim.x / 64) * CPW;
   for (long item = L.item; item < total; item += stride) {
@@ -828,9 +828,9 @@ __global__ __launch_bounds__(256) void k_muscl(HotArgs<T> a, int direct) {
 template <int DIM, typename T>
 __global__ __launch_bounds__(256) void k_flux(int NF, int N, const T *fs, const int *gp_off, const int *fc,
                                               const int *fgb, const T *fn, const T *gpw, T gamma, int hllc,
-                                              T *Ff) {
+                                              T *Ff, int xcd) {
   constexpr int NV = DIM + 2;
-  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  const int f = (int)(block_id(xcd) * blockDim.x + threadIdx.x);
   if (f >= NF) return;
   T n[DIM];
 #pragma unroll
@@ -859,8 +859,8 @@ __global__ __launch_bounds__(256) void k_flux(int NF, int N, const T *fs, const 
 
 template <int NV, typename T>
 __global__ __launch_bounds__(256) void k_gather(int N, int NF, const int *cf_off, const int *cf, const T *Ff,
-                                                const T *ivol, T *R) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+                                                const T *ivol, T *R, int xcd) {
+  const int c = (int)(block_id(xcd) * blockDim.x + threadIdx.x);
   if (c >= N) return;
   T acc[NV] = {};
   for (int e = cf_off[c]; e < cf_off[c + 1]; ++e) {
@@ -884,9 +884,10 @@ __global__ __launch_bounds__(256) void k_gather(int N, int NF, const int *cf_off
 template <int DIM, typename T>
 __global__ __launch_bounds__(256) void k_residual(int N, int NF, const T *fs, const int *cf_off, const int *cf,
                                                   const int *fc, const int *fgb, const int *gp_off, const T *fn,
-                                                  const T *gpw, const T *ivol, T gamma, int hllc, T *R) {
+                                                  const T *gpw, const T *ivol, T gamma, int hllc, T *R,
+                                                  int xcd) {
   constexpr int NV = DIM + 2;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = (int)(block_id(xcd) * blockDim.x + threadIdx.x);
   if (c >= N) return;
   T acc[NV] = {};
   for (int e = cf_off[c]; e < cf_off[c + 1]; ++e) {
@@ -936,6 +937,7 @@ static HotArgs<T> make_args(hfv_ctx *ctx, Tables<T> &t, const void *U, void *fs,
   a.U = (const T *)U;
   a.fs = (T *)fs;
   a.coef = (ctx->cw_reuse && ctx->p.mode == HFV_HYBRID) ? (T *)ctx->coef : nullptr;
+  a.xcd = ctx->xcd_remap;
   a.own = ctx->own;
   a.cls = cls;
   a.lists = ctx->lists;
@@ -1104,25 +1106,25 @@ static hfv_status tail_t(hfv_ctx *ctx, Tables<T> &t, const void *fs, void *R, hi
     ProfScope ps(ctx, HFV_SLOT_FLUX, s);
     if (ctx->dim == 2)
       k_residual<2, T><<<gc, 256, 0, s>>>(ctx->N, ctx->NF, (const T *)fs, t.cf_off, t.cf, t.face_cells, t.fgb,
-                                          t.gp_off, t.fnormal, t.gpw, t.ivol, (T)ctx->p.gamma, hllc, (T *)R);
+                                          t.gp_off, t.fnormal, t.gpw, t.ivol, (T)ctx->p.gamma, hllc, (T *)R, ctx->xcd_remap);
     else
       k_residual<3, T><<<gc, 256, 0, s>>>(ctx->N, ctx->NF, (const T *)fs, t.cf_off, t.cf, t.face_cells, t.fgb,
-                                          t.gp_off, t.fnormal, t.gpw, t.ivol, (T)ctx->p.gamma, hllc, (T *)R);
+                                          t.gp_off, t.fnormal, t.gpw, t.ivol, (T)ctx->p.gamma, hllc, (T *)R, ctx->xcd_remap);
     HFV_HIP(hipGetLastError());
     return HFV_OK;
   }
   if (ctx->dim == 2) {
     { ProfScope ps(ctx, HFV_SLOT_FLUX, s);
       k_flux<2, T><<<gf, 256, 0, s>>>(ctx->NF, ctx->N, (const T *)fs, t.gp_off, t.face_cells, t.fgb, t.fnormal,
-                                       t.gpw, (T)ctx->p.gamma, hllc, Ff); }
+                                       t.gpw, (T)ctx->p.gamma, hllc, Ff, ctx->xcd_remap); }
     { ProfScope ps(ctx, HFV_SLOT_GATHER, s);
-      k_gather<4, T><<<gc, 256, 0, s>>>(ctx->N, ctx->NF, t.cf_off, t.cf, Ff, t.ivol, (T *)R); }
+      k_gather<4, T><<<gc, 256, 0, s>>>(ctx->N, ctx->NF, t.cf_off, t.cf, Ff, t.ivol, (T *)R, ctx->xcd_remap); }
   } else {
     { ProfScope ps(ctx, HFV_SLOT_FLUX, s);
       k_flux<3, T><<<gf, 256, 0, s>>>(ctx->NF, ctx->N, (const T *)fs, t.gp_off, t.face_cells, t.fgb, t.fnormal,
-                                       t.gpw, (T)ctx->p.gamma, hllc, Ff); }
+                                       t.gpw, (T)ctx->p.gamma, hllc, Ff, ctx->xcd_remap); }
     { ProfScope ps(ctx, HFV_SLOT_GATHER, s);
-      k_gather<5, T><<<gc, 256, 0, s>>>(ctx->N, ctx->NF, t.cf_off, t.cf, Ff, t.ivol, (T *)R); }
+      k_gather<5, T><<<gc, 256, 0, s>>>(ctx->N, ctx->NF, t.cf_off, t.cf, Ff, t.ivol, (T *)R, ctx->xcd_remap); }
   }
   HFV_HIP(hipGetLastError());
   return HFV_OK;

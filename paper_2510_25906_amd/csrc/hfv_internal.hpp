@@ -121,6 +121,7 @@ struct hfv_ctx {
   int lin_split = 0, lin_lanes = 4;  // linear kernel: 0 variables, 1 stencil members, 2 unknowns per lane
   int cw_reuse = 0;                  // CWENOZ starts from the linear pass's central fit
   int fused_residual = 0;            // one owner-computes residual kernel instead of flux + gather
+  int xcd_remap = 1;                 // XCD-contiguous block order (block_id)
   int device = 0, n_cu = 256;
   // kernel timing (hfv_profile_*)
   struct ProfEv {

@@ -12,7 +12,8 @@
 //      (skipped when no cell can reach a class list's kernels in numbers,
 //      i.e. in all-linear mode, where only first-order cells use them);
 //   3. in hybrid mode, whether CWENOZ reuses the linear pass's central fits;
-//   4. the fused (owner-computes) residual kernel against face fluxes + gather.
+//   4. the fused (owner-computes) residual kernel against face fluxes + gather;
+//   5. XCD-contiguous block order against plain block order.
 // Each candidate runs once untimed, then `reps` times with HIP events around
 // each call; its score is the median.
 #include <algorithm>
@@ -141,6 +142,12 @@ extern "C" hfv_status hfv_autotune(hfv_ctx *ctx, const void *U, int32_t reps, hf
     {
       hfv_launch c = best;
       c.fused_residual = 1 - best.fused_residual;
+      tu.pick({c}, best, best_ms);
+    }
+    // 5. block order
+    {
+      hfv_launch c = best;
+      c.xcd_remap = 1 - best.xcd_remap;
       tu.pick({c}, best, best_ms);
     }
     if (hfv_set_launch(ctx, &best) != HFV_OK) st = HFV_ERR_PARAM;

@@ -23,7 +23,7 @@ ERRORS = {-1: "HFV_ERR_PARAM", -2: "HFV_ERR_MESH", -3: "HFV_ERR_RANK", -4: "HFV_
 Q = dict(N_CELLS=0, N_FACES=1, N_GP=2, NVAR=3, K=4, M=5, PRECISION=6, DIM=7, TABLE_BYTES=8,
          COUNT_CWENOZ=9, COUNT_MUSCL=10, COUNT_FIRST=11, NGP_CELL_MAX=12)
 SLOTS = dict(linear=0, classify=1, cwenoz=2, muscl=3, flux=5, gather=6, vjp=7)
-TABLES = dict(PINV=0, OI=1, PSIBAR=2, GEOM=3, PDIR=4, PMUS=5, FACE_SLOTS=6)
+TABLES = dict(PINV=0, OI=1, PSIBAR=2, GEOM=3, PDIR=4, PMUS=5, FACE_SLOTS=6, GP_XI=7)
 
 _p = C.c_void_p
 _i32p = C.POINTER(C.c_int32)
@@ -92,7 +92,7 @@ def load():
 
 class HfvLaunch(C.Structure):
     _fields_ = [(n, C.c_int32) for n in ("lanes_per_cell", "block", "list_blocks", "linear_split",
-                                         "linear_lanes", "cwenoz_reuse", "fused_residual")]
+                                         "linear_lanes", "cwenoz_reuse", "fused_residual", "xcd_remap")]
 
 
 class HfvTuneRecord(C.Structure):
@@ -211,11 +211,12 @@ class Context:
         return {n: getattr(cfg, n) for n, _ in HfvLaunch._fields_}
 
     def set_launch(self, lanes=None, block=None, list_blocks=None, linear_split=None, linear_lanes=None,
-                   cwenoz_reuse=None, fused_residual=None):
+                   cwenoz_reuse=None, fused_residual=None, xcd_remap=None):
         """Change the launch configuration; fields left None keep their current value."""
         cur = self.get_launch()
         new = dict(lanes_per_cell=lanes, block=block, list_blocks=list_blocks, linear_split=linear_split,
-                   linear_lanes=linear_lanes, cwenoz_reuse=cwenoz_reuse, fused_residual=fused_residual)
+                   linear_lanes=linear_lanes, cwenoz_reuse=cwenoz_reuse, fused_residual=fused_residual,
+                   xcd_remap=xcd_remap)
         cur.update({k: int(v) for k, v in new.items() if v is not None})
         self._check(self.lib.hfv_set_launch(self.h, C.byref(HfvLaunch(**cur))))
 
@@ -246,7 +247,8 @@ class Context:
         N, K, M, d = self.n_cells, self.K, self.M, self.dim
         nfm = 4 if d == 2 else 6
         shapes = dict(PINV=(K, M, N), OI=(K * (K + 1) // 2, N), PSIBAR=(K, N), GEOM=(d + 2, N),
-                      PDIR=(nfm, d, 2 * d, N), PMUS=(d, nfm, N), FACE_SLOTS=(self.n_faces,))
+                      PDIR=(nfm, d, 2 * d, N), PMUS=(d, nfm, N), FACE_SLOTS=(self.n_faces,),
+                      GP_XI=(self.ngp_cell, d, N))
         if name == "FACE_SLOTS":
             dt = np.int32
         else:

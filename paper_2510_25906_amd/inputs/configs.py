@@ -3,6 +3,11 @@
 Seeds: 0 for the mesh, 1 for field noise or perturbation, 2 for random
 directions.  The workloads mirror the paper's test cases (Section 3) at the
 sizes listed in ``CONFIGS``.
+
+When the environment variable HFV_INPUT_CACHE names a directory, meshes with
+their stencils (and the mixed box's field) are stored there on first use and
+loaded from there afterwards; the cache is keyed by workload and size only, so
+clear it after changing a generator.
 """
 from __future__ import annotations
 
@@ -24,6 +29,9 @@ class Workload:
     stencils: Stencils
     U: np.ndarray      # float64 [N, nvar] cell averages of conserved variables
     params: Params
+    # point values of the conserved variables, f(points [..., d]) -> [..., nvar],
+    # where the field is smooth everywhere (None otherwise)
+    exact: object = None
 
 
 def _cache_path(key):
@@ -106,9 +114,9 @@ def tgv_hex(n=64, r=4, perturb=True) -> Workload:
     mesh = hex_3d(n, n, n, hi=(L, L, L), periodic=True, name=f"hex{n}")
     st = build_stencils_periodic_hex(mesh, (n, n, n), r) if n > 16 else build_stencils(mesh, r)
     pert = fields.tgv_perturbation(seed=1) if perturb else None
-    U = fields.cell_average(mesh, lambda p: fields.prim_to_cons(fields.tgv_prim(p, perturb=pert)),
-                            nq=max(3, (r + 3) // 2 + 1))
-    return Workload(f"tgv_hex{n}_r{r}", mesh, st, U, Params(order_r=r, riemann=0))
+    exact = lambda p: fields.prim_to_cons(fields.tgv_prim(p, perturb=pert))
+    U = fields.cell_average(mesh, exact, nq=max(3, (r + 3) // 2 + 1))
+    return Workload(f"tgv_hex{n}_r{r}", mesh, st, U, Params(order_r=r, riemann=0), exact)
 
 
 def vortex_2d(n=16, r=2) -> Workload:
@@ -147,6 +155,12 @@ def c4_mixed(size="small", r=3, workers=1) -> Workload:
     mesh, st = mesh_and_stencils(f"c4_{size}_r{r}",
                                  lambda: mixed_box(nx, ny, nz, core=core, prism_layers=kb, jitter=0.2, seed=0),
                                  r, workers=workers)
-    U = fields.cell_average(mesh, lambda p: fields.prim_to_cons(fields.shock_vortices_prim(p, length, x_shock)),
-                            nq=4, workers=workers)
+    upath = _cache_path(f"c4_{size}_field")
+    if upath and os.path.exists(upath):
+        U = np.load(upath)["U"]
+    else:
+        U = fields.cell_average(mesh, lambda p: fields.prim_to_cons(fields.shock_vortices_prim(p, length, x_shock)),
+                                nq=4, workers=workers)
+        if upath:
+            np.savez(upath, U=U)
     return Workload(f"c4_mixed_{size}_r{r}", mesh, st, U, Params(order_r=r, riemann=0))

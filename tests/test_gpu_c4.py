@@ -131,3 +131,25 @@ def test_c4_medium_sampled(hfv):
         print(f"fp{prec} sampled state error {e:.2e}", flush=True)
         assert e <= (1e-12 if prec == 64 else 1e-5)
         ctx.close()
+
+
+@pytest.mark.parametrize("cfg", [dict(), dict(linear_split=1, linear_lanes=4, list_blocks=64, fused_residual=1),
+                                 dict(linear_split=2, linear_lanes=8, lanes=1, cwenoz_reuse=1, list_blocks=0)])
+def test_c4_block_order_does_not_change_results(hfv, small, cfg):
+    """XCD-contiguous and plain block orders give bitwise identical classes,
+    face states and residuals (the remap only permutes block ids)."""
+    w, _ = small
+    ctx = hfv.Context(w.mesh, w.stencils, w.params, 64)
+    Ud = to_dev(w.U, torch.float64)
+    out = []
+    for remap in (0, 1):
+        ctx.set_launch(xcd_remap=remap, **cfg)
+        fs = torch.zeros_like(ctx.new_face_states())   # slots past a cell's Gauss points stay 0
+        cls = torch.empty(w.mesh.n_cells, dtype=torch.uint8, device="cuda")
+        R = ctx.residual(Ud, face_states=fs, cell_class=cls)
+        torch.cuda.synchronize()
+        out.append((fs, cls, R))
+    assert torch.equal(out[0][1], out[1][1])
+    assert torch.equal(out[0][0], out[1][0])
+    assert torch.equal(out[0][2], out[1][2])
+    ctx.close()
