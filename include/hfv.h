@@ -163,6 +163,17 @@ hfv_status hfv_residual(hfv_ctx *ctx, const void *U, void *R, void *face_states,
  *   cell_class  device [n_cells] classes (HFV_CLASS_*), read only */
 hfv_status hfv_residual_frozen(hfv_ctx *ctx, const void *U, const uint8_t *cell_class, void *R, void *stream);
 
+/* One stage of an explicit Runge-Kutta method in Shu-Osher form, the form of
+ * the strong-stability-preserving methods of Spiteri and Ruuth that the paper
+ * integrates in time with (Section 2.4):
+ *   out = a U0 + b U1 + c R, evaluated as (a U0 + b U1) + c R,
+ * elementwise over device [nvar][n_cells] arrays in the context's precision
+ * (R is a residual from hfv_residual, the step size folded into c).  U0, U1
+ * or R may be NULL (the term is left out); any input may alias `out`.
+ * Errors: HFV_ERR_PARAM for a NULL `out` or a non-finite coefficient. */
+hfv_status hfv_rk_stage(hfv_ctx *ctx, double a, const void *U0, double b, const void *U1, double c, const void *R,
+                        void *out, void *stream);
+
 /* Vector-Jacobian product of the residual with the cell classes frozen (a
  * project addition, not in the paper):  gU = (dR/dU)^T gR, every switch
  * (class, Harten fallback, limiter argmin, Riemann branch) held at the

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhfv.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-SOURCES = ["hfv_api.cpp", "hfv_setup.cpp", "hfv_hot.cpp", "hfv_vjp.cpp", "hfv_tune.cpp"]
+SOURCES = ["hfv_api.cpp", "hfv_setup.cpp", "hfv_hot.cpp", "hfv_vjp.cpp", "hfv_tune.cpp", "hfv_time.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-x", "hip",
          # no packed FP32 instructions anywhere in device code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

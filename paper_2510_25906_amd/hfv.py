@@ -68,6 +68,7 @@ def load():
     lib.hfv_residual.argtypes = [_p, _p, _p, _p, _p, _p]
     lib.hfv_residual_vjp.argtypes = [_p, _p, _p, _p, _p, _p]
     lib.hfv_residual_frozen.argtypes = [_p, _p, _p, _p, _p]
+    lib.hfv_rk_stage.argtypes = [_p, C.c_double, _p, C.c_double, _p, C.c_double, _p, _p, _p]
     lib.hfv_query.argtypes = [_p, C.c_int32, C.POINTER(C.c_int64)]
     lib.hfv_copy_table.argtypes = [_p, C.c_int32, _p, C.c_int64]
     lib.hfv_set_launch.argtypes = [_p, C.POINTER(HfvLaunch)]
@@ -81,7 +82,7 @@ def load():
     lib.hfv_destroy.argtypes = [_p]
     lib.hfv_destroy.restype = None
     for name in ("hfv_create", "hfv_set_params", "hfv_reconstruct", "hfv_residual", "hfv_residual_vjp",
-                 "hfv_residual_frozen",
+                 "hfv_residual_frozen", "hfv_rk_stage",
                  "hfv_query", "hfv_copy_table", "hfv_set_launch", "hfv_get_launch", "hfv_autotune",
                  "hfv_profile_enable",
                  "hfv_profile_read"):
@@ -297,6 +298,16 @@ class Context:
                                               C.c_void_p(gR.data_ptr()), C.c_void_p(gU.data_ptr()),
                                               _stream_handle(stream)))
         return gU
+
+    def rk_stage(self, out, a, U0, b=0.0, U1=None, c=0.0, R=None, stream=None):
+        """out = a U0 + b U1 + c R (one Shu-Osher Runge-Kutta stage); None terms are left out."""
+        for x in (out, U0, U1, R):
+            if x is not None:
+                self._chk_u(x)
+        ptr = lambda x: C.c_void_p(x.data_ptr()) if x is not None else None
+        self._check(self.lib.hfv_rk_stage(self.h, a, ptr(U0), b, ptr(U1), c, ptr(R), ptr(out),
+                                          _stream_handle(stream)))
+        return out
 
     def residual_frozen(self, U, cell_class, R=None, stream=None):
         """Residual with the given classes held fixed (what the VJP linearises)."""
