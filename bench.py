@@ -288,10 +288,10 @@ WORKLOADS = {
 }
 
 
-def make_workload(name, workers):
+def make_workload(name, workers, cell_order="lattice"):
     from paper_2510_25906_amd.inputs import configs
     return {"c2": lambda: configs.c2_riemann(256, 3), "c3": lambda: configs.tgv_hex(64, 4),
-            "c4": lambda: configs.c4_mixed("full", workers=workers),
+            "c4": lambda: configs.c4_mixed("full", workers=workers, cell_order=cell_order),
             "c5": lambda: configs.tgv_hex(64, 2)}[name]()
 
 
@@ -315,6 +315,8 @@ def main():
     ap.add_argument("--workers", type=int, default=max(1, min(16, os.cpu_count() or 1)),
                     help="processes for input generation (1 when a profiler has initialised the GPU "
                          "before the program starts: the generator forks)")
+    ap.add_argument("--cell-order", choices=("lattice", "morton"), default="lattice",
+                    help="cell numbering of the mixed box: cubes in lattice order or along a Morton curve")
     ap.add_argument("--cold", type=int, default=10,
                     help="also time this many single residuals, each after a 1 GiB cache-flushing write "
                          "(0: skip)")
@@ -329,7 +331,7 @@ def main():
     # inputs first: the mixed-mesh generator forks worker processes, which must
     # happen before this process touches the GPU
     t0 = time.perf_counter()
-    w = make_workload(args.workload, workers=args.workers)
+    w = make_workload(args.workload, workers=args.workers, cell_order=args.cell_order)
     wl_text, wl_tag, head_prec = WORKLOADS[args.workload]
     log(f"workload {args.workload}: {w.mesh.n_cells} cells, built in {time.perf_counter() - t0:.1f} s")
 

@@ -174,6 +174,18 @@ hfv_status hfv_residual_frozen(hfv_ctx *ctx, const void *U, const uint8_t *cell_
 hfv_status hfv_rk_stage(hfv_ctx *ctx, double a, const void *U0, double b, const void *U1, double c, const void *R,
                         void *out, void *stream);
 
+/* Largest spectral radius of the cells' upwind updates,
+ *   rate = max_i (|u_i| + c_i) sum_{f of i} |S_f| / |V_i|,
+ * of the cell averages U (device [nvar][n_cells]), computed in double and
+ * written to out (device, one double).  The explicit step at CFL number nu is
+ * nu / rate (Sections 2.4 and 3 fix the CFL number, not its definition): at
+ * nu = 1 a forward-Euler step of the first-order upwind scheme is at its
+ * positivity limit, and the SSP Runge-Kutta method of hfv_rk_stage keeps
+ * strong stability up to its SSP coefficient times that.  A cell whose
+ * density or pressure is not positive gives +inf.  A fixed-order two-pass
+ * reduction (no atomics) through a buffer allocated at create. */
+hfv_status hfv_cfl_rate(hfv_ctx *ctx, const void *U, double *out, void *stream);
+
 /* Vector-Jacobian product of the residual with the cell classes frozen (a
  * project addition, not in the paper):  gU = (dR/dU)^T gR, every switch
  * (class, Harten fallback, limiter argmin, Riemann branch) held at the

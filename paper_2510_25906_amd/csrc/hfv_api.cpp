@@ -158,7 +158,8 @@ hfv_status hfv_create(const hfv_mesh *mesh, const hfv_stencils *st, const hfv_pa
         (e = dev_alloc(ctx, (void **)&ctx->counts, sizeof(int) * 8)) == HFV_OK &&
         (e = dev_alloc(ctx, &ctx->coef, ts * ctx->K * ctx->nvar * (size_t)N)) == HFV_OK &&
         (e = dev_alloc(ctx, &ctx->fs_ws, ts * ctx->nvar * (size_t)ctx->NGPC * ctx->N)) == HFV_OK &&
-        (e = dev_alloc(ctx, &ctx->fflux, ts * ctx->nvar * (size_t)ctx->NF)) == HFV_OK) {
+        (e = dev_alloc(ctx, &ctx->fflux, ts * ctx->nvar * (size_t)ctx->NF)) == HFV_OK &&
+        (e = dev_alloc(ctx, (void **)&ctx->red, sizeof(double) * RED_BLOCKS)) == HFV_OK) {
       if (hipMemsetAsync(ctx->counts, 0, sizeof(int) * 8, s) != hipSuccess ||
           hipStreamSynchronize(s) != hipSuccess) {
         ctx->err = "workspace initialisation failed";

@@ -95,6 +95,8 @@ struct Params {
 
 }  // namespace hfv
 
+constexpr int RED_BLOCKS = 1024;
+
 struct hfv_ctx {
   int dim = 0, r = 0, prec = 64, N = 0, NF = 0, NGPT = 0, NGPC = 0, K = 0, M = 0, Md = 0, NFM = 0, nvar = 0;
   hfv::Params p{};
@@ -110,6 +112,7 @@ struct hfv_ctx {
   void *coef = nullptr;        // [K][nvar][N] central fits kept by the linear pass for CWENOZ
   void *fs_ws = nullptr;       // [NGPC][nvar][N] Gauss-point states, cell-major
   void *fflux = nullptr;       // [nvar][NF]
+  double *red = nullptr;       // [RED_BLOCKS] per-block partial results of reductions
   void *vjp_C = nullptr;       // adjoint: per stencil slot contributions [M][nvar][N]
   void *vjp_S = nullptr;       // adjoint: self contributions [nvar][N]
   void *vjp_gfs = nullptr;     // adjoint: Gauss-point state cotangents [NGPC][nvar][N]

@@ -60,6 +60,9 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"hfv HIP library not built: {LIB_PATH} missing (run __graft_entry__.build())")
+    # torch first: the library then binds to the HIP runtime torch has loaded,
+    # so that device memory and streams from torch are valid in its calls
+    import torch  # noqa: F401
     lib = C.CDLL(LIB_PATH)
     lib.hfv_create.argtypes = [C.POINTER(HfvMesh), C.POINTER(HfvStencils), C.POINTER(HfvParams), _p,
                                C.POINTER(_p)]
@@ -69,6 +72,7 @@ def load():
     lib.hfv_residual_vjp.argtypes = [_p, _p, _p, _p, _p, _p]
     lib.hfv_residual_frozen.argtypes = [_p, _p, _p, _p, _p]
     lib.hfv_rk_stage.argtypes = [_p, C.c_double, _p, C.c_double, _p, C.c_double, _p, _p, _p]
+    lib.hfv_cfl_rate.argtypes = [_p, _p, _p, _p]
     lib.hfv_query.argtypes = [_p, C.c_int32, C.POINTER(C.c_int64)]
     lib.hfv_copy_table.argtypes = [_p, C.c_int32, _p, C.c_int64]
     lib.hfv_set_launch.argtypes = [_p, C.POINTER(HfvLaunch)]
@@ -82,7 +86,7 @@ def load():
     lib.hfv_destroy.argtypes = [_p]
     lib.hfv_destroy.restype = None
     for name in ("hfv_create", "hfv_set_params", "hfv_reconstruct", "hfv_residual", "hfv_residual_vjp",
-                 "hfv_residual_frozen", "hfv_rk_stage",
+                 "hfv_residual_frozen", "hfv_rk_stage", "hfv_cfl_rate",
                  "hfv_query", "hfv_copy_table", "hfv_set_launch", "hfv_get_launch", "hfv_autotune",
                  "hfv_profile_enable",
                  "hfv_profile_read"):
@@ -306,6 +310,15 @@ class Context:
                 self._chk_u(x)
         ptr = lambda x: C.c_void_p(x.data_ptr()) if x is not None else None
         self._check(self.lib.hfv_rk_stage(self.h, a, ptr(U0), b, ptr(U1), c, ptr(R), ptr(out),
+                                          _stream_handle(stream)))
+        return out
+
+    def cfl_rate(self, U, out=None, stream=None):
+        """Device tensor [1] (float64): max over cells of (|u| + c) / h_c."""
+        import torch
+        self._chk_u(U)
+        out = out if out is not None else torch.empty(1, dtype=torch.float64, device="cuda")
+        self._check(self.lib.hfv_cfl_rate(self.h, C.c_void_p(U.data_ptr()), C.c_void_p(out.data_ptr()),
                                           _stream_handle(stream)))
         return out
 

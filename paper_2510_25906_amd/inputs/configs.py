@@ -142,7 +142,7 @@ C4_SIZES = {"small": (24, 8, 8, (8, 16), 2), "medium": (60, 20, 20, (24, 36), 3)
             "full": (160, 56, 56, (64, 96), 8)}
 
 
-def c4_mixed(size="small", r=3, workers=1) -> Workload:
+def c4_mixed(size="small", r=3, workers=1, cell_order="lattice") -> Workload:
     """3D Euler on the mixed tetrahedron / prism / pyramid / hexahedron box of
     ``mixed_box`` (tetrahedral core with a prism layer on the wall z = 0,
     pyramid-and-tetrahedron transition columns, hexahedral far field): a
@@ -152,10 +152,12 @@ def c4_mixed(size="small", r=3, workers=1) -> Workload:
     h = 1.0 / ny
     length = nx * h
     x_shock = 0.5 * (core[0] + core[1]) * h + 0.37 * h   # inside a cube layer, not on a lattice plane
-    mesh, st = mesh_and_stencils(f"c4_{size}_r{r}",
-                                 lambda: mixed_box(nx, ny, nz, core=core, prism_layers=kb, jitter=0.2, seed=0),
+    tag = "" if cell_order == "lattice" else f"_{cell_order}"
+    mesh, st = mesh_and_stencils(f"c4_{size}{tag}_r{r}",
+                                 lambda: mixed_box(nx, ny, nz, core=core, prism_layers=kb, jitter=0.2, seed=0,
+                                                   cell_order=cell_order),
                                  r, workers=workers)
-    upath = _cache_path(f"c4_{size}_field")
+    upath = _cache_path(f"c4_{size}{tag}_field")
     if upath and os.path.exists(upath):
         U = np.load(upath)["U"]
     else:

@@ -338,7 +338,15 @@ _HEX_CORNER = np.array([(0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 1, 0), (0, 0, 1), (
 CUBE_HEX, CUBE_PRISM, CUBE_TET, CUBE_TRANSITION = 0, 1, 2, 3
 
 
-def mixed_box(nx, ny, nz, core=None, prism_layers=2, jitter=0.2, seed=0, h=None, name=""):
+def _morton3(i, j, k):
+    """Morton (Z-order) key of integer lattice coordinates below 2^10."""
+    key = np.zeros(np.shape(i), np.int64)
+    for b in range(10):
+        key |= (((i >> b) & 1) << (3 * b)) | (((j >> b) & 1) << (3 * b + 1)) | (((k >> b) & 1) << (3 * b + 2))
+    return key
+
+
+def mixed_box(nx, ny, nz, core=None, prism_layers=2, jitter=0.2, seed=0, h=None, name="", cell_order="lattice"):
     """Conforming mixed tetrahedron / prism / pyramid / hexahedron mesh of a box.
 
     A lattice of nx x ny x nz cubes of edge h (default 1/ny) is split by
@@ -352,8 +360,12 @@ def mixed_box(nx, ny, nz, core=None, prism_layers=2, jitter=0.2, seed=0, h=None,
     face; every other cube is a hexahedron.  Every split quad face is cut along
     the diagonal from its lowest to its highest lattice corner, which is the
     cut the Kuhn tetrahedra and the prism caps make, so all faces match.
-    Cells are numbered cube by cube in lattice order (x fastest).
+    Cells are numbered cube by cube, the cubes in lattice order (x fastest)
+    or, with ``cell_order="morton"``, along a Morton (Z-order) curve, which
+    keeps cells that are close in space close in memory in every direction.
     """
+    if cell_order not in ("lattice", "morton"):
+        raise ValueError("cell_order must be 'lattice' or 'morton'")
     h = 1.0 / ny if h is None else h
     i1, i2 = core if core is not None else (nx // 3, nx - nx // 3)
     kb = prism_layers
@@ -426,6 +438,8 @@ def mixed_box(nx, ny, nz, core=None, prism_layers=2, jitter=0.2, seed=0, h=None,
             c_[neg, 1], c_[neg, 2] = c_[neg, 2].copy(), c_[neg, 1].copy()
     # cube-major order, cells padded to 8 vertices (-1) and then flattened
     own = np.concatenate(owner)
+    if cell_order == "morton":
+        own = _morton3(I[own], J[own], Kk[own])
     order = np.argsort(own, kind="stable")
     types = np.concatenate(ctype)[order]
     padded = np.concatenate([np.pad(c_, ((0, 0), (0, 8 - c_.shape[1])), constant_values=-1) for c_ in cells])[order]

@@ -28,16 +28,13 @@ SSP54 = (
 )
 
 
-def cfl_dt(ctx, U_host, cfl, gamma=1.4):
-    """cfl * min over cells of h_c / (|u| + c) for cell averages U_host
-    [n_cells][nvar] (h_c = |V|^(1/d), from the context's geometry table)."""
-    d = ctx.dim
-    h = ctx.table("GEOM")[d + 1]
-    rho = U_host[:, 0]
-    vel = U_host[:, 1:1 + d] / rho[:, None]
-    p = (gamma - 1.0) * (U_host[:, -1] - 0.5 * rho * (vel ** 2).sum(1))
-    speed = np.sqrt((vel ** 2).sum(1)) + np.sqrt(gamma * p / rho)
-    return float(cfl * (h / speed).min())
+def cfl_dt(ctx, U, cfl):
+    """Step size cfl / rate for the device state U, with the library's
+    spectral-radius rate max_i (|u_i| + c_i) sum_f |S_f| / |V_i|."""
+    r = float(ctx.cfl_rate(U).item())
+    if not np.isfinite(r) or r <= 0.0:
+        raise FloatingPointError("non-physical state")
+    return cfl / r
 
 
 class SSPRK54:
@@ -46,6 +43,7 @@ class SSPRK54:
     ceil(t_end / dt_max) equal steps ending exactly at t_end."""
 
     def __init__(self, ctx, stream=None):
+        """Stage buffers are allocated here, once."""
         import torch
         self.ctx = ctx
         self.stream = stream
@@ -85,3 +83,29 @@ class SSPRK54:
         for _ in range(n):
             self.step(U, dt)
         return n, dt
+
+    def run_cfl(self, U, t_end, cfl, max_steps=1_000_000, on_step=None, collapse=1e-3):
+        """Steps of dt = cfl / rate(U) (hfv_cfl_rate, read back once per
+        step), the last one shortened to end at t_end.  Raises
+        FloatingPointError if the state stops being physical or the step
+        size collapses below `collapse` times the first one (a blowing-up
+        solution).  on_step(n, t) is called after each step."""
+        import torch
+        rate = torch.empty(1, dtype=torch.float64, device="cuda")
+        t, n, dt0 = 0.0, 0, None
+        while t < t_end * (1 - 1e-14):
+            r = float(self.ctx.cfl_rate(U, rate, stream=self.stream).item())
+            if not np.isfinite(r) or r <= 0.0:
+                raise FloatingPointError(f"non-physical state after {n} steps at t = {t:.6g}")
+            dt0 = cfl / r if dt0 is None else dt0
+            if cfl / r < collapse * dt0:
+                raise FloatingPointError(f"step size collapsed after {n} steps at t = {t:.6g}")
+            dt = min(cfl / r, t_end - t)
+            self.step(U, dt)
+            t += dt
+            n += 1
+            if on_step is not None:
+                on_step(n, t)
+            if n >= max_steps:
+                raise RuntimeError(f"more than {max_steps} steps")
+        return n, t

@@ -1,6 +1,8 @@
 """The SSP(5,4) time loop around the library's residual (Section 2.4) against
 the oracle's, and the isentropic-vortex convergence study of Section 3.1
 (Eq. 2DVortex, Table 1) on periodic triangle meshes."""
+import json
+
 import numpy as np
 import pytest
 
@@ -51,8 +53,8 @@ def test_time_loop_matches_oracle(hfv, prec, mode):
     w = configs.vortex_2d(16, 2)
     p = w.params.with_(scheme_mode=mode)
     ctx = hfv.Context(w.mesh, w.stencils, p, prec)
-    dt = cfl_dt(ctx, w.U, 0.6)
     U = to_dev(w.U, torch.float64 if prec == 64 else torch.float32)
+    dt = cfl_dt(ctx, to_dev(w.U, torch.float64) if prec == 64 else U, 0.6)
     rk = SSPRK54(ctx)
     for _ in range(3):
         rk.step(U, dt)
@@ -73,7 +75,7 @@ def vortex_errors(hfv, w, mode, prec=64, cfl=0.6, t_end=10.0):
     from paper_2510_25906_amd.timestep import SSPRK54, cfl_dt
     ctx = hfv.Context(w.mesh, w.stencils, w.params.with_(scheme_mode=mode), prec)
     U = to_dev(w.U, torch.float64 if prec == 64 else torch.float32)
-    steps, dt = SSPRK54(ctx).run(U, t_end, cfl_dt(ctx, w.U, cfl))
+    steps, dt = SSPRK54(ctx).run(U, t_end, cfl_dt(ctx, U, cfl))
     torch.cuda.synchronize()
     Uc = U.cpu().numpy().T.astype(np.float64)
     vol = ctx.table("GEOM")[2]
@@ -83,7 +85,8 @@ def vortex_errors(hfv, w, mode, prec=64, cfl=0.6, t_end=10.0):
 
 
 def test_vortex_convergence(hfv):
-    """Orders of accuracy after one period (t = 10, CFL 0.6, lambda_1' = 1e4)
+    """Orders of accuracy after one period (t = 10, CFL 0.6 of the spectral-radius
+    rate, fixed from the initial state, lambda_1' = 1e4)
     on 16 to 128 edges per side: third order at r = 2, fourth at r = 3, fifth
     at r = 4 in the limit.  The hybrid scheme runs as the linear scheme on this
     smooth flow: the NAD tags (almost) no cell, and where it tags one, CWENOZ's
@@ -125,3 +128,73 @@ def test_vortex_convergence(hfv):
     print("r  n  steps  linear Linf  L2  |  CWENOZ Linf  L2  |  max |hybrid - linear|")
     for row in table:
         print("%d %4d %5d  %.3e %.3e | %.3e %.3e | %.1e" % row, flush=True)
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_cfl_rate(hfv, prec):
+    """max over cells of (|u| + c) sum_f |S_f| / |V|, against NumPy on the
+    oracle's exact face areas and volumes; a non-physical cell gives +inf."""
+    w = configs.c2_riemann(32, 2)
+    ctx = hfv.Context(w.mesh, w.stencils, w.params, prec)
+    U = to_dev(w.U, torch.float64 if prec == 64 else torch.float32)
+    got = ctx.cfl_rate(U).item()
+    om = OracleModel(w.mesh, w.stencils, w.params)
+    Uh = U.double().cpu().numpy().T
+    rho, m, E = Uh[:, 0], Uh[:, 1:3], Uh[:, 3]
+    p = 0.4 * (E - 0.5 * (m * m).sum(1) / rho)
+    cf, off = w.mesh.cell_face, w.mesh.cell_face_off
+    perim = np.add.reduceat(om.geo.area[cf], off[:-1])
+    want = ((np.sqrt((m * m).sum(1)) / rho + np.sqrt(1.4 * p / rho)) * perim / om.geo.vol).max()
+    assert abs(got - want) <= (1e-12 if prec == 64 else 1e-6) * want, (got, want)   # FP32 weights
+    U[3, 17] = 0.0                                   # zero energy: negative pressure
+    assert ctx.cfl_rate(U).item() == float("inf")
+    ctx.close()
+
+
+def test_riemann_study_short_run(hfv):
+    """The time-integrated Riemann problem (Section 3.5) on a 64 x 64 mixed
+    mesh to t = 0.05: every variant stays physical, the default hybrid uses
+    all three reconstructions, all-CWENOZ tags every cell CWENOZ (or first
+    order), and the class fractions add up."""
+    from paper_2510_25906_amd import riemann_study as rs
+    w = configs.c2_riemann(64, 3, noise=0.0)
+    recs = {}
+    for name, mode, margins in rs.VARIANTS:
+        rec, Uh = rs.run_variant(w, name, mode, margins, 0.05, 0.6, 64, tune=False)
+        print(json.dumps(rec), flush=True)
+        assert rec["status"] == "ok" and rec["rho_min"] > 0 and np.isfinite(Uh).all(), name
+        f = rec["class_fractions"]
+        assert abs(sum(f.values()) - 1) < 1e-3          # fractions are reported rounded
+        recs[name] = rec
+    fd = recs["a_default"]["class_fractions"]
+    assert fd["linear"] > 0 and fd["cwenoz"] > 0 and fd["muscl"] > 0
+    fc = recs["all_cwenoz"]["final_class_fractions"]
+    assert fc[1] + fc[3] > 0.999
+    assert recs["c_linear_cwenoz"]["class_fractions"]["muscl"] == 0
+
+
+@pytest.mark.parametrize("preset", ["a_default", "d_linear_muscl"])
+def test_riemann_time_loop_matches_oracle(hfv, preset):
+    """Thirty SSP(5,4) steps of the four-quadrant Riemann problem (Section
+    3.5) on a 24 x 24 mixed mesh, shocks and all: the GPU time loop against
+    the oracle's, FP64, same step sizes."""
+    from paper_2510_25906_amd.inputs.params import PRESETS
+    from paper_2510_25906_amd.timestep import SSPRK54
+    w = configs.c2_riemann(24, 3, noise=0.0)
+    p = w.params.with_(**PRESETS[preset])
+    ctx = hfv.Context(w.mesh, w.stencils, p, 64)
+    U = to_dev(w.U, torch.float64)
+    rk = SSPRK54(ctx)
+    om = OracleModel(w.mesh, w.stencils, p)
+    U_o = w.U.copy()
+    from oracle import flux as oflux
+    Lo = lambda V: oflux.residual(om, V)[0].T
+    for k in range(30):
+        dt = 0.6 / ctx.cfl_rate(U).item()
+        rk.step(U, dt)
+        U_o = otime.step(Lo, U_o, dt)
+    torch.cuda.synchronize()
+    err = (np.abs(U.cpu().numpy().T - U_o) / np.abs(U_o).max(0)).max()
+    print(f"{preset}: 30 steps, max relative state error {err:.2e}", flush=True)
+    assert err <= 1e-10
+    ctx.close()
