@@ -72,6 +72,9 @@ enum { HFV_HLLC = 0, HFV_HLL = 1 };
 /* CWENOZ weight form: Z form w_s = l_s (1 + (tau/(eps+SI_s))^b) (default) or the
  * printed placement l_s (1 + tau^b/(eps+SI_s)) of Section 2.3 */
 enum { HFV_WENOZ_POW = 0, HFV_LITERAL = 1 };
+/* MUSCL slope limiter (Section 2.2; the comparison of Section 3.2): Barth-
+ * Jespersen (default) or Venkatakrishnan with eps^2 = (kappa h_c)^3 */
+enum { HFV_LIM_BJ = 0, HFV_LIM_VENKAT = 1 };
 /* cell classes written to cell_class[] */
 enum { HFV_CLASS_LINEAR = 0, HFV_CLASS_CWENOZ = 1, HFV_CLASS_MUSCL = 2, HFV_CLASS_FIRST_ORDER = 3 };
 
@@ -116,9 +119,11 @@ typedef struct {
 /* Parameters.  order_r is the polynomial degree r (order r+1, Section 2.1).
  * NAD margins alpha/beta (Eqs. marginm, marginw), deactivation
  * delta U < (kappa h_c)^n_exp (Eq. NADDeactivatedCriteria), CWENOZ lambda_1',
- * eps, b (Section 2.3), Harten theta, eps (Eq. harten_jump_fix). */
+ * eps, b (Section 2.3), Harten theta, eps (Eq. harten_jump_fix); limiter
+ * HFV_LIM_* of the MUSCL reconstruction (kappa also sets the Venkatakrishnan
+ * eps^2 = (kappa h_c)^3: the paper quotes kappa = 5 for both). */
 typedef struct {
-  int32_t order_r, scheme_mode, precision, riemann, cweno_form, reserved;
+  int32_t order_r, scheme_mode, precision, riemann, cweno_form, limiter;
   double gamma, alpha_m, beta_m, alpha_w, beta_w, kappa, n_exp, lambda1_prime, eps_w, b_w,
       tvd_theta, tvd_eps;
 } hfv_params;
@@ -191,7 +196,9 @@ hfv_status hfv_cfl_rate(hfv_ctx *ctx, const void *U, double *out, void *stream);
  * (class, Harten fallback, limiter argmin, Riemann branch) held at the
  * value the forward evaluation of U takes.
  *   cell_class  device [n_cells] classes from hfv_residual on the same U
- *   gR, gU      device [nvar][n_cells] */
+ *   gR, gU      device [nvar][n_cells]
+ * Differentiates the Barth-Jespersen limiter only: HFV_ERR_PARAM with the
+ * Venkatakrishnan limiter selected. */
 hfv_status hfv_residual_vjp(hfv_ctx *ctx, const void *U, const uint8_t *cell_class, const void *gR, void *gU,
                             void *stream);
 

@@ -35,7 +35,9 @@ Readings of the paper used here (each is also listed in the design notes):
 * Tagging: one max-dilation over face neighbours, after deactivation.
 * MUSCL: degree-1 least squares over the face neighbours (padded from the
   central stencil to d+1 cells), Barth-Jespersen limited per variable at the
-  face Gauss points against the NAD bounds m, M (Section 2.2).
+  face Gauss points against the NAD bounds m, M (Section 2.2); optionally
+  Venkatakrishnan's limiter (compared in Section 3.2, kappa = 5) with
+  eps^2 = (kappa h_c)^3, the same kappa as the deactivation.
 * Harten check on density and pressure at every face Gauss point of the final
   reconstruction, for every class (Eq. harten_jump_fix).
 """
@@ -50,6 +52,7 @@ from .quadrature import simplex_monomial_integrals
 
 LIN, CW, MU, FO = 0, 1, 2, 3
 HYBRID, ALL_LINEAR, ALL_CWENOZ, ALL_MUSCL = 0, 1, 2, 3
+BJ, VENKAT = 0, 1
 
 
 def basis_exponents(d: int, r: int) -> np.ndarray:
@@ -87,6 +90,16 @@ def _deriv_coef(alpha, beta):
         for t in range(b):
             c *= (a - t)
     return c
+
+
+def venkatakrishnan(dm, dp, eps2):
+    """Venkatakrishnan's limiter function (J. Comput. Phys. 118, 1995) for an
+    unlimited increment dm (nonzero) towards a face point and the room dp to
+    the neighbourhood bound in the same direction:
+        phi = (dp^2 + 2 dm dp + eps^2) / (dp^2 + 2 dm^2 + dm dp + eps^2),
+    which for eps = 0 is the function (y^2 + 2y) / (y^2 + y + 2) of y = dp/dm."""
+    with np.errstate(divide="ignore", invalid="ignore"):
+        return (dp * dp + 2.0 * dm * dp + eps2) / (dp * dp + 2.0 * dm * dm + dm * dp + eps2)
 
 
 class OracleModel:
@@ -315,7 +328,8 @@ class OracleModel:
         return fv, dict(om1=om1, oms=oms, SI1=SI1, SIs=SIs, tau=tau, lam1=lam1, lams=lams)
 
     def muscl(self, cells, U):
-        """MUSCL with the Barth-Jespersen limiter (Section 2.2)."""
+        """MUSCL (Section 2.2) with the Barth-Jespersen limiter, or with
+        Venkatakrishnan's (the comparison of Section 3.2), eps^2 = (kappa h)^3."""
         tab = self.tables(cells)
         d = self.d
         ids = np.where(self.st.muscl[cells] >= 0, self.st.muscl[cells], cells[:, None])
@@ -327,12 +341,17 @@ class OracleModel:
         Ui = U[cells]
         up = (M - Ui)[:, None, :]
         dn = (m - Ui)[:, None, :]
-        with np.errstate(divide="ignore", invalid="ignore"):
-            ratio = np.where(delta > 0, np.minimum(1.0, up / delta),
-                             np.where(delta < 0, np.minimum(1.0, dn / delta), 1.0))
+        if self.p.limiter == VENKAT:
+            room = np.where(delta > 0, up, dn)
+            eps2 = ((self.p.kappa * self.geo.h[cells]) ** 3)[:, None, None]
+            ratio = np.where(delta != 0, venkatakrishnan(delta, room, eps2), 1.0)
+        else:
+            with np.errstate(divide="ignore", invalid="ignore"):
+                ratio = np.where(delta > 0, np.minimum(1.0, up / delta),
+                                 np.where(delta < 0, np.minimum(1.0, dn / delta), 1.0))
         valid = np.arange(delta.shape[1])[None, :] < self.geo.c_ngp[cells][:, None]
         ratio = np.where(valid[..., None], ratio, 1.0)
-        theta = ratio.min(1)
+        theta = np.minimum(1.0, ratio.min(1))
         fv = Ui[:, None, :] + theta[:, None, :] * delta
         return fv, dict(theta=theta, g=g)
 

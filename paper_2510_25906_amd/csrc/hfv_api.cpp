@@ -29,6 +29,7 @@ static hfv_status check_params(const hfv_params *p, std::string &err) {
   if (p->scheme_mode < 0 || p->scheme_mode > 3) return err = "unknown scheme_mode", HFV_ERR_PARAM;
   if (p->riemann < 0 || p->riemann > 1) return err = "unknown riemann solver", HFV_ERR_PARAM;
   if (p->cweno_form < 0 || p->cweno_form > 1) return err = "unknown cweno_form", HFV_ERR_PARAM;
+  if (p->limiter != HFV_LIM_BJ && p->limiter != HFV_LIM_VENKAT) return err = "unknown limiter", HFV_ERR_PARAM;
   return HFV_OK;
 }
 
@@ -37,6 +38,7 @@ static void copy_params(hfv_ctx *ctx, const hfv_params *p) {
   ctx->p.mode = p->scheme_mode;
   ctx->p.riemann = p->riemann;
   ctx->p.form = p->cweno_form;
+  ctx->p.limiter = p->limiter;
   ctx->p.gamma = p->gamma;
   ctx->p.alpha_m = p->alpha_m;
   ctx->p.beta_m = p->beta_m;
@@ -267,6 +269,8 @@ hfv_status hfv_residual_vjp(hfv_ctx *ctx, const void *U, const uint8_t *cls, con
                             void *stream) {
   if (!ctx) return HFV_ERR_PARAM;
   if (!U || !cls || !gR || !gU) return ctx->err = "NULL device pointer", HFV_ERR_PARAM;
+  if (ctx->p.limiter != HFV_LIM_BJ)
+    return ctx->err = "the adjoint differentiates the Barth-Jespersen limiter only", HFV_ERR_PARAM;
   return run_vjp(ctx, U, cls, gR, gU, (hipStream_t)stream);
 }
 

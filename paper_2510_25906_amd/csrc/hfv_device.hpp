@@ -22,6 +22,7 @@ struct HotArgs {
   T gamma, alpha_m, beta_m, alpha_w, beta_w, lam1p, eps_w, b_w, theta, tvd_eps;
   int ib_w;  // b_w when it is an integer in [1, 8] (powers by multiplication), else 0
   int xcd;   // block ids remapped so each XCD takes one contiguous range (block_id)
+  int limiter;  // HFV_LIM_*
 };
 
 // Block id, optionally permuted.  The dispatcher hands workgroups to the 8

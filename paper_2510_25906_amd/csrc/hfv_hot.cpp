@@ -752,6 +752,8 @@ __global__ __launch_bounds__(256) void k_muscl(HotArgs<T> a, int direct) {
 #pragma unroll
     for (int j = 0; j < DIM; ++j) psb[j] = a.t.psibar[(long)j * N + cell];
     const int ng = a.t.ngp[cell];
+    const bool venkat = a.limiter == HFV_LIM_VENKAT;
+    const T e2 = venkat ? a.t.veps2[cell] : (T)0;
     T th[VPL];
 #pragma unroll
     for (int q = 0; q < VPL; ++q) th[q] = (T)1;
@@ -766,10 +768,13 @@ __global__ __launch_bounds__(256) void k_muscl(HotArgs<T> a, int direct) {
 #pragma unroll
         for (int j = 0; j < DIM; ++j) d += gr[j][q] * phi[j];
         T ratio = (T)1;
-        if (d > 0)
-          ratio = fmin((T)1, (mx[q] - u0[q]) / d);
-        else if (d < 0)
-          ratio = fmin((T)1, (mn[q] - u0[q]) / d);
+        if (d != 0) {
+          const T dp = (d > 0 ? mx[q] : mn[q]) - u0[q];   // room to the bound in the direction of d
+          if (venkat)   // smooth limiter function of Venkatakrishnan (1995)
+            ratio = ((dp * dp + e2) * d + (T)2 * d * d * dp) / (d * (dp * dp + (T)2 * d * d + dp * d + e2));
+          else          // Barth-Jespersen
+            ratio = fmin((T)1, dp / d);
+        }
         th[q] = fmin(th[q], ratio);
       }
     }
@@ -938,6 +943,7 @@ static HotArgs<T> make_args(hfv_ctx *ctx, Tables<T> &t, const void *U, void *fs,
   a.fs = (T *)fs;
   a.coef = (ctx->cw_reuse && ctx->p.mode == HFV_HYBRID) ? (T *)ctx->coef : nullptr;
   a.xcd = ctx->xcd_remap;
+  a.limiter = ctx->p.limiter;
   a.own = ctx->own;
   a.cls = cls;
   a.lists = ctx->lists;

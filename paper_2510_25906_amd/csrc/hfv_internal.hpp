@@ -63,6 +63,7 @@ struct Tables {
   int *nbr = nullptr;      // [NFM][N]   face neighbours, -1 at boundaries
   uint8_t *nfc = nullptr;  // [N]
   T *thr = nullptr;        // [N]  NAD deactivation threshold (kappa h)^n
+  T *veps2 = nullptr;      // [N]  Venkatakrishnan limiter eps^2 = (kappa h)^3
   T *OI = nullptr;         // [K(K+1)/2][N]
   int *dsten = nullptr;    // [NFM][Md][N]
   T *Pdir = nullptr;       // [NFM][DIM][Md][N]
@@ -89,7 +90,7 @@ struct Tables {
 };
 
 struct Params {
-  int order_r, mode, riemann, form;
+  int order_r, mode, riemann, form, limiter;
   double gamma, alpha_m, beta_m, alpha_w, beta_w, kappa, n_exp, lam1p, eps_w, b_w, theta, tvd_eps;
 };
 

@@ -620,10 +620,13 @@ __global__ void k_convert(long n, const double *src, T *dst) {
 }
 
 template <typename T>
-__global__ void k_thresholds(int N, int DIM, const double *geom, double kappa, double nexp, T *thr, T *ivol) {
+__global__ void k_thresholds(int N, int DIM, const double *geom, double kappa, double nexp, T *thr, T *ivol,
+                             T *veps2) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= N) return;
-  thr[c] = (T)pow(kappa * geom[(DIM + 1) * N + c], nexp);
+  const double kh = kappa * geom[(DIM + 1) * N + c];
+  thr[c] = (T)pow(kh, nexp);
+  veps2[c] = (T)(kh * kh * kh);
   ivol[c] = (T)(1.0 / geom[DIM * N + c]);
 }
 
@@ -862,7 +865,9 @@ static hfv_status setup_dr(hfv_ctx *ctx, const hfv_mesh *mesh, const hfv_stencil
     if ((e = conv(&tabs.gpw, gpw, (size_t)NGPT))) return e;
     if ((e = dev_alloc(ctx, (void **)&tabs.thr, sizeof(T) * N))) return e;
     if ((e = dev_alloc(ctx, (void **)&tabs.ivol, sizeof(T) * N))) return e;
-    k_thresholds<T><<<nblk(N, 256), 256, 0, s>>>(N, DIM, geom, ctx->p.kappa, ctx->p.n_exp, tabs.thr, tabs.ivol);
+    if ((e = dev_alloc(ctx, (void **)&tabs.veps2, sizeof(T) * N))) return e;
+    k_thresholds<T><<<nblk(N, 256), 256, 0, s>>>(N, DIM, geom, ctx->p.kappa, ctx->p.n_exp, tabs.thr, tabs.ivol,
+                                                 tabs.veps2);
     // integer tables (shared layout for both precisions)
     if ((e = dev_alloc(ctx, (void **)&tabs.ngp, N))) return e;
     HFV_HIP(hipMemcpyAsync(tabs.ngp, ngp, N, hipMemcpyDeviceToDevice, s));
@@ -1073,10 +1078,10 @@ hfv_status refresh_thresholds(hfv_ctx *ctx, hipStream_t s) {
   const int N = ctx->N;
   if (ctx->prec == 64)
     k_thresholds<double><<<nblk(N, 256), 256, 0, s>>>(N, ctx->dim, ctx->geom, ctx->p.kappa, ctx->p.n_exp,
-                                                      ctx->t64.thr, ctx->t64.ivol);
+                                                      ctx->t64.thr, ctx->t64.ivol, ctx->t64.veps2);
   else
     k_thresholds<float><<<nblk(N, 256), 256, 0, s>>>(N, ctx->dim, ctx->geom, ctx->p.kappa, ctx->p.n_exp,
-                                                     ctx->t32.thr, ctx->t32.ivol);
+                                                     ctx->t32.thr, ctx->t32.ivol, ctx->t32.veps2);
   HFV_HIP(hipGetLastError());
   return HFV_OK;
 }

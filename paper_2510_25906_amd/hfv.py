@@ -46,7 +46,7 @@ class HfvStencils(C.Structure):
 
 class HfvParams(C.Structure):
     _fields_ = [("order_r", C.c_int32), ("scheme_mode", C.c_int32), ("precision", C.c_int32),
-                ("riemann", C.c_int32), ("cweno_form", C.c_int32), ("reserved", C.c_int32),
+                ("riemann", C.c_int32), ("cweno_form", C.c_int32), ("limiter", C.c_int32),
                 ("gamma", C.c_double), ("alpha_m", C.c_double), ("beta_m", C.c_double), ("alpha_w", C.c_double),
                 ("beta_w", C.c_double), ("kappa", C.c_double), ("n_exp", C.c_double),
                 ("lambda1_prime", C.c_double), ("eps_w", C.c_double), ("b_w", C.c_double),
@@ -116,7 +116,7 @@ def _ptr(a, ctype):
 
 def params_struct(p: Params, precision: int) -> HfvParams:
     return HfvParams(order_r=p.order_r, scheme_mode=p.scheme_mode, precision=precision, riemann=p.riemann,
-                     cweno_form=p.cweno_form, reserved=0, gamma=p.gamma, alpha_m=p.alpha_m, beta_m=p.beta_m,
+                     cweno_form=p.cweno_form, limiter=p.limiter, gamma=p.gamma, alpha_m=p.alpha_m, beta_m=p.beta_m,
                      alpha_w=p.alpha_w, beta_w=p.beta_w, kappa=p.kappa, n_exp=p.n_exp,
                      lambda1_prime=p.lambda1_prime, eps_w=p.eps_w, b_w=p.b_w, tvd_theta=p.tvd_theta,
                      tvd_eps=p.tvd_eps)

@@ -13,6 +13,8 @@ MODE_NAMES = {HYBRID: "hybrid", ALL_LINEAR: "linear", ALL_CWENOZ: "cwenoz", ALL_
 HLLC, HLL = 0, 1
 # CWENOZ weight forms: the Z form (default) and the text's literal form
 WENOZ_POW, LITERAL = 0, 1
+# MUSCL slope limiters (Sections 2.2, 3.2): Barth-Jespersen, Venkatakrishnan
+BJ, VENKAT = 0, 1
 # cell classes, ordered by dissipation
 LINEAR_CLASS, CWENOZ_CLASS, MUSCL_CLASS, FIRST_ORDER_CLASS = 0, 1, 2, 3
 
@@ -23,6 +25,7 @@ class Params:
     scheme_mode: int = HYBRID
     riemann: int = HLLC
     cweno_form: int = WENOZ_POW
+    limiter: int = BJ
     gamma: float = 1.4
     # NAD margins (Eqs. marginm, marginw); default preset (a)
     alpha_m: float = 5e-3

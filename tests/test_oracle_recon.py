@@ -313,3 +313,46 @@ def test_hllc_hll_consistency_and_symmetry():
         Ls, Rs = fields.prim_to_cons(prim_s), fields.prim_to_cons(prim_s2)
         for fn in (flux.hllc, flux.hll):
             assert np.allclose(fn(Ls, Rs, n, 1.4), flux.euler_flux(Ls, n, 1.4), rtol=1e-13)
+
+
+def test_venkatakrishnan_limiter_function():
+    """Venkatakrishnan's function at eps = 0 is (y^2 + 2y)/(y^2 + y + 2) of
+    y = room / increment: 0 at y = 0, 3/4 at y = 1, 1 at y = 2, tending to 1,
+    increasing on [0, 2] and never above Barth-Jespersen's min(1, y) there;
+    a large eps switches limiting off."""
+    from oracle.reconstruction import venkatakrishnan
+    y = np.linspace(0.0, 2.0, 201)
+    phi = venkatakrishnan(np.ones_like(y), y, 0.0)
+    assert abs(phi[0]) < 1e-15 and abs(phi[100] - 0.75) < 1e-15 and abs(phi[-1] - 1.0) < 1e-15
+    assert np.all(np.diff(phi) > 0) and np.all(phi <= np.minimum(1.0, y) + 1e-15)
+    assert abs(venkatakrishnan(1.0, 1e6, 0.0) - 1.0) < 1e-5
+    # scale invariance at eps = 0, sign symmetry
+    assert abs(venkatakrishnan(-2.0, -1.0, 0.0) - venkatakrishnan(1.0, 0.5, 0.0)) < 1e-15
+    assert abs(venkatakrishnan(1e-3, 0.0, 1e3) - 1.0) < 1e-6
+
+
+def test_venkatakrishnan_muscl_is_exact_on_affine_data_without_limiting():
+    """With a huge kappa (eps^2 dominating every increment) the
+    Venkatakrishnan-limited MUSCL reproduces affine data exactly; with the
+    paper's kappa = 5 on a fine mesh it limits, and theta stays in (0, 1]."""
+    from paper_2510_25906_amd.inputs.params import ALL_MUSCL, VENKAT
+    w = configs.c1_density_jump(8, 2)
+    cells = np.arange(w.mesh.n_cells)
+    om = OracleModel(w.mesh, w.stencils, w.params.with_(scheme_mode=ALL_MUSCL, limiter=VENKAT, kappa=1e4))
+    a = np.array([[0.3, -0.2], [0.1, 0.4], [-0.5, 0.2], [0.2, 0.1]])   # [nvar, d]
+    b = np.array([2.0, 0.5, 0.7, 3.0])
+    x0 = np.array([0.5, 0.5])
+    cen = om.geo.cen
+    # cell averages of an affine field are its centroid values; the mesh is periodic, so
+    # use the field on a patch away from the wrap (interior cells only)
+    U = b[None, :] + (cen - x0) @ a.T
+    fv, info = om.muscl(cells, U)
+    inner = np.all(np.abs(cen - 0.5) < 0.3, axis=1)
+    x = om.geo.c_x[cells]
+    exact = b[None, None, :] + np.einsum("ngd,vd->ngv", x - x0, a)
+    valid = np.arange(x.shape[1])[None, :] < om.geo.c_ngp[cells][:, None]
+    err = np.abs(fv - exact)[inner][valid[inner]]
+    assert err.max() < 1e-10
+    om5 = OracleModel(w.mesh, w.stencils, w.params.with_(scheme_mode=ALL_MUSCL, limiter=VENKAT))
+    _, info5 = om5.muscl(cells, U)
+    assert np.all(info5["theta"] > 0) and np.all(info5["theta"] <= 1.0)
