@@ -23,7 +23,9 @@ median of single residuals started after a 1 GiB write that flushes the
 last-level cache (`ms_residual_cold`) and, on workloads whose field is
 smooth and known in closed form (the hexahedral Taylor-Green cases), the RMS
 error of its face states against the exact point values
-(`face_err_rms_rel`), the accuracy at which the modes are compared.
+(`face_err_rms_rel`), the accuracy at which the modes are compared.  FP32 modes report their face states' largest error against the
+FP64 path's on cells of equal class (`fp32_state_err_vs_fp64`) and the number
+of class flips (`fp32_class_flips`).
 Progress goes to stderr.
 """
 from __future__ import annotations
@@ -206,6 +208,22 @@ class FaceAccuracy:
         return float((np.sqrt(e2) / self.scale).max())
 
 
+def fp32_error(ref, fs32, cls32, ngp, U):
+    """FP32 face states against the FP64 path's (which the parity tests hold to
+    1e-12 of the FP64 oracle): largest error over the Gauss points of cells of
+    equal class, relative to the variable's largest cell average, and the number
+    of cells whose class differs (FP32 flips near an NAD threshold)."""
+    fs64, cls64 = ref
+    same = cls64 == cls32
+    valid = (np.arange(fs64.shape[0])[:, None] < ngp[None, :]) & same[None, :]     # [NGPC][N]
+    scale = np.abs(U).max(0)                                                        # [nvar]
+    err = 0.0
+    for v in range(fs64.shape[1]):
+        d = np.abs(fs32[:, v, :].astype(np.float64) - fs64[:, v, :])
+        err = max(err, float(np.where(valid, d, 0.0).max()) / scale[v])
+    return {"fp32_state_err_vs_fp64": float(f"{err:.4g}"), "fp32_class_flips": int((~same).sum())}
+
+
 def source_hash():
     h = hashlib.sha256()
     for f in sorted(os.listdir(CSRC)):
@@ -351,6 +369,7 @@ def main():
     log(f"copy probe {probe:.0f} GB/s")
     flush = torch.empty(1 << 28, dtype=torch.float32, device="cuda") if args.cold else None
     acc = None
+    ref64 = {}    # FP64 face states and classes per mode, for the FP32 error
     mesh = w.mesh
     N = mesh.n_cells
     names = {HYBRID: "hybrid", ALL_CWENOZ: "cwenoz", ALL_LINEAR: "linear"}
@@ -434,6 +453,11 @@ def main():
                 if acc is None:
                     acc = FaceAccuracy(ctx, w, bm.ngp)
                 face_err = acc.error(fs)
+            fp32_err = None
+            if prec == 64 and any(p_ == 32 for p_, m_ in variants if m_ == mode):
+                ref64[mode] = (fs.cpu().numpy(), cl_dev.copy())
+            elif prec == 32 and mode in ref64:
+                fp32_err = fp32_error(ref64.pop(mode), fs.cpu().numpy(), cl_dev, bm.ngp, w.U)
             cl = np.bincount(cl_dev, minlength=4)
             rec_b = sum(v for k, v in byts.items() if k not in ("flux", "gather"))
             modes[f"{name}_fp{prec}"] = {
@@ -453,6 +477,8 @@ def main():
                 modes[f"{name}_fp{prec}"]["ms_residual_cold"] = round(ms_cold, 4)
             if face_err is not None:
                 modes[f"{name}_fp{prec}"]["face_err_rms_rel"] = float(f"{face_err:.6g}")
+            if fp32_err is not None:
+                modes[f"{name}_fp{prec}"].update(fp32_err)
         ctx.close()
         del U, fs, cls, R
         torch.cuda.empty_cache()
