@@ -215,6 +215,9 @@ hfv_status hfv_set_launch(hfv_ctx *ctx, const hfv_launch *c) {
   if (c->fused_residual != 0 && c->fused_residual != 1)
     return ctx->err = "fused_residual must be 0 or 1", HFV_ERR_PARAM;
   if (c->xcd_remap != 0 && c->xcd_remap != 1) return ctx->err = "xcd_remap must be 0 or 1", HFV_ERR_PARAM;
+  const int ml = c->muscl_lanes;
+  if (!(ml == 0 || ml == 1 || ml == ctx->nvar || (ctx->dim == 2 && ml == 2)))
+    return ctx->err = "muscl_lanes must be 0, 1 or nvar (or 2 in 2D)", HFV_ERR_PARAM;
   ctx->lanes = lanes;
   ctx->block = c->block;
   ctx->list_blocks = c->list_blocks;
@@ -223,6 +226,7 @@ hfv_status hfv_set_launch(hfv_ctx *ctx, const hfv_launch *c) {
   ctx->cw_reuse = c->cwenoz_reuse;
   ctx->fused_residual = c->fused_residual;
   ctx->xcd_remap = c->xcd_remap;
+  ctx->muscl_lanes = c->muscl_lanes;
   return HFV_OK;
 }
 
@@ -236,6 +240,7 @@ hfv_status hfv_get_launch(const hfv_ctx *ctx, hfv_launch *c) {
   c->cwenoz_reuse = ctx->cw_reuse;
   c->fused_residual = ctx->fused_residual;
   c->xcd_remap = ctx->xcd_remap;
+  c->muscl_lanes = ctx->muscl_lanes;
   return HFV_OK;
 }
 

@@ -990,6 +990,28 @@ static void launch_linear(const hfv_ctx *ctx, const HotArgs<T> &a, hipStream_t s
   }
 }
 
+// The MUSCL / first-order pass with its own lane count (muscl_lanes, or the
+// class-list kernels' lanes_per_cell when 0) and the grid that count needs.
+template <int DIM, int R, typename T, int G>
+static void launch_muscl_g(hfv_ctx *ctx, const HotArgs<T> &a, int direct, hipStream_t s) {
+  const int B = ctx->block;
+  const long waves = ((long)ctx->N + 64 / G - 1) / (64 / G);
+  const unsigned grid_cells = nblk(waves * 64, B);
+  const unsigned grid =
+      ctx->list_blocks > 0 ? std::min<unsigned>(grid_cells, (unsigned)ctx->list_blocks) : grid_cells;
+  k_muscl<DIM, R, T, G><<<grid, B, 0, s>>>(a, direct);
+}
+template <int DIM, int R, typename T>
+static void launch_muscl(hfv_ctx *ctx, const HotArgs<T> &a, int direct, hipStream_t s) {
+  const int l = ctx->muscl_lanes ? ctx->muscl_lanes : ctx->lanes;
+  if (l == 1)
+    launch_muscl_g<DIM, R, T, 1>(ctx, a, direct, s);
+  else if (l == DIM + 2)
+    launch_muscl_g<DIM, R, T, DIM + 2>(ctx, a, direct, s);
+  else if constexpr (DIM == 2)
+    launch_muscl_g<DIM, R, T, 2>(ctx, a, direct, s);
+}
+
 template <int DIM, int R, typename T, int G>
 static hfv_status recon_impl(hfv_ctx *ctx, Tables<T> &t, const void *U, void *fs, uint8_t *cls, hipStream_t s) {
   HotArgs<T> a = make_args<T>(ctx, t, U, fs, cls);
@@ -1005,7 +1027,7 @@ static hfv_status recon_impl(hfv_ctx *ctx, Tables<T> &t, const void *U, void *fs
     { ProfScope ps(ctx, HFV_SLOT_CWENOZ, s); k_cwenoz<DIM, R, T, G, false><<<grid_list, B, 0, s>>>(a, 1); }
   } else if (mode == HFV_ALL_MUSCL) {
     k_zero_counts<<<1, 64, 0, s>>>(ctx->counts);
-    { ProfScope ps(ctx, HFV_SLOT_MUSCL, s); k_muscl<DIM, R, T, G><<<grid_list, B, 0, s>>>(a, 1); }
+    { ProfScope ps(ctx, HFV_SLOT_MUSCL, s); launch_muscl<DIM, R, T>(ctx, a, 1, s); }
   } else {
     { ProfScope ps(ctx, HFV_SLOT_LINEAR, s); launch_linear<DIM, R, T>(ctx, a, s); }
     { ProfScope ps(ctx, HFV_SLOT_CLASSIFY, s); k_classify<T><<<nblk(ctx->N, CLASSIFY_BLOCK), CLASSIFY_BLOCK, 0, s>>>(a, ctx->NFM); }
@@ -1017,7 +1039,7 @@ static hfv_status recon_impl(hfv_ctx *ctx, Tables<T> &t, const void *U, void *fs
         k_cwenoz<DIM, R, T, G, false><<<grid_list, B, 0, s>>>(a, 0);
     }
     // MUSCL list (empty unless hybrid) and the first-order list
-    { ProfScope ps(ctx, HFV_SLOT_MUSCL, s); k_muscl<DIM, R, T, G><<<grid_list, B, 0, s>>>(a, 0); }
+    { ProfScope ps(ctx, HFV_SLOT_MUSCL, s); launch_muscl<DIM, R, T>(ctx, a, 0, s); }
   }
   HFV_HIP(hipGetLastError());
   return HFV_OK;
@@ -1042,7 +1064,7 @@ static hfv_status frozen_impl(hfv_ctx *ctx, Tables<T> &t, const void *U, void *f
   launch_linear<DIM, R, T>(ctx, a, s);
   k_classify<T><<<nblk(ctx->N, CLASSIFY_BLOCK), CLASSIFY_BLOCK, 0, s>>>(a, ctx->NFM);
   k_cwenoz<DIM, R, T, G, false><<<grid_list, B, 0, s>>>(a, 0);
-  k_muscl<DIM, R, T, G><<<grid_list, B, 0, s>>>(a, 0);
+  launch_muscl<DIM, R, T>(ctx, a, 0, s);
   HFV_HIP(hipGetLastError());
   return HFV_OK;
 }

@@ -13,7 +13,8 @@
 //      i.e. in all-linear mode, where only first-order cells use them);
 //   3. in hybrid mode, whether CWENOZ reuses the linear pass's central fits;
 //   4. the fused (owner-computes) residual kernel against face fluxes + gather;
-//   5. XCD-contiguous block order against plain block order.
+//   5. XCD-contiguous block order against plain block order;
+//   6. in hybrid mode, the MUSCL pass's own lane count.
 // Each candidate runs once untimed, then `reps` times with HIP events around
 // each call; its score is the median.
 #include <algorithm>
@@ -149,6 +150,17 @@ extern "C" hfv_status hfv_autotune(hfv_ctx *ctx, const void *U, int32_t reps, hf
       hfv_launch c = best;
       c.xcd_remap = 1 - best.xcd_remap;
       tu.pick({c}, best, best_ms);
+    }
+    // 6. MUSCL lanes (0 = as the other class-list kernels)
+    if (ctx->p.mode == HFV_HYBRID) {
+      cands.clear();
+      for (int l : var_lanes)
+        if (l != best.lanes_per_cell) {
+          hfv_launch c = best;
+          c.muscl_lanes = l;
+          cands.push_back(c);
+        }
+      tu.pick(cands, best, best_ms);
     }
     if (hfv_set_launch(ctx, &best) != HFV_OK) st = HFV_ERR_PARAM;
   } else {
