@@ -20,7 +20,8 @@ the live measurement of the kernel that takes the most time in the headline
 hybrid residual, against the 8 TB/s peak and against the bandwidth a plain
 1 GiB device copy reaches in the same process.  Each mode also reports the
 median of single residuals started after a 1 GiB write that flushes the
-last-level cache (`ms_residual_cold`) and, on workloads whose field is
+last-level cache (`ms_residual_cold`), the step captured once into a HIP graph
+and replayed (`ms_residual_graph`) and, on workloads whose field is
 smooth and known in closed form (the hexahedral Taylor-Green cases), the RMS
 error of its face states against the exact point values
 (`face_err_rms_rel`), the accuracy at which the modes are compared.  FP32 modes report their face states' largest error against the
@@ -448,6 +449,10 @@ def main():
                 headline = ms_res
                 classes = np.bincount(cl_dev, minlength=4)
             ms_cold = time_cold(lambda: ctx.residual(U, R, fs, cls), args.cold, flush, torch) if args.cold else None
+            # the same step captured once into a HIP graph and replayed (one launch per step)
+            graph = ctx.graph_residual(U, R, fs, cls)
+            ms_graph = time_steps(graph.replay, args.steps, args.warmup, torch)
+            del graph
             face_err = None
             if w.exact is not None:
                 if acc is None:
@@ -473,6 +478,7 @@ def main():
                                     for k in kern if k in byts},
                 "launch": launch, "tune_s": round(t_tune, 2), "setup_s": round(t_setup, 3),
             }
+            modes[f"{name}_fp{prec}"]["ms_residual_graph"] = round(ms_graph, 4)
             if ms_cold is not None:
                 modes[f"{name}_fp{prec}"]["ms_residual_cold"] = round(ms_cold, 4)
             if face_err is not None:

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhfv.so")
 _lib = None
 
 HFV_OK = 0
+HFV_ERR_STATE = -7
 ERRORS = {-1: "HFV_ERR_PARAM", -2: "HFV_ERR_MESH", -3: "HFV_ERR_RANK", -4: "HFV_ERR_DTYPE",
           -5: "HFV_ERR_HIP", -6: "HFV_ERR_OOM", -7: "HFV_ERR_STATE"}
 Q = dict(N_CELLS=0, N_FACES=1, N_GP=2, NVAR=3, K=4, M=5, PRECISION=6, DIM=7, TABLE_BYTES=8,
@@ -241,6 +242,10 @@ class Context:
     def profile_enable(self, capacity: int, slots=None):
         mask = 0xff if slots is None else sum(1 << SLOTS[k] for k in slots)
         self._check(self.lib.hfv_profile_enable(self.h, capacity, mask))
+        self._prof_on = capacity > 0
+
+    def prof_enabled(self) -> bool:
+        return getattr(self, "_prof_on", False)
 
     def profile_read(self):
         """{slot: (total ms, launches)} of the timed launches since the last read."""
@@ -294,6 +299,27 @@ class Context:
         self._check(self.lib.hfv_residual(self.h, C.c_void_p(U.data_ptr()), C.c_void_p(R.data_ptr()), fsp, clp,
                                           _stream_handle(stream)))
         return R
+
+    def graph_residual(self, U, R, face_states=None, cell_class=None):
+        """Capture one residual evaluation on these buffers into a HIP graph
+        (torch.cuda.CUDAGraph); `graph.replay()` then re-runs the whole hot path
+        with one launch.  The graph keeps the buffers' addresses: refill U in
+        place between replays.  The launch configuration and parameters in
+        force at capture are baked in.  The library's per-kernel timing must be
+        off while capturing."""
+        import torch
+        if self.prof_enabled():
+            raise HfvError(HFV_ERR_STATE, "disable hfv kernel timing before capturing a graph")
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):                    # warm-up outside the capture
+            self.residual(U, R, face_states, cell_class)
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.residual(U, R, face_states, cell_class)
+        return g
 
     def residual_vjp(self, U, cell_class, gR, gU=None, stream=None):
         import torch

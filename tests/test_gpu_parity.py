@@ -252,3 +252,49 @@ def test_autotune_keeps_results(hfv, c1):
     assert np.array_equal(cls.cpu().numpy(), cls_o)
     assert states_err(fs, fs_o, om.geo, state_scale(w.U)) <= 1e-12
     ctx.close()
+
+
+def test_gauss_point_frame_table(hfv, c1):
+    """HFV_T_GP_XI: every cell's Gauss-point slots in its own frame,
+    (x - x_c) / h_c, against the oracle's per-cell Gauss points; padded slots
+    hold 0."""
+    w, om = c1
+    ctx = hfv.Context(w.mesh, w.stencils, w.params, 64)
+    xi = ctx.table("GP_XI")                              # [NGPC][d][N]
+    geo = om.geo
+    want = (geo.c_x - geo.cen[:, None, :]) / geo.h[:, None, None]   # [N][NGPC][d]
+    valid = np.arange(xi.shape[0])[None, :] < geo.c_ngp[:, None]
+    got = xi.transpose(2, 0, 1)
+    assert np.abs(np.where(valid[..., None], got - want, 0.0)).max() <= 1e-12
+    assert np.all(np.where(valid[..., None], 0.0, got) == 0.0)
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_graph_replays_match_eager(hfv, c1, prec):
+    """A residual captured into a HIP graph and replayed several times, with
+    eager work and synchronisations between the replays and a new state
+    written into the captured input each time, gives the eager residual bit
+    for bit every time."""
+    w, _ = c1
+    dt = torch.float64 if prec == 64 else torch.float32
+    ctx = hfv.Context(w.mesh, w.stencils, w.params, prec)
+    U = to_dev(w.U, dt)
+    R = torch.empty_like(U)
+    fs = ctx.new_face_states()
+    cls = torch.empty(w.mesh.n_cells, dtype=torch.uint8, device="cuda")
+    g = ctx.graph_residual(U, R, fs, cls)
+    rng = np.random.default_rng(5)
+    for k in range(4):
+        Uk = w.U * (1.0 + 0.01 * k * rng.uniform(-1, 1, size=w.U.shape))
+        U.copy_(to_dev(Uk, dt))
+        g.replay()
+        torch.cuda.synchronize()
+        R_graph, cls_graph = R.clone(), cls.clone()
+        R_eager = ctx.residual(U.clone())                 # eager evaluation on the same state
+        cls_eager = torch.empty_like(cls)
+        ctx.residual(U.clone(), cell_class=cls_eager)
+        torch.cuda.synchronize()
+        assert torch.equal(R_graph, R_eager), k
+        assert torch.equal(cls_graph, cls_eager), k
+    ctx.close()
