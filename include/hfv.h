@@ -197,8 +197,8 @@ hfv_status hfv_cfl_rate(hfv_ctx *ctx, const void *U, double *out, void *stream);
  * value the forward evaluation of U takes.
  *   cell_class  device [n_cells] classes from hfv_residual on the same U
  *   gR, gU      device [nvar][n_cells]
- * Differentiates the Barth-Jespersen limiter only: HFV_ERR_PARAM with the
- * Venkatakrishnan limiter selected. */
+ * Either MUSCL limiter is differentiated through its limiting Gauss point and
+ * the neighbour that sets the bound. */
 hfv_status hfv_residual_vjp(hfv_ctx *ctx, const void *U, const uint8_t *cell_class, const void *gR, void *gU,
                             void *stream);
 

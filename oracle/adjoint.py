@@ -6,8 +6,9 @@ PyTorch CPU float64 operations, step by step as in ``reconstruction`` and
 constants; torch autograd then gives the exact vector-Jacobian product.
 Switch conventions match the library: the class of every cell, the Harten
 fallback and the CWENOZ |SI_s - SI_1| sign (0 at a tie) are frozen; the
-Barth-Jespersen limiter differentiates through its minimising Gauss point
-and bound cell; the Riemann solver through its active branch.
+Barth-Jespersen and Venkatakrishnan limiters differentiate through their
+minimising Gauss point and bound cell; the Riemann solver through its active
+branch.
 
 Pinned in tests against central finite differences of the NumPy oracle.
 """
@@ -16,7 +17,7 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-from .reconstruction import OracleModel, LIN, CW, MU
+from .reconstruction import OracleModel, LIN, CW, MU, VENKAT
 
 
 def _t(x):
@@ -62,7 +63,7 @@ def frozen_face_values(model: OracleModel, U: torch.Tensor, cls: np.ndarray) -> 
     tot = w1 + ws.sum(1)
     a_cw = (w1 / tot)[:, None, :] * a1 + torch.einsum("nfv,nfkv->nkv", ws / tot[:, None, :], a_hat)
     fv_cw = U0 + torch.einsum("ngk,nkv->ngv", phi, a_cw)
-    # MUSCL + Barth-Jespersen (Section 2.2)
+    # MUSCL + Barth-Jespersen or Venkatakrishnan (Sections 2.2, 3.2)
     mid = np.where(st.muscl >= 0, st.muscl, cells[:, None]).astype(np.int64)
     g = torch.einsum("njm,nmv->njv", _t(tab["Pmus"]), U[_t(mid)] - U0)
     delta = torch.einsum("ngj,njv->ngv", phi[..., :d], g)
@@ -75,11 +76,20 @@ def frozen_face_values(model: OracleModel, U: torch.Tensor, cls: np.ndarray) -> 
     dn = (mn - U)[:, None, :]
     safe = torch.where(delta == 0, torch.ones_like(delta), delta)
     one = torch.ones_like(delta)
-    ratio = torch.where(delta > 0, torch.minimum(one, up / safe),
-                        torch.where(delta < 0, torch.minimum(one, dn / safe), one))
+    if p.limiter == VENKAT:
+        room = torch.where(delta > 0, up, dn)
+        eps2 = _t((p.kappa * model.geo.h) ** 3)[:, None, None]
+        num = room * room + 2.0 * delta * room + eps2
+        den = room * room + 2.0 * delta * delta + delta * room + eps2
+        ratio = torch.where(delta != 0, num / den, one)
+    else:
+        ratio = torch.where(delta > 0, torch.minimum(one, up / safe),
+                            torch.where(delta < 0, torch.minimum(one, dn / safe), one))
     valid = _t(np.arange(phi.shape[1])[None, :] < model.geo.c_ngp[:, None])[..., None]
     ratio = torch.where(valid, ratio, one)
     theta = ratio.min(1).values
+    if p.limiter == VENKAT:          # its function exceeds 1 past twice the room; theta stays <= 1
+        theta = torch.clamp(theta, max=1.0)
     fv_mu = U0 + theta[:, None, :] * delta
     c = _t(cls.astype(np.int64))[:, None, None]
     return torch.where(c == LIN, fv_lin, torch.where(c == CW, fv_cw, torch.where(c == MU, fv_mu, U0.expand_as(fv_lin))))

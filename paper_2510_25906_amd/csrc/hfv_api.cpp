@@ -274,8 +274,6 @@ hfv_status hfv_residual_vjp(hfv_ctx *ctx, const void *U, const uint8_t *cls, con
                             void *stream) {
   if (!ctx) return HFV_ERR_PARAM;
   if (!U || !cls || !gR || !gU) return ctx->err = "NULL device pointer", HFV_ERR_PARAM;
-  if (ctx->p.limiter != HFV_LIM_BJ)
-    return ctx->err = "the adjoint differentiates the Barth-Jespersen limiter only", HFV_ERR_PARAM;
   return run_vjp(ctx, U, cls, gR, gU, (hipStream_t)stream);
 }
 

@@ -22,7 +22,7 @@ namespace hfv {
 
 template <typename T>
 struct VjpArgs {
-  int N, form;
+  int N, form, limiter;
   const T *U;
   const uint8_t *cls;
   const T *gfs;
@@ -344,7 +344,7 @@ __global__ __launch_bounds__(256) void k_recon_vjp(VjpArgs<T> a) {
     return;
   }
 
-  // ---- MUSCL with the Barth-Jespersen limiter (Section 2.2)
+  // ---- MUSCL with the Barth-Jespersen or Venkatakrishnan limiter (Sections 2.2, 3.2)
   for (int m = 0; m < M; ++m) C[m * MS] = 0;
   const int nm = t.nmus[cell];
   T gr[DIM];
@@ -372,7 +372,10 @@ __global__ __launch_bounds__(256) void k_recon_vjp(VjpArgs<T> a) {
       }
     }
   }
-  T th = 1, dstar = 0;
+  // theta = min over the points of the limiter function, as in the forward pass
+  const bool venkat = a.limiter == HFV_LIM_VENKAT;
+  const T e2 = venkat ? t.veps2[cell] : (T)0;
+  T th = 1, dstar = 0, dpstar = 0;
   int gstar = -1;
   for (int g = 0; g < ng; ++g) {
     T xi[DIM];
@@ -380,15 +383,19 @@ __global__ __launch_bounds__(256) void k_recon_vjp(VjpArgs<T> a) {
     T d = 0;
 #pragma unroll
     for (int j = 0; j < DIM; ++j) d += gr[j] * (xi[j] - psb[j]);
-    T ratio = 1;
-    if (d > 0)
-      ratio = fmin((T)1, (mx - u0) / d);
-    else if (d < 0)
-      ratio = fmin((T)1, (mn - u0) / d);
+    T ratio = 1, dp = 0;
+    if (d != 0) {
+      dp = (d > 0 ? mx : mn) - u0;
+      if (venkat)
+        ratio = ((dp * dp + e2) * d + (T)2 * d * d * dp) / (d * (dp * dp + (T)2 * d * d + dp * d + e2));
+      else
+        ratio = fmin((T)1, dp / d);
+    }
     if (ratio < th) {
       th = ratio;
       gstar = g;
       dstar = d;
+      dpstar = dp;
     }
   }
   T gth = 0, gg[DIM];
@@ -407,8 +414,21 @@ __global__ __launch_bounds__(256) void k_recon_vjp(VjpArgs<T> a) {
     for (int j = 0; j < DIM; ++j) gg[j] += th * gq * (xi[j] - psb[j]);
   }
   T self = gsum;
-  if (gstar >= 0) {  // theta = (bound - U_i) / Delta at the limiting point
-    const T ginv = gth / dstar;
+  if (gstar >= 0) {
+    // theta as a function of the room dp = bound - U_i and the increment d at
+    // the limiting point: Barth-Jespersen dp / d; Venkatakrishnan
+    // (dp^2 + 2 d dp + e2) / (dp^2 + 2 d^2 + d dp + e2)
+    T th_dp, th_d;
+    if (venkat) {
+      const T num = dpstar * dpstar + (T)2 * dstar * dpstar + e2;
+      const T den = dpstar * dpstar + (T)2 * dstar * dstar + dstar * dpstar + e2;
+      th_dp = (((T)2 * dpstar + (T)2 * dstar) * den - num * ((T)2 * dpstar + dstar)) / (den * den);
+      th_d = ((T)2 * dpstar * den - num * ((T)4 * dstar + dpstar)) / (den * den);
+    } else {
+      th_dp = (T)1 / dstar;
+      th_d = -th / dstar;
+    }
+    const T ginv = gth * th_dp;
     self -= ginv;
     const int ib = dstar > 0 ? imx : imn;
     if (ib < 0)
@@ -417,7 +437,7 @@ __global__ __launch_bounds__(256) void k_recon_vjp(VjpArgs<T> a) {
       C[(long)t.nbpos[(long)ib * N + cell] * MS] += ginv;
     T xi[DIM];
     xi_at(gstar, xi);
-    const T gd = -gth * th / dstar;
+    const T gd = gth * th_d;
 #pragma unroll
     for (int j = 0; j < DIM; ++j) gg[j] += gd * (xi[j] - psb[j]);
   }
@@ -465,6 +485,7 @@ static hfv_status vjp_impl(hfv_ctx *ctx, Tables<T> &t, const void *U, const uint
   VjpArgs<T> a;
   a.N = ctx->N;
   a.form = ctx->p.form;
+  a.limiter = ctx->p.limiter;
   a.U = (const T *)U;
   a.cls = cls;
   a.gfs = (const T *)ctx->vjp_gfs;

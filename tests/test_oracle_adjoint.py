@@ -10,7 +10,7 @@ from oracle.adjoint import frozen_residual, residual_vjp
 from paper_2510_25906_amd.inputs import configs, fields
 from paper_2510_25906_amd.inputs.mesh import tet_box
 from paper_2510_25906_amd.inputs.stencil import build_stencils, cell_centroids
-from paper_2510_25906_amd.inputs.params import Params
+from paper_2510_25906_amd.inputs.params import Params, VENKAT
 
 
 def tet_case(r=3):
@@ -35,6 +35,8 @@ def cases():
     yield "c1_16", w.mesh, w.stencils, noisy(w.U), w.params
     yield "c1_16_muscl", w.mesh, w.stencils, noisy(w.U), w.params.with_(scheme_mode=3)
     yield "c1_16_cwenoz_literal", w.mesh, w.stencils, noisy(w.U), w.params.with_(scheme_mode=2, cweno_form=1)
+    yield "c1_16_muscl_venkat", w.mesh, w.stencils, noisy(w.U), w.params.with_(scheme_mode=3, limiter=VENKAT)
+    yield "c1_16_venkat", w.mesh, w.stencils, noisy(w.U), w.params.with_(limiter=VENKAT)
     w = configs.c2_riemann(12, 3)
     yield "c2_12", w.mesh, w.stencils, w.U, w.params
     yield ("tet3",) + tet_case()
