@@ -226,9 +226,14 @@ def fp32_error(ref, fs32, cls32, ngp, U):
     return {"fp32_state_err_vs_fp64": float(f"{err:.4g}"), "fp32_class_flips": int((~same).sum())}
 
 
+# the sources the forward hot-path kernels are compiled from: a change to any of
+# them invalidates counter records taken before it
+HOT_SOURCES = ("hfv_hot.cpp", "hfv_device.hpp", "hfv_internal.hpp")
+
+
 def source_hash():
     h = hashlib.sha256()
-    for f in sorted(os.listdir(CSRC)):
+    for f in HOT_SOURCES:
         with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
