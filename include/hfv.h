@@ -165,7 +165,8 @@ hfv_status hfv_residual(hfv_ctx *ctx, const void *U, void *R, void *face_states,
 /* Residual with given cell classes (the switches of a previous evaluation
  * held fixed): the reconstruction of each cell follows cell_class, with no
  * NAD and no Harten re-check.  The residual a VJP linearises.
- *   cell_class  device [n_cells] classes (HFV_CLASS_*), read only */
+ *   cell_class  device [n_cells] classes (HFV_CLASS_*), read only; a value
+ *               above HFV_CLASS_FIRST_ORDER is taken as first order */
 hfv_status hfv_residual_frozen(hfv_ctx *ctx, const void *U, const uint8_t *cell_class, void *R, void *stream);
 
 /* One stage of an explicit Runge-Kutta method in Shu-Osher form, the form of
@@ -195,7 +196,8 @@ hfv_status hfv_cfl_rate(hfv_ctx *ctx, const void *U, double *out, void *stream);
  * project addition, not in the paper):  gU = (dR/dU)^T gR, every switch
  * (class, Harten fallback, limiter argmin, Riemann branch) held at the
  * value the forward evaluation of U takes.
- *   cell_class  device [n_cells] classes from hfv_residual on the same U
+ *   cell_class  device [n_cells] classes from hfv_residual on the same U (a
+ *               value above HFV_CLASS_FIRST_ORDER is taken as first order)
  *   gR, gU      device [nvar][n_cells]
  * Either MUSCL limiter is differentiated through its limiting Gauss point and
  * the neighbour that sets the bound. */

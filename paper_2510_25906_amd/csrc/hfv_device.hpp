@@ -225,57 +225,21 @@ __device__ inline void store(const HotArgs<T> &a, int g, int cell, int v, T val)
   a.fs[((long)g * NV + v) * a.N + cell] = val;
 }
 
-// ---------------------------------------------------------------------------
-// Forward-mode dual number (one tangent) for exact Jacobian columns of the
-// Riemann fluxes in the adjoint; branches follow the primal value.
-using ::fmax;
-using ::fmin;
-using ::sqrt;
-template <typename T>
-struct Dual {
-  T v, d;
-  __device__ Dual() : v(0), d(0) {}
-  __device__ Dual(T a) : v(a), d(0) {}
-  __device__ Dual(T a, T b) : v(a), d(b) {}
-};
-template <typename T> __device__ inline Dual<T> operator+(Dual<T> a, Dual<T> b) { return {a.v + b.v, a.d + b.d}; }
-template <typename T> __device__ inline Dual<T> operator-(Dual<T> a, Dual<T> b) { return {a.v - b.v, a.d - b.d}; }
-template <typename T> __device__ inline Dual<T> operator-(Dual<T> a) { return {-a.v, -a.d}; }
-template <typename T> __device__ inline Dual<T> operator*(Dual<T> a, Dual<T> b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
-template <typename T> __device__ inline Dual<T> operator/(Dual<T> a, Dual<T> b) {
-  const T q = a.v / b.v;
-  return {q, (a.d - q * b.d) / b.v};
-}
-template <typename T> __device__ inline Dual<T> operator+(T a, Dual<T> b) { return {a + b.v, b.d}; }
-template <typename T> __device__ inline Dual<T> operator-(T a, Dual<T> b) { return {a - b.v, -b.d}; }
-template <typename T> __device__ inline Dual<T> operator*(T a, Dual<T> b) { return {a * b.v, a * b.d}; }
-template <typename T> __device__ inline Dual<T> operator*(Dual<T> a, T b) { return {a.v * b, a.d * b}; }
-template <typename T> __device__ inline Dual<T> &operator+=(Dual<T> &a, Dual<T> b) { a = a + b; return a; }
-template <typename T> __device__ inline Dual<T> sqrt(Dual<T> a) {
-  const T r = sqrt(a.v);
-  return {r, a.d / (2 * r)};
-}
-template <typename T> __device__ inline Dual<T> fmin(Dual<T> a, Dual<T> b) { return a.v <= b.v ? a : b; }
-template <typename T> __device__ inline Dual<T> fmax(Dual<T> a, Dual<T> b) { return a.v >= b.v ? a : b; }
-template <typename T> __device__ inline T primal(T a) { return a; }
-template <typename T> __device__ inline T primal(Dual<T> a) { return a.v; }
-
 // Riemann fluxes (Section 2.4): HLLC and HLL with Davis wave-speed estimates.
-// S is the state type (a scalar or a dual number), T the scalar type.
-template <int DIM, typename S, typename T>
-__device__ inline void euler_flux(const S (&q)[DIM + 2], const T (&n)[DIM], S p, S un, S (&F)[DIM + 2]) {
+template <int DIM, typename T>
+__device__ inline void euler_flux(const T (&q)[DIM + 2], const T (&n)[DIM], T p, T un, T (&F)[DIM + 2]) {
   F[0] = q[0] * un;
 #pragma unroll
   for (int j = 0; j < DIM; ++j) F[1 + j] = q[1 + j] * un + p * n[j];
   F[DIM + 1] = un * (q[DIM + 1] + p);
 }
 
-template <int DIM, typename S, typename T>
-__device__ inline void riemann(const S (&qL)[DIM + 2], const S (&qR)[DIM + 2], const T (&n)[DIM], T gamma,
-                               int hllc, S (&F)[DIM + 2]) {
+template <int DIM, typename T>
+__device__ inline void riemann(const T (&qL)[DIM + 2], const T (&qR)[DIM + 2], const T (&n)[DIM], T gamma,
+                               int hllc, T (&F)[DIM + 2]) {
   constexpr int NV = DIM + 2;
-  const S rL = qL[0], rR = qR[0];
-  S vL[DIM], vR[DIM], unL = S(0), unR = S(0), kL = S(0), kR = S(0);
+  const T rL = qL[0], rR = qR[0];
+  T vL[DIM], vR[DIM], unL = T(0), unR = T(0), kL = T(0), kR = T(0);
 #pragma unroll
   for (int j = 0; j < DIM; ++j) {
     vL[j] = qL[1 + j] / rL;
@@ -286,20 +250,20 @@ __device__ inline void riemann(const S (&qL)[DIM + 2], const S (&qR)[DIM + 2], c
     kR += vR[j] * vR[j];
   }
   const T gm1 = gamma - (T)1, half = (T)0.5;
-  const S pL = gm1 * (qL[NV - 1] - half * rL * kL);
-  const S pR = gm1 * (qR[NV - 1] - half * rR * kR);
-  const S cL = sqrt(gamma * pL / rL), cR = sqrt(gamma * pR / rR);
-  const S SL = fmin(unL - cL, unR - cR), SR = fmax(unL + cL, unR + cR);
-  S FL[NV], FR[NV];
-  euler_flux<DIM, S, T>(qL, n, pL, unL, FL);
-  euler_flux<DIM, S, T>(qR, n, pR, unR, FR);
-  if (primal(SL) >= (T)0) {
+  const T pL = gm1 * (qL[NV - 1] - half * rL * kL);
+  const T pR = gm1 * (qR[NV - 1] - half * rR * kR);
+  const T cL = sqrt(gamma * pL / rL), cR = sqrt(gamma * pR / rR);
+  const T SL = fmin(unL - cL, unR - cR), SR = fmax(unL + cL, unR + cR);
+  T FL[NV], FR[NV];
+  euler_flux<DIM, T>(qL, n, pL, unL, FL);
+  euler_flux<DIM, T>(qR, n, pR, unR, FR);
+  if (SL >= (T)0) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) F[v] = FL[v];
     return;
   }
   if (!hllc) {
-    if (primal(SR) <= (T)0) {
+    if (SR <= (T)0) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) F[v] = FR[v];
       return;
@@ -308,16 +272,16 @@ __device__ inline void riemann(const S (&qL)[DIM + 2], const S (&qR)[DIM + 2], c
     for (int v = 0; v < NV; ++v) F[v] = (SR * FL[v] - SL * FR[v] + SL * SR * (qR[v] - qL[v])) / (SR - SL);
     return;
   }
-  const S Ss = (pR - pL + rL * unL * (SL - unL) - rR * unR * (SR - unR)) / (rL * (SL - unL) - rR * (SR - unR));
-  if (primal(Ss) >= (T)0) {
-    const S fac = rL * (SL - unL) / (SL - Ss);
+  const T Ss = (pR - pL + rL * unL * (SL - unL) - rR * unR * (SR - unR)) / (rL * (SL - unL) - rR * (SR - unR));
+  if (Ss >= (T)0) {
+    const T fac = rL * (SL - unL) / (SL - Ss);
     F[0] = FL[0] + SL * (fac - qL[0]);
 #pragma unroll
     for (int j = 0; j < DIM; ++j) F[1 + j] = FL[1 + j] + SL * (fac * (vL[j] + (Ss - unL) * n[j]) - qL[1 + j]);
     F[NV - 1] = FL[NV - 1] + SL * (fac * (qL[NV - 1] / rL + (Ss - unL) * (Ss + pL / (rL * (SL - unL)))) -
                                    qL[NV - 1]);
-  } else if (primal(SR) > (T)0) {
-    const S fac = rR * (SR - unR) / (SR - Ss);
+  } else if (SR > (T)0) {
+    const T fac = rR * (SR - unR) / (SR - Ss);
     F[0] = FR[0] + SR * (fac - qR[0]);
 #pragma unroll
     for (int j = 0; j < DIM; ++j) F[1 + j] = FR[1 + j] + SR * (fac * (vR[j] + (Ss - unR) * n[j]) - qR[1 + j]);

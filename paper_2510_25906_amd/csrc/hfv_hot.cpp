@@ -484,7 +484,7 @@ __global__ __launch_bounds__(CLASSIFY_BLOCK) void k_classify(HotArgs<T> a, int n
   const bool valid = cell < a.N;
   int c = 0;
   if (valid && a.frozen) {
-    c = a.cls_in[cell];
+    c = min((int)a.cls_in[cell], (int)HFV_CLASS_FIRST_ORDER);  // larger values: first order
   } else if (valid) {
     const int o = a.own[cell];
     c = o & 3;
@@ -853,7 +853,7 @@ __global__ __launch_bounds__(256) void k_flux(int NF, int N, const T *fs, const 
       qR[v] = pR[((long)i * NV + v) * N];
     }
     T F[NV];
-    riemann<DIM, T, T>(qL, qR, n, gamma, hllc, F);
+    riemann<DIM, T>(qL, qR, n, gamma, hllc, F);
     const T w = gpw[g];
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] += w * F[v];
@@ -915,7 +915,7 @@ __global__ __launch_bounds__(256) void k_residual(int N, int NF, const T *fs, co
         qR[v] = pR[((long)i * NV + v) * N];
       }
       T F[NV];
-      riemann<DIM, T, T>(qL, qR, n, gamma, hllc, F);
+      riemann<DIM, T>(qL, qR, n, gamma, hllc, F);
       const T w = gpw[g];
 #pragma unroll
       for (int v = 0; v < NV; ++v) af[v] += w * F[v];

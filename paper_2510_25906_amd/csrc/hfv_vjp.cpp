@@ -4,19 +4,22 @@
 // reconstruction of each cell's class), face states -> integrated face
 // fluxes, face fluxes -> residual (Eq. EulerEquationsDetails).  The adjoint
 // runs them backwards:
-//   k_flux_vjp    dJ/dF from dJ/dR, then through the Riemann solver at every
-//                 Gauss point; its Jacobian columns come from forward-mode dual
-//                 numbers, branches (wave-speed choices, HLLC region) held at
-//                 the primal values
+//   k_flux_vjp    dJ/dF from dJ/dR, then back through the Riemann solver at
+//                 every Gauss point in hand-written reverse mode, branches
+//                 (wave-speed choices, HLLC region) held at the primal values
 //   k_recon_vjp   per cell and variable, back through the cell's frozen class:
 //                 linear (Section 2.1), CWENOZ including its nonlinear weights
-//                 (Section 2.3), Barth-Jespersen MUSCL with the limiting point
-//                 and bound frozen (Section 2.2), or first order; contributions
+//                 (Section 2.3), MUSCL (Barth-Jespersen or Venkatakrishnan)
+//                 through its limiting point and the neighbour that sets the
+//                 bound (Section 2.2), or first order; contributions
 //                 to each central-stencil slot are stored, not scattered
 //   k_gather_vjp  each cell sums the slot contributions that refer to it
 //                 through the transposed stencil, in a fixed order
 // No floating-point atomics are used, so the result is deterministic.
+#include <algorithm>
+
 #include "hfv_device.hpp"
+#include "hfv_riemann_adj.hpp"
 
 namespace hfv {
 
@@ -25,6 +28,8 @@ struct VjpArgs {
   int N, form, limiter;
   const T *U;
   const uint8_t *cls;
+  const int *lists;   // [3][N] class lists of the frozen forward recompute: CWENOZ, MUSCL, first order
+  const int *counts;  // list lengths at 1 + list index
   const T *gfs;
   T *C;
   T *S;
@@ -59,23 +64,11 @@ __global__ __launch_bounds__(256) void k_flux_vjp(int NF, int N, const T *fs, co
     }
     const T w = gpw[g];
     T gl[NV], gr[NV];
+    riemann_vjp<DIM, T>(qL, qR, n, gamma, hllc, gF, gl, gr);
 #pragma unroll
-    for (int tg = 0; tg < 2 * NV; ++tg) {
-      Dual<T> dL[NV], dR[NV];
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        dL[v] = Dual<T>(qL[v], tg == v ? (T)1 : (T)0);
-        dR[v] = Dual<T>(qR[v], tg == NV + v ? (T)1 : (T)0);
-      }
-      Dual<T> F[NV];
-      riemann<DIM, Dual<T>, T>(dL, dR, n, gamma, hllc, F);
-      T acc = 0;
-#pragma unroll
-      for (int u = 0; u < NV; ++u) acc += gF[u] * F[u].d;
-      if (tg < NV)
-        gl[tg] = w * acc;
-      else
-        gr[tg - NV] = w * acc;
+    for (int v = 0; v < NV; ++v) {
+      gl[v] *= w;
+      gr[v] *= w;
     }
     // every cell slot belongs to exactly one face side, so each is written once
 #pragma unroll
@@ -92,20 +85,20 @@ __global__ __launch_bounds__(256) void k_flux_vjp(int NF, int N, const T *fs, co
 
 __device__ inline double pow_safe(double x, double e) { return (x == 0.0 && e > 0.0) ? 0.0 : pow(x, e); }
 
-template <int DIM, int R, typename T>
-__global__ __launch_bounds__(256) void k_recon_vjp(VjpArgs<T> a) {
+// Reverse pass of one cell and variable through the cell's class.  PASS 0
+// holds the linear and first-order code, PASS 1 CWENOZ's, PASS 2 MUSCL's, so
+// that each launch is compiled with the registers of its own class only.
+template <int DIM, int R, typename T, int PASS>
+__device__ inline void recon_vjp_cell(const VjpArgs<T> &a, int cell, int v, int cls) {
   constexpr int NV = DIM + 2, K = n_unknowns(DIM, R), M = 2 * K, NFM = nf_max(DIM), MD = 2 * DIM;
-  Lane<NV> L;
-  if (!L.ok || L.item >= a.N) return;
-  const int cell = L.item, v = L.sub, N = a.N;
+  const int N = a.N;
   const Tables<T> &t = a.t;
-  const int cls = a.cls[cell];
   const int ng = t.ngp[cell];
   const long MS = (long)NV * N;
   T *C = a.C + (long)v * N + cell;  // slot m lives at C[m * MS]
   auto gq_at = [&](int g) -> T { return a.gfs[((long)g * NV + v) * N + cell]; };
   T gsum = 0;
-  if (cls == HFV_CLASS_FIRST_ORDER) {
+  if (PASS == 0 && cls >= HFV_CLASS_FIRST_ORDER) {
     for (int g = 0; g < ng; ++g) gsum += gq_at(g);
     for (int m = 0; m < M; ++m) C[m * MS] = 0;
     a.S[(long)v * N + cell] = gsum;
@@ -120,7 +113,7 @@ __global__ __launch_bounds__(256) void k_recon_vjp(VjpArgs<T> a) {
     for (int j = 0; j < DIM; ++j) xi[j] = t.gpxi[((long)g * DIM + j) * N + cell];
   };
 
-  if (cls == HFV_CLASS_LINEAR) {
+  if constexpr (PASS == 0) {  // linear
     T b[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) b[k] = 0;
@@ -145,7 +138,7 @@ __global__ __launch_bounds__(256) void k_recon_vjp(VjpArgs<T> a) {
     return;
   }
 
-  if (cls == HFV_CLASS_CWENOZ) {
+  if constexpr (PASS == 1) {  // CWENOZ
     // ---- forward recompute (Section 2.3)
     T co[K];
 #pragma unroll
@@ -344,7 +337,7 @@ __global__ __launch_bounds__(256) void k_recon_vjp(VjpArgs<T> a) {
     return;
   }
 
-  // ---- MUSCL with the Barth-Jespersen or Venkatakrishnan limiter (Sections 2.2, 3.2)
+  if constexpr (PASS == 2) {  // MUSCL with the Barth-Jespersen or Venkatakrishnan limiter (Sections 2.2, 3.2)
   for (int m = 0; m < M; ++m) C[m * MS] = 0;
   const int nm = t.nmus[cell];
   T gr[DIM];
@@ -449,6 +442,29 @@ __global__ __launch_bounds__(256) void k_recon_vjp(VjpArgs<T> a) {
     self -= x;
   }
   a.S[(long)v * N + cell] = self;
+  }
+}
+
+// One lane per (cell, variable).  Pass 0 runs over every cell and takes the
+// linear and first-order cells; passes 1 and 2 run over the CWENOZ and MUSCL
+// lists that the frozen forward recompute compacted, so that no wave carries
+// the heavy classes' code for a few of its lanes.
+template <int DIM, int R, typename T, int PASS>
+__global__ __launch_bounds__(256) void k_recon_vjp(VjpArgs<T> a) {
+  constexpr int NV = DIM + 2, CPW = 64 / NV;
+  Lane<NV> L;
+  if (!L.ok) return;
+  if constexpr (PASS == 0) {
+    if (L.item >= a.N) return;
+    const int c = a.cls[L.item];
+    if (c != HFV_CLASS_CWENOZ && c != HFV_CLASS_MUSCL) recon_vjp_cell<DIM, R, T, 0>(a, L.item, L.sub, c);
+  } else {
+    const int total = a.counts[PASS];
+    const int *list = a.lists + (long)(PASS - 1) * a.N;
+    const int c = PASS == 1 ? HFV_CLASS_CWENOZ : HFV_CLASS_MUSCL;
+    const long stride = (long)gridDim.x * (blockDim.x / 64) * CPW;
+    for (long item = L.item; item < total; item += stride) recon_vjp_cell<DIM, R, T, PASS>(a, list[item], L.sub, c);
+  }
 }
 
 template <int NV, typename T>
@@ -495,9 +511,15 @@ static hfv_status vjp_impl(hfv_ctx *ctx, Tables<T> &t, const void *U, const uint
   a.lam1p = (T)ctx->p.lam1p;
   a.eps_w = (T)ctx->p.eps_w;
   a.b_w = (T)ctx->p.b_w;
+  a.lists = ctx->lists;
+  a.counts = ctx->counts;
   constexpr int CPW = 64 / NV;
   const long waves = ((long)ctx->N + CPW - 1) / CPW;
-  k_recon_vjp<DIM, R, T><<<nblk(waves * 64, 256), 256, 0, s>>>(a);
+  const unsigned grid_cells = nblk(waves * 64, 256);
+  const unsigned grid_list = std::min<unsigned>(grid_cells, 2048u);
+  k_recon_vjp<DIM, R, T, 0><<<grid_cells, 256, 0, s>>>(a);
+  k_recon_vjp<DIM, R, T, 1><<<grid_list, 256, 0, s>>>(a);
+  k_recon_vjp<DIM, R, T, 2><<<grid_list, 256, 0, s>>>(a);
   k_gather_vjp<NV, T><<<nblk(ctx->N, 256), 256, 0, s>>>(ctx->N, t.inv_off, t.inv_idx, (const T *)ctx->vjp_C,
                                                        (const T *)ctx->vjp_S, (T *)gU);
   HFV_HIP(hipGetLastError());

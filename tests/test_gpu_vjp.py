@@ -125,6 +125,25 @@ def test_vjp_dot_product_with_frozen_residual(hfv):
     ctx.close()
 
 
+def test_class_bytes_above_first_order_are_first_order(hfv):
+    """Given classes above HFV_CLASS_FIRST_ORDER are taken as first order by the
+    frozen residual and the VJP: bitwise the same results as class 3."""
+    mesh, st, U, p = case("c2")
+    ctx = hfv.Context(mesh, st, p, 64)
+    Ud = to_dev(U, torch.float64)
+    cls = torch.empty(mesh.n_cells, dtype=torch.uint8, device="cuda")
+    ctx.residual(Ud, cell_class=cls)
+    rng = np.random.default_rng(8)
+    pick = torch.tensor(rng.choice(mesh.n_cells, mesh.n_cells // 4, replace=False), device="cuda")
+    c3, cx = cls.clone(), cls.clone()
+    c3[pick] = 3
+    cx[pick] = torch.tensor(rng.integers(4, 256, len(pick)), dtype=torch.uint8, device="cuda")
+    gR = to_dev(rng.normal(size=U.shape), torch.float64)
+    assert torch.equal(ctx.residual_frozen(Ud, c3), ctx.residual_frozen(Ud, cx))
+    assert torch.equal(ctx.residual_vjp(Ud, c3, gR), ctx.residual_vjp(Ud, cx, gR))
+    ctx.close()
+
+
 def test_slab_pressure_objective_on_262k_hex(hfv):
     """J(U) = sum_{z_c < 1/2} |V_i| p(U_i + dt R_i(U)) on the 64^3 TGV mesh, r = 2:
     autograd through the library's VJP against central differences (h = 1e-6,
