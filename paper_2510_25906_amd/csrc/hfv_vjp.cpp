@@ -16,8 +16,6 @@
 //   k_gather_vjp  each cell sums the slot contributions that refer to it
 //                 through the transposed stencil, in a fixed order
 // No floating-point atomics are used, so the result is deterministic.
-#include <algorithm>
-
 #include "hfv_device.hpp"
 #include "hfv_riemann_adj.hpp"
 
@@ -85,20 +83,40 @@ __global__ __launch_bounds__(256) void k_flux_vjp(int NF, int N, const T *fs, co
 
 __device__ inline double pow_safe(double x, double e) { return (x == 0.0 && e > 0.0) ? 0.0 : pow(x, e); }
 
-// Reverse pass of one cell and variable through the cell's class.  PASS 0
-// holds the linear and first-order code, PASS 1 CWENOZ's, PASS 2 MUSCL's, so
-// that each launch is compiled with the registers of its own class only.
+// Reverse pass per (cell, variable) through the cell's class, one lane each.
+// PASS 0 runs over every cell and takes the linear and first-order cells;
+// PASS 1 and 2 run over the CWENOZ and MUSCL lists that the frozen forward
+// recompute compacted, one list entry per lane group over a grid sized for
+// every cell (a loop over entries would hold its registers across
+// iterations).  PASS 0 and 2 compile only their classes' code, so they carry
+// few registers; PASS 1 keeps the run-time switch over all classes (only
+// CWENOZ cells reach it; at 3D r = 3 it needs fewer spill slots than a
+// CWENOZ-only build, at equal occupancy).  The body stays in the kernel:
+// moved into a device function (inlined or not), the CWENOZ path took 256
+// VGPRs instead of 172 at 2D r = 3 FP64 and spilled to scratch at 3D r = 3.
 template <int DIM, int R, typename T, int PASS>
-__device__ inline void recon_vjp_cell(const VjpArgs<T> &a, int cell, int v, int cls) {
+__global__ __launch_bounds__(256) void k_recon_vjp(VjpArgs<T> a) {
   constexpr int NV = DIM + 2, K = n_unknowns(DIM, R), M = 2 * K, NFM = nf_max(DIM), MD = 2 * DIM;
-  const int N = a.N;
+  Lane<NV> L;
+  if (!L.ok) return;
+  int cell;
+  if constexpr (PASS == 0) {
+    if (L.item >= a.N) return;
+    cell = L.item;
+  } else {
+    if (L.item >= a.counts[PASS]) return;
+    cell = a.lists[(long)(PASS - 1) * a.N + L.item];
+  }
+  const int v = L.sub, N = a.N;
+  const int cls = PASS == 2 ? (int)HFV_CLASS_MUSCL : (int)a.cls[cell];
+  if (PASS == 0 && (cls == HFV_CLASS_CWENOZ || cls == HFV_CLASS_MUSCL)) return;
   const Tables<T> &t = a.t;
   const int ng = t.ngp[cell];
   const long MS = (long)NV * N;
   T *C = a.C + (long)v * N + cell;  // slot m lives at C[m * MS]
   auto gq_at = [&](int g) -> T { return a.gfs[((long)g * NV + v) * N + cell]; };
   T gsum = 0;
-  if (PASS == 0 && cls >= HFV_CLASS_FIRST_ORDER) {
+  if (PASS != 2 && cls >= HFV_CLASS_FIRST_ORDER) {
     for (int g = 0; g < ng; ++g) gsum += gq_at(g);
     for (int m = 0; m < M; ++m) C[m * MS] = 0;
     a.S[(long)v * N + cell] = gsum;
@@ -113,7 +131,7 @@ __device__ inline void recon_vjp_cell(const VjpArgs<T> &a, int cell, int v, int 
     for (int j = 0; j < DIM; ++j) xi[j] = t.gpxi[((long)g * DIM + j) * N + cell];
   };
 
-  if constexpr (PASS == 0) {  // linear
+  if (PASS == 0 || (PASS == 1 && cls == HFV_CLASS_LINEAR)) {
     T b[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) b[k] = 0;
@@ -138,7 +156,7 @@ __device__ inline void recon_vjp_cell(const VjpArgs<T> &a, int cell, int v, int 
     return;
   }
 
-  if constexpr (PASS == 1) {  // CWENOZ
+  if (PASS == 1 && cls == HFV_CLASS_CWENOZ) {
     // ---- forward recompute (Section 2.3)
     T co[K];
 #pragma unroll
@@ -337,7 +355,7 @@ __device__ inline void recon_vjp_cell(const VjpArgs<T> &a, int cell, int v, int 
     return;
   }
 
-  if constexpr (PASS == 2) {  // MUSCL with the Barth-Jespersen or Venkatakrishnan limiter (Sections 2.2, 3.2)
+  if (PASS != 0) {  // MUSCL with the Barth-Jespersen or Venkatakrishnan limiter (Sections 2.2, 3.2)
   for (int m = 0; m < M; ++m) C[m * MS] = 0;
   const int nm = t.nmus[cell];
   T gr[DIM];
@@ -445,28 +463,6 @@ __device__ inline void recon_vjp_cell(const VjpArgs<T> &a, int cell, int v, int 
   }
 }
 
-// One lane per (cell, variable).  Pass 0 runs over every cell and takes the
-// linear and first-order cells; passes 1 and 2 run over the CWENOZ and MUSCL
-// lists that the frozen forward recompute compacted, so that no wave carries
-// the heavy classes' code for a few of its lanes.
-template <int DIM, int R, typename T, int PASS>
-__global__ __launch_bounds__(256) void k_recon_vjp(VjpArgs<T> a) {
-  constexpr int NV = DIM + 2, CPW = 64 / NV;
-  Lane<NV> L;
-  if (!L.ok) return;
-  if constexpr (PASS == 0) {
-    if (L.item >= a.N) return;
-    const int c = a.cls[L.item];
-    if (c != HFV_CLASS_CWENOZ && c != HFV_CLASS_MUSCL) recon_vjp_cell<DIM, R, T, 0>(a, L.item, L.sub, c);
-  } else {
-    const int total = a.counts[PASS];
-    const int *list = a.lists + (long)(PASS - 1) * a.N;
-    const int c = PASS == 1 ? HFV_CLASS_CWENOZ : HFV_CLASS_MUSCL;
-    const long stride = (long)gridDim.x * (blockDim.x / 64) * CPW;
-    for (long item = L.item; item < total; item += stride) recon_vjp_cell<DIM, R, T, PASS>(a, list[item], L.sub, c);
-  }
-}
-
 template <int NV, typename T>
 __global__ __launch_bounds__(256) void k_gather_vjp(int N, const int *inv_off, const int *inv_idx, const T *C,
                                                     const T *S, T *gU) {
@@ -516,10 +512,9 @@ static hfv_status vjp_impl(hfv_ctx *ctx, Tables<T> &t, const void *U, const uint
   constexpr int CPW = 64 / NV;
   const long waves = ((long)ctx->N + CPW - 1) / CPW;
   const unsigned grid_cells = nblk(waves * 64, 256);
-  const unsigned grid_list = std::min<unsigned>(grid_cells, 2048u);
   k_recon_vjp<DIM, R, T, 0><<<grid_cells, 256, 0, s>>>(a);
-  k_recon_vjp<DIM, R, T, 1><<<grid_list, 256, 0, s>>>(a);
-  k_recon_vjp<DIM, R, T, 2><<<grid_list, 256, 0, s>>>(a);
+  k_recon_vjp<DIM, R, T, 1><<<grid_cells, 256, 0, s>>>(a);
+  k_recon_vjp<DIM, R, T, 2><<<grid_cells, 256, 0, s>>>(a);
   k_gather_vjp<NV, T><<<nblk(ctx->N, 256), 256, 0, s>>>(ctx->N, t.inv_off, t.inv_idx, (const T *)ctx->vjp_C,
                                                        (const T *)ctx->vjp_S, (T *)gU);
   HFV_HIP(hipGetLastError());
