@@ -113,7 +113,7 @@ __global__ __launch_bounds__(256) void k_recon_vjp(VjpArgs<T> a) {
   const Tables<T> &t = a.t;
   const int ng = t.ngp[cell];
   const long MS = (long)NV * N;
-  T *C = a.C + (long)v * N + cell;  // slot m lives at C[m * MS]
+  T *C = a.C + (long)cell * NV + v;  // [M][N][nvar]: slot m lives at C[m * MS]
   auto gq_at = [&](int g) -> T { return a.gfs[((long)g * NV + v) * N + cell]; };
   T gsum = 0;
   if (PASS != 2 && cls >= HFV_CLASS_FIRST_ORDER) {
@@ -475,7 +475,7 @@ __global__ __launch_bounds__(256) void k_gather_vjp(int N, const int *inv_off, c
     const int code = inv_idx[e];
     const int m = code / N, i = code - m * N;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) acc[v] += C[((long)m * NV + v) * N + i];
+    for (int v = 0; v < NV; ++v) acc[v] += C[((long)m * N + i) * NV + v];  // one cache line per entry
   }
 #pragma unroll
   for (int v = 0; v < NV; ++v) gU[(long)v * N + j] = acc[v];
