@@ -22,7 +22,8 @@ hybrid residual, against the 8 TB/s peak and against the bandwidth a plain
 median of single residuals started after a 1 GiB write that flushes the
 last-level cache (`ms_residual_cold`), the step captured once into a HIP graph
 and replayed (`ms_residual_graph`), the adjoint (vector-Jacobian product of
-the residual with the step's classes frozen: `ms_vjp`, `vjp_evals_per_s`) and, on workloads whose field is
+the residual with the step's classes frozen: `ms_vjp`, `vjp_evals_per_s`; `ms_vjp_given_states` when the
+step's face states are passed in and not recomputed) and, on workloads whose field is
 smooth and known in closed form (the hexahedral Taylor-Green cases), the RMS
 error of its face states against the exact point values
 (`face_err_rms_rel`), the accuracy at which the modes are compared.  FP32 modes report their face states' largest error against the
@@ -509,6 +510,8 @@ def main():
             gU = torch.empty_like(U)
             ctx.residual(U, R, fs, cls)
             ms_vjp = time_steps(lambda: ctx.residual_vjp(U, cls, gR, gU), args.steps, args.warmup, torch)
+            ms_vjp_states = time_steps(lambda: ctx.residual_vjp(U, cls, gR, gU, face_states=fs), args.steps,
+                                       args.warmup, torch)
             del gR, gU
             # the same step captured once into a HIP graph and replayed (one launch per step)
             graph = ctx.graph_residual(U, R, fs, cls)
@@ -543,6 +546,7 @@ def main():
             modes[f"{name}_fp{prec}"]["ms_vjp"] = round(ms_vjp, 4)
             modes[f"{name}_fp{prec}"]["vjp_evals_per_s"] = round(1.0 / (ms_vjp * 1e-3), 2)
             modes[f"{name}_fp{prec}"]["vjp_over_residual"] = round(ms_vjp / ms_res, 3)
+            modes[f"{name}_fp{prec}"]["ms_vjp_given_states"] = round(ms_vjp_states, 4)
             if ms_cold is not None:
                 modes[f"{name}_fp{prec}"]["ms_residual_cold"] = round(ms_cold, 4)
             if face_err is not None:

@@ -204,6 +204,18 @@ hfv_status hfv_cfl_rate(hfv_ctx *ctx, const void *U, double *out, void *stream);
 hfv_status hfv_residual_vjp(hfv_ctx *ctx, const void *U, const uint8_t *cell_class, const void *gR, void *gU,
                             void *stream);
 
+/* The same product when the caller holds the face states of U (project
+ * addition): the frozen forward reconstruction that hfv_residual_vjp runs
+ * first is skipped and only the class lists are rebuilt from cell_class.
+ *   face_states  device [ngp_cell_max][nvar][n_cells], read only: the states
+ *                hfv_residual or hfv_reconstruct wrote for this U and these
+ *                classes (other states give the product at those states)
+ * The result equals hfv_residual_vjp's up to the rounding of the states (the
+ * forward pass may take CWENOZ's central fit from the linear pass).
+ * Errors: HFV_ERR_PARAM for a NULL pointer; HFV_ERR_STATE as hfv_residual_vjp. */
+hfv_status hfv_residual_vjp_states(hfv_ctx *ctx, const void *U, const uint8_t *cell_class, const void *face_states,
+                                   const void *gR, void *gU, void *stream);
+
 /* Queries (synchronous for the class counts, which read device counters). */
 enum {
   HFV_Q_N_CELLS = 0, HFV_Q_N_FACES = 1, HFV_Q_N_GP = 2, HFV_Q_NVAR = 3, HFV_Q_K = 4, HFV_Q_M = 5,

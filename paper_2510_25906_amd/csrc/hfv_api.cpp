@@ -274,7 +274,14 @@ hfv_status hfv_residual_vjp(hfv_ctx *ctx, const void *U, const uint8_t *cls, con
                             void *stream) {
   if (!ctx) return HFV_ERR_PARAM;
   if (!U || !cls || !gR || !gU) return ctx->err = "NULL device pointer", HFV_ERR_PARAM;
-  return run_vjp(ctx, U, cls, gR, gU, (hipStream_t)stream);
+  return run_vjp(ctx, U, cls, nullptr, gR, gU, (hipStream_t)stream);
+}
+
+hfv_status hfv_residual_vjp_states(hfv_ctx *ctx, const void *U, const uint8_t *cls, const void *face_states,
+                                   const void *gR, void *gU, void *stream) {
+  if (!ctx) return HFV_ERR_PARAM;
+  if (!U || !cls || !face_states || !gR || !gU) return ctx->err = "NULL device pointer", HFV_ERR_PARAM;
+  return run_vjp(ctx, U, cls, face_states, gR, gU, (hipStream_t)stream);
 }
 
 hfv_status hfv_query(const hfv_ctx *ctx, int32_t what, int64_t *out) {

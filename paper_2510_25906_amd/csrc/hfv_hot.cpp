@@ -1085,6 +1085,24 @@ static hfv_status frozen_t(hfv_ctx *ctx, Tables<T> &t, const void *U, void *fs, 
   return HFV_ERR_PARAM;
 }
 
+// Class lists of given classes alone (no face states): the lengths are
+// cleared by a fill kernel, then the compaction runs in frozen mode.
+
+template <typename T>
+static hfv_status lists_t(hfv_ctx *ctx, Tables<T> &t, const uint8_t *cls, hipStream_t s) {
+  HotArgs<T> a = make_args<T>(ctx, t, nullptr, nullptr, nullptr);
+  a.frozen = 1;
+  a.cls_in = cls;
+  k_zero_counts<<<1, 64, 0, s>>>(ctx->counts);
+  k_classify<T><<<nblk(ctx->N, CLASSIFY_BLOCK), CLASSIFY_BLOCK, 0, s>>>(a, ctx->NFM);
+  HFV_HIP(hipGetLastError());
+  return HFV_OK;
+}
+
+hfv_status run_class_lists(hfv_ctx *ctx, const uint8_t *cls, hipStream_t s) {
+  return ctx->prec == 64 ? lists_t<double>(ctx, ctx->t64, cls, s) : lists_t<float>(ctx, ctx->t32, cls, s);
+}
+
 hfv_status run_reconstruct_frozen(hfv_ctx *ctx, const void *U, void *fs, const uint8_t *cls, hipStream_t s) {
   return ctx->prec == 64 ? frozen_t<double>(ctx, ctx->t64, U, fs, cls, s)
                          : frozen_t<float>(ctx, ctx->t32, U, fs, cls, s);

@@ -144,8 +144,10 @@ namespace hfv {
 hfv_status setup_tables(hfv_ctx *ctx, const hfv_mesh *mesh, const hfv_stencils *st, hipStream_t s);
 hfv_status run_reconstruct(hfv_ctx *ctx, const void *U, void *fs, uint8_t *cls, hipStream_t s);
 hfv_status run_reconstruct_frozen(hfv_ctx *ctx, const void *U, void *fs, const uint8_t *cls, hipStream_t s);
+hfv_status run_class_lists(hfv_ctx *ctx, const uint8_t *cls, hipStream_t s);
 hfv_status run_residual_tail(hfv_ctx *ctx, const void *fs, void *R, hipStream_t s);
-hfv_status run_vjp(hfv_ctx *ctx, const void *U, const uint8_t *cls, const void *gR, void *gU, hipStream_t s);
+hfv_status run_vjp(hfv_ctx *ctx, const void *U, const uint8_t *cls, const void *fs, const void *gR, void *gU,
+                   hipStream_t s);
 hfv_status dev_alloc(hfv_ctx *ctx, void **p, size_t bytes);
 
 // Brackets one kernel launch with HIP events when its slot is being timed.

@@ -484,13 +484,16 @@ __global__ __launch_bounds__(256) void k_gather_vjp(int N, const int *inv_off, c
 static inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
 
 template <int DIM, int R, typename T>
-static hfv_status vjp_impl(hfv_ctx *ctx, Tables<T> &t, const void *U, const uint8_t *cls, const void *gR, void *gU,
-                           hipStream_t s) {
+static hfv_status vjp_impl(hfv_ctx *ctx, Tables<T> &t, const void *U, const uint8_t *cls, const void *fs,
+                           const void *gR, void *gU, hipStream_t s) {
   constexpr int NV = DIM + 2;
-  hfv_status e = run_reconstruct_frozen(ctx, U, ctx->fs_ws, cls, s);
+  // face states given: only the class lists are rebuilt; else the frozen
+  // forward reconstruction recomputes the states (and builds the lists)
+  hfv_status e = fs ? run_class_lists(ctx, cls, s) : run_reconstruct_frozen(ctx, U, ctx->fs_ws, cls, s);
   if (e != HFV_OK) return e;
+  const T *fsu = (const T *)(fs ? fs : ctx->fs_ws);
   ProfScope ps(ctx, HFV_SLOT_VJP, s);
-  k_flux_vjp<DIM, T><<<nblk(ctx->NF, 256), 256, 0, s>>>(ctx->NF, ctx->N, (const T *)ctx->fs_ws, t.gp_off, t.fgb,
+  k_flux_vjp<DIM, T><<<nblk(ctx->NF, 256), 256, 0, s>>>(ctx->NF, ctx->N, fsu, t.gp_off, t.fgb,
                                                          t.fnormal, t.gpw, t.face_cells, t.ivol, (const T *)gR,
                                                          (T)ctx->p.gamma, ctx->p.riemann == HFV_HLLC,
                                                          (T *)ctx->vjp_gfs);
@@ -522,29 +525,30 @@ static hfv_status vjp_impl(hfv_ctx *ctx, Tables<T> &t, const void *U, const uint
 }
 
 template <typename T>
-static hfv_status vjp_t(hfv_ctx *ctx, Tables<T> &t, const void *U, const uint8_t *cls, const void *gR, void *gU,
-                        hipStream_t s) {
+static hfv_status vjp_t(hfv_ctx *ctx, Tables<T> &t, const void *U, const uint8_t *cls, const void *fs,
+                        const void *gR, void *gU, hipStream_t s) {
   switch (ctx->dim * 10 + ctx->r) {
-    case 21: return vjp_impl<2, 1, T>(ctx, t, U, cls, gR, gU, s);
-    case 22: return vjp_impl<2, 2, T>(ctx, t, U, cls, gR, gU, s);
-    case 23: return vjp_impl<2, 3, T>(ctx, t, U, cls, gR, gU, s);
-    case 24: return vjp_impl<2, 4, T>(ctx, t, U, cls, gR, gU, s);
-    case 31: return vjp_impl<3, 1, T>(ctx, t, U, cls, gR, gU, s);
-    case 32: return vjp_impl<3, 2, T>(ctx, t, U, cls, gR, gU, s);
-    case 33: return vjp_impl<3, 3, T>(ctx, t, U, cls, gR, gU, s);
-    case 34: return vjp_impl<3, 4, T>(ctx, t, U, cls, gR, gU, s);
+    case 21: return vjp_impl<2, 1, T>(ctx, t, U, cls, fs, gR, gU, s);
+    case 22: return vjp_impl<2, 2, T>(ctx, t, U, cls, fs, gR, gU, s);
+    case 23: return vjp_impl<2, 3, T>(ctx, t, U, cls, fs, gR, gU, s);
+    case 24: return vjp_impl<2, 4, T>(ctx, t, U, cls, fs, gR, gU, s);
+    case 31: return vjp_impl<3, 1, T>(ctx, t, U, cls, fs, gR, gU, s);
+    case 32: return vjp_impl<3, 2, T>(ctx, t, U, cls, fs, gR, gU, s);
+    case 33: return vjp_impl<3, 3, T>(ctx, t, U, cls, fs, gR, gU, s);
+    case 34: return vjp_impl<3, 4, T>(ctx, t, U, cls, fs, gR, gU, s);
   }
   ctx->err = "unsupported (dim, order_r)";
   return HFV_ERR_PARAM;
 }
 
-hfv_status run_vjp(hfv_ctx *ctx, const void *U, const uint8_t *cls, const void *gR, void *gU, hipStream_t s) {
+hfv_status run_vjp(hfv_ctx *ctx, const void *U, const uint8_t *cls, const void *fs, const void *gR, void *gU,
+                   hipStream_t s) {
   if (!ctx->vjp_ok) {
     ctx->err = "residual VJP unavailable for these stencils: " + ctx->vjp_why;
     return HFV_ERR_STATE;
   }
-  return ctx->prec == 64 ? vjp_t<double>(ctx, ctx->t64, U, cls, gR, gU, s)
-                         : vjp_t<float>(ctx, ctx->t32, U, cls, gR, gU, s);
+  return ctx->prec == 64 ? vjp_t<double>(ctx, ctx->t64, U, cls, fs, gR, gU, s)
+                         : vjp_t<float>(ctx, ctx->t32, U, cls, fs, gR, gU, s);
 }
 
 }  // namespace hfv

@@ -71,6 +71,7 @@ def load():
     lib.hfv_reconstruct.argtypes = [_p, _p, _p, _p, _p]
     lib.hfv_residual.argtypes = [_p, _p, _p, _p, _p, _p]
     lib.hfv_residual_vjp.argtypes = [_p, _p, _p, _p, _p, _p]
+    lib.hfv_residual_vjp_states.argtypes = [_p, _p, _p, _p, _p, _p, _p]
     lib.hfv_residual_frozen.argtypes = [_p, _p, _p, _p, _p]
     lib.hfv_rk_stage.argtypes = [_p, C.c_double, _p, C.c_double, _p, C.c_double, _p, _p, _p]
     lib.hfv_cfl_rate.argtypes = [_p, _p, _p, _p]
@@ -87,6 +88,7 @@ def load():
     lib.hfv_destroy.argtypes = [_p]
     lib.hfv_destroy.restype = None
     for name in ("hfv_create", "hfv_set_params", "hfv_reconstruct", "hfv_residual", "hfv_residual_vjp",
+                 "hfv_residual_vjp_states",
                  "hfv_residual_frozen", "hfv_rk_stage", "hfv_cfl_rate",
                  "hfv_query", "hfv_copy_table", "hfv_set_launch", "hfv_get_launch", "hfv_autotune",
                  "hfv_profile_enable",
@@ -321,13 +323,24 @@ class Context:
             self.residual(U, R, face_states, cell_class)
         return g
 
-    def residual_vjp(self, U, cell_class, gR, gU=None, stream=None):
+    def residual_vjp(self, U, cell_class, gR, gU=None, stream=None, face_states=None):
+        """gU = (dR/dU)^T gR with cell_class frozen; face_states, when given, are
+        the states of U from residual / reconstruct (the recompute is skipped)."""
         import torch
         self._chk_u(U)
         gU = gU if gU is not None else torch.empty_like(U)
-        self._check(self.lib.hfv_residual_vjp(self.h, C.c_void_p(U.data_ptr()), C.c_void_p(cell_class.data_ptr()),
-                                              C.c_void_p(gR.data_ptr()), C.c_void_p(gU.data_ptr()),
-                                              _stream_handle(stream)))
+        if face_states is None:
+            self._check(self.lib.hfv_residual_vjp(self.h, C.c_void_p(U.data_ptr()),
+                                                  C.c_void_p(cell_class.data_ptr()), C.c_void_p(gR.data_ptr()),
+                                                  C.c_void_p(gU.data_ptr()), _stream_handle(stream)))
+        else:
+            if tuple(face_states.shape) != (self.ngp_cell, self.nvar, self.n_cells) \
+                    or face_states.dtype != self.dtype or not face_states.is_contiguous():
+                raise HfvError(-4, "face_states must be a contiguous tensor shaped like new_face_states()")
+            self._check(self.lib.hfv_residual_vjp_states(
+                self.h, C.c_void_p(U.data_ptr()), C.c_void_p(cell_class.data_ptr()),
+                C.c_void_p(face_states.data_ptr()), C.c_void_p(gR.data_ptr()), C.c_void_p(gU.data_ptr()),
+                _stream_handle(stream)))
         return gU
 
     def rk_stage(self, out, a, U0, b=0.0, U1=None, c=0.0, R=None, stream=None):

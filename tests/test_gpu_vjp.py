@@ -125,6 +125,33 @@ def test_vjp_dot_product_with_frozen_residual(hfv):
     ctx.close()
 
 
+@pytest.mark.parametrize("name,prec", [("c2", 64), ("tet", 64), ("c4", 64), ("c4", 32)])
+def test_vjp_with_given_face_states(hfv, name, prec):
+    """hfv_residual_vjp_states on the residual's own face states equals
+    hfv_residual_vjp, which recomputes them, and the oracle gradient."""
+    mesh, st, U, p = case(name)
+    dt = torch.float64 if prec == 64 else torch.float32
+    ctx = hfv.Context(mesh, st, p, prec)
+    Ud = to_dev(U, dt)
+    fs = ctx.new_face_states()
+    cls = torch.empty(mesh.n_cells, dtype=torch.uint8, device="cuda")
+    ctx.residual(Ud, face_states=fs, cell_class=cls)
+    rng = np.random.default_rng(12)
+    gR = to_dev(rng.normal(size=U.shape), dt)
+    ref = ctx.residual_vjp(Ud, cls, gR)
+    got = ctx.residual_vjp(Ud, cls, gR, face_states=fs)
+    torch.cuda.synchronize()
+    err = float((got - ref).abs().max() / ref.abs().max())
+    print(f"{name} fp{prec}: given states vs recompute {err:.2e}", flush=True)
+    assert err <= (1e-12 if prec == 64 else 1e-5)
+    if prec == 64 and name != "c4":
+        om = OracleModel(mesh, st, p)
+        want = residual_vjp(om, U, cls.cpu().numpy(), gR.cpu().numpy().T)
+        g = got.cpu().numpy().T
+        assert (np.abs(g - want) / np.abs(want).max(0)).max() <= 1e-12
+    ctx.close()
+
+
 def test_class_bytes_above_first_order_are_first_order(hfv):
     """Given classes above HFV_CLASS_FIRST_ORDER are taken as first order by the
     frozen residual and the VJP: bitwise the same results as class 3."""
