@@ -374,7 +374,8 @@ class Context:
 
     def residual_autograd(self, U):
         """R(U) as a differentiable torch op; backward is the library's VJP with
-        the classes of this forward evaluation frozen."""
+        the classes of this forward evaluation frozen, on the face states the
+        forward kept (no recompute; one face-state array held per evaluation)."""
         return _residual_function().apply(U, self)
 
 
@@ -392,15 +393,16 @@ def _residual_function():
         def forward(fctx, U, hctx):
             U = U.contiguous()
             cls = torch.empty(hctx.n_cells, dtype=torch.uint8, device=U.device)
-            R = hctx.residual(U, cell_class=cls)
-            fctx.save_for_backward(U, cls)
+            fs = hctx.new_face_states()
+            R = hctx.residual(U, face_states=fs, cell_class=cls)
+            fctx.save_for_backward(U, cls, fs)
             fctx.hctx = hctx
             return R
 
         @staticmethod
         def backward(fctx, gR):
-            U, cls = fctx.saved_tensors
-            gU = fctx.hctx.residual_vjp(U, cls, gR.contiguous())
+            U, cls, fs = fctx.saved_tensors
+            gU = fctx.hctx.residual_vjp(U, cls, gR.contiguous(), face_states=fs)
             return gU, None
 
     _RF = Residual
