@@ -52,7 +52,12 @@ def hll(UL, UR, n, gamma):
     return np.where((SL >= 0)[..., None], FL, np.where((SR <= 0)[..., None], FR, mid))
 
 
-def hllc(UL, UR, n, gamma):
+def hllc_star_states(UL, UR, n, gamma):
+    """Toro's HLLC intermediate states: (S_L, S_R, S*, U*_L, U*_R, F_L, F_R).
+
+    S* is the contact speed that makes the two star states carry equal
+    pressure; each star state keeps its side's tangential velocity and moves
+    with normal velocity S*."""
     (rL, vL, pL, unL), (rR, vR, pR, unR), SL, SR = _speeds(UL, UR, n, gamma)
     FL = euler_flux(UL, n, gamma)
     FR = euler_flux(UR, n, gamma)
@@ -66,8 +71,13 @@ def hllc(UL, UR, n, gamma):
         Us[..., -1] = fac * (U[..., -1] / r + (Ss - un) * (Ss + p / (r * (S - un))))
         return Us
 
-    FsL = FL + SL[..., None] * (star(UL, rL, vL, pL, unL, SL) - UL)
-    FsR = FR + SR[..., None] * (star(UR, rR, vR, pR, unR, SR) - UR)
+    return SL, SR, Ss, star(UL, rL, vL, pL, unL, SL), star(UR, rR, vR, pR, unR, SR), FL, FR
+
+
+def hllc(UL, UR, n, gamma):
+    SL, SR, Ss, UsL, UsR, FL, FR = hllc_star_states(UL, UR, n, gamma)
+    FsL = FL + SL[..., None] * (UsL - UL)
+    FsR = FR + SR[..., None] * (UsR - UR)
     return np.where((SL >= 0)[..., None], FL,
                     np.where((Ss >= 0)[..., None], FsL,
                              np.where((SR > 0)[..., None], FsR, FR)))

@@ -325,7 +325,7 @@ class OracleModel:
         a_cw = om1[:, None, :] * a1 + np.einsum("nfv,nfkv->nkv", oms, a_hat)
         phi = self.phi_at_gp(tab)
         fv = U[cells][:, None, :] + np.einsum("ngk,nkv->ngv", phi, a_cw)
-        return fv, dict(om1=om1, oms=oms, SI1=SI1, SIs=SIs, tau=tau, lam1=lam1, lams=lams)
+        return fv, dict(om1=om1, oms=oms, SI1=SI1, SIs=SIs, tau=tau, lam1=lam1, lams=lams, a_cw=a_cw)
 
     def muscl(self, cells, U):
         """MUSCL (Section 2.2) with the Barth-Jespersen limiter, or with

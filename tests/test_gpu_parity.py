@@ -1,7 +1,10 @@
 """GPU path (through the C ABI) against the FP64 oracle.
 
-FP64: classes bit-exact, states and residuals within 1e-12 relative
-(|x - x_ref| <= 1e-12 max(|x_ref|, S_v), S_v = max_cells |U_v|).
+FP64: classes bit-exact, states within 1e-12 relative
+(|x - x_ref| <= 1e-12 max(|x_ref|, S_v), S_v = max_cells |U_v|); residuals
+within 1e-11 of the variable's largest |R|: R_i sums face fluxes that cancel
+to a small difference, so a rounding of the fluxes at the 1e-16 level becomes
+1e-13 - 1e-12 of the largest residual, and the bound keeps a factor of ten.
 FP32: states within 1e-5 relative, class flips only in cells flagged within
 1e-6 of a threshold (or their face neighbours, through the tagging step).
 """

@@ -101,6 +101,9 @@ def test_cwenoz_reduces_to_linear_on_affine_data():
 
 
 def test_cwenoz_weights_convex_and_mean_preserving():
+    """Sum of the weights is one, each weight is non-negative, the combined
+    polynomial keeps the cell average (Section 2.3: every basis function has
+    zero mean over the cell), and across the jump the central weight drops."""
     w = configs.c1_density_jump(16, 2)
     om = OracleModel(w.mesh, w.stencils, w.params.with_(scheme_mode=ALL_CWENOZ))
     cells = np.arange(w.mesh.n_cells)
@@ -108,8 +111,52 @@ def test_cwenoz_weights_convex_and_mean_preserving():
     tot = info["om1"] + info["oms"].sum(1)
     assert np.allclose(tot, 1.0, atol=1e-14)
     assert info["om1"].min() >= 0 and info["oms"].min() >= 0
+    # mean over the cell of U_i + sum_k a_k phi_k by a Gauss rule of its own
+    sel = cells[::7]
+    pts, wq = fields.cell_quadrature(w.mesh, sel, 5)
+    tab = om.tables(sel)
+    xi = (pts - om.geo.cen[sel][:, None, :]) / om.geo.h[sel][:, None, None]
+    phi = monomials(xi, om.exps) - tab["psibar"][:, None, :]
+    vals = w.U[sel][:, None, :] + np.einsum("cqk,ckv->cqv", phi, info["a_cw"][sel])
+    mean = np.einsum("cqv,cq->cv", vals, wq) / wq.sum(1)[:, None]
+    assert np.abs(mean - w.U[sel]).max() < 1e-13 * np.abs(w.U).max()
+    # the solution varies across the jump: the weights move off the linear ones
+    assert np.abs(info["om1"] - info["lam1"]).max() > 1e-3
     # across the jump the central weight must drop well below lambda_1
     assert info["om1"].min() < 0.5
+
+
+def _weight_deviation(n, b):
+    """Largest |omega - lambda| over the cells and their valid stencils of the
+    smooth periodic field, and the largest tau, on the n x n triangle mesh."""
+    w = configs.c1_density_jump(n, 2, jump=False)
+    om = OracleModel(w.mesh, w.stencils, w.params.with_(scheme_mode=ALL_CWENOZ, b_w=b))
+    cells = np.arange(w.mesh.n_cells)
+    _, info = om.cwenoz(cells, w.U)
+    valid = np.arange(info["oms"].shape[1])[None, :] < w.stencils.n_dir[cells][:, None]
+    dev = max(np.abs(info["om1"] - info["lam1"]).max(),
+              np.abs(info["oms"] - info["lams"][:, None, None])[valid].max())
+    return dev, info["tau"].max(), info["SI1"].max()
+
+
+def test_cwenoz_weights_converge_to_linear_weights():
+    """On smooth data the nonlinear weights tend to the linear weights
+    (Section 2.3) at a rate fixed by the exponent b.
+
+    In the reference frame the degree-1 directional fits and the central fit
+    agree on the gradient to O(h^2), so every SI is h^2 |grad u|^2 + O(h^3)
+    and tau = mean |SI_s - SI_1| = O(h^3); with eps fixed, the ratio
+    tau / (eps + SI_s) is O(h^3) and the weights' departure from lambda,
+    which is O(ratio^b), falls at rate >= 3 b under refinement."""
+    ns = (16, 32, 64)
+    for b, use in ((4.0, (16, 32)), (2.0, ns)):
+        devs, taus, sis = zip(*[_weight_deviation(n, b) for n in use])
+        rate_tau = np.log2(np.array(taus[:-1]) / np.array(taus[1:]))
+        rate_si = np.log2(np.array(sis[:-1]) / np.array(sis[1:]))
+        rate_w = np.log2(np.array(devs[:-1]) / np.array(devs[1:]))
+        assert np.all(rate_tau > 2.9), rate_tau
+        assert np.all(rate_si > 1.5) and np.all(rate_si < 2.5), rate_si
+        assert np.all(rate_w >= 3 * b), (b, rate_w)
 
 
 def test_nad_smooth_vortex_all_linear():
@@ -313,6 +360,92 @@ def test_hllc_hll_consistency_and_symmetry():
         Ls, Rs = fields.prim_to_cons(prim_s), fields.prim_to_cons(prim_s2)
         for fn in (flux.hllc, flux.hll):
             assert np.allclose(fn(Ls, Rs, n, 1.4), flux.euler_flux(Ls, n, 1.4), rtol=1e-13)
+
+
+def _subsonic_states(rng, d, n):
+    prim = np.concatenate([rng.uniform(0.5, 2, (n, 1)), 0.3 * rng.normal(size=(n, d)),
+                           rng.uniform(0.5, 2, (n, 1))], 1)
+    prim2 = np.concatenate([rng.uniform(0.5, 2, (n, 1)), 0.3 * rng.normal(size=(n, d)),
+                            rng.uniform(0.5, 2, (n, 1))], 1)
+    nrm = rng.normal(size=(n, d))
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    return fields.prim_to_cons(prim), fields.prim_to_cons(prim2), nrm
+
+
+def test_hllc_star_states_satisfy_integral_conservation():
+    """Toro's HLLC (Section 2.4): over the wave fan [S_L t, S_R t] the two
+    star states hold exactly the conserved quantity the integral form of the
+    conservation law leaves there,
+        (S* - S_L) U*_L + (S_R - S*) U*_R = S_R U_R - S_L U_L - (F_R - F_L),
+    both move with normal velocity S*, and each keeps its side's tangential
+    velocity."""
+    rng = np.random.default_rng(21)
+    for d in (2, 3):
+        UL, UR, nrm = _subsonic_states(rng, d, 400)
+        SL, SR, Ss, UsL, UsR, FL, FR = flux.hllc_star_states(UL, UR, nrm, 1.4)
+        assert np.all(SL < 0) and np.all(SR > 0)
+        lhs = (Ss - SL)[:, None] * UsL + (SR - Ss)[:, None] * UsR
+        rhs = SR[:, None] * UR - SL[:, None] * UL - (FR - FL)
+        assert np.abs(lhs - rhs).max() < 1e-12 * np.abs(rhs).max()
+        for U, Us in ((UL, UsL), (UR, UsR)):
+            vs = Us[:, 1:-1] / Us[:, :1]
+            v = U[:, 1:-1] / U[:, :1]
+            assert np.allclose((vs * nrm).sum(1), Ss, rtol=0, atol=1e-12)
+            tang = lambda x: x - (x * nrm).sum(1, keepdims=True) * nrm
+            assert np.allclose(tang(vs), tang(v), rtol=0, atol=1e-12)
+
+
+def test_hll_flux_is_the_wave_fan_average():
+    """HLL (Section 2.4): the single intermediate state is the wave-fan
+    average U* = (S_R U_R - S_L U_L - (F_R - F_L)) / (S_R - S_L) of the
+    integral conservation law, and the flux across the face follows from
+    either outer wave's Rankine-Hugoniot relation:
+        F = F_L + S_L (U* - U_L) = F_R + S_R (U* - U_R)."""
+    rng = np.random.default_rng(22)
+    for d in (2, 3):
+        UL, UR, nrm = _subsonic_states(rng, d, 400)
+        _, _, SL, SR = flux._speeds(UL, UR, nrm, 1.4)
+        FL, FR = flux.euler_flux(UL, nrm, 1.4), flux.euler_flux(UR, nrm, 1.4)
+        Us = (SR[:, None] * UR - SL[:, None] * UL - (FR - FL)) / (SR - SL)[:, None]
+        F = flux.hll(UL, UR, nrm, 1.4)
+        scale = np.abs(F).max()
+        assert np.abs(F - (FL + SL[:, None] * (Us - UL))).max() < 1e-12 * scale
+        assert np.abs(F - (FR + SR[:, None] * (Us - UR))).max() < 1e-12 * scale
+
+
+def test_stationary_and_moving_contacts():
+    """A contact (equal pressure and velocity, different density) is resolved
+    exactly by HLLC, which carries the contact wave, and smeared by HLL:
+    at rest HLLC gives the flux (0, p n, 0) and HLL moves mass from the
+    dense side to the light side; a contact moving with normal velocity u
+    gets HLLC's upwind flux F(U_L) for u > 0 and F(U_R) for u < 0."""
+    rng = np.random.default_rng(23)
+    for d in (2, 3):
+        n = 200
+        nrm = rng.normal(size=(n, d))
+        nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+        p = rng.uniform(0.5, 2.0, n)
+        rl, rr = rng.uniform(0.2, 3.0, n), rng.uniform(0.2, 3.0, n)
+        zero = np.zeros((n, d))
+        UL = fields.prim_to_cons(np.concatenate([rl[:, None], zero, p[:, None]], 1))
+        UR = fields.prim_to_cons(np.concatenate([rr[:, None], zero, p[:, None]], 1))
+        F = flux.hllc(UL, UR, nrm, 1.4)
+        assert np.abs(F[:, 0]).max() < 1e-14 and np.abs(F[:, -1]).max() < 1e-14
+        assert np.allclose(F[:, 1:-1], p[:, None] * nrm, rtol=0, atol=1e-14)
+        Fh = flux.hll(UL, UR, nrm, 1.4)
+        assert np.all(Fh[:, 0] * (rr - rl) < 0)                         # dense -> light
+        assert np.allclose(Fh[:, 1:-1], p[:, None] * nrm, rtol=0, atol=1e-13)
+        # moving contact: velocity u n plus a tangential part, subsonic
+        t = rng.normal(size=(n, d))
+        t -= (t * nrm).sum(1, keepdims=True) * nrm
+        for sgn in (1.0, -1.0):
+            u = sgn * rng.uniform(0.05, 0.5, n)
+            vel = u[:, None] * nrm + 0.3 * t
+            UL = fields.prim_to_cons(np.concatenate([rl[:, None], vel, p[:, None]], 1))
+            UR = fields.prim_to_cons(np.concatenate([rr[:, None], vel, p[:, None]], 1))
+            F = flux.hllc(UL, UR, nrm, 1.4)
+            up = flux.euler_flux(UL if sgn > 0 else UR, nrm, 1.4)
+            assert np.abs(F - up).max() < 1e-13 * np.abs(up).max()
 
 
 def test_venkatakrishnan_limiter_function():
