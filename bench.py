@@ -15,20 +15,33 @@ and the r = 2 hexahedral case, FP32 for the r = 4 hexahedral case and the
 mixed tetrahedron / prism / hexahedron box, as their configurations state);
 `modes` holds cells reconstructed/s, residual evaluations/s, the fraction of
 the HBM roofline of the reconstruction and of the residual, and per-kernel
-times, for hybrid, all-CWENOZ and all-linear in FP64 and FP32.  `roofline` is
-the live measurement of the kernel that takes the most time in the headline
-hybrid residual, against the 8 TB/s peak and against the bandwidth a plain
-1 GiB device copy reaches in the same process.  Each mode also reports the
-median of single residuals started after a 1 GiB write that flushes the
-last-level cache (`ms_residual_cold`), the step captured once into a HIP graph
-and replayed (`ms_residual_graph`), the adjoint (vector-Jacobian product of
-the residual with the step's classes frozen: `ms_vjp`, `vjp_evals_per_s`; `ms_vjp_given_states` when the
-step's face states are passed in and not recomputed) and, on workloads whose field is
-smooth and known in closed form (the hexahedral Taylor-Green cases), the RMS
-error of its face states against the exact point values
-(`face_err_rms_rel`), the accuracy at which the modes are compared.  FP32 modes report their face states' largest error against the
-FP64 path's on cells of equal class (`fp32_state_err_vs_fp64`) and the number
-of class flips (`fp32_class_flips`).
+times, for hybrid, all-CWENOZ and all-linear in FP64 and FP32.
+
+Bytes: `roofline.bytes_per_launch` and every `*_hbm_frac` count the
+algorithmic bytes of the scope definition (ByteModel.s_*: per-cell tables and
+states the method must move, neighbours' averages as cache hits, the linear
+fit kept on chip for CWENOZ); the `*_model` keys count what each kernel as
+built must read and write (it re-reads the fit's tables or the kept fit).
+`roofline` is the live measurement of the kernel that takes the most time in
+the headline hybrid residual, against the 8 TB/s peak and against the
+bandwidth a plain 1 GiB device copy reaches in the same process;
+`roofline.traffic` is the counted HBM traffic of that kernel (rocprofv3
+FETCH_SIZE + WRITE_SIZE, calibrated) while its sources are unchanged.
+
+Each mode also reports the median of single residuals started after a 1 GiB
+write that flushes the last-level cache (`ms_residual_cold`), the step
+captured once into a HIP graph and replayed (`ms_residual_graph`), the
+adjoint (vector-Jacobian product of the residual with the step's classes
+frozen: `ms_vjp`, `vjp_evals_per_s`; `ms_vjp_given_states` when the step's
+face states are passed in and not recomputed) and, on workloads whose field
+is smooth and known in closed form (the hexahedral Taylor-Green cases), the
+RMS error of its face states against the exact point values
+(`face_err_rms_rel`), the accuracy at which the modes are compared.  FP32
+modes report their face states' largest error against the FP64 path's on
+cells of equal class (`fp32_state_err_vs_fp64`) and the number of class
+flips (`fp32_class_flips`).  `workloads` repeats the FP32 hybrid /
+all-CWENOZ / all-linear measurement, warm and cache-flushed, on the ~1M-cell
+mixed 3D box (`--extra`), whose working set exceeds the last-level cache.
 Progress goes to stderr.
 """
 from __future__ import annotations
@@ -74,6 +87,7 @@ class ByteModel:
         owner = np.repeat(np.arange(mesh.n_cells), np.diff(mesh.cell_face_off))
         self.ngp = np.bincount(owner, weights=fgp[mesh.cell_face], minlength=mesh.n_cells)
         self.nfc = np.diff(mesh.cell_face_off)
+        self.nvtx = np.diff(mesh.cell_vtx_off)
         self.ndir = st.n_dir.astype(np.float64)
         self.nmus = st.n_muscl.astype(np.float64)
         self.N, self.NF = mesh.n_cells, mesh.n_faces
@@ -114,6 +128,61 @@ class ByteModel:
         # flux and gather without the face-flux array between them
         s, nv = self.s, self.nv
         return self.flux() - self.NF * s * nv + self.gather() - self.nfc.sum() * s * nv
+
+    # --- the scope definition's algorithmic bytes --------------------------
+    # What the method must move per unit, the neighbours' averages taken as
+    # cache hits and the linear pass's fit as kept on chip:
+    #   linear (every cell): s K M (pseudo-inverse) + 4 M (stencil ids)
+    #     + s nvar (U) + s K (basis means) + s d n_vtx (geometry for the Gauss
+    #     points) + s nvar n_gp (face states) + 1 (class);
+    #   CWENOZ extra (listed cell): s K (K+1)/2 (OI) + N_f (s d M_d + 4 M_d)
+    #     (directional fits and ids) + s nvar n_gp (states re-written);
+    #   MUSCL extra: s d N_f + s nvar n_gp;  first-order extra: s nvar n_gp;
+    #   residual: both sides' face states, face geometry (normal, weight x
+    #     area), F written (nvar per face), F gathered (twice per face), R.
+    def s_linear(self):
+        s, K, M, nv, d = self.s, self.K, self.M, self.nv, self.d
+        return (self.N * (s * K * M + 4 * M + s * nv + s * K + 1) + s * d * self.nvtx.sum()
+                + self.ngp.sum() * s * nv)
+
+    def s_cwenoz_extra(self, m):
+        s, K, nv, d, Md = self.s, self.K, self.nv, self.d, self.Md
+        return (m.sum() * s * K * (K + 1) // 2 + (self.ndir[m] * (s * d * Md + 4 * Md)).sum()
+                + self.ngp[m].sum() * s * nv)
+
+    def s_muscl_extra(self, m):
+        return (self.s * self.d * self.nfc[m].sum() + self.ngp[m].sum() * self.s * self.nv)
+
+    def s_first_extra(self, m):
+        return self.ngp[m].sum() * self.s * self.nv
+
+    def s_flux(self):
+        s, nv, d = self.s, self.nv, self.d
+        return self.fgp.sum() * (2 * s * nv + s) + self.NF * (s * d + s * nv)
+
+    def s_gather(self):
+        s, nv = self.s, self.nv
+        return 2 * self.NF * s * nv + self.N * s * nv
+
+    def s_per_kernel(self, mode, cls, fused):
+        """{kernel: bytes} of one reconstruction + residual in `mode` by the
+        scope definition (all-CWENOZ cells count the linear bytes too, with
+        one write of the states: the direct CWENOZ pass does the fit itself)."""
+        cw, mu, fo = cls == 1, cls == 2, cls == 3
+        if mode == "cwenoz":   # the direct pass writes each cell's states once
+            out = {"cwenoz": self.s_linear() + self.s_cwenoz_extra(np.ones(self.N, bool))
+                   - self.ngp.sum() * self.s * self.nv}
+        else:
+            out = {"linear": self.s_linear()}
+            if mode == "hybrid":
+                out["cwenoz"] = self.s_cwenoz_extra(cw)
+            out["muscl"] = self.s_muscl_extra(mu) + self.s_first_extra(fo)
+        if fused:
+            out["flux"] = self.s_flux() + self.s_gather() - 3 * self.NF * self.s * self.nv
+        else:
+            out["flux"] = self.s_flux()
+            out["gather"] = self.s_gather()
+        return {k: int(v) for k, v in out.items()}
 
     def per_kernel(self, mode, cls, reuse, fused):
         """{kernel: bytes} of one reconstruction + residual in `mode`."""
@@ -367,12 +436,15 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def main():
+def parse_args(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c2")
+    ap.add_argument("--extra", default="c4",
+                    help="comma-separated workloads also measured (FP32 hybrid / all-CWENOZ / all-linear, "
+                         "warm and cache-flushed) under `workloads` in the JSON line; empty for none")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the library's default launch configuration")
     ap.add_argument("--launch", default="",
@@ -390,48 +462,19 @@ def main():
                          "(0: skip)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU sharding of the mesh "
-                                   "is described in the design notes but not built", "n_gpus": args.gpus}))
-        sys.exit(2)
+    return ap.parse_args(argv)
 
-    # inputs first: the mixed-mesh generator forks worker processes, which must
-    # happen before this process touches the GPU
-    t0 = time.perf_counter()
-    w = make_workload(args.workload, workers=args.workers, cell_order=args.cell_order)
-    wl_text, wl_tag, head_prec = WORKLOADS[args.workload]
-    log(f"workload {args.workload}: {w.mesh.n_cells} cells, built in {time.perf_counter() - t0:.1f} s")
-    # the oracle on the host cores, before the GPU is touched (the all-core leg forks)
-    cpu1 = cpuN = None
-    if not args.no_cpu_baseline and args.workload == "c2":
-        cpu1 = cpu_baseline(w)
-        cpuN = cpu_baseline_all_cores(w, args.workers) if args.workers > 1 else None
-        log(f"oracle: {cpu1['value']:.3g} cells/s on 1 core"
-            + (f", {cpuN['value']:.3g} on {cpuN['cores']}" if cpuN else ""))
 
-    import torch
-    from paper_2510_25906_amd import hfv
+def measure(w, wl_tag, head_prec, variants, args, torch, hfv, probe, flush, extra_leg=False):
+    """Autotune and time each (precision, mode) variant of workload `w`.
+    Returns (modes, headline ms per residual, roofline of the headline's
+    dominant kernel, headline class counts)."""
     from paper_2510_25906_amd.inputs.params import HYBRID, ALL_CWENOZ, ALL_LINEAR
-
-    hfv.load()
-    if args.copy_mib:
-        n = args.copy_mib * (1 << 20) // 4
-        x = torch.ones(n, dtype=torch.float32, device="cuda")
-        y = torch.empty_like(x)
-        y.copy_(x)
-        torch.cuda.synchronize()
-        del x, y
-    probe = probe_bandwidth(torch)
-    log(f"copy probe {probe:.0f} GB/s")
-    flush = torch.empty(1 << 28, dtype=torch.float32, device="cuda") if args.cold else None
     acc = None
     ref64 = {}    # FP64 face states and classes per mode, for the FP32 error
     mesh = w.mesh
     N = mesh.n_cells
     names = {HYBRID: "hybrid", ALL_CWENOZ: "cwenoz", ALL_LINEAR: "linear"}
-    variants = [(head_prec, HYBRID)] if args.quick else [(p, m) for p in (64, 32) for m in (HYBRID, ALL_CWENOZ, ALL_LINEAR)]
-
     modes, headline, roof, classes = {}, None, None, None
     for prec in sorted(set(p for p, _ in variants), reverse=True):
         t0 = time.perf_counter()
@@ -453,7 +496,7 @@ def main():
             dl = dict(default_launch)
             ctx.set_launch(lanes=dl.pop("lanes_per_cell"), **dl)
             t_tune = 0.0
-            if args.launch:
+            if args.launch and not extra_leg:
                 fixed = dict(kv.split("=") for kv in args.launch.split(","))
                 fixed = {k: int(v) for k, v in fixed.items()}
                 if "lanes_per_cell" in fixed:
@@ -464,7 +507,7 @@ def main():
                 ctx.autotune(U, reps=5)
                 t_tune = time.perf_counter() - t0
             launch = ctx.get_launch()
-            log(f"FP{prec} {name}: setup {t_setup:.1f} s, tuned in {t_tune:.1f} s")
+            log(f"{wl_tag} FP{prec} {name}: setup {t_setup:.1f} s, tuned in {t_tune:.1f} s")
             # spin-up: first launches load code objects, and the clocks settle
             # under sustained load
             t_end = time.perf_counter() + args.spinup
@@ -488,35 +531,49 @@ def main():
                 ctx.profile_enable(args.steps * 2, slots=[dominant])
             ms_res = time_steps(lambda: ctx.residual(U, R, fs, cls), args.steps, 0 if live else args.warmup, torch)
             cl_dev = cls.cpu().numpy()
-            byts = bm.per_kernel(name, cl_dev, bool(launch["cwenoz_reuse"]), bool(launch["fused_residual"]))
+            reuse, fused = bool(launch["cwenoz_reuse"]), bool(launch["fused_residual"])
+            mbyts = bm.per_kernel(name, cl_dev, reuse, fused)       # the kernels' own byte counts
+            sbyts = bm.s_per_kernel(name, cl_dev, fused)            # the scope definition's bytes
             if live:
                 prof = ctx.profile_read()
                 ctx.profile_enable(0)
                 k_ms, k_n = prof[dominant]
                 avg = k_ms / k_n
-                ach = byts[dominant] / (avg * 1e-3) / 1e9
-                kname = FUSED_NAME if (dominant == "flux" and launch["fused_residual"]) else KERNELS[dominant]
+                ach = sbyts[dominant] / (avg * 1e-3) / 1e9
+                ach_m = mbyts[dominant] / (avg * 1e-3) / 1e9
+                kname = FUSED_NAME if (dominant == "flux" and fused) else KERNELS[dominant]
                 traffic = measured_traffic(kname, wl_tag)
                 roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
+                        "traffic_over_bytes": round(traffic / sbyts[dominant], 3) if traffic else None,
                         "probe_copy_GBps": round(probe, 1), "frac_of_probe": round(ach / probe, 4),
                         "kernel": f"{kname} ({name}, FP{prec})",
-                        "bytes_per_launch": byts[dominant], "avg_launch_ms": round(avg, 5)}
+                        "bytes_per_launch": sbyts[dominant], "avg_launch_ms": round(avg, 5),
+                        "model_bytes_per_launch": mbyts[dominant], "achieved_model": round(ach_m, 1),
+                        "frac_model": round(ach_m / HBM_PEAK_GBS, 4),
+                        "step_bytes": int(sum(sbyts.values())),
+                        "step_frac": round(sum(sbyts.values()) / (ms_res * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
                 headline = ms_res
                 classes = np.bincount(cl_dev, minlength=4)
             ms_cold = time_cold(lambda: ctx.residual(U, R, fs, cls), args.cold, flush, torch) if args.cold else None
-            # the adjoint with these classes frozen (vector-Jacobian product of the residual)
-            gR = torch.ones_like(U)
-            gU = torch.empty_like(U)
-            ctx.residual(U, R, fs, cls)
-            ms_vjp = time_steps(lambda: ctx.residual_vjp(U, cls, gR, gU), args.steps, args.warmup, torch)
-            ms_vjp_states = time_steps(lambda: ctx.residual_vjp(U, cls, gR, gU, face_states=fs), args.steps,
-                                       args.warmup, torch)
-            del gR, gU
-            # the same step captured once into a HIP graph and replayed (one launch per step)
-            graph = ctx.graph_residual(U, R, fs, cls)
-            ms_graph = time_steps(graph.replay, args.steps, args.warmup, torch)
-            del graph
+            rec = {}
+            if not extra_leg:
+                # the adjoint with these classes frozen (vector-Jacobian product of the residual)
+                gR = torch.ones_like(U)
+                gU = torch.empty_like(U)
+                ctx.residual(U, R, fs, cls)
+                ms_vjp = time_steps(lambda: ctx.residual_vjp(U, cls, gR, gU), args.steps, args.warmup, torch)
+                ms_vjp_states = time_steps(lambda: ctx.residual_vjp(U, cls, gR, gU, face_states=fs), args.steps,
+                                           args.warmup, torch)
+                del gR, gU
+                # the same step captured once into a HIP graph and replayed (one launch per step)
+                graph = ctx.graph_residual(U, R, fs, cls)
+                ms_graph = time_steps(graph.replay, args.steps, args.warmup, torch)
+                del graph
+                rec.update(ms_residual_graph=round(ms_graph, 4), ms_vjp=round(ms_vjp, 4),
+                           vjp_evals_per_s=round(1.0 / (ms_vjp * 1e-3), 2),
+                           vjp_over_residual=round(ms_vjp / ms_res, 3),
+                           ms_vjp_given_states=round(ms_vjp_states, 4))
             face_err = None
             if w.exact is not None:
                 if acc is None:
@@ -528,27 +585,28 @@ def main():
             elif prec == 32 and mode in ref64:
                 fp32_err = fp32_error(ref64.pop(mode), fs.cpu().numpy(), cl_dev, bm.ngp, w.U)
             cl = np.bincount(cl_dev, minlength=4)
-            rec_b = sum(v for k, v in byts.items() if k not in ("flux", "gather"))
+            rec_s = sum(v for k, v in sbyts.items() if k not in ("flux", "gather"))
+            rec_m = sum(v for k, v in mbyts.items() if k not in ("flux", "gather"))
+            frac = lambda b, ms: round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
             modes[f"{name}_fp{prec}"] = {
                 "recon_cells_per_s": round(N / (ms_rec * 1e-3), 1),
                 "residual_evals_per_s": round(1.0 / (ms_res * 1e-3), 2),
                 "residual_cells_per_s": round(N / (ms_res * 1e-3), 1),
                 "ms_recon": round(ms_rec, 4), "ms_residual": round(ms_res, 4),
-                "recon_hbm_frac": round(rec_b / (ms_rec * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                "residual_hbm_frac": round(sum(byts.values()) / (ms_res * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "recon_hbm_frac": frac(rec_s, ms_rec),
+                "residual_hbm_frac": frac(sum(sbyts.values()), ms_res),
+                "recon_hbm_frac_model": frac(rec_m, ms_rec),
+                "residual_hbm_frac_model": frac(sum(mbyts.values()), ms_res),
                 "class_fractions": [round(x / N, 4) for x in cl],
                 "kernel_us": {k: round(v * 1e3, 1) for k, v in kern.items()},
-                "kernel_hbm_frac": {k: round(byts[k] / (kern[k] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
-                                    for k in kern if k in byts},
+                "kernel_hbm_frac": {k: frac(sbyts[k], kern[k]) for k in kern if k in sbyts},
+                "kernel_hbm_frac_model": {k: frac(mbyts[k], kern[k]) for k in kern if k in mbyts},
                 "launch": launch, "tune_s": round(t_tune, 2), "setup_s": round(t_setup, 3),
+                **rec,
             }
-            modes[f"{name}_fp{prec}"]["ms_residual_graph"] = round(ms_graph, 4)
-            modes[f"{name}_fp{prec}"]["ms_vjp"] = round(ms_vjp, 4)
-            modes[f"{name}_fp{prec}"]["vjp_evals_per_s"] = round(1.0 / (ms_vjp * 1e-3), 2)
-            modes[f"{name}_fp{prec}"]["vjp_over_residual"] = round(ms_vjp / ms_res, 3)
-            modes[f"{name}_fp{prec}"]["ms_vjp_given_states"] = round(ms_vjp_states, 4)
             if ms_cold is not None:
                 modes[f"{name}_fp{prec}"]["ms_residual_cold"] = round(ms_cold, 4)
+                modes[f"{name}_fp{prec}"]["residual_hbm_frac_cold"] = frac(sum(sbyts.values()), ms_cold)
             if face_err is not None:
                 modes[f"{name}_fp{prec}"]["face_err_rms_rel"] = float(f"{face_err:.6g}")
             if fp32_err is not None:
@@ -561,7 +619,71 @@ def main():
         if h and c:
             h["speedup_vs_cwenoz_residual"] = round(c["ms_residual"] / h["ms_residual"], 3)
             h["speedup_vs_cwenoz_recon"] = round(c["ms_recon"] / h["ms_recon"], 3)
+            if "ms_residual_cold" in h and "ms_residual_cold" in c:
+                h["speedup_vs_cwenoz_residual_cold"] = round(c["ms_residual_cold"] / h["ms_residual_cold"], 3)
+    return modes, headline, roof, classes
 
+
+def main():
+    args = parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU sharding of the mesh "
+                                   "is described in the design notes but not built", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    # inputs first: the mixed-mesh generator forks worker processes, which must
+    # happen before this process touches the GPU
+    t0 = time.perf_counter()
+    w = make_workload(args.workload, workers=args.workers, cell_order=args.cell_order)
+    wl_text, wl_tag, head_prec = WORKLOADS[args.workload]
+    log(f"workload {args.workload}: {w.mesh.n_cells} cells, built in {time.perf_counter() - t0:.1f} s")
+    extras = [x for x in args.extra.split(",") if x and x != args.workload] if not args.quick else []
+    extra_w = {}
+    for x in extras:
+        t0 = time.perf_counter()
+        extra_w[x] = make_workload(x, workers=args.workers, cell_order=args.cell_order)
+        log(f"extra workload {x}: {extra_w[x].mesh.n_cells} cells, built in {time.perf_counter() - t0:.1f} s")
+    # the oracle on the host cores, before the GPU is touched (the all-core leg forks)
+    cpu1 = cpuN = None
+    if not args.no_cpu_baseline and args.workload == "c2":
+        cpu1 = cpu_baseline(w)
+        cpuN = cpu_baseline_all_cores(w, args.workers) if args.workers > 1 else None
+        log(f"oracle: {cpu1['value']:.3g} cells/s on 1 core"
+            + (f", {cpuN['value']:.3g} on {cpuN['cores']}" if cpuN else ""))
+        for rec in (cpu1, cpuN):
+            if rec is not None:
+                rec["host_cpu"] = host_cpu_model()
+
+    import torch
+    from paper_2510_25906_amd import hfv
+    from paper_2510_25906_amd.inputs.params import HYBRID, ALL_CWENOZ, ALL_LINEAR
+
+    hfv.load()
+    if args.copy_mib:
+        n = args.copy_mib * (1 << 20) // 4
+        x = torch.ones(n, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
+    probe = probe_bandwidth(torch)
+    log(f"copy probe {probe:.0f} GB/s")
+    flush = torch.empty(1 << 28, dtype=torch.float32, device="cuda") if args.cold else None
+    variants = [(head_prec, HYBRID)] if args.quick else \
+        [(p, m) for p in (64, 32) for m in (HYBRID, ALL_CWENOZ, ALL_LINEAR)]
+    modes, headline, roof, classes = measure(w, wl_tag, head_prec, variants, args, torch, hfv, probe, flush)
+    N = w.mesh.n_cells
+    others = {}
+    for x, wx in extra_w.items():
+        text_x, tag_x, prec_x = WORKLOADS[x]
+        m_x, h_x, roof_x, cls_x = measure(wx, tag_x, prec_x,
+                                          [(prec_x, HYBRID), (prec_x, ALL_CWENOZ), (prec_x, ALL_LINEAR)],
+                                          args, torch, hfv, probe, flush, extra_leg=True)
+        Nx = wx.mesh.n_cells
+        others[x] = {"workload": text_x, "n_cells": Nx, "precision": f"fp{prec_x}",
+                     "residual_cells_per_s": round(Nx / (h_x * 1e-3), 1), "ms_per_step": round(h_x, 5),
+                     "class_fractions": [round(v / Nx, 4) for v in cls_x], "roofline": roof_x, "modes": m_x}
+        del wx
     out = {
         "metric": "cells reconstructed/s & residual evals/s: hybrid vs all-CWENOZ, FP32 vs FP64",
         "value": round(N / (headline * 1e-3), 1),
@@ -582,11 +704,25 @@ def main():
         "paper_context": "paper: up to 2.5x hybrid over CWENOZ, whole viscous solver on ARCHER2 CPUs "
                          "(10 nodes x 128 cores), 128^3 hex TGV",
     }
+    if others:
+        out["workloads"] = others
     if cpu1 is not None:
         out["cpu_baseline"] = cpu1
     if cpuN is not None:
         out["cpu_baseline_all_cores"] = cpuN
     print(json.dumps(out), flush=True)
+
+
+def host_cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 if __name__ == "__main__":

@@ -216,7 +216,14 @@ hfv_status hfv_residual_vjp(hfv_ctx *ctx, const void *U, const uint8_t *cell_cla
 hfv_status hfv_residual_vjp_states(hfv_ctx *ctx, const void *U, const uint8_t *cell_class, const void *face_states,
                                    const void *gR, void *gU, void *stream);
 
-/* Queries (synchronous for the class counts, which read device counters). */
+/* Queries.  HFV_Q_COUNT_* are the lengths of the CWENOZ, MUSCL and
+ * first-order work lists as the last compaction built them (hybrid and
+ * all-linear reconstructions, the frozen residual and the VJP): cells that
+ * the CWENOZ or MUSCL pass then demotes to first order by the Harten check
+ * are still counted in their list, and the all-CWENOZ and all-MUSCL modes,
+ * which build no lists, leave them at 0.  The final classes are the
+ * cell_class output.  Reading a count synchronises the whole device (every
+ * stream) first, then copies the counters. */
 enum {
   HFV_Q_N_CELLS = 0, HFV_Q_N_FACES = 1, HFV_Q_N_GP = 2, HFV_Q_NVAR = 3, HFV_Q_K = 4, HFV_Q_M = 5,
   HFV_Q_PRECISION = 6, HFV_Q_DIM = 7, HFV_Q_TABLE_BYTES = 8,

@@ -13,6 +13,7 @@ using namespace hfv;
 
 static thread_local std::string g_create_err;
 
+
 static const int kTypeDim[6] = {2, 2, 3, 3, 3, 3};
 static const int kTypeNv[6] = {3, 4, 4, 5, 6, 8};
 static const int kTypeNf[6] = {3, 4, 4, 5, 5, 6};
@@ -301,6 +302,8 @@ hfv_status hfv_query(const hfv_ctx *ctx, int32_t what, int64_t *out) {
     case HFV_Q_COUNT_MUSCL:
     case HFV_Q_COUNT_FIRST: {
       int c[8];
+      // the counters may be written by work on any of the caller's streams
+      if (hipDeviceSynchronize() != hipSuccess) return HFV_ERR_HIP;
       if (hipMemcpy(c, ctx->counts, sizeof c, hipMemcpyDeviceToHost) != hipSuccess) return HFV_ERR_HIP;
       *out = c[1 + what - HFV_Q_COUNT_CWENOZ];
       return HFV_OK;

@@ -270,12 +270,37 @@ class Context:
         self._check(self.lib.hfv_copy_table(self.h, TABLES[name], out.ctypes.data_as(C.c_void_p), out.nbytes))
         return out
 
-    def _chk_u(self, U):
+    def _chk(self, *bufs):
+        """Check every device buffer argument of a call before any address
+        crosses the ABI (the library trusts the pointers it is given).
+
+        bufs: (tensor or None, name, kind) with kind "u" ([nvar, n_cells] in
+        the context's dtype), "cls" (uint8 [n_cells]), "fs" (the shape of
+        new_face_states()) or "rate" (float64 [1]); None entries are skipped.
+        Dtype, shape and layout of all buffers are checked first, then that
+        each is a CUDA tensor; HfvError on the first failure."""
         import torch
-        if U.dtype != self.dtype or not U.is_cuda or tuple(U.shape) != (self.nvar, self.n_cells) \
-                or not U.is_contiguous():
-            raise HfvError(-4, f"U must be a contiguous {self.dtype} CUDA tensor of shape "
-                               f"({self.nvar}, {self.n_cells})")
+        kinds = dict(u=(self.dtype, (self.nvar, self.n_cells)),
+                     cls=(torch.uint8, (self.n_cells,)),
+                     fs=(self.dtype, (self.ngp_cell, self.nvar, self.n_cells)),
+                     rate=(torch.float64, (1,)))
+        given = [(x, name, kind) for x, name, kind in bufs if x is not None]
+        for x, name, kind in given:
+            dtype, shape = kinds[kind]
+            if not isinstance(x, torch.Tensor):
+                raise HfvError(-1, f"{name} must be a torch tensor, got {type(x).__name__}")
+            if x.dtype != dtype:
+                raise HfvError(-4, f"{name} must have dtype {dtype}, got {x.dtype}")
+            if tuple(x.shape) != tuple(shape):
+                raise HfvError(-1, f"{name} must have shape {tuple(shape)}, got {tuple(x.shape)}")
+            if not x.is_contiguous():
+                raise HfvError(-1, f"{name} must be contiguous")
+        for x, name, kind in given:
+            if not x.is_cuda:
+                raise HfvError(-1, f"{name} must be a CUDA (device) tensor")
+
+    def _chk_u(self, U, name="U"):
+        self._chk((U, name, "u"))
         return U
 
     def new_face_states(self):
@@ -284,7 +309,7 @@ class Context:
 
     def reconstruct(self, U, face_states=None, cell_class=None, stream=None):
         import torch
-        self._chk_u(U)
+        self._chk((U, "U", "u"), (face_states, "face_states", "fs"), (cell_class, "cell_class", "cls"))
         fs = face_states if face_states is not None else self.new_face_states()
         cls = cell_class if cell_class is not None else torch.empty(self.n_cells, dtype=torch.uint8,
                                                                      device="cuda")
@@ -294,7 +319,8 @@ class Context:
 
     def residual(self, U, R=None, face_states=None, cell_class=None, stream=None):
         import torch
-        self._chk_u(U)
+        self._chk((U, "U", "u"), (R, "R", "u"), (face_states, "face_states", "fs"),
+                  (cell_class, "cell_class", "cls"))
         R = R if R is not None else torch.empty_like(U)
         fsp = C.c_void_p(face_states.data_ptr()) if face_states is not None else None
         clp = C.c_void_p(cell_class.data_ptr()) if cell_class is not None else None
@@ -327,16 +353,16 @@ class Context:
         """gU = (dR/dU)^T gR with cell_class frozen; face_states, when given, are
         the states of U from residual / reconstruct (the recompute is skipped)."""
         import torch
-        self._chk_u(U)
+        if cell_class is None or gR is None:
+            raise HfvError(-1, "cell_class and gR must be given")
+        self._chk((U, "U", "u"), (cell_class, "cell_class", "cls"), (gR, "gR", "u"), (gU, "gU", "u"),
+                  (face_states, "face_states", "fs"))
         gU = gU if gU is not None else torch.empty_like(U)
         if face_states is None:
             self._check(self.lib.hfv_residual_vjp(self.h, C.c_void_p(U.data_ptr()),
                                                   C.c_void_p(cell_class.data_ptr()), C.c_void_p(gR.data_ptr()),
                                                   C.c_void_p(gU.data_ptr()), _stream_handle(stream)))
         else:
-            if tuple(face_states.shape) != (self.ngp_cell, self.nvar, self.n_cells) \
-                    or face_states.dtype != self.dtype or not face_states.is_contiguous():
-                raise HfvError(-4, "face_states must be a contiguous tensor shaped like new_face_states()")
             self._check(self.lib.hfv_residual_vjp_states(
                 self.h, C.c_void_p(U.data_ptr()), C.c_void_p(cell_class.data_ptr()),
                 C.c_void_p(face_states.data_ptr()), C.c_void_p(gR.data_ptr()), C.c_void_p(gU.data_ptr()),
@@ -345,9 +371,9 @@ class Context:
 
     def rk_stage(self, out, a, U0, b=0.0, U1=None, c=0.0, R=None, stream=None):
         """out = a U0 + b U1 + c R (one Shu-Osher Runge-Kutta stage); None terms are left out."""
-        for x in (out, U0, U1, R):
-            if x is not None:
-                self._chk_u(x)
+        if out is None:
+            raise HfvError(-1, "out must be given")
+        self._chk((out, "out", "u"), (U0, "U0", "u"), (U1, "U1", "u"), (R, "R", "u"))
         ptr = lambda x: C.c_void_p(x.data_ptr()) if x is not None else None
         self._check(self.lib.hfv_rk_stage(self.h, a, ptr(U0), b, ptr(U1), c, ptr(R), ptr(out),
                                           _stream_handle(stream)))
@@ -356,7 +382,7 @@ class Context:
     def cfl_rate(self, U, out=None, stream=None):
         """Device tensor [1] (float64): max over cells of (|u| + c) / h_c."""
         import torch
-        self._chk_u(U)
+        self._chk((U, "U", "u"), (out, "out", "rate"))
         out = out if out is not None else torch.empty(1, dtype=torch.float64, device="cuda")
         self._check(self.lib.hfv_cfl_rate(self.h, C.c_void_p(U.data_ptr()), C.c_void_p(out.data_ptr()),
                                           _stream_handle(stream)))
@@ -365,18 +391,27 @@ class Context:
     def residual_frozen(self, U, cell_class, R=None, stream=None):
         """Residual with the given classes held fixed (what the VJP linearises)."""
         import torch
-        self._chk_u(U)
+        if cell_class is None:
+            raise HfvError(-1, "cell_class must be given")
+        self._chk((U, "U", "u"), (cell_class, "cell_class", "cls"), (R, "R", "u"))
         R = R if R is not None else torch.empty_like(U)
         self._check(self.lib.hfv_residual_frozen(self.h, C.c_void_p(U.data_ptr()),
                                                  C.c_void_p(cell_class.data_ptr()), C.c_void_p(R.data_ptr()),
                                                  _stream_handle(stream)))
         return R
 
-    def residual_autograd(self, U):
+    def residual_autograd(self, U, keep_states: bool = True):
         """R(U) as a differentiable torch op; backward is the library's VJP with
-        the classes of this forward evaluation frozen, on the face states the
-        forward kept (no recompute; one face-state array held per evaluation)."""
-        return _residual_function().apply(U, self)
+        the classes of this forward evaluation frozen.
+
+        keep_states=True saves the forward's face states for the backward pass
+        (no frozen recompute there), at the cost of one [ngp_cell, nvar,
+        n_cells] array held per evaluation until backward: ngp_cell * nvar *
+        n_cells * 8 bytes in FP64, e.g. 24 * 5 * 1e6 * 4 B = 480 MB in FP32 on
+        a million mixed 3D cells at r = 3, once per Runge-Kutta stage of an
+        unrolled time loop.  keep_states=False saves only U and the classes
+        (n_cells bytes) and the backward pass recomputes the states."""
+        return _residual_function().apply(U, self, bool(keep_states))
 
 
 _RF = None
@@ -390,20 +425,26 @@ def _residual_function():
 
     class Residual(torch.autograd.Function):
         @staticmethod
-        def forward(fctx, U, hctx):
+        def forward(fctx, U, hctx, keep_states):
             U = U.contiguous()
             cls = torch.empty(hctx.n_cells, dtype=torch.uint8, device=U.device)
-            fs = hctx.new_face_states()
+            fs = hctx.new_face_states() if keep_states else None
             R = hctx.residual(U, face_states=fs, cell_class=cls)
-            fctx.save_for_backward(U, cls, fs)
+            if keep_states:
+                fctx.save_for_backward(U, cls, fs)
+            else:
+                fctx.save_for_backward(U, cls)
             fctx.hctx = hctx
+            fctx.keep_states = keep_states
             return R
 
         @staticmethod
         def backward(fctx, gR):
-            U, cls, fs = fctx.saved_tensors
+            saved = fctx.saved_tensors
+            U, cls = saved[0], saved[1]
+            fs = saved[2] if fctx.keep_states else None
             gU = fctx.hctx.residual_vjp(U, cls, gR.contiguous(), face_states=fs)
-            return gU, None
+            return gU, None, None
 
     _RF = Residual
     return _RF

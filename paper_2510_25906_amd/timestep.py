@@ -50,6 +50,8 @@ class SSPRK54:
         shape = (ctx.nvar, ctx.n_cells)
         self.u = [None] + [torch.empty(shape, dtype=ctx.dtype, device="cuda") for _ in range(4)]
         self.r = [torch.empty(shape, dtype=ctx.dtype, device="cuda") for _ in range(2)]
+        # classes of the last stage's evaluation, R(u_4), of the latest step
+        self.cls = torch.empty(ctx.n_cells, dtype=torch.uint8, device="cuda")
         self.steps = 0
 
     def step(self, U, dt):
@@ -71,7 +73,7 @@ class SSPRK54:
         last = SSP54[4]
         # u_1 is free: (a_52 u_2 + a_53 u_3) + dt b_53 R(u_3), with R(u_3) in r[1]
         ctx.rk_stage(u[1], last[2][0], u[2], last[3][0], u[3], dt * last[3][1], r[1], stream=s)
-        R4 = ctx.residual(u[4], r[0], stream=s)
+        R4 = ctx.residual(u[4], r[0], cell_class=self.cls, stream=s)
         ctx.rk_stage(U, 1.0, u[1], last[4][0], u[4], dt * last[4][1], R4, stream=s)
         u[0] = None
         self.steps += 1

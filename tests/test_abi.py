@@ -97,3 +97,66 @@ def hfv_ctx_no_gpu(hfv, mesh, st, params):
     if rc != 0:
         raise hfv.HfvError(rc, lib.hfv_last_error(None).decode())
     raise AssertionError("validation unexpectedly passed")
+
+
+def _shell_context():
+    """A Context with the sizes of a small mesh but no device tables: the
+    buffer checks run before any library call, so they can be exercised on
+    the CPU."""
+    import torch
+    from paper_2510_25906_amd import hfv
+    ctx = hfv.Context.__new__(hfv.Context)
+    ctx.h = None
+    ctx.lib = None
+    ctx.precision, ctx.dtype = 64, torch.float64
+    ctx.n_cells, ctx.nvar, ctx.ngp_cell, ctx.n_faces = 10, 4, 6, 15
+    return ctx
+
+
+def test_every_buffer_argument_is_checked_before_the_abi():
+    """Wrong dtype, shape, layout or device on any buffer argument raises
+    HfvError before its address reaches the library (the calls would
+    otherwise hand a CPU pointer or an undersized buffer to the kernels)."""
+    import torch
+    from paper_2510_25906_amd import hfv
+    ctx = _shell_context()
+    N, nv, ng = ctx.n_cells, ctx.nvar, ctx.ngp_cell
+    f64 = lambda *s: torch.zeros(s, dtype=torch.float64)
+    u8 = lambda *s: torch.zeros(s, dtype=torch.uint8)
+    good_u, good_cls, good_fs = f64(nv, N), u8(N), f64(ng, nv, N)
+    bad = {
+        "dtype": (f64(nv, N).float(), u8(N).int(), f64(ng, nv, N).float()),
+        "shape": (f64(nv, N + 1), u8(N - 1), f64(ng - 1, nv, N)),
+        "contiguous": (f64(N, nv).t(), u8(2 * N)[::2], f64(ng, N, nv).transpose(1, 2)),
+        "CUDA": (good_u, good_cls, good_fs),   # right layout, host memory
+    }
+
+    def calls(u, cls, fs):
+        """(name, thunk) for each buffer argument of every entry point, the
+        buffer under test in that argument and well-formed CPU tensors
+        elsewhere (U is checked first, so it is the bad one or good)."""
+        yield "U", lambda: ctx.reconstruct(u)
+        yield "reconstruct face_states", lambda: ctx.reconstruct(good_u, face_states=fs)
+        yield "reconstruct cell_class", lambda: ctx.reconstruct(good_u, cell_class=cls)
+        yield "residual R", lambda: ctx.residual(good_u, R=u)
+        yield "residual face_states", lambda: ctx.residual(good_u, face_states=fs)
+        yield "residual cell_class", lambda: ctx.residual(good_u, cell_class=cls)
+        yield "frozen cell_class", lambda: ctx.residual_frozen(good_u, cls)
+        yield "frozen R", lambda: ctx.residual_frozen(good_u, good_cls, R=u)
+        yield "vjp cell_class", lambda: ctx.residual_vjp(good_u, cls, good_u)
+        yield "vjp gR", lambda: ctx.residual_vjp(good_u, good_cls, u)
+        yield "vjp gU", lambda: ctx.residual_vjp(good_u, good_cls, good_u, gU=u)
+        yield "vjp face_states", lambda: ctx.residual_vjp(good_u, good_cls, good_u, face_states=fs)
+        yield "rk_stage out", lambda: ctx.rk_stage(u, 1.0, good_u)
+        yield "rk_stage U1", lambda: ctx.rk_stage(good_u, 1.0, good_u, 1.0, u)
+
+    for what, (u, cls, fs) in bad.items():
+        for name, thunk in calls(u, cls, fs):
+            with pytest.raises(hfv.HfvError) as ei:
+                thunk()
+            msg = str(ei.value)
+            # layouts are checked before devices, so the message names the
+            # bad buffer's fault, not the host placement of the good ones
+            assert what in msg, (what, name, msg)
+            if what != "CUDA":
+                assert name.split()[-1] in msg, (what, name, msg)

@@ -26,3 +26,35 @@ def test_fp32_error_masks_padding_and_class_flips():
 def test_workloads_are_described():
     for key, (text, tag, prec) in bench.WORKLOADS.items():
         assert prec in (32, 64) and tag and "cells" in text
+
+
+def test_scope_byte_model_per_cell():
+    """The scope definition's bytes on a uniform periodic triangle mesh, where
+    every cell has 3 faces, 3 vertices and the same Gauss-point count, against
+    the per-cell formulas written out."""
+    from types import SimpleNamespace
+    from paper_2510_25906_amd.inputs import configs
+    w = configs.c1_density_jump(8, 2)
+    m, st = w.mesh, w.stencils
+    ctx = SimpleNamespace(K=5, M=10, nvar=4)
+    for prec, s in ((64, 8), (32, 4)):
+        bm = bench.ByteModel(m, st, ctx, prec, 2)
+        N, NF = m.n_cells, m.n_faces
+        ngp = 3 * 2                                   # 3 edges x 2 Gauss-Legendre points (r = 2)
+        K, M, nv, d, Md, nf = 5, 10, 4, 2, 4, 3
+        lin = s * K * M + 4 * M + s * nv + s * K + s * d * 3 + s * nv * ngp + 1
+        assert bm.s_linear() == N * lin
+        allc = np.ones(N, bool)
+        cw = s * K * (K + 1) // 2 + nf * (s * d * Md + 4 * Md) + s * nv * ngp
+        assert bm.s_cwenoz_extra(allc) == N * cw
+        assert bm.s_muscl_extra(allc) == N * (s * d * nf + s * nv * ngp)
+        assert bm.s_flux() == NF * 2 * (2 * s * nv + s) + NF * (s * d + s * nv)
+        assert bm.s_gather() == 2 * NF * s * nv + N * s * nv
+        # the kernels as built never move fewer bytes than the scope definition
+        cls = np.zeros(N, np.uint8)
+        cls[: N // 3] = 1
+        cls[N // 3: N // 2] = 2
+        for mode in ("hybrid", "cwenoz", "linear"):
+            sb = bm.s_per_kernel(mode, cls, False)
+            mb = bm.per_kernel(mode, cls, False, False)
+            assert sum(sb.values()) <= sum(mb.values())
