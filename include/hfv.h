@@ -162,6 +162,28 @@ hfv_status hfv_reconstruct(hfv_ctx *ctx, const void *U, void *face_states, uint8
 hfv_status hfv_residual(hfv_ctx *ctx, const void *U, void *R, void *face_states, uint8_t *cell_class,
                         void *stream);
 
+/* The residual of hfv_residual without any device allocation and without
+ * the context's workspace: for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  The kernels' scratch (own classes, class lists and their
+ * lengths, face fluxes: HFV_Q_NOALLOC_BYTES bytes for this context) is carved
+ * from one fixed array of HFV_NOALLOC_SCRATCH_BYTES bytes in the library,
+ * one per device, held until the process ends; the library takes its device
+ * address during hfv_create.
+ *   U, R         device [nvar][n_cells]
+ *   face_states  device [ngp_cell_max][nvar][n_cells] output (required)
+ *   cell_class   device [n_cells] output (required)
+ * The CWENOZ pass always refits its central polynomial here (cwenoz_reuse
+ * is ignored), so results equal hfv_residual's to rounding, and bit for bit
+ * when cwenoz_reuse is 0.  Every call on one device uses that device's one
+ * array: calls that overlap on a device (other streams, other contexts,
+ * other threads) race and must be serialised by the caller.
+ * Errors: HFV_ERR_PARAM for a NULL pointer or a mesh needing more scratch
+ * than the maximum (the message gives both sizes). */
+#define HFV_NOALLOC_SCRATCH_BYTES (64u << 20)
+hfv_status hfv_residual_noalloc(hfv_ctx *ctx, const void *U, void *R, void *face_states, uint8_t *cell_class,
+                                void *stream);
+
 /* Residual with given cell classes (the switches of a previous evaluation
  * held fixed): the reconstruction of each cell follows cell_class, with no
  * NAD and no Harten re-check.  The residual a VJP linearises.
@@ -227,7 +249,8 @@ hfv_status hfv_residual_vjp_states(hfv_ctx *ctx, const void *U, const uint8_t *c
 enum {
   HFV_Q_N_CELLS = 0, HFV_Q_N_FACES = 1, HFV_Q_N_GP = 2, HFV_Q_NVAR = 3, HFV_Q_K = 4, HFV_Q_M = 5,
   HFV_Q_PRECISION = 6, HFV_Q_DIM = 7, HFV_Q_TABLE_BYTES = 8,
-  HFV_Q_COUNT_CWENOZ = 9, HFV_Q_COUNT_MUSCL = 10, HFV_Q_COUNT_FIRST = 11, HFV_Q_NGP_CELL_MAX = 12
+  HFV_Q_COUNT_CWENOZ = 9, HFV_Q_COUNT_MUSCL = 10, HFV_Q_COUNT_FIRST = 11, HFV_Q_NGP_CELL_MAX = 12,
+  HFV_Q_NOALLOC_BYTES = 13  /* scratch bytes hfv_residual_noalloc needs for this context */
 };
 hfv_status hfv_query(const hfv_ctx *ctx, int32_t what, int64_t *out);
 

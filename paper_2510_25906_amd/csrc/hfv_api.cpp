@@ -1,6 +1,7 @@
 // C ABI of the hfv library: argument validation, ownership, dispatch.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "hfv_internal.hpp"
@@ -13,6 +14,45 @@ using namespace hfv;
 
 static thread_local std::string g_create_err;
 
+// Scratch of hfv_residual_noalloc: a fixed array in the library's code
+// object, one copy per device, held until the process ends.  Host code never
+// uses its name as an address: the device address of each device's copy is
+// looked up once, with that device current, and kept in g_scratch_addr.
+static __device__ __align__(256) unsigned char scratch[HFV_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_addr[kMaxDevices] = {};
+
+// Device address of `device`'s scratch array (the current device at create).
+hfv_status scratch_address(int device, void **out, std::string &err) {
+  *out = nullptr;
+  if (device < 0 || device >= kMaxDevices) return err = "device ordinal out of range", HFV_ERR_HIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+      return HFV_ERR_HIP;
+    }
+    g_scratch_addr[device] = p;
+  }
+  *out = g_scratch_addr[device];
+  return HFV_OK;
+}
+
+constexpr size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Bytes of scratch hfv_residual_noalloc carves for a context: own classes
+// [N], class lists [3][N], list lengths [8], face fluxes [nvar][NF].
+size_t noalloc_bytes(const hfv_ctx *ctx) {
+  const size_t ts = ctx->prec == 64 ? 8 : 4, N = (size_t)ctx->N;
+  return align256(N) + align256(sizeof(int) * 3 * N) + align256(sizeof(int) * 8) +
+         align256(ts * ctx->nvar * (size_t)ctx->NF);
+}
+}  // namespace
 
 static const int kTypeDim[6] = {2, 2, 3, 3, 3, 3};
 static const int kTypeNv[6] = {3, 4, 4, 5, 6, 8};
@@ -151,7 +191,8 @@ hfv_status hfv_create(const hfv_mesh *mesh, const hfv_stencils *st, const hfv_pa
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) ctx->n_cu = prop.multiProcessorCount;
   ctx->list_blocks = 8 * ctx->n_cu;
-  e = setup_tables(ctx, mesh, st, s);
+  e = scratch_address(ctx->device, &ctx->noalloc_scratch, ctx->err);
+  if (e == HFV_OK) e = setup_tables(ctx, mesh, st, s);
   if (e == HFV_OK) {
     const size_t ts = ctx->prec == 64 ? 8 : 4;
     const int N = ctx->N;
@@ -262,6 +303,49 @@ hfv_status hfv_residual(hfv_ctx *ctx, const void *U, void *R, void *fs, uint8_t 
   return run_residual_tail(ctx, f, R, s);
 }
 
+hfv_status hfv_residual_noalloc(hfv_ctx *ctx, const void *U, void *R, void *fs, uint8_t *cls, void *stream) {
+  if (!ctx) return HFV_ERR_PARAM;
+  if (!U || !R || !fs || !cls) return ctx->err = "NULL device pointer", HFV_ERR_PARAM;
+  const size_t need = noalloc_bytes(ctx);
+  if (need > (size_t)HFV_NOALLOC_SCRATCH_BYTES) {
+    ctx->err = "hfv_residual_noalloc needs " + std::to_string(need) + " bytes of scratch for this mesh, more than its " +
+               std::to_string((size_t)HFV_NOALLOC_SCRATCH_BYTES) + "-byte maximum";
+    return HFV_ERR_PARAM;
+  }
+  if (!ctx->noalloc_scratch) return ctx->err = "scratch array address unknown", HFV_ERR_STATE;
+  // The same kernels as hfv_residual, with the workspace they write carved
+  // from the scratch array; the context's own workspace is put back on every
+  // return path.  The kernels clear the list lengths themselves (the first
+  // block of the linear pass, or a fill kernel), so nothing needs zeroing here.
+  struct Swap {
+    hfv_ctx *c;
+    uint8_t *own;
+    int *lists, *counts;
+    void *coef, *fflux;
+    ~Swap() {
+      c->own = own;
+      c->lists = lists;
+      c->counts = counts;
+      c->coef = coef;
+      c->fflux = fflux;
+    }
+  } keep{ctx, ctx->own, ctx->lists, ctx->counts, ctx->coef, ctx->fflux};
+  unsigned char *b = (unsigned char *)ctx->noalloc_scratch;
+  const size_t N = (size_t)ctx->N;
+  ctx->own = b;
+  b += align256(N);
+  ctx->lists = (int *)b;
+  b += align256(sizeof(int) * 3 * N);
+  ctx->counts = (int *)b;
+  b += align256(sizeof(int) * 8);
+  ctx->fflux = b;
+  ctx->coef = nullptr;  // CWENOZ refits its central polynomial (no kept fits)
+  hipStream_t s = (hipStream_t)stream;
+  hfv_status e = run_reconstruct(ctx, U, fs, cls, s);
+  if (e != HFV_OK) return e;
+  return run_residual_tail(ctx, fs, R, s);
+}
+
 hfv_status hfv_residual_frozen(hfv_ctx *ctx, const void *U, const uint8_t *cls, void *R, void *stream) {
   if (!ctx) return HFV_ERR_PARAM;
   if (!U || !cls || !R) return ctx->err = "NULL device pointer", HFV_ERR_PARAM;
@@ -298,6 +382,7 @@ hfv_status hfv_query(const hfv_ctx *ctx, int32_t what, int64_t *out) {
     case HFV_Q_DIM: *out = ctx->dim; return HFV_OK;
     case HFV_Q_TABLE_BYTES: *out = (int64_t)ctx->table_bytes; return HFV_OK;
     case HFV_Q_NGP_CELL_MAX: *out = ctx->NGPC; return HFV_OK;
+    case HFV_Q_NOALLOC_BYTES: *out = (int64_t)noalloc_bytes(ctx); return HFV_OK;
     case HFV_Q_COUNT_CWENOZ:
     case HFV_Q_COUNT_MUSCL:
     case HFV_Q_COUNT_FIRST: {

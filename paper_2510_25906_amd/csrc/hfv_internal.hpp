@@ -114,6 +114,7 @@ struct hfv_ctx {
   void *fs_ws = nullptr;       // [NGPC][nvar][N] Gauss-point states, cell-major
   void *fflux = nullptr;       // [nvar][NF]
   double *red = nullptr;       // [RED_BLOCKS] per-block partial results of reductions
+  void *noalloc_scratch = nullptr;  // this device's static scratch array (hfv_residual_noalloc)
   void *vjp_C = nullptr;       // adjoint: per stencil slot contributions [M][N][nvar]
   void *vjp_S = nullptr;       // adjoint: self contributions [nvar][N]
   void *vjp_gfs = nullptr;     // adjoint: Gauss-point state cotangents [NGPC][nvar][N]

@@ -22,7 +22,8 @@ HFV_ERR_STATE = -7
 ERRORS = {-1: "HFV_ERR_PARAM", -2: "HFV_ERR_MESH", -3: "HFV_ERR_RANK", -4: "HFV_ERR_DTYPE",
           -5: "HFV_ERR_HIP", -6: "HFV_ERR_OOM", -7: "HFV_ERR_STATE"}
 Q = dict(N_CELLS=0, N_FACES=1, N_GP=2, NVAR=3, K=4, M=5, PRECISION=6, DIM=7, TABLE_BYTES=8,
-         COUNT_CWENOZ=9, COUNT_MUSCL=10, COUNT_FIRST=11, NGP_CELL_MAX=12)
+         COUNT_CWENOZ=9, COUNT_MUSCL=10, COUNT_FIRST=11, NGP_CELL_MAX=12, NOALLOC_BYTES=13)
+NOALLOC_SCRATCH_BYTES = 64 << 20   # HFV_NOALLOC_SCRATCH_BYTES
 SLOTS = dict(linear=0, classify=1, cwenoz=2, muscl=3, flux=5, gather=6, vjp=7)
 TABLES = dict(PINV=0, OI=1, PSIBAR=2, GEOM=3, PDIR=4, PMUS=5, FACE_SLOTS=6, GP_XI=7)
 
@@ -70,6 +71,7 @@ def load():
     lib.hfv_set_params.argtypes = [_p, C.POINTER(HfvParams)]
     lib.hfv_reconstruct.argtypes = [_p, _p, _p, _p, _p]
     lib.hfv_residual.argtypes = [_p, _p, _p, _p, _p, _p]
+    lib.hfv_residual_noalloc.argtypes = [_p, _p, _p, _p, _p, _p]
     lib.hfv_residual_vjp.argtypes = [_p, _p, _p, _p, _p, _p]
     lib.hfv_residual_vjp_states.argtypes = [_p, _p, _p, _p, _p, _p, _p]
     lib.hfv_residual_frozen.argtypes = [_p, _p, _p, _p, _p]
@@ -87,7 +89,8 @@ def load():
     lib.hfv_last_error.restype = C.c_char_p
     lib.hfv_destroy.argtypes = [_p]
     lib.hfv_destroy.restype = None
-    for name in ("hfv_create", "hfv_set_params", "hfv_reconstruct", "hfv_residual", "hfv_residual_vjp",
+    for name in ("hfv_create", "hfv_set_params", "hfv_reconstruct", "hfv_residual", "hfv_residual_noalloc",
+                 "hfv_residual_vjp",
                  "hfv_residual_vjp_states",
                  "hfv_residual_frozen", "hfv_rk_stage", "hfv_cfl_rate",
                  "hfv_query", "hfv_copy_table", "hfv_set_launch", "hfv_get_launch", "hfv_autotune",
@@ -326,6 +329,19 @@ class Context:
         clp = C.c_void_p(cell_class.data_ptr()) if cell_class is not None else None
         self._check(self.lib.hfv_residual(self.h, C.c_void_p(U.data_ptr()), C.c_void_p(R.data_ptr()), fsp, clp,
                                           _stream_handle(stream)))
+        return R
+
+    def residual_noalloc(self, U, R, face_states, cell_class, stream=None):
+        """hfv_residual_noalloc: the residual with the kernels' scratch in the
+        library's fixed per-device array (no device allocation anywhere in
+        the call); every output buffer is the caller's."""
+        if R is None or face_states is None or cell_class is None:
+            raise HfvError(-1, "R, face_states and cell_class must be given")
+        self._chk((U, "U", "u"), (R, "R", "u"), (face_states, "face_states", "fs"),
+                  (cell_class, "cell_class", "cls"))
+        self._check(self.lib.hfv_residual_noalloc(self.h, C.c_void_p(U.data_ptr()), C.c_void_p(R.data_ptr()),
+                                                  C.c_void_p(face_states.data_ptr()),
+                                                  C.c_void_p(cell_class.data_ptr()), _stream_handle(stream)))
         return R
 
     def graph_residual(self, U, R, face_states=None, cell_class=None):
