@@ -280,12 +280,15 @@ class FaceAccuracy:
         return float((np.sqrt(e2) / self.scale).max())
 
 
-def fp32_error(ref, fs32, cls32, ngp, U):
+def fp32_error(ref, fs32, cls32, ngp, U, face_cells=None):
     """FP32 face states against the FP64 path's (which the parity tests hold to
     1e-12 of the FP64 oracle): largest error over the Gauss points of cells of
     equal class, relative to the variable's largest cell average, and the number
-    of cells whose class differs (FP32 flips near an NAD threshold)."""
-    fs64, cls64 = ref
+    of cells whose class differs (FP32 flips near an NAD threshold).  With the
+    FP64 path's near_margin in `ref` and the mesh's face_cells, also the flips
+    in cells neither within 1e-6 of a threshold nor next to such a cell."""
+    fs64, cls64 = ref[0], ref[1]
+    margin = ref[2] if len(ref) > 2 else None
     same = cls64 == cls32
     valid = (np.arange(fs64.shape[0])[:, None] < ngp[None, :]) & same[None, :]     # [NGPC][N]
     scale = np.abs(U).max(0)                                                        # [nvar]
@@ -293,7 +296,17 @@ def fp32_error(ref, fs32, cls32, ngp, U):
     for v in range(fs64.shape[1]):
         d = np.abs(fs32[:, v, :].astype(np.float64) - fs64[:, v, :])
         err = max(err, float(np.where(valid, d, 0.0).max()) / scale[v])
-    return {"fp32_state_err_vs_fp64": float(f"{err:.4g}"), "fp32_class_flips": int((~same).sum())}
+    out = {"fp32_state_err_vs_fp64": float(f"{err:.4g}"), "fp32_class_flips": int((~same).sum())}
+    if margin is not None and face_cells is not None:
+        small = margin <= 1e-6
+        flagged = small.copy()
+        inner = face_cells[:, 1] >= 0
+        a, b = face_cells[inner, 0], face_cells[inner, 1]
+        np.logical_or.at(flagged, a, small[b])
+        np.logical_or.at(flagged, b, small[a])
+        out["fp32_flips_unflagged"] = int((~same & ~flagged).sum())
+        out["cells_margin_le_1e-6"] = int(small.sum())
+    return out
 
 
 # the sources the forward hot-path kernels are compiled from: a change to any of
@@ -581,9 +594,12 @@ def measure(w, wl_tag, head_prec, variants, args, torch, hfv, probe, flush, extr
                 face_err = acc.error(fs)
             fp32_err = None
             if prec == 64 and any(p_ == 32 for p_, m_ in variants if m_ == mode):
-                ref64[mode] = (fs.cpu().numpy(), cl_dev.copy())
+                mg = torch.empty(N, dtype=torch.float64, device="cuda")
+                ctx.reconstruct(U, fs, cls, near_margin=mg)
+                ref64[mode] = (fs.cpu().numpy(), cls.cpu().numpy(), mg.cpu().numpy())
+                del mg
             elif prec == 32 and mode in ref64:
-                fp32_err = fp32_error(ref64.pop(mode), fs.cpu().numpy(), cl_dev, bm.ngp, w.U)
+                fp32_err = fp32_error(ref64.pop(mode), fs.cpu().numpy(), cl_dev, bm.ngp, w.U, mesh.face_cells)
             cl = np.bincount(cl_dev, minlength=4)
             rec_s = sum(v for k, v in sbyts.items() if k not in ("flux", "gather"))
             rec_m = sum(v for k, v in mbyts.items() if k not in ("flux", "gather"))

@@ -75,6 +75,14 @@ enum { HFV_WENOZ_POW = 0, HFV_LITERAL = 1 };
 /* MUSCL slope limiter (Section 2.2; the comparison of Section 3.2): Barth-
  * Jespersen (default) or Venkatakrishnan with eps^2 = (kappa h_c)^3 */
 enum { HFV_LIM_BJ = 0, HFV_LIM_VENKAT = 1 };
+/* variables the CWENOZ reconstruction acts on (Section 2.3: characteristic,
+ * primitive or conserved): conserved (default), or characteristic, face by
+ * face: the eigenvectors of the Euler flux Jacobian in the face's normal at
+ * the Roe average of the cell and the cell across the face project the
+ * stencil data (W = L U), CWENOZ weights are taken per characteristic field,
+ * and the values at the face's Gauss points are mapped back (U = R W).
+ * The VJP entry points support conserved variables only (HFV_ERR_STATE). */
+enum { HFV_CONSERVED = 0, HFV_CHARACTERISTIC = 1 };
 /* cell classes written to cell_class[] */
 enum { HFV_CLASS_LINEAR = 0, HFV_CLASS_CWENOZ = 1, HFV_CLASS_MUSCL = 2, HFV_CLASS_FIRST_ORDER = 3 };
 
@@ -116,16 +124,30 @@ typedef struct {
   const int32_t *n_muscl;       /* [n_cells] */
 } hfv_stencils;
 
-/* Parameters.  order_r is the polynomial degree r (order r+1, Section 2.1).
+/* Parameters.  order_r is the polynomial degree r (order r+1, Section 2.1):
+ * 1..6 in 2D (Table 1 runs r = 2, 4, 6), 1..4 in 3D; the VJP entry points
+ * are built for r <= 4 (HFV_ERR_PARAM above).
  * NAD margins alpha/beta (Eqs. marginm, marginw), deactivation
  * delta U < (kappa h_c)^n_exp (Eq. NADDeactivatedCriteria), CWENOZ lambda_1',
  * eps, b (Section 2.3), Harten theta, eps (Eq. harten_jump_fix); limiter
  * HFV_LIM_* of the MUSCL reconstruction (kappa also sets the Venkatakrishnan
- * eps^2 = (kappa h_c)^3: the paper quotes kappa = 5 for both). */
+ * eps^2 = (kappa h_c)^3: the paper quotes kappa = 5 for both).
+ * viscous = 1 adds the Navier-Stokes viscous fluxes F_v of Eq.
+ * EulerEquationsDetails (Section 2, Eqs. Terms1, sutherlandlaw, HeatConduct,
+ * Stresses): temperature T = p / rho, viscosity mu = mu0 (T/T0)^(3/2)
+ * (T0 + S) / (T + S) with S = sutherland_S, conduction (mu / Pr) gamma /
+ * (gamma - 1) grad T with Pr = prandtl; gradients at the face Gauss points
+ * from each side's central least-squares polynomial, averaged with the
+ * penalty (visc_alpha / L_int) (U_R - U_L) n of Eq. viscous_jump (alpha =
+ * 4/3 in the paper; L_int the distance between the cell centres; no jump at
+ * boundary faces); the flux is taken at the mean of the two face states.
+ * The VJP entry points and hfv_residual_noalloc refuse viscous contexts
+ * (HFV_ERR_STATE). */
 typedef struct {
-  int32_t order_r, scheme_mode, precision, riemann, cweno_form, limiter;
+  int32_t order_r, scheme_mode, precision, riemann, cweno_form, limiter, cweno_vars, viscous;
   double gamma, alpha_m, beta_m, alpha_w, beta_w, kappa, n_exp, lambda1_prime, eps_w, b_w,
       tvd_theta, tvd_eps;
+  double mu0, T0, sutherland_S, prandtl, visc_alpha;
 } hfv_params;
 
 /* Build a context: validates the mesh and stencils, uploads them, and
@@ -150,8 +172,29 @@ hfv_status hfv_set_params(hfv_ctx *ctx, const hfv_params *p);
  *   U            device [nvar][n_cells] cell averages
  *   face_states  device [ngp_cell_max][nvar][n_cells] output (layout above)
  *   cell_class   device [n_cells] uint8 output (HFV_CLASS_*)
+ *   near_margin  device [n_cells] output in the context's precision, or
+ *                NULL: how close each cell's class decisions came to their
+ *                thresholds, the smallest of these relative distances
+ *                (a diagnostic; values near 0 mark decisions that rounding
+ *                can flip, e.g. between the FP32 and FP64 paths):
+ *                - NAD (Eqs. NADMUSCL, NADCWENOZ, marginm, marginw), per
+ *                  conserved variable with a non-zero range R = M - m of the
+ *                  cell and its face neighbours: min(|d - delta_w|,
+ *                  |d - delta_m|) / max(|m|, |M|, R), d the linear
+ *                  candidate's largest excursion past [m, M] at the cell's
+ *                  face Gauss points (hybrid mode);
+ *                - deactivation (Eq. NADDeactivatedCriteria):
+ *                  |dU - (kappa h)^n| / max(dU, (kappa h)^n) (hybrid mode);
+ *                - Harten (Eq. harten_jump_fix) at every face Gauss point of
+ *                  the linear candidate, density and pressure:
+ *                  | |q - q_bar| - theta s | / s, s = max(|q_bar|, eps)
+ *                  (hybrid and all-linear modes).
+ *                +inf in the all-CWENOZ and all-MUSCL modes, which have no
+ *                linear pass.  The Harten checks of the CWENOZ and MUSCL
+ *                states are not included.
  * Asynchronous on `stream`. */
-hfv_status hfv_reconstruct(hfv_ctx *ctx, const void *U, void *face_states, uint8_t *cell_class, void *stream);
+hfv_status hfv_reconstruct(hfv_ctx *ctx, const void *U, void *face_states, uint8_t *cell_class, void *near_margin,
+                           void *stream);
 
 /* Residual R_i = -(1/|V_i|) sum_f sum_alpha F(U_L, U_R) w_alpha |S_f| of
  * Eq. EulerEquationsDetails (F_v = 0) with HLLC or HLL fluxes (Section 2.4).
@@ -303,11 +346,19 @@ hfv_status hfv_copy_table(const hfv_ctx *ctx, int32_t which, void *host_dst, int
  *                   gathers share that XCD's L2; 0: plain block order
  *   muscl_lanes     lanes per cell of the MUSCL / first-order pass: 0 (the
  *                   same as lanes_per_cell), 1 or nvar (or 2 in 2D)
+ *   cwenoz_fuse     1: in hybrid mode with conserved-variable CWENOZ, the
+ *                   variable-split linear kernel (linear_split 0 only) runs
+ *                   CWENOZ itself, from the fit in registers, on every cell
+ *                   its NAD flags for CWENOZ (Section 2.3's central
+ *                   polynomial is the linear candidate); the class-1 list
+ *                   then holds only the cells that tagging adds, and flagged
+ *                   cells that tagging raises to MUSCL are overwritten by the
+ *                   MUSCL pass; cwenoz_reuse is then ignored; 0: off
  * hfv_set_launch validates every field (HFV_ERR_PARAM, nothing changed, on
  * an invalid one); hfv_get_launch reads the current configuration. */
 typedef struct {
   int32_t lanes_per_cell, block, list_blocks, linear_split, linear_lanes, cwenoz_reuse, fused_residual, xcd_remap,
-      muscl_lanes;
+      muscl_lanes, cwenoz_fuse;
 } hfv_launch;
 hfv_status hfv_set_launch(hfv_ctx *ctx, const hfv_launch *cfg);
 hfv_status hfv_get_launch(const hfv_ctx *ctx, hfv_launch *cfg);
@@ -317,7 +368,8 @@ hfv_status hfv_get_launch(const hfv_ctx *ctx, hfv_launch *cfg);
  * candidate launch configurations, searched one coordinate at a time (linear
  * kernel mapping; class-list kernel lanes, block and grid;
  * CWENOZ reuse in hybrid mode; fused or two-kernel residual; XCD block
- * order; MUSCL lanes in hybrid mode), and keeps the
+ * order; MUSCL lanes in hybrid mode; CWENOZ fused into the linear pass, with
+ * its lane count, in hybrid mode), and keeps the
  * fastest (median of `reps`
  * timed calls after one untimed call, reps in [1, 1000]).  Synchronous; it
  * allocates and frees one residual-sized buffer.  `best` (may be NULL)

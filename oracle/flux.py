@@ -6,9 +6,10 @@
   speeds are not given in the paper, Davis estimates are used:
   S_L = min(u_nL - c_L, u_nR - c_R), S_R = max(u_nL + c_L, u_nR + c_R), and
   the contact speed S* of the HLLC solver.
-* Residual of Eq. EulerEquationsDetails with F_v = 0:
-  R_i = -(1/|V_i|) sum_faces sum_alpha F(U_L, U_R) w_alpha |S_l|, the flux
-  taken along the normal pointing out of the face's left cell.
+* Residual of Eq. EulerEquationsDetails:
+  R_i = -(1/|V_i|) sum_faces sum_alpha (F_c(U_L, U_R) - F_v) w_alpha |S_l|,
+  the flux taken along the normal pointing out of the face's left cell;
+  F_v = 0 (Euler) unless the parameters turn the viscous fluxes on.
 """
 from __future__ import annotations
 
@@ -110,7 +111,11 @@ def residual_from_face_fluxes(model, Ff):
 
 
 def residual(model, U):
-    """R(U) [nvar, N], face states and classes (Eq. EulerEquationsDetails)."""
+    """R(U) [nvar, N], face states and classes (Eq. EulerEquationsDetails);
+    with viscous fluxes when the parameters ask for them (oracle/viscous.py)."""
     fs, cls = model.reconstruct(U)
     Ff = face_fluxes(model, fs, model.p.riemann)
+    if getattr(model.p, "viscous", 0):
+        from .viscous import face_viscous_fluxes
+        Ff = Ff - face_viscous_fluxes(model, fs, U)
     return residual_from_face_fluxes(model, Ff), fs, cls

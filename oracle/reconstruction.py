@@ -272,8 +272,61 @@ class OracleModel:
         thr = (p.kappa * self.geo.h[cells]) ** p.n_exp
         deact = dU < thr
         own = np.where(deact, LIN, own)
-        info = dict(dv=dv, wmarg=wmarg, dmarg=dmarg, dU=dU, thr=thr, deact=deact, R=R, m=m, M=M)
+        info = dict(dv=dv, wmarg=wmarg, dmarg=dmarg, dU=dU, thr=thr, deact=deact, R=R, m=m, M=M, cls_v=cls_v)
         return own, info
+
+    def near_margin(self, cells, U, parts=False):
+        """Relative distance of each cell's class decisions to their
+        thresholds, the smallest over the decisions (the library's
+        near_margin output); +inf where no decision is taken.
+
+        NAD (Eqs. NADMUSCL, NADCWENOZ with marginm, marginw), hybrid mode,
+        per conserved variable whose range R = M - m over the cell and its
+        face neighbours is non-zero: min(|d - delta_w|, |d - delta_m|) / S,
+        S = max(|m|, |M|, R).  Deactivation (Eq. NADDeactivatedCriteria),
+        hybrid mode: |dU - (kappa h)^n| / max(dU, (kappa h)^n), 0 when both
+        vanish.  Harten (Eq. harten_jump_fix), hybrid and all-linear modes,
+        density and pressure at every face Gauss point of the linear
+        candidate: | |q - q_bar| - theta s | / s with s = max(|q_bar|, eps).
+        All-CWENOZ and all-MUSCL modes take no such decision: +inf.
+        parts=True returns the pieces as well: dict(nad [n, nvar],
+        deact [n], harten [n], total [n]), +inf where a piece does not apply."""
+        cells = np.asarray(cells, np.int64)
+        p = self.p
+        out = np.full(cells.size, np.inf)
+        nad = np.full((cells.size, self.nvar), np.inf)
+        deact = np.full(cells.size, np.inf)
+        harten = np.full(cells.size, np.inf)
+        mode = p.scheme_mode
+        if mode not in (HYBRID, ALL_LINEAR):
+            return dict(nad=nad, deact=deact, harten=harten, total=out) if parts else out
+        if mode == HYBRID:
+            _, info = self.own_class(cells, U)
+            m, M, R, dv = info["m"], info["M"], info["R"], info["dv"]
+            S = np.maximum(np.maximum(np.abs(m), np.abs(M)), R)
+            with np.errstate(divide="ignore", invalid="ignore"):
+                nad = np.where(R > 0, np.minimum(np.abs(dv - info["wmarg"]), np.abs(dv - info["dmarg"])) / S, np.inf)
+            den = np.maximum(info["dU"], info["thr"])
+            with np.errstate(divide="ignore", invalid="ignore"):
+                deact = np.where(den > 0, np.abs(info["dU"] - info["thr"]) / den, 0.0)
+            out = np.fmin(np.fmin(out, nad.min(1)), deact)
+        _, fv, _ = self.linear(cells, U)
+        g = p.gamma
+        ngp = self.geo.c_ngp[cells]
+        valid = np.arange(fv.shape[1])[None, :] < ngp[:, None]
+        Ub = U[cells]
+        rho_b = Ub[:, 0]
+        pres_b = (g - 1) * (Ub[:, -1] - 0.5 * (Ub[:, 1:-1] ** 2).sum(1) / rho_b)
+        sr = np.maximum(np.abs(rho_b), p.tvd_eps)[:, None]
+        sp = np.maximum(np.abs(pres_b), p.tvd_eps)[:, None]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            pres = (g - 1) * (fv[..., -1] - 0.5 * (fv[..., 1:-1] ** 2).sum(-1) / fv[..., 0])
+            hr = np.abs(np.abs(fv[..., 0] - rho_b[:, None]) - p.tvd_theta * sr) / sr
+            hp = np.abs(np.abs(pres - pres_b[:, None]) - p.tvd_theta * sp) / sp
+        h = np.where(valid, np.fmin(hr, hp), np.inf)
+        harten = np.where(np.isnan(h), np.inf, h).min(1)
+        out = np.fmin(out, harten)
+        return dict(nad=nad, deact=deact, harten=harten, total=out) if parts else out
 
     def harten_ok(self, fv, Ucell, ngp):
         """Harten bound check on density and pressure (Eq. harten_jump_fix)."""
@@ -290,7 +343,25 @@ class OracleModel:
         return np.all(~valid | (ok_r & ok_p), axis=1)
 
     def cwenoz(self, cells, U):
-        """CWENOZ reconstruction (Section 2.3), per conserved variable."""
+        """CWENOZ reconstruction (Section 2.3): face values [n, NGPC, nvar].
+
+        Conserved variables (default): every conserved variable on its own.
+        Characteristic variables (cweno_vars = 1): per face, on the
+        projection W = L U of reading in oracle/characteristic.py, mapped
+        back at the face's Gauss points."""
+        if self.p.cweno_vars == 1:
+            return self.cwenoz_characteristic(cells, U)
+        tab, a1, a_hat, svalid, nd, lam1, lams = self.cwenoz_fits(cells, U)
+        om1, oms, SI1, SIs, tau, a_cw = self.cwenoz_weights(a1, a_hat, tab["OI"], svalid, nd, lam1, lams)
+        phi = self.phi_at_gp(tab)
+        fv = U[cells][:, None, :] + np.einsum("ngk,nkv->ngv", phi, a_cw)
+        return fv, dict(om1=om1, oms=oms, SI1=SI1, SIs=SIs, tau=tau, lam1=lam1, lams=lams, a_cw=a_cw)
+
+    def cwenoz_fits(self, cells, U):
+        """The candidate polynomials of Section 2.3 in conserved variables:
+        p_1's coefficients a1 [n, K, nvar] (from the central fit a_opt =
+        lam_1 p_1 + sum_s lam_s p_s) and the directional degree-1 fits a_hat
+        [n, NF, K, nvar] (zero past degree 1 and past the cell's count)."""
         p = self.p
         d, K = self.d, self.K
         a_opt, _, tab = self.linear(cells, U)
@@ -307,25 +378,66 @@ class OracleModel:
         svalid = np.arange(NF)[None, :] < nd[:, None]               # [n, NF]
         a_hat = a_hat * svalid[..., None, None]
         a1 = (a_opt - lams[:, None, None] * a_hat.sum(1)) / lam1
-        OI = tab["OI"]
-        SI1 = np.einsum("nkv,nkq,nqv->nv", a1, OI, a1)
-        SIs = np.einsum("nfkv,nkq,nfqv->nfv", a_hat, OI, a_hat)
-        tau = (np.abs(SIs - SI1[:, None, :]) * svalid[..., None]).sum(1) / nd[:, None]
+        return tab, a1, a_hat, svalid, nd, lam1, lams
+
+    def cwenoz_weights(self, a1, a_hat, OI, svalid, nd, lam1, lams):
+        """Smoothness indicators SI = a^T OI a, tau, nonlinear weights and the
+        combined coefficients, per variable (last axis), for any leading
+        shape: a1 [..., K, V], a_hat [..., NF, K, V], OI [..., K, K],
+        svalid [..., NF], nd and lams [...]."""
+        p = self.p
+        SI1 = np.einsum("...kv,...kq,...qv->...v", a1, OI, a1)
+        SIs = np.einsum("...fkv,...kq,...fqv->...fv", a_hat, OI, a_hat)
+        tau = (np.abs(SIs - SI1[..., None, :]) * svalid[..., None]).sum(-2) / nd[..., None]
+        lams = lams[..., None, None]
         if p.cweno_form == 0:
             w1 = lam1 * (1.0 + (tau / (p.eps_w + SI1)) ** p.b_w)
-            ws = lams[:, None, None] * (1.0 + (tau[:, None, :] / (p.eps_w + SIs)) ** p.b_w)
+            ws = lams * (1.0 + (tau[..., None, :] / (p.eps_w + SIs)) ** p.b_w)
         else:
             tb = tau ** p.b_w
             w1 = lam1 * (1.0 + tb / (p.eps_w + SI1))
-            ws = lams[:, None, None] * (1.0 + tb[:, None, :] / (p.eps_w + SIs))
+            ws = lams * (1.0 + tb[..., None, :] / (p.eps_w + SIs))
         ws = ws * svalid[..., None]
-        tot = w1 + ws.sum(1)
+        tot = w1 + ws.sum(-2)
         om1 = w1 / tot
-        oms = ws / tot[:, None, :]
-        a_cw = om1[:, None, :] * a1 + np.einsum("nfv,nfkv->nkv", oms, a_hat)
-        phi = self.phi_at_gp(tab)
-        fv = U[cells][:, None, :] + np.einsum("ngk,nkv->ngv", phi, a_cw)
-        return fv, dict(om1=om1, oms=oms, SI1=SI1, SIs=SIs, tau=tau, lam1=lam1, lams=lams, a_cw=a_cw)
+        oms = ws / tot[..., None, :]
+        a_cw = om1[..., None, :] * a1 + np.einsum("...fv,...fkv->...kv", oms, a_hat)
+        return om1, oms, SI1, SIs, tau, a_cw
+
+    def cwenoz_characteristic(self, cells, U, eig=None):
+        """CWENOZ in characteristic variables, face by face (reading in
+        oracle/characteristic.py): every Gauss-point slot of a cell takes the
+        projection of its face.  The fits are linear in the data, so the
+        characteristic fits are L times the conserved ones; the weights are
+        taken per characteristic field; the face values are U_i + R dW(x).
+        `eig(UL, UR, n) -> (R, L)` replaces the eigenvectors (tests)."""
+        from .characteristic import roe_average, eigenvectors
+        g = self.p.gamma
+        geo, mesh = self.geo, self.mesh
+        tab, a1, a_hat, svalid, nd, lam1, lams = self.cwenoz_fits(cells, U)
+        gidx = np.maximum(geo.c_gidx[cells], 0)                     # [n, S]
+        side = geo.c_side[cells]
+        face = np.searchsorted(geo.gp_off, gidx, side="right") - 1
+        nrm = geo.normal[face] * np.where(side == 0, 1.0, -1.0)[..., None]
+        other = mesh.face_cells[face, 1 - side]
+        other = np.where(other >= 0, other, cells[:, None])
+        UL = np.broadcast_to(U[cells][:, None, :], other.shape + (self.nvar,))
+        UR = U[other]
+        if eig is None:
+            v, H, c = roe_average(UL, UR, g)
+            Rm, Lm, _ = eigenvectors(v, H, c, nrm, g)               # [n, S, nv, nv]
+        else:
+            Rm, Lm = eig(UL, UR, nrm)
+        a1W = np.einsum("nsvu,nku->nskv", Lm, a1)
+        ahW = np.einsum("nsvu,nfku->nsfkv", Lm, a_hat)
+        S = gidx.shape[1]
+        rep = lambda x: np.repeat(x[:, None], S, axis=1)
+        om1, oms, SI1, SIs, tau, a_cw = self.cwenoz_weights(a1W, ahW, rep(tab["OI"]), rep(svalid), rep(nd),
+                                                           lam1, rep(lams))
+        phi = self.phi_at_gp(tab)                                   # [n, S, K]
+        dW = np.einsum("nsk,nskv->nsv", phi, a_cw)
+        fv = U[cells][:, None, :] + np.einsum("nsuv,nsv->nsu", Rm, dW)
+        return fv, dict(om1=om1, oms=oms, SI1=SI1, SIs=SIs, tau=tau, a_cw=a_cw)
 
     def muscl(self, cells, U):
         """MUSCL (Section 2.2) with the Barth-Jespersen limiter, or with

@@ -71,6 +71,13 @@ static hfv_status check_params(const hfv_params *p, std::string &err) {
   if (p->riemann < 0 || p->riemann > 1) return err = "unknown riemann solver", HFV_ERR_PARAM;
   if (p->cweno_form < 0 || p->cweno_form > 1) return err = "unknown cweno_form", HFV_ERR_PARAM;
   if (p->limiter != HFV_LIM_BJ && p->limiter != HFV_LIM_VENKAT) return err = "unknown limiter", HFV_ERR_PARAM;
+  if (p->cweno_vars != HFV_CONSERVED && p->cweno_vars != HFV_CHARACTERISTIC)
+    return err = "unknown cweno_vars", HFV_ERR_PARAM;
+  if (p->viscous != 0 && p->viscous != 1) return err = "viscous must be 0 or 1", HFV_ERR_PARAM;
+  if (p->viscous && (!(p->mu0 >= 0.0) || !(p->T0 > 0.0) || !(p->sutherland_S >= 0.0) || !(p->prandtl > 0.0) ||
+                     !(p->visc_alpha >= 0.0) || !std::isfinite(p->mu0) || !std::isfinite(p->visc_alpha)))
+    return err = "viscous fluxes need mu0 >= 0, T0 > 0, sutherland_S >= 0, prandtl > 0, visc_alpha >= 0",
+           HFV_ERR_PARAM;
   return HFV_OK;
 }
 
@@ -80,6 +87,13 @@ static void copy_params(hfv_ctx *ctx, const hfv_params *p) {
   ctx->p.riemann = p->riemann;
   ctx->p.form = p->cweno_form;
   ctx->p.limiter = p->limiter;
+  ctx->p.cvars = p->cweno_vars;
+  ctx->p.viscous = p->viscous;
+  ctx->p.mu0 = p->mu0;
+  ctx->p.T0 = p->T0;
+  ctx->p.suth_S = p->sutherland_S;
+  ctx->p.prandtl = p->prandtl;
+  ctx->p.visc_alpha = p->visc_alpha;
   ctx->p.gamma = p->gamma;
   ctx->p.alpha_m = p->alpha_m;
   ctx->p.beta_m = p->beta_m;
@@ -100,7 +114,8 @@ static hfv_status validate(const hfv_mesh *m, const hfv_stencils *st, const hfv_
   if (e != HFV_OK) return e;
   const int d = m->dim;
   if (d != 2 && d != 3) return err = "dim must be 2 or 3", HFV_ERR_PARAM;
-  if (p->order_r < 1 || p->order_r > 4) return err = "order_r must be in 1..4", HFV_ERR_PARAM;
+  if (p->order_r < 1 || p->order_r > (d == 2 ? 6 : 4))
+    return err = d == 2 ? "order_r must be in 1..6 in 2D" : "order_r must be in 1..4 in 3D", HFV_ERR_PARAM;
   if (p->precision != 64 && p->precision != 32) return err = "precision must be 64 or 32", HFV_ERR_DTYPE;
   if (m->n_cells <= 0 || m->n_faces <= 0 || m->n_vertices <= 0) return err = "empty mesh", HFV_ERR_MESH;
   if (!m->vertices || !m->cell_type || !m->cell_vtx_off || !m->cell_vtx || !m->face_cells || !m->face_vtx_off ||
@@ -260,6 +275,9 @@ hfv_status hfv_set_launch(hfv_ctx *ctx, const hfv_launch *c) {
   const int ml = c->muscl_lanes;
   if (!(ml == 0 || ml == 1 || ml == ctx->nvar || (ctx->dim == 2 && ml == 2)))
     return ctx->err = "muscl_lanes must be 0, 1 or nvar (or 2 in 2D)", HFV_ERR_PARAM;
+  if (c->cwenoz_fuse != 0 && c->cwenoz_fuse != 1) return ctx->err = "cwenoz_fuse must be 0 or 1", HFV_ERR_PARAM;
+  if (c->cwenoz_fuse && c->linear_split != 0)
+    return ctx->err = "cwenoz_fuse needs the variable split (linear_split 0)", HFV_ERR_PARAM;
   ctx->lanes = lanes;
   ctx->block = c->block;
   ctx->list_blocks = c->list_blocks;
@@ -269,6 +287,7 @@ hfv_status hfv_set_launch(hfv_ctx *ctx, const hfv_launch *c) {
   ctx->fused_residual = c->fused_residual;
   ctx->xcd_remap = c->xcd_remap;
   ctx->muscl_lanes = c->muscl_lanes;
+  ctx->cw_fuse = c->cwenoz_fuse;
   return HFV_OK;
 }
 
@@ -283,13 +302,14 @@ hfv_status hfv_get_launch(const hfv_ctx *ctx, hfv_launch *c) {
   c->fused_residual = ctx->fused_residual;
   c->xcd_remap = ctx->xcd_remap;
   c->muscl_lanes = ctx->muscl_lanes;
+  c->cwenoz_fuse = ctx->cw_fuse;
   return HFV_OK;
 }
 
-hfv_status hfv_reconstruct(hfv_ctx *ctx, const void *U, void *fs, uint8_t *cls, void *stream) {
+hfv_status hfv_reconstruct(hfv_ctx *ctx, const void *U, void *fs, uint8_t *cls, void *near_margin, void *stream) {
   if (!ctx) return HFV_ERR_PARAM;
   if (!U || !fs || !cls) return ctx->err = "NULL device pointer", HFV_ERR_PARAM;
-  return run_reconstruct(ctx, U, fs, cls, (hipStream_t)stream);
+  return run_reconstruct(ctx, U, fs, cls, (hipStream_t)stream, near_margin);
 }
 
 hfv_status hfv_residual(hfv_ctx *ctx, const void *U, void *R, void *fs, uint8_t *cls, void *stream) {
@@ -313,6 +333,7 @@ hfv_status hfv_residual_noalloc(hfv_ctx *ctx, const void *U, void *R, void *fs, 
     return HFV_ERR_PARAM;
   }
   if (!ctx->noalloc_scratch) return ctx->err = "scratch array address unknown", HFV_ERR_STATE;
+  if (ctx->p.viscous) return ctx->err = "hfv_residual_noalloc computes inviscid residuals only", HFV_ERR_STATE;
   // The same kernels as hfv_residual, with the workspace they write carved
   // from the scratch array; the context's own workspace is put back on every
   // return path.  The kernels clear the list lengths themselves (the first

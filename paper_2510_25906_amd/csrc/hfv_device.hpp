@@ -8,7 +8,7 @@ namespace hfv {
 
 template <typename T>
 struct HotArgs {
-  int N, mode, form;
+  int N, NF, mode, form;
   int frozen;              // adjoint recompute: classes given, no NAD or Harten re-check
   const uint8_t *cls_in;   // given classes when frozen
   const T *U;
@@ -23,7 +23,14 @@ struct HotArgs {
   int ib_w;  // b_w when it is an integer in [1, 8] (powers by multiplication), else 0
   int xcd;   // block ids remapped so each XCD takes one contiguous range (block_id)
   int limiter;  // HFV_LIM_*
+  T *margin;    // [N] near_margin output of the linear pass, or null
+  bool fuse;    // CWENOZ of own-flagged cells inside the linear pass
 };
+
+// CWENOZ on characteristic variables (hfv_char.cpp) over the class-1 list,
+// or over every cell when direct.
+template <typename T>
+hfv_status launch_cwenoz_char(hfv_ctx *ctx, const HotArgs<T> &a, int direct, hipStream_t s);
 
 // Block id, optionally permuted.  The dispatcher hands workgroups to the 8
 // XCDs in turn (block b to XCD b mod 8), and each XCD has its own L2.  With
@@ -79,6 +86,14 @@ __device__ inline int group_max(int x, int base) {
   for (int t = 0; t < G; ++t) s = max(s, __shfl(x, base + t));
   return s;
 }
+template <int G, typename V>
+__device__ inline V group_min(V x, int base) {
+  if constexpr (G == 1) return x;
+  V s = x;
+#pragma unroll
+  for (int t = 0; t < G; ++t) s = fmin(s, __shfl(x, base + t));
+  return s;
+}
 template <int G>
 __device__ inline bool group_all(bool x, int base) {
   if constexpr (G == 1) return x;
@@ -119,6 +134,34 @@ __device__ inline T pressure(const T (&q)[NV], T gamma) {
 #pragma unroll
   for (int j = 1; j < NV - 1; ++j) m2 += q[j] * q[j];
   return (gamma - (T)1) * (q[NV - 1] - (T)0.5 * m2 / q[0]);
+}
+
+// near_margin: how far a cell's class decisions are from their thresholds,
+// each as a relative distance; the output is the smallest.
+//   Harten (Eq. harten_jump_fix) at one point, density and pressure:
+//     | |q - q_bar| - theta s | / s,  s = max(|q_bar|, eps)
+template <int NV, typename T>
+__device__ inline T harten_margin(const T (&q)[NV], T rho_b, T p_b, const HotArgs<T> &a) {
+  const T sr = fmax(fabs(rho_b), a.tvd_eps), sp = fmax(fabs(p_b), a.tvd_eps);
+  const T p = pressure<NV, T>(q, a.gamma);
+  return fmin(fabs(fabs(q[0] - rho_b) - a.theta * sr) / sr, fabs(fabs(p - p_b) - a.theta * sp) / sp);
+}
+//   NAD (Eqs. NADMUSCL, NADCWENOZ, marginm, marginw) for one variable with
+//   a non-zero range R = M - m: min(|d - delta_w|, |d - delta_m|) / S with
+//   S = max(|m|, |M|, R); a variable with R = 0 has no threshold (+inf)
+template <typename T>
+__device__ inline T nad_margin(T exc, T mn, T mx, T dw, T dm) {
+  const T Rg = mx - mn;
+  if (!(Rg > (T)0)) return (T)INFINITY;
+  const T S = fmax(fmax(fabs(mn), fabs(mx)), Rg);
+  return fmin(fabs(exc - dw), fabs(exc - dm)) / S;
+}
+//   deactivation (Eq. NADDeactivatedCriteria): |dU - thr| / max(dU, thr)
+//   (0 when both are 0: the strict test sits exactly at its threshold)
+template <typename T>
+__device__ inline T deact_margin(T dU, T thr) {
+  const T den = fmax(dU, thr);
+  return den > (T)0 ? fabs(dU - thr) / den : (T)0;
 }
 
 // phi_k(xi) = xi^alpha_k - psi_bar_k for the hierarchical monomial basis.

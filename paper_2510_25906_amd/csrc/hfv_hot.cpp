@@ -33,8 +33,164 @@ __device__ inline void keep_fit(const HotArgs<T> &a, int cell, int v0, const T (
     for (int q = 0; q < VPL; ++q) a.coef[((long)k * NV + v0 + q) * a.N + cell] = co[k][q];
 }
 
-// K1: linear candidate, face states, NAD own class, Harten flag.
+// CWENOZ of one cell from its central fit (Section 2.3): directional degree-1
+// fits, p_1, smoothness indicators and nonlinear weights (FP64), the combined
+// polynomial at the face Gauss points and the Harten check.  Writes the
+// cell's states (the first-order state at every point when the check fails)
+// and returns whether it passed.  co holds the central fit on entry and is
+// overwritten.  Shared by the class-list kernel and the linear kernel's fused
+// path.
 template <int DIM, int R, typename T, int G>
+__device__ __forceinline__ bool cwenoz_cell(const HotArgs<T> &a, int cell, const Lane<G> &L,
+                                            const T (&u0)[(DIM + 2) / G], T (&co)[n_unknowns(DIM, R)][(DIM + 2) / G]) {
+  constexpr int NV = DIM + 2, K = n_unknowns(DIM, R), VPL = NV / G, NFM = nf_max(DIM), MD = 2 * DIM;
+  const int N = a.N, v0 = L.sub * VPL;
+  // directional degree-1 fits (Section 2.3)
+  const int nd = a.t.ndir[cell];
+  T ad[NFM][DIM][VPL];
+#pragma unroll
+  for (int s = 0; s < NFM; ++s) {
+#pragma unroll
+    for (int j = 0; j < DIM; ++j)
+#pragma unroll
+      for (int q = 0; q < VPL; ++q) ad[s][j][q] = (T)0;
+    // the guard also keeps the compiler from hoisting every stencil's loads
+    // at once, which would cost occupancy
+    if (s < nd) {
+#pragma unroll
+      for (int m = 0; m < MD; ++m) {
+        const int jc = a.t.dsten[((long)s * MD + m) * N + cell];
+        T du[VPL];
+#pragma unroll
+        for (int q = 0; q < VPL; ++q) du[q] = a.U[(long)(v0 + q) * N + jc] - u0[q];
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) {
+          const T p = a.t.Pdir[(((long)s * DIM + j) * MD + m) * N + cell];
+#pragma unroll
+          for (int q = 0; q < VPL; ++q) ad[s][j][q] += p * du[q];
+        }
+      }
+    }
+  }
+  const T lam1 = (T)1 - (T)1 / a.lam1p;
+  const T lams = ((T)1 - lam1) / (T)nd;
+  // p_1 = (p_opt - sum lambda_s p_s) / lambda_1, in place
+#pragma unroll
+  for (int j = 0; j < DIM; ++j)
+#pragma unroll
+    for (int q = 0; q < VPL; ++q) {
+      T sdir = 0;
+#pragma unroll
+      for (int s = 0; s < NFM; ++s) sdir += ad[s][j][q];
+      co[j][q] = co[j][q] - lams * sdir;
+    }
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int q = 0; q < VPL; ++q) co[k][q] /= lam1;
+  // smoothness indicators SI = a^T OI a, accumulated in double, then the
+  // nonlinear weights and the CWENOZ coefficients omega_1 p_1 + sum_s
+  // omega_s p_s; one variable at a time keeps few doubles live
+  const double eps = (double)a.eps_w, b = (double)a.b_w;
+#pragma unroll
+  for (int q = 0; q < VPL; ++q) {
+    double si1 = 0, sis[NFM];
+#pragma unroll
+    for (int s = 0; s < NFM; ++s) sis[s] = 0;
+    int pidx = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const double ck = (double)co[k][q];
+      double row = 0;
+#pragma unroll
+      for (int kq = k; kq < K; ++kq, ++pidx) {
+        const double o = (double)a.t.OI[(long)pidx * N + cell];
+        row += (kq == k ? o : 2.0 * o) * (double)co[kq][q];
+        if (kq < DIM) {
+#pragma unroll
+          for (int s = 0; s < NFM; ++s)
+            sis[s] += (kq == k ? o : 2.0 * o) * (double)ad[s][k][q] * (double)ad[s][kq][q];
+        }
+      }
+      si1 += ck * row;
+      // large K in FP64: keep each row's loads from being hoisted over the
+      // others (measured: spills otherwise; FP32 is faster without)
+      if constexpr (K > 20 && sizeof(T) == 8) __builtin_amdgcn_sched_barrier(0);
+    }
+    double tau = 0;
+#pragma unroll
+    for (int s = 0; s < NFM; ++s)
+      if (s < nd) tau += fabs(sis[s] - si1);
+    tau /= (double)nd;
+    const bool zform = a.form == HFV_WENOZ_POW;
+    const double taub = zform ? 0.0 : powb(tau, b, a.ib_w);
+    const double w1 = (double)lam1 * (1.0 + (zform ? powb(tau / (eps + si1), b, a.ib_w) : taub / (eps + si1)));
+    double tot = w1, ws[NFM];
+#pragma unroll
+    for (int s = 0; s < NFM; ++s) {
+      ws[s] = 0;
+      if (s < nd)
+        ws[s] = (double)lams * (1.0 + (zform ? powb(tau / (eps + sis[s]), b, a.ib_w) : taub / (eps + sis[s])));
+      tot += ws[s];
+    }
+    const double it = 1.0 / tot;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double v = w1 * it * (double)co[k][q];
+      if (k < DIM) {
+#pragma unroll
+        for (int s = 0; s < NFM; ++s) v += ws[s] * it * (double)ad[s][k][q];
+      }
+      co[k][q] = (T)v;
+    }
+  }
+  // face states, Harten check
+  T all0[NV];
+  group_state<NV, G, T>(u0, all0, L.base);
+  const T rho_b = all0[0];
+  const T p_b = pressure<NV, T>(all0, a.gamma);
+  T psb[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) psb[k] = a.t.psibar[(long)k * N + cell];
+  const int ng = a.t.ngp[cell];
+  bool hok = true;
+  for (int g = 0; g < ng; ++g) {
+    T xi[DIM];
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) xi[j] = a.t.gpxi[((long)g * DIM + j) * N + cell];
+    T phi[K];
+    basis_at<DIM, R, T>(xi, psb, phi);
+    T val[VPL];
+#pragma unroll
+    for (int q = 0; q < VPL; ++q) {
+      T s = 0;
+#pragma unroll
+      for (int k = 0; k < K; ++k) s += co[k][q] * phi[k];
+      val[q] = u0[q] + s;
+    }
+    T all[NV];
+    group_state<NV, G, T>(val, all, L.base);
+    hok = a.frozen || (hok && harten_point<NV, T>(all, rho_b, p_b, a));
+#pragma unroll
+    for (int q = 0; q < VPL; ++q) store<NV, T>(a, g, cell, v0 + q, hok ? val[q] : u0[q]);
+    if (!hok) {
+      // first-order fallback: overwrite every point of the cell with U_i
+      for (int g2 = 0; g2 < ng; ++g2) {
+#pragma unroll
+        for (int q = 0; q < VPL; ++q) store<NV, T>(a, g2, cell, v0 + q, u0[q]);
+      }
+      break;
+    }
+  }
+  return hok;
+}
+
+// K1: linear candidate, face states, NAD own class, Harten flag.  FUSE: a
+// cell the NAD flags for CWENOZ (own class 1, active) takes CWENOZ here, from
+// the fit in registers, instead of its linear states; its own byte records
+// that (bit 3) and whether CWENOZ's Harten check failed (bit 4).  Tagging
+// may still raise it to MUSCL, whose pass then overwrites its states.
+template <int DIM, int R, typename T, int G, bool FUSE = false>
 __global__ __launch_bounds__(256) void k_linear(HotArgs<T> a) {
   constexpr int NV = DIM + 2, K = n_unknowns(DIM, R), VPL = NV / G, NFM = nf_max(DIM);
   if (blockIdx.x == 0 && threadIdx.x < 8) a.counts[threadIdx.x] = 0;
@@ -86,6 +242,7 @@ __global__ __launch_bounds__(256) void k_linear(HotArgs<T> a) {
 #pragma unroll
   for (int q = 0; q < VPL; ++q) exc[q] = -INFINITY;
   bool hok = true;
+  T mg = (T)INFINITY;  // near_margin (every lane sees the full state at each point)
   const int ng = a.t.ngp[cell];
   for (int g = 0; g < ng; ++g) {
     T xi[DIM];
@@ -98,11 +255,15 @@ __global__ __launch_bounds__(256) void k_linear(HotArgs<T> a) {
     T all[NV];
     group_state<NV, G, T>(val, all, L.base);
     hok = hok && harten_point<NV, T>(all, rho_b, p_b, a);
+    if (a.margin) mg = fmin(mg, harten_margin<NV, T>(all, rho_b, p_b, a));
+    if constexpr (!FUSE) {
 #pragma unroll
-    for (int q = 0; q < VPL; ++q) store<NV, T>(a, g, cell, v0 + q, val[q]);
+      for (int q = 0; q < VPL; ++q) store<NV, T>(a, g, cell, v0 + q, val[q]);
+    }
   }
   int c = 0;
   if (a.mode == HFV_HYBRID) {
+    T nm = (T)INFINITY;
 #pragma unroll
     for (int q = 0; q < VPL; ++q) {
       const T Rg = mx[q] - mn[q];
@@ -111,13 +272,35 @@ __global__ __launch_bounds__(256) void k_linear(HotArgs<T> a) {
       const T dw = sgn * fmax(a.alpha_w, fabs(a.beta_w * Rg));
       const int cq = exc[q] <= dw ? HFV_CLASS_LINEAR : (exc[q] >= dm ? HFV_CLASS_MUSCL : HFV_CLASS_CWENOZ);
       c = max(c, cq);
+      nm = fmin(nm, nad_margin(exc[q], mn[q], mx[q], dw, dm));
     }
     c = group_max<G>(c, L.base);
     const T dU = has_nb ? dmax - dmin : (T)0;
     if (dU < a.t.thr[cell]) c = HFV_CLASS_LINEAR;
+    if (a.margin) mg = fmin(fmin(mg, group_min<G>(nm, L.base)), deact_margin(dU, a.t.thr[cell]));
   }
-  if (a.coef) keep_fit<NV>(a, cell, v0, co);
-  if (L.sub == 0) a.own[cell] = (uint8_t)(c | (hok ? 0 : 4));
+  int own = c | (hok ? 0 : 4);
+  if constexpr (FUSE) {
+    if (c == HFV_CLASS_CWENOZ) {   // the same in every lane of the group
+      own = HFV_CLASS_CWENOZ | 8 | (cwenoz_cell<DIM, R, T, G>(a, cell, L, u0, co) ? 0 : 16);
+    } else {                        // the linear states, whose stores were held back
+      for (int g = 0; g < ng; ++g) {
+        T xi[DIM];
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) xi[j] = a.t.gpxi[((long)g * DIM + j) * N + cell];
+        T val[VPL];
+        poly_at<DIM, R, VPL, T>(xi, co, c0, val);
+#pragma unroll
+        for (int q = 0; q < VPL; ++q) store<NV, T>(a, g, cell, v0 + q, val[q]);
+      }
+    }
+  } else {
+    if (a.coef) keep_fit<NV>(a, cell, v0, co);
+  }
+  if (L.sub == 0) {
+    a.own[cell] = (uint8_t)own;
+    if (a.margin) a.margin[cell] = mg;
+  }
 }
 
 // K1, member-split mapping: the G lanes of a cell's group each take every G-th
@@ -224,6 +407,7 @@ __global__ __launch_bounds__(256) void k_linear_ms(HotArgs<T> a) {
 #pragma unroll
   for (int v = 0; v < NV; ++v) exc[v] = -INFINITY;
   bool hok = true;
+  T mg = (T)INFINITY;  // near_margin, this lane's points
   const int ng = a.t.ngp[cell];
   for (int g = q; g < ng; g += G) {
     T xi[DIM];
@@ -236,6 +420,7 @@ __global__ __launch_bounds__(256) void k_linear_ms(HotArgs<T> a) {
       exc[v] = fmax(exc[v], fmax(mn[v] - val[v], val[v] - mx[v]));
     }
     hok = hok && harten_point<NV, T>(val, rho_b, p_b, a);
+    if (a.margin) mg = fmin(mg, harten_margin<NV, T>(val, rho_b, p_b, a));
 #pragma unroll
     for (int v = 0; v < NV; ++v) store<NV, T>(a, g, cell, v, val[v]);
   }
@@ -247,6 +432,7 @@ __global__ __launch_bounds__(256) void k_linear_ms(HotArgs<T> a) {
     for (int off = 1; off < G; off <<= 1) hv &= __shfl_xor(hv, off);
     hok = hv != 0;
   }
+  if (a.margin) mg = xor_min<G>(mg);
   int c = 0;
   if (a.mode == HFV_HYBRID) {
 #pragma unroll
@@ -257,9 +443,11 @@ __global__ __launch_bounds__(256) void k_linear_ms(HotArgs<T> a) {
       const T dw = sgn * fmax(a.alpha_w, fabs(a.beta_w * Rg));
       const int cv = exc[v] <= dw ? HFV_CLASS_LINEAR : (exc[v] >= dm ? HFV_CLASS_MUSCL : HFV_CLASS_CWENOZ);
       c = max(c, cv);
+      if (a.margin) mg = fmin(mg, nad_margin(exc[v], mn[v], mx[v], dw, dm));
     }
     const T dU = has_nb ? dmax - dmin : (T)0;
     if (dU < a.t.thr[cell]) c = HFV_CLASS_LINEAR;
+    if (a.margin) mg = fmin(mg, deact_margin(dU, a.t.thr[cell]));
   }
   if (a.coef) {  // every lane holds the full fit: split the stores
 #pragma unroll
@@ -268,7 +456,10 @@ __global__ __launch_bounds__(256) void k_linear_ms(HotArgs<T> a) {
       for (int v = 0; v < NV; ++v)
         if ((k * NV + v) % G == q) a.coef[((long)k * NV + v) * N + cell] = co[k][v];
   }
-  if (q == 0) a.own[cell] = (uint8_t)(c | (hok ? 0 : 4));
+  if (q == 0) {
+    a.own[cell] = (uint8_t)(c | (hok ? 0 : 4));
+    if (a.margin) a.margin[cell] = mg;
+  }
 }
 
 // K1, unknown-split mapping: lane q of a cell's group of G owns the unknowns
@@ -370,6 +561,7 @@ __global__ __launch_bounds__(256) void k_linear_ks(HotArgs<T> a) {
 #pragma unroll
   for (int v = 0; v < NV; ++v) exc[v] = -INFINITY;
   bool hok = true;
+  T mg = (T)INFINITY;  // near_margin, this lane's points
   const int ng = a.t.ngp[cell];
   for (int g0 = 0; g0 < ng; g0 += G) {
     T part[G][NV];
@@ -437,6 +629,7 @@ __global__ __launch_bounds__(256) void k_linear_ks(HotArgs<T> a) {
         exc[v] = fmax(exc[v], fmax(mn[v] - val[v], val[v] - mx[v]));
       }
       hok = hok && harten_point<NV, T>(val, rho_b, p_b, a);
+      if (a.margin) mg = fmin(mg, harten_margin<NV, T>(val, rho_b, p_b, a));
 #pragma unroll
       for (int v = 0; v < NV; ++v) store<NV, T>(a, g, cell, v, val[v]);
     }
@@ -449,6 +642,7 @@ __global__ __launch_bounds__(256) void k_linear_ks(HotArgs<T> a) {
     for (int off = 1; off < G; off <<= 1) hv &= __shfl_xor(hv, off);
     hok = hv != 0;
   }
+  if (a.margin) mg = xor_min<G>(mg);
   int c = 0;
   if (a.mode == HFV_HYBRID) {
 #pragma unroll
@@ -459,9 +653,11 @@ __global__ __launch_bounds__(256) void k_linear_ks(HotArgs<T> a) {
       const T dw = sgn * fmax(a.alpha_w, fabs(a.beta_w * Rg));
       const int cv = exc[v] <= dw ? HFV_CLASS_LINEAR : (exc[v] >= dm ? HFV_CLASS_MUSCL : HFV_CLASS_CWENOZ);
       c = max(c, cv);
+      if (a.margin) mg = fmin(mg, nad_margin(exc[v], mn[v], mx[v], dw, dm));
     }
     const T dU = has_nb ? dmax - dmin : (T)0;
     if (dU < a.t.thr[cell]) c = HFV_CLASS_LINEAR;
+    if (a.margin) mg = fmin(mg, deact_margin(dU, a.t.thr[cell]));
   }
   if (a.coef) {
 #pragma unroll
@@ -473,7 +669,10 @@ __global__ __launch_bounds__(256) void k_linear_ks(HotArgs<T> a) {
       }
     }
   }
-  if (q == 0) a.own[cell] = (uint8_t)(c | (hok ? 0 : 4));
+  if (q == 0) {
+    a.own[cell] = (uint8_t)(c | (hok ? 0 : 4));
+    if (a.margin) a.margin[cell] = mg;
+  }
 }
 
 // K2: final class (dilation over face neighbours) and per-class lists.
@@ -483,6 +682,7 @@ __global__ __launch_bounds__(CLASSIFY_BLOCK) void k_classify(HotArgs<T> a, int n
   const int cell = (int)(block_id(a.xcd) * blockDim.x + threadIdx.x);
   const bool valid = cell < a.N;
   int c = 0;
+  bool done = false;
   if (valid && a.frozen) {
     c = min((int)a.cls_in[cell], (int)HFV_CLASS_FIRST_ORDER);  // larger values: first order
   } else if (valid) {
@@ -498,10 +698,14 @@ __global__ __launch_bounds__(CLASSIFY_BLOCK) void k_classify(HotArgs<T> a, int n
       c = HFV_CLASS_LINEAR;
     }
     if (c == HFV_CLASS_LINEAR && (o & 4)) c = HFV_CLASS_FIRST_ORDER;
+    if (c == HFV_CLASS_CWENOZ && (o & 8)) {   // CWENOZ already done by the fused linear pass
+      c = (o & 16) ? HFV_CLASS_FIRST_ORDER : HFV_CLASS_CWENOZ;
+      done = true;
+    }
     a.cls[cell] = (uint8_t)c;
   }
   // List of the cell: CWENOZ (0), MUSCL (1), first order (2).
-  const int li = c - 1;
+  const int li = done ? -1 : c - 1;
   // Compaction: wave ballots give each lane its rank inside the wave; the
   // waves of the block combine their counts in LDS and the block reserves its
   // range of each list with one atomic per list.
@@ -532,7 +736,10 @@ __global__ __launch_bounds__(CLASSIFY_BLOCK) void k_classify(HotArgs<T> a, int n
 }
 
 // K3: CWENOZ over the class-1 list (every cell when direct).  REUSE: the
-// central fit is read from the linear pass's copy instead of refitted.
+// central fit is read from the linear pass's copy instead of refitted.  The
+// body is cwenoz_cell's written out: as a call (inlined) it was allocated
+// more registers (2D r = 3 FP64, two lanes: 255 + 12 AGPRs instead of 245,
+// one wave per SIMD instead of two).
 template <int DIM, int R, typename T, int G, bool REUSE>
 __global__ __launch_bounds__(256) void k_cwenoz(HotArgs<T> a, int direct) {
   constexpr int NV = DIM + 2, K = n_unknowns(DIM, R), VPL = NV / G, NFM = nf_max(DIM), MD = 2 * DIM;
@@ -935,13 +1142,22 @@ template <typename T>
 static HotArgs<T> make_args(hfv_ctx *ctx, Tables<T> &t, const void *U, void *fs, uint8_t *cls) {
   HotArgs<T> a;
   a.N = ctx->N;
+  a.NF = ctx->NF;
   a.mode = ctx->p.mode;
   a.form = ctx->p.form;
   a.frozen = 0;
   a.cls_in = nullptr;
   a.U = (const T *)U;
   a.fs = (T *)fs;
-  a.coef = (ctx->cw_reuse && ctx->p.mode == HFV_HYBRID) ? (T *)ctx->coef : nullptr;
+  // CWENOZ fused into the variable-split linear pass (hybrid, conserved
+  // variables); then no fit is kept
+  // (and not with viscous fluxes, whose gradients come from the kept fits:
+  // the linear pass then keeps every cell's fit, which CWENOZ also reads)
+  a.fuse = ctx->cw_fuse && ctx->lin_split == 0 && ctx->p.mode == HFV_HYBRID && ctx->p.cvars == HFV_CONSERVED &&
+           !ctx->p.viscous;
+  const bool keep = ctx->p.viscous ? (ctx->p.mode == HFV_HYBRID || ctx->p.mode == HFV_ALL_LINEAR)
+                                   : (ctx->cw_reuse && ctx->p.mode == HFV_HYBRID && !a.fuse);
+  a.coef = keep ? (T *)ctx->coef : nullptr;
   a.xcd = ctx->xcd_remap;
   a.limiter = ctx->p.limiter;
   a.own = ctx->own;
@@ -961,11 +1177,18 @@ static HotArgs<T> make_args(hfv_ctx *ctx, Tables<T> &t, const void *U, void *fs,
   a.tvd_eps = (T)ctx->p.tvd_eps;
   const double bw = ctx->p.b_w;
   a.ib_w = (bw >= 1.0 && bw <= 8.0 && bw == (double)(int)bw) ? (int)bw : 0;
+  a.margin = nullptr;
   return a;
 }
 
-__global__ void k_zero_counts(int *c) {
+static __global__ void k_zero_counts(int *c) {
   if (threadIdx.x < 8) c[threadIdx.x] = 0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill(T *x, int n, T v) {
+  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i < n) x[i] = v;
 }
 
 // The linear + NAD kernel in the configured mapping: variables (split 0),
@@ -975,12 +1198,22 @@ static void launch_linear(const hfv_ctx *ctx, const HotArgs<T> &a, hipStream_t s
   const int B = ctx->block, GL = ctx->lin_lanes;
   const long waves = ((long)ctx->N + 64 / GL - 1) / (64 / GL);
   const unsigned grid = nblk(waves * 64, B);
+  const bool fuse = a.fuse;
   switch (ctx->lin_split * 16 + GL) {
-    case 1: k_linear<DIM, R, T, 1><<<grid, B, 0, s>>>(a); break;
-    case 2:
-      if constexpr (DIM == 2) k_linear<DIM, R, T, 2><<<grid, B, 0, s>>>(a);
+    case 1:
+      if (fuse) k_linear<DIM, R, T, 1, true><<<grid, B, 0, s>>>(a);
+      else k_linear<DIM, R, T, 1><<<grid, B, 0, s>>>(a);
       break;
-    case DIM + 2: k_linear<DIM, R, T, DIM + 2><<<grid, B, 0, s>>>(a); break;
+    case 2:
+      if constexpr (DIM == 2) {
+        if (fuse) k_linear<DIM, R, T, 2, true><<<grid, B, 0, s>>>(a);
+        else k_linear<DIM, R, T, 2><<<grid, B, 0, s>>>(a);
+      }
+      break;
+    case DIM + 2:
+      if (fuse) k_linear<DIM, R, T, DIM + 2, true><<<grid, B, 0, s>>>(a);
+      else k_linear<DIM, R, T, DIM + 2><<<grid, B, 0, s>>>(a);
+      break;
     case 16 + 2: k_linear_ms<DIM, R, T, 2><<<grid, B, 0, s>>>(a); break;
     case 16 + 4: k_linear_ms<DIM, R, T, 4><<<grid, B, 0, s>>>(a); break;
     case 16 + 8: k_linear_ms<DIM, R, T, 8><<<grid, B, 0, s>>>(a); break;
@@ -1013,8 +1246,10 @@ static void launch_muscl(hfv_ctx *ctx, const HotArgs<T> &a, int direct, hipStrea
 }
 
 template <int DIM, int R, typename T, int G>
-static hfv_status recon_impl(hfv_ctx *ctx, Tables<T> &t, const void *U, void *fs, uint8_t *cls, hipStream_t s) {
+static hfv_status recon_impl(hfv_ctx *ctx, Tables<T> &t, const void *U, void *fs, uint8_t *cls, void *margin,
+                             hipStream_t s) {
   HotArgs<T> a = make_args<T>(ctx, t, U, fs, cls);
+  a.margin = (T *)margin;
   const int B = ctx->block;
   const long items = (long)ctx->N;
   const long waves = (items + 64 / G - 1) / (64 / G);
@@ -1022,9 +1257,24 @@ static hfv_status recon_impl(hfv_ctx *ctx, Tables<T> &t, const void *U, void *fs
   const unsigned grid_list =
       ctx->list_blocks > 0 ? std::min<unsigned>(grid_cells, (unsigned)ctx->list_blocks) : grid_cells;
   const int mode = ctx->p.mode;
+  if (margin && (mode == HFV_ALL_CWENOZ || mode == HFV_ALL_MUSCL))   // no linear pass: no decision to report
+    k_fill<T><<<nblk(ctx->N, 256), 256, 0, s>>>((T *)margin, ctx->N, (T)INFINITY);
+  const bool chr = ctx->p.cvars == HFV_CHARACTERISTIC;
+  if (ctx->p.viscous && (mode == HFV_ALL_CWENOZ || mode == HFV_ALL_MUSCL)) {
+    // no linear pass to keep the central fits the viscous gradients use
+    hfv_status e = run_keep_fits(ctx, U, s);
+    if (e != HFV_OK) return e;
+  }
   if (mode == HFV_ALL_CWENOZ) {
     k_zero_counts<<<1, 64, 0, s>>>(ctx->counts);
-    { ProfScope ps(ctx, HFV_SLOT_CWENOZ, s); k_cwenoz<DIM, R, T, G, false><<<grid_list, B, 0, s>>>(a, 1); }
+    ProfScope ps(ctx, HFV_SLOT_CWENOZ, s);
+    if (chr) {
+      a.coef = nullptr;
+      hfv_status e = launch_cwenoz_char<T>(ctx, a, 1, s);
+      if (e != HFV_OK) return e;
+    } else {
+      k_cwenoz<DIM, R, T, G, false><<<grid_list, B, 0, s>>>(a, 1);
+    }
   } else if (mode == HFV_ALL_MUSCL) {
     k_zero_counts<<<1, 64, 0, s>>>(ctx->counts);
     { ProfScope ps(ctx, HFV_SLOT_MUSCL, s); launch_muscl<DIM, R, T>(ctx, a, 1, s); }
@@ -1033,10 +1283,14 @@ static hfv_status recon_impl(hfv_ctx *ctx, Tables<T> &t, const void *U, void *fs
     { ProfScope ps(ctx, HFV_SLOT_CLASSIFY, s); k_classify<T><<<nblk(ctx->N, CLASSIFY_BLOCK), CLASSIFY_BLOCK, 0, s>>>(a, ctx->NFM); }
     if (mode == HFV_HYBRID) {
       ProfScope ps(ctx, HFV_SLOT_CWENOZ, s);
-      if (a.coef)
+      if (chr) {
+        hfv_status e = launch_cwenoz_char<T>(ctx, a, 0, s);
+        if (e != HFV_OK) return e;
+      } else if (a.coef) {
         k_cwenoz<DIM, R, T, G, true><<<grid_list, B, 0, s>>>(a, 0);
-      else
+      } else {
         k_cwenoz<DIM, R, T, G, false><<<grid_list, B, 0, s>>>(a, 0);
+      }
     }
     // MUSCL list (empty unless hybrid) and the first-order list
     { ProfScope ps(ctx, HFV_SLOT_MUSCL, s); launch_muscl<DIM, R, T>(ctx, a, 0, s); }
@@ -1056,6 +1310,7 @@ static hfv_status frozen_impl(hfv_ctx *ctx, Tables<T> &t, const void *U, void *f
   a.cls_in = cls;
   a.mode = HFV_ALL_LINEAR;
   a.coef = nullptr;
+  a.fuse = false;
   const int B = ctx->block;
   const long waves = ((long)ctx->N + 64 / G - 1) / (64 / G);
   const unsigned grid_cells = nblk(waves * 64, B);
@@ -1063,23 +1318,125 @@ static hfv_status frozen_impl(hfv_ctx *ctx, Tables<T> &t, const void *U, void *f
       ctx->list_blocks > 0 ? std::min<unsigned>(grid_cells, (unsigned)ctx->list_blocks) : grid_cells;
   launch_linear<DIM, R, T>(ctx, a, s);
   k_classify<T><<<nblk(ctx->N, CLASSIFY_BLOCK), CLASSIFY_BLOCK, 0, s>>>(a, ctx->NFM);
-  k_cwenoz<DIM, R, T, G, false><<<grid_list, B, 0, s>>>(a, 0);
+  if (ctx->p.cvars == HFV_CHARACTERISTIC) {
+    hfv_status e = launch_cwenoz_char<T>(ctx, a, 0, s);
+    if (e != HFV_OK) return e;
+  } else {
+    k_cwenoz<DIM, R, T, G, false><<<grid_list, B, 0, s>>>(a, 0);
+  }
   launch_muscl<DIM, R, T>(ctx, a, 0, s);
   HFV_HIP(hipGetLastError());
+  if (ctx->p.viscous) return run_keep_fits(ctx, U, s);   // the viscous gradients' fits
   return HFV_OK;
 }
 
+// Per (dim, order) entry points of the forward kernels.  The translation unit
+// is compiled once per group of orders (HFV_HOT_PART 1..8, each instantiating
+// its orders' kernels) and once for the dispatch below (HFV_HOT_PART 0), so
+// the build runs in parallel; without HFV_HOT_PART it holds everything.
+template <int DIM, int R, typename T>
+hfv_status frozen_dr(hfv_ctx *ctx, Tables<T> &t, const void *U, void *fs, const uint8_t *cls, hipStream_t s) {
+  return frozen_impl<DIM, R, T, DIM + 2>(ctx, t, U, fs, cls, s);
+}
+
+template <int DIM, int R, typename T>
+hfv_status recon_dr(hfv_ctx *ctx, Tables<T> &t, const void *U, void *fs, uint8_t *cls, void *mg, hipStream_t s) {
+  switch (ctx->lanes) {
+    case 1: return recon_impl<DIM, R, T, 1>(ctx, t, U, fs, cls, mg, s);
+    case DIM + 2: return recon_impl<DIM, R, T, DIM + 2>(ctx, t, U, fs, cls, mg, s);
+    default:
+      if constexpr (DIM == 2) {
+        if (ctx->lanes == 2) return recon_impl<DIM, R, T, 2>(ctx, t, U, fs, cls, mg, s);
+      }
+      ctx->err = "unsupported lanes per cell";
+      return HFV_ERR_PARAM;
+  }
+}
+
+#ifndef HFV_HOT_PART
+#define HFV_HOT_PART -1
+#endif
+// X: "extern" to declare the instantiations made in another part, or empty
+#define HFV_ORDER(X, D, R)                                                                                          \
+  X template hfv_status recon_dr<D, R, double>(hfv_ctx *, Tables<double> &, const void *, void *, uint8_t *,     \
+                                               void *, hipStream_t);                                                \
+  X template hfv_status recon_dr<D, R, float>(hfv_ctx *, Tables<float> &, const void *, void *, uint8_t *, void *, \
+                                              hipStream_t);                                                         \
+  X template hfv_status frozen_dr<D, R, double>(hfv_ctx *, Tables<double> &, const void *, void *,                 \
+                                                const uint8_t *, hipStream_t);                                      \
+  X template hfv_status frozen_dr<D, R, float>(hfv_ctx *, Tables<float> &, const void *, void *, const uint8_t *,  \
+                                               hipStream_t);
+#define HFV_NOTHING
+#if HFV_HOT_PART == 0
+#define HFV_PART_ORDER(P, D, R) HFV_ORDER(extern, D, R)
+#else
+#define HFV_PART_ORDER(P, D, R) HFV_PART_ORDER_##P(D, R)
+#endif
+#if HFV_HOT_PART == -1 || HFV_HOT_PART == 1
+#define HFV_PART_ORDER_1(D, R) HFV_ORDER(HFV_NOTHING, D, R)
+#else
+#define HFV_PART_ORDER_1(D, R)
+#endif
+#if HFV_HOT_PART == -1 || HFV_HOT_PART == 2
+#define HFV_PART_ORDER_2(D, R) HFV_ORDER(HFV_NOTHING, D, R)
+#else
+#define HFV_PART_ORDER_2(D, R)
+#endif
+#if HFV_HOT_PART == -1 || HFV_HOT_PART == 3
+#define HFV_PART_ORDER_3(D, R) HFV_ORDER(HFV_NOTHING, D, R)
+#else
+#define HFV_PART_ORDER_3(D, R)
+#endif
+#if HFV_HOT_PART == -1 || HFV_HOT_PART == 4
+#define HFV_PART_ORDER_4(D, R) HFV_ORDER(HFV_NOTHING, D, R)
+#else
+#define HFV_PART_ORDER_4(D, R)
+#endif
+#if HFV_HOT_PART == -1 || HFV_HOT_PART == 5
+#define HFV_PART_ORDER_5(D, R) HFV_ORDER(HFV_NOTHING, D, R)
+#else
+#define HFV_PART_ORDER_5(D, R)
+#endif
+#if HFV_HOT_PART == -1 || HFV_HOT_PART == 6
+#define HFV_PART_ORDER_6(D, R) HFV_ORDER(HFV_NOTHING, D, R)
+#else
+#define HFV_PART_ORDER_6(D, R)
+#endif
+#if HFV_HOT_PART == -1 || HFV_HOT_PART == 7
+#define HFV_PART_ORDER_7(D, R) HFV_ORDER(HFV_NOTHING, D, R)
+#else
+#define HFV_PART_ORDER_7(D, R)
+#endif
+#if HFV_HOT_PART == -1 || HFV_HOT_PART == 8
+#define HFV_PART_ORDER_8(D, R) HFV_ORDER(HFV_NOTHING, D, R)
+#else
+#define HFV_PART_ORDER_8(D, R)
+#endif
+HFV_PART_ORDER(1, 2, 1)
+HFV_PART_ORDER(1, 2, 2)
+HFV_PART_ORDER(2, 2, 3)
+HFV_PART_ORDER(3, 2, 4)
+HFV_PART_ORDER(4, 2, 5)
+HFV_PART_ORDER(5, 2, 6)
+HFV_PART_ORDER(6, 3, 1)
+HFV_PART_ORDER(6, 3, 2)
+HFV_PART_ORDER(7, 3, 3)
+HFV_PART_ORDER(8, 3, 4)
+
+#if HFV_HOT_PART <= 0
 template <typename T>
 static hfv_status frozen_t(hfv_ctx *ctx, Tables<T> &t, const void *U, void *fs, const uint8_t *cls, hipStream_t s) {
   switch (ctx->dim * 10 + ctx->r) {
-    case 21: return frozen_impl<2, 1, T, 4>(ctx, t, U, fs, cls, s);
-    case 22: return frozen_impl<2, 2, T, 4>(ctx, t, U, fs, cls, s);
-    case 23: return frozen_impl<2, 3, T, 4>(ctx, t, U, fs, cls, s);
-    case 24: return frozen_impl<2, 4, T, 4>(ctx, t, U, fs, cls, s);
-    case 31: return frozen_impl<3, 1, T, 5>(ctx, t, U, fs, cls, s);
-    case 32: return frozen_impl<3, 2, T, 5>(ctx, t, U, fs, cls, s);
-    case 33: return frozen_impl<3, 3, T, 5>(ctx, t, U, fs, cls, s);
-    case 34: return frozen_impl<3, 4, T, 5>(ctx, t, U, fs, cls, s);
+    case 21: return frozen_dr<2, 1, T>(ctx, t, U, fs, cls, s);
+    case 22: return frozen_dr<2, 2, T>(ctx, t, U, fs, cls, s);
+    case 23: return frozen_dr<2, 3, T>(ctx, t, U, fs, cls, s);
+    case 24: return frozen_dr<2, 4, T>(ctx, t, U, fs, cls, s);
+    case 25: return frozen_dr<2, 5, T>(ctx, t, U, fs, cls, s);
+    case 26: return frozen_dr<2, 6, T>(ctx, t, U, fs, cls, s);
+    case 31: return frozen_dr<3, 1, T>(ctx, t, U, fs, cls, s);
+    case 32: return frozen_dr<3, 2, T>(ctx, t, U, fs, cls, s);
+    case 33: return frozen_dr<3, 3, T>(ctx, t, U, fs, cls, s);
+    case 34: return frozen_dr<3, 4, T>(ctx, t, U, fs, cls, s);
   }
   ctx->err = "unsupported (dim, order_r)";
   return HFV_ERR_PARAM;
@@ -1108,39 +1465,28 @@ hfv_status run_reconstruct_frozen(hfv_ctx *ctx, const void *U, void *fs, const u
                          : frozen_t<float>(ctx, ctx->t32, U, fs, cls, s);
 }
 
-template <int DIM, int R, typename T>
-static hfv_status recon_lanes(hfv_ctx *ctx, Tables<T> &t, const void *U, void *fs, uint8_t *cls, hipStream_t s) {
-  switch (ctx->lanes) {
-    case 1: return recon_impl<DIM, R, T, 1>(ctx, t, U, fs, cls, s);
-    case DIM + 2: return recon_impl<DIM, R, T, DIM + 2>(ctx, t, U, fs, cls, s);
-    default:
-      if constexpr (DIM == 2) {
-        if (ctx->lanes == 2) return recon_impl<DIM, R, T, 2>(ctx, t, U, fs, cls, s);
-      }
-      ctx->err = "unsupported lanes per cell";
-      return HFV_ERR_PARAM;
-  }
-}
-
 template <typename T>
-static hfv_status recon_t(hfv_ctx *ctx, Tables<T> &t, const void *U, void *fs, uint8_t *cls, hipStream_t s) {
+static hfv_status recon_t(hfv_ctx *ctx, Tables<T> &t, const void *U, void *fs, uint8_t *cls, void *mg,
+                          hipStream_t s) {
   switch (ctx->dim * 10 + ctx->r) {
-    case 21: return recon_lanes<2, 1, T>(ctx, t, U, fs, cls, s);
-    case 22: return recon_lanes<2, 2, T>(ctx, t, U, fs, cls, s);
-    case 23: return recon_lanes<2, 3, T>(ctx, t, U, fs, cls, s);
-    case 24: return recon_lanes<2, 4, T>(ctx, t, U, fs, cls, s);
-    case 31: return recon_lanes<3, 1, T>(ctx, t, U, fs, cls, s);
-    case 32: return recon_lanes<3, 2, T>(ctx, t, U, fs, cls, s);
-    case 33: return recon_lanes<3, 3, T>(ctx, t, U, fs, cls, s);
-    case 34: return recon_lanes<3, 4, T>(ctx, t, U, fs, cls, s);
+    case 21: return recon_dr<2, 1, T>(ctx, t, U, fs, cls, mg, s);
+    case 22: return recon_dr<2, 2, T>(ctx, t, U, fs, cls, mg, s);
+    case 23: return recon_dr<2, 3, T>(ctx, t, U, fs, cls, mg, s);
+    case 24: return recon_dr<2, 4, T>(ctx, t, U, fs, cls, mg, s);
+    case 25: return recon_dr<2, 5, T>(ctx, t, U, fs, cls, mg, s);
+    case 26: return recon_dr<2, 6, T>(ctx, t, U, fs, cls, mg, s);
+    case 31: return recon_dr<3, 1, T>(ctx, t, U, fs, cls, mg, s);
+    case 32: return recon_dr<3, 2, T>(ctx, t, U, fs, cls, mg, s);
+    case 33: return recon_dr<3, 3, T>(ctx, t, U, fs, cls, mg, s);
+    case 34: return recon_dr<3, 4, T>(ctx, t, U, fs, cls, mg, s);
   }
   ctx->err = "unsupported (dim, order_r)";
   return HFV_ERR_PARAM;
 }
 
-hfv_status run_reconstruct(hfv_ctx *ctx, const void *U, void *fs, uint8_t *cls, hipStream_t s) {
-  return ctx->prec == 64 ? recon_t<double>(ctx, ctx->t64, U, fs, cls, s)
-                         : recon_t<float>(ctx, ctx->t32, U, fs, cls, s);
+hfv_status run_reconstruct(hfv_ctx *ctx, const void *U, void *fs, uint8_t *cls, hipStream_t s, void *margin) {
+  return ctx->prec == 64 ? recon_t<double>(ctx, ctx->t64, U, fs, cls, margin, s)
+                         : recon_t<float>(ctx, ctx->t32, U, fs, cls, margin, s);
 }
 
 template <typename T>
@@ -1148,7 +1494,7 @@ static hfv_status tail_t(hfv_ctx *ctx, Tables<T> &t, const void *fs, void *R, hi
   const int hllc = ctx->p.riemann == HFV_HLLC;
   T *Ff = (T *)ctx->fflux;
   const unsigned gf = nblk(ctx->NF, 256), gc = nblk(ctx->N, 256);
-  if (ctx->fused_residual) {
+  if (ctx->fused_residual && !ctx->p.viscous) {
     ProfScope ps(ctx, HFV_SLOT_FLUX, s);
     if (ctx->dim == 2)
       k_residual<2, T><<<gc, 256, 0, s>>>(ctx->N, ctx->NF, (const T *)fs, t.cf_off, t.cf, t.face_cells, t.fgb,
@@ -1162,13 +1508,21 @@ static hfv_status tail_t(hfv_ctx *ctx, Tables<T> &t, const void *fs, void *R, hi
   if (ctx->dim == 2) {
     { ProfScope ps(ctx, HFV_SLOT_FLUX, s);
       k_flux<2, T><<<gf, 256, 0, s>>>(ctx->NF, ctx->N, (const T *)fs, t.gp_off, t.face_cells, t.fgb, t.fnormal,
-                                       t.gpw, (T)ctx->p.gamma, hllc, Ff, ctx->xcd_remap); }
+                                       t.gpw, (T)ctx->p.gamma, hllc, Ff, ctx->xcd_remap);
+      if (ctx->p.viscous) {
+        hfv_status e = run_viscous_flux(ctx, fs, Ff, s);
+        if (e != HFV_OK) return e;
+      } }
     { ProfScope ps(ctx, HFV_SLOT_GATHER, s);
       k_gather<4, T><<<gc, 256, 0, s>>>(ctx->N, ctx->NF, t.cf_off, t.cf, Ff, t.ivol, (T *)R, ctx->xcd_remap); }
   } else {
     { ProfScope ps(ctx, HFV_SLOT_FLUX, s);
       k_flux<3, T><<<gf, 256, 0, s>>>(ctx->NF, ctx->N, (const T *)fs, t.gp_off, t.face_cells, t.fgb, t.fnormal,
-                                       t.gpw, (T)ctx->p.gamma, hllc, Ff, ctx->xcd_remap); }
+                                       t.gpw, (T)ctx->p.gamma, hllc, Ff, ctx->xcd_remap);
+      if (ctx->p.viscous) {
+        hfv_status e = run_viscous_flux(ctx, fs, Ff, s);
+        if (e != HFV_OK) return e;
+      } }
     { ProfScope ps(ctx, HFV_SLOT_GATHER, s);
       k_gather<5, T><<<gc, 256, 0, s>>>(ctx->N, ctx->NF, t.cf_off, t.cf, Ff, t.ivol, (T *)R, ctx->xcd_remap); }
   }
@@ -1179,5 +1533,6 @@ static hfv_status tail_t(hfv_ctx *ctx, Tables<T> &t, const void *fs, void *R, hi
 hfv_status run_residual_tail(hfv_ctx *ctx, const void *fs, void *R, hipStream_t s) {
   return ctx->prec == 64 ? tail_t<double>(ctx, ctx->t64, fs, R, s) : tail_t<float>(ctx, ctx->t32, fs, R, s);
 }
+#endif  // dispatch
 
 }  // namespace hfv

@@ -81,6 +81,8 @@ struct Tables {
   int *cf_off = nullptr;   // [N+1]
   int *cf = nullptr;       // [..] face | (side << 31)
   T *ivol = nullptr;       // [N]
+  T *hinv = nullptr;       // [N]  1 / h_c (gradients in physical units)
+  T *linv = nullptr;       // [NF] 1 / (distance between the face's two cell centres); 0 at boundaries
   // adjoint: positions inside the central stencil and its transpose
   uint8_t *dpos = nullptr;  // [NFM][Md][N] directional member -> central slot
   uint8_t *mpos = nullptr;  // [NFM][N]     MUSCL member -> central slot
@@ -90,8 +92,9 @@ struct Tables {
 };
 
 struct Params {
-  int order_r, mode, riemann, form, limiter;
+  int order_r, mode, riemann, form, limiter, cvars, viscous;
   double gamma, alpha_m, beta_m, alpha_w, beta_w, kappa, n_exp, lam1p, eps_w, b_w, theta, tvd_eps;
+  double mu0, T0, suth_S, prandtl, visc_alpha;
 };
 
 }  // namespace hfv
@@ -128,6 +131,7 @@ struct hfv_ctx {
   int fused_residual = 0;            // one owner-computes residual kernel instead of flux + gather
   int xcd_remap = 1;                 // XCD-contiguous block order (block_id)
   int muscl_lanes = 0;               // lanes per cell of the MUSCL pass (0: lanes)
+  int cw_fuse = 0;                   // CWENOZ of own-flagged cells in the variable-split linear pass
   int device = 0, n_cu = 256;
   // kernel timing (hfv_profile_*)
   struct ProfEv {
@@ -143,13 +147,19 @@ struct hfv_ctx {
 namespace hfv {
 
 hfv_status setup_tables(hfv_ctx *ctx, const hfv_mesh *mesh, const hfv_stencils *st, hipStream_t s);
-hfv_status run_reconstruct(hfv_ctx *ctx, const void *U, void *fs, uint8_t *cls, hipStream_t s);
+hfv_status run_reconstruct(hfv_ctx *ctx, const void *U, void *fs, uint8_t *cls, hipStream_t s,
+                           void *margin = nullptr);
 hfv_status run_reconstruct_frozen(hfv_ctx *ctx, const void *U, void *fs, const uint8_t *cls, hipStream_t s);
 hfv_status run_class_lists(hfv_ctx *ctx, const uint8_t *cls, hipStream_t s);
 hfv_status run_residual_tail(hfv_ctx *ctx, const void *fs, void *R, hipStream_t s);
 hfv_status run_vjp(hfv_ctx *ctx, const void *U, const uint8_t *cls, const void *fs, const void *gR, void *gU,
                    hipStream_t s);
 hfv_status dev_alloc(hfv_ctx *ctx, void **p, size_t bytes);
+// viscous fluxes (hfv_visc.cpp): the central fit of every cell kept in
+// ctx->coef (for the modes without a linear pass), and F_v subtracted from
+// the integrated face fluxes
+hfv_status run_keep_fits(hfv_ctx *ctx, const void *U, hipStream_t s);
+hfv_status run_viscous_flux(hfv_ctx *ctx, const void *fs, void *Ff, hipStream_t s);
 
 // Brackets one kernel launch with HIP events when its slot is being timed.
 struct ProfScope {

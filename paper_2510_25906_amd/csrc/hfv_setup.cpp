@@ -619,6 +619,29 @@ __global__ void k_convert(long n, const double *src, T *dst) {
   if (i < n) dst[i] = (T)src[i];
 }
 
+// 1 / h_c per cell, and per face 1 / L_int, the distance between the two
+// cell centres with the right cell's periodic image next to the left cell
+// (0 at boundary faces): the penalty of Eq. viscous_jump.
+template <typename T>
+__global__ void k_visc_geom(int N, int NF, int DIM, const double *geom, const int *fcells, const int8_t *fshift,
+                            const double *period, T *hinv, T *linv) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) hinv[i] = (T)(1.0 / geom[(DIM + 1) * N + i]);
+  if (i < NF) {
+    const int l = fcells[i], r = fcells[NF + i];
+    double v = 0.0;
+    if (r >= 0) {
+      double d2 = 0.0;
+      for (int j = 0; j < DIM; ++j) {
+        const double dx = geom[j * N + r] + (fshift ? fshift[(long)i * DIM + j] * period[j] : 0.0) - geom[j * N + l];
+        d2 += dx * dx;
+      }
+      v = 1.0 / sqrt(d2);
+    }
+    linv[i] = (T)v;
+  }
+}
+
 template <typename T>
 __global__ void k_thresholds(int N, int DIM, const double *geom, double kappa, double nexp, T *thr, T *ivol,
                              T *veps2) {
@@ -868,6 +891,10 @@ static hfv_status setup_dr(hfv_ctx *ctx, const hfv_mesh *mesh, const hfv_stencil
     if ((e = dev_alloc(ctx, (void **)&tabs.veps2, sizeof(T) * N))) return e;
     k_thresholds<T><<<nblk(N, 256), 256, 0, s>>>(N, DIM, geom, ctx->p.kappa, ctx->p.n_exp, tabs.thr, tabs.ivol,
                                                  tabs.veps2);
+    if ((e = dev_alloc(ctx, (void **)&tabs.hinv, sizeof(T) * N))) return e;
+    if ((e = dev_alloc(ctx, (void **)&tabs.linv, sizeof(T) * NF))) return e;
+    k_visc_geom<T><<<nblk(std::max(N, NF), 256), 256, 0, s>>>(N, NF, DIM, geom, fcells, fshift, period, tabs.hinv,
+                                                             tabs.linv);
     // integer tables (shared layout for both precisions)
     if ((e = dev_alloc(ctx, (void **)&tabs.ngp, N))) return e;
     HFV_HIP(hipMemcpyAsync(tabs.ngp, ngp, N, hipMemcpyDeviceToDevice, s));
@@ -943,6 +970,8 @@ hfv_status setup_tables(hfv_ctx *ctx, const hfv_mesh *mesh, const hfv_stencils *
     case 22: e = setup_dr<2, 2>(ctx, mesh, st, s, RU, cf_off, cf, gp_off); break;
     case 23: e = setup_dr<2, 3>(ctx, mesh, st, s, RU, cf_off, cf, gp_off); break;
     case 24: e = setup_dr<2, 4>(ctx, mesh, st, s, RU, cf_off, cf, gp_off); break;
+    case 25: e = setup_dr<2, 5>(ctx, mesh, st, s, RU, cf_off, cf, gp_off); break;
+    case 26: e = setup_dr<2, 6>(ctx, mesh, st, s, RU, cf_off, cf, gp_off); break;
     case 31: e = setup_dr<3, 1>(ctx, mesh, st, s, RU, cf_off, cf, gp_off); break;
     case 32: e = setup_dr<3, 2>(ctx, mesh, st, s, RU, cf_off, cf, gp_off); break;
     case 33: e = setup_dr<3, 3>(ctx, mesh, st, s, RU, cf_off, cf, gp_off); break;

@@ -537,7 +537,7 @@ static hfv_status vjp_t(hfv_ctx *ctx, Tables<T> &t, const void *U, const uint8_t
     case 33: return vjp_impl<3, 3, T>(ctx, t, U, cls, fs, gR, gU, s);
     case 34: return vjp_impl<3, 4, T>(ctx, t, U, cls, fs, gR, gU, s);
   }
-  ctx->err = "unsupported (dim, order_r)";
+  ctx->err = "the residual VJP is built for order_r <= 4";
   return HFV_ERR_PARAM;
 }
 
@@ -545,6 +545,14 @@ hfv_status run_vjp(hfv_ctx *ctx, const void *U, const uint8_t *cls, const void *
                    hipStream_t s) {
   if (!ctx->vjp_ok) {
     ctx->err = "residual VJP unavailable for these stencils: " + ctx->vjp_why;
+    return HFV_ERR_STATE;
+  }
+  if (ctx->p.cvars != HFV_CONSERVED) {
+    ctx->err = "the residual VJP differentiates conserved-variable CWENOZ only";
+    return HFV_ERR_STATE;
+  }
+  if (ctx->p.viscous) {
+    ctx->err = "the residual VJP differentiates the inviscid residual only";
     return HFV_ERR_STATE;
   }
   return ctx->prec == 64 ? vjp_t<double>(ctx, ctx->t64, U, cls, fs, gR, gU, s)

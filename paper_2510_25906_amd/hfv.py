@@ -49,10 +49,13 @@ class HfvStencils(C.Structure):
 class HfvParams(C.Structure):
     _fields_ = [("order_r", C.c_int32), ("scheme_mode", C.c_int32), ("precision", C.c_int32),
                 ("riemann", C.c_int32), ("cweno_form", C.c_int32), ("limiter", C.c_int32),
+                ("cweno_vars", C.c_int32), ("viscous", C.c_int32),
                 ("gamma", C.c_double), ("alpha_m", C.c_double), ("beta_m", C.c_double), ("alpha_w", C.c_double),
                 ("beta_w", C.c_double), ("kappa", C.c_double), ("n_exp", C.c_double),
                 ("lambda1_prime", C.c_double), ("eps_w", C.c_double), ("b_w", C.c_double),
-                ("tvd_theta", C.c_double), ("tvd_eps", C.c_double)]
+                ("tvd_theta", C.c_double), ("tvd_eps", C.c_double),
+                ("mu0", C.c_double), ("T0", C.c_double), ("sutherland_S", C.c_double), ("prandtl", C.c_double),
+                ("visc_alpha", C.c_double)]
 
 
 def load():
@@ -69,7 +72,7 @@ def load():
     lib.hfv_create.argtypes = [C.POINTER(HfvMesh), C.POINTER(HfvStencils), C.POINTER(HfvParams), _p,
                                C.POINTER(_p)]
     lib.hfv_set_params.argtypes = [_p, C.POINTER(HfvParams)]
-    lib.hfv_reconstruct.argtypes = [_p, _p, _p, _p, _p]
+    lib.hfv_reconstruct.argtypes = [_p, _p, _p, _p, _p, _p]
     lib.hfv_residual.argtypes = [_p, _p, _p, _p, _p, _p]
     lib.hfv_residual_noalloc.argtypes = [_p, _p, _p, _p, _p, _p]
     lib.hfv_residual_vjp.argtypes = [_p, _p, _p, _p, _p, _p]
@@ -104,7 +107,7 @@ def load():
 class HfvLaunch(C.Structure):
     _fields_ = [(n, C.c_int32) for n in ("lanes_per_cell", "block", "list_blocks", "linear_split",
                                          "linear_lanes", "cwenoz_reuse", "fused_residual", "xcd_remap",
-                                         "muscl_lanes")]
+                                         "muscl_lanes", "cwenoz_fuse")]
 
 
 class HfvTuneRecord(C.Structure):
@@ -123,10 +126,11 @@ def _ptr(a, ctype):
 
 def params_struct(p: Params, precision: int) -> HfvParams:
     return HfvParams(order_r=p.order_r, scheme_mode=p.scheme_mode, precision=precision, riemann=p.riemann,
-                     cweno_form=p.cweno_form, limiter=p.limiter, gamma=p.gamma, alpha_m=p.alpha_m, beta_m=p.beta_m,
+                     cweno_form=p.cweno_form, limiter=p.limiter, cweno_vars=p.cweno_vars, gamma=p.gamma, alpha_m=p.alpha_m, beta_m=p.beta_m,
                      alpha_w=p.alpha_w, beta_w=p.beta_w, kappa=p.kappa, n_exp=p.n_exp,
                      lambda1_prime=p.lambda1_prime, eps_w=p.eps_w, b_w=p.b_w, tvd_theta=p.tvd_theta,
-                     tvd_eps=p.tvd_eps)
+                     tvd_eps=p.tvd_eps, viscous=p.viscous, mu0=p.mu0, T0=p.T0, sutherland_S=p.sutherland_S,
+                     prandtl=p.prandtl, visc_alpha=p.visc_alpha)
 
 
 def _stream_handle(stream):
@@ -223,12 +227,12 @@ class Context:
         return {n: getattr(cfg, n) for n, _ in HfvLaunch._fields_}
 
     def set_launch(self, lanes=None, block=None, list_blocks=None, linear_split=None, linear_lanes=None,
-                   cwenoz_reuse=None, fused_residual=None, xcd_remap=None, muscl_lanes=None):
+                   cwenoz_reuse=None, fused_residual=None, xcd_remap=None, muscl_lanes=None, cwenoz_fuse=None):
         """Change the launch configuration; fields left None keep their current value."""
         cur = self.get_launch()
         new = dict(lanes_per_cell=lanes, block=block, list_blocks=list_blocks, linear_split=linear_split,
                    linear_lanes=linear_lanes, cwenoz_reuse=cwenoz_reuse, fused_residual=fused_residual,
-                   xcd_remap=xcd_remap, muscl_lanes=muscl_lanes)
+                   xcd_remap=xcd_remap, muscl_lanes=muscl_lanes, cwenoz_fuse=cwenoz_fuse)
         cur.update({k: int(v) for k, v in new.items() if v is not None})
         self._check(self.lib.hfv_set_launch(self.h, C.byref(HfvLaunch(**cur))))
 
@@ -286,6 +290,7 @@ class Context:
         kinds = dict(u=(self.dtype, (self.nvar, self.n_cells)),
                      cls=(torch.uint8, (self.n_cells,)),
                      fs=(self.dtype, (self.ngp_cell, self.nvar, self.n_cells)),
+                     margin=(self.dtype, (self.n_cells,)),
                      rate=(torch.float64, (1,)))
         given = [(x, name, kind) for x, name, kind in bufs if x is not None]
         for x, name, kind in given:
@@ -310,14 +315,19 @@ class Context:
         import torch
         return torch.empty((self.ngp_cell, self.nvar, self.n_cells), dtype=self.dtype, device="cuda")
 
-    def reconstruct(self, U, face_states=None, cell_class=None, stream=None):
+    def reconstruct(self, U, face_states=None, cell_class=None, stream=None, near_margin=None):
+        """Face states and classes of U; near_margin, when given (a [n_cells]
+        tensor of the context's dtype), receives each cell's relative distance
+        to its nearest class threshold."""
         import torch
-        self._chk((U, "U", "u"), (face_states, "face_states", "fs"), (cell_class, "cell_class", "cls"))
+        self._chk((U, "U", "u"), (face_states, "face_states", "fs"), (cell_class, "cell_class", "cls"),
+                  (near_margin, "near_margin", "margin"))
         fs = face_states if face_states is not None else self.new_face_states()
         cls = cell_class if cell_class is not None else torch.empty(self.n_cells, dtype=torch.uint8,
                                                                      device="cuda")
+        mgp = C.c_void_p(near_margin.data_ptr()) if near_margin is not None else None
         self._check(self.lib.hfv_reconstruct(self.h, C.c_void_p(U.data_ptr()), C.c_void_p(fs.data_ptr()),
-                                             C.c_void_p(cls.data_ptr()), _stream_handle(stream)))
+                                             C.c_void_p(cls.data_ptr()), mgp, _stream_handle(stream)))
         return fs, cls
 
     def residual(self, U, R=None, face_states=None, cell_class=None, stream=None):

@@ -15,6 +15,9 @@ HLLC, HLL = 0, 1
 WENOZ_POW, LITERAL = 0, 1
 # MUSCL slope limiters (Sections 2.2, 3.2): Barth-Jespersen, Venkatakrishnan
 BJ, VENKAT = 0, 1
+# variables CWENOZ reconstructs (Section 2.3): conserved, or characteristic
+# (per face, eigenvectors of the flux Jacobian at the Roe average across it)
+CONSERVED, CHARACTERISTIC = 0, 1
 # cell classes, ordered by dissipation
 LINEAR_CLASS, CWENOZ_CLASS, MUSCL_CLASS, FIRST_ORDER_CLASS = 0, 1, 2, 3
 
@@ -26,6 +29,7 @@ class Params:
     riemann: int = HLLC
     cweno_form: int = WENOZ_POW
     limiter: int = BJ
+    cweno_vars: int = CONSERVED
     gamma: float = 1.4
     # NAD margins (Eqs. marginm, marginw); default preset (a)
     alpha_m: float = 5e-3
@@ -42,6 +46,16 @@ class Params:
     # Harten bound check (Eq. harten_jump_fix)
     tvd_theta: float = 0.9
     tvd_eps: float = 1e-14
+    # Navier-Stokes viscous fluxes (Section 2, Eqs. sutherlandlaw, HeatConduct,
+    # Stresses; Section 2.4, Eq. viscous_jump); off by default (Euler).
+    # Temperature T = p / rho; Sutherland mu = mu0 (T/T0)^1.5 (T0+S)/(T+S);
+    # S = 110.4 K over a 273.15 K reference; penalty alpha = 4/3
+    viscous: int = 0
+    mu0: float = 0.0
+    T0: float = 1.0
+    sutherland_S: float = 110.4 / 273.15
+    prandtl: float = 0.72
+    visc_alpha: float = 4.0 / 3.0
 
     def with_(self, **kw) -> "Params":
         return replace(self, **kw)

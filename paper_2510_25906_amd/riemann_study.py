@@ -1,7 +1,9 @@
 """Time-integrated four-quadrant Riemann problem (Section 3.5, Eq.
 2DRiemannProblem) on one GPU: the hybrid scheme with each NAD margin preset
 of Fig. NADMargin (and the default one with the Venkatakrishnan limiter of the
-comparison in Section 3.2), against all-CWENOZ and all-MUSCL, integrated in time at
+comparison in Section 3.2), against all-CWENOZ and all-MUSCL, with CWENOZ on
+conserved variables and (the `_char` variants) on characteristic variables
+(Section 2.3), integrated in time at
 CFL 0.6 with HLL fluxes and the SSP(5,4) time loop.
 
 For every variant it reports the device time of the whole integration (the
@@ -28,11 +30,14 @@ import time
 import numpy as np
 
 from .inputs import configs
-from .inputs.params import HYBRID, ALL_CWENOZ, ALL_MUSCL, PRESETS, VENKAT
+from .inputs.params import HYBRID, ALL_CWENOZ, ALL_MUSCL, PRESETS, VENKAT, CHARACTERISTIC
 
+CHAR = dict(cweno_vars=CHARACTERISTIC)
 VARIANTS = [(name, HYBRID, PRESETS[name]) for name in PRESETS] + \
            [("a_default_venkat", HYBRID, dict(PRESETS["a_default"], limiter=VENKAT)),
-            ("all_cwenoz", ALL_CWENOZ, {}), ("all_muscl", ALL_MUSCL, {})]
+            ("all_cwenoz", ALL_CWENOZ, {}), ("all_muscl", ALL_MUSCL, {})] + \
+           [(name + "_char", HYBRID, dict(PRESETS[name], **CHAR)) for name in PRESETS] + \
+           [("all_cwenoz_char", ALL_CWENOZ, CHAR)]
 
 
 def run_variant(w, name, mode, margins, t_end, cfl, prec, tune=True):
@@ -106,14 +111,15 @@ def main(argv=None):
         out[name] = rec
         print(json.dumps(rec), flush=True)
     summ = {}
-    d = out.get("a_default")
-    c = out.get("all_cwenoz")
-    if d and c and d["status"] == "ok" and c["status"] == "ok":
-        summ["cwenoz_time_over_default_hybrid"] = round(c["ms_total"] / d["ms_total"], 3)
-    if d and d["status"] == "ok":
-        for k, v in out.items():
-            if v["status"] == "ok":
-                summ[f"{k}_time_over_default"] = round(v["ms_total"] / d["ms_total"], 3)
+    for tag in ("", "_char"):
+        d = out.get("a_default" + tag)
+        c = out.get("all_cwenoz" + tag)
+        if d and c and d["status"] == "ok" and c["status"] == "ok":
+            summ[f"cwenoz{tag}_time_over_default{tag}"] = round(c["ms_total"] / d["ms_total"], 3)
+        if d and d["status"] == "ok":
+            for k, v in out.items():
+                if v["status"] == "ok" and k.endswith(tag) and (tag or not k.endswith("_char")):
+                    summ[f"{k}_time_over_default{tag}"] = round(v["ms_total"] / d["ms_total"], 3)
     print(json.dumps({"summary": summ}), flush=True)
     return out
 

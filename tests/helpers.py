@@ -121,3 +121,17 @@ def near_threshold(om, U, cells, tol):
         hp = np.abs(np.abs(pr - pb) - om.p.tvd_theta * np.abs(pb)) <= tol * np.abs(pb)
     flag |= np.any(valid & (hr | hp), axis=1)
     return flag
+
+
+def margin_tolerance(om, U, cells, tol):
+    """Per-cell bound on the error of near_margin when the states carry an
+    error of tol * S_v (S_v = max over cells of |U_v|, the state bar): the
+    margin divides an excursion by the cell's own scale max(|m|, |M|, R), so
+    the bound is tol * max over the cell's live variables of max(1, S_v /
+    that scale)."""
+    _, info = om.own_class(cells, U)
+    Sc = np.maximum(np.maximum(np.abs(info["m"]), np.abs(info["M"])), info["R"])
+    Sv = state_scale(U)[None, :]
+    with np.errstate(divide="ignore"):
+        ratio = np.where(info["R"] > 0, np.maximum(1.0, Sv / Sc), 1.0)
+    return tol * ratio.max(1)

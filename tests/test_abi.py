@@ -125,19 +125,20 @@ def test_every_buffer_argument_is_checked_before_the_abi():
     u8 = lambda *s: torch.zeros(s, dtype=torch.uint8)
     good_u, good_cls, good_fs = f64(nv, N), u8(N), f64(ng, nv, N)
     bad = {
-        "dtype": (f64(nv, N).float(), u8(N).int(), f64(ng, nv, N).float()),
-        "shape": (f64(nv, N + 1), u8(N - 1), f64(ng - 1, nv, N)),
-        "contiguous": (f64(N, nv).t(), u8(2 * N)[::2], f64(ng, N, nv).transpose(1, 2)),
-        "CUDA": (good_u, good_cls, good_fs),   # right layout, host memory
+        "dtype": (f64(nv, N).float(), u8(N).int(), f64(ng, nv, N).float(), f64(N).float()),
+        "shape": (f64(nv, N + 1), u8(N - 1), f64(ng - 1, nv, N), f64(N + 1)),
+        "contiguous": (f64(N, nv).t(), u8(2 * N)[::2], f64(ng, N, nv).transpose(1, 2), f64(2 * N)[::2]),
+        "CUDA": (good_u, good_cls, good_fs, f64(N)),   # right layout, host memory
     }
 
-    def calls(u, cls, fs):
+    def calls(u, cls, fs, mg):
         """(name, thunk) for each buffer argument of every entry point, the
         buffer under test in that argument and well-formed CPU tensors
         elsewhere (U is checked first, so it is the bad one or good)."""
         yield "U", lambda: ctx.reconstruct(u)
         yield "reconstruct face_states", lambda: ctx.reconstruct(good_u, face_states=fs)
         yield "reconstruct cell_class", lambda: ctx.reconstruct(good_u, cell_class=cls)
+        yield "reconstruct near_margin", lambda: ctx.reconstruct(good_u, near_margin=mg)
         yield "residual R", lambda: ctx.residual(good_u, R=u)
         yield "residual face_states", lambda: ctx.residual(good_u, face_states=fs)
         yield "residual cell_class", lambda: ctx.residual(good_u, cell_class=cls)
@@ -150,8 +151,8 @@ def test_every_buffer_argument_is_checked_before_the_abi():
         yield "rk_stage out", lambda: ctx.rk_stage(u, 1.0, good_u)
         yield "rk_stage U1", lambda: ctx.rk_stage(good_u, 1.0, good_u, 1.0, u)
 
-    for what, (u, cls, fs) in bad.items():
-        for name, thunk in calls(u, cls, fs):
+    for what, (u, cls, fs, mg) in bad.items():
+        for name, thunk in calls(u, cls, fs, mg):
             with pytest.raises(hfv.HfvError) as ei:
                 thunk()
             msg = str(ei.value)

@@ -58,3 +58,21 @@ def test_scope_byte_model_per_cell():
             sb = bm.s_per_kernel(mode, cls, False)
             mb = bm.per_kernel(mode, cls, False, False)
             assert sum(sb.values()) <= sum(mb.values())
+
+
+def test_fp32_flips_split_by_margin():
+    """A flip in a cell next to a near-threshold cell is flagged; a flip far
+    from one is not."""
+    n, ngpc, nvar = 6, 2, 1
+    fs = np.zeros((ngpc, nvar, n))
+    ngp = np.full(n, 2)
+    cls64 = np.zeros(n, np.uint8)
+    cls32 = cls64.copy()
+    cls32[[1, 4]] = 1
+    margin = np.full(n, 0.3)
+    margin[0] = 1e-7                            # cell 0 near a threshold; cell 1 its neighbour
+    face_cells = np.array([[0, 1], [1, 2], [2, 3], [3, 4], [4, 5], [5, -1]])
+    out = bench.fp32_error((fs, cls64, margin), fs.astype(np.float32), cls32, ngp, np.ones((n, nvar)),
+                           face_cells)
+    assert out["fp32_class_flips"] == 2 and out["fp32_flips_unflagged"] == 1
+    assert out["cells_margin_le_1e-6"] == 1

@@ -155,3 +155,30 @@ def test_c4_block_order_does_not_change_results(hfv, small, cfg):
     assert torch.equal(out[0][0], out[1][0])
     assert torch.equal(out[0][2], out[1][2])
     ctx.close()
+
+
+def test_c4_small_near_margin(hfv, small):
+    """near_margin on the mixed 3D box (four element types, ragged Gauss-point
+    counts) under two linear mappings equals the oracle's in FP64, to the
+    state bar 1e-12 carried through the margin's local normalisation
+    (helpers.margin_tolerance)."""
+    from helpers import margin_tolerance
+    w, om = small
+    N = w.mesh.n_cells
+    ref = om.near_margin(np.arange(N), w.U)
+    tol = margin_tolerance(om, w.U, np.arange(N), 1e-12)
+    ctx = hfv.Context(w.mesh, w.stencils, w.params, 64)
+    Ud = to_dev(w.U, torch.float64)
+    for split, ll in ((0, 5), (2, 8)):
+        ctx.set_launch(linear_split=split, linear_lanes=ll)
+        mg = torch.empty(N, dtype=torch.float64, device="cuda")
+        ctx.reconstruct(Ud, near_margin=mg)
+        torch.cuda.synchronize()
+        got = mg.cpu().numpy()
+        fin = np.isfinite(ref)
+        assert np.array_equal(np.isfinite(got), fin)
+        err = float(np.abs(got[fin] - ref[fin]).max())
+        worst = float((np.abs(got[fin] - ref[fin]) / tol[fin]).max())
+        print(f"split {split}: margin error {err:.2e}, largest error / bound {worst:.2f}", flush=True)
+        assert worst <= 1.0
+    ctx.close()

@@ -1,0 +1,167 @@
+"""Parity of the launches the benchmark times, against the FP64 oracle.
+
+* The 85,197-cell mixed 2D mesh (r = 3, four-quadrant Riemann data with 1 %
+  noise) in full, under the configuration the autotuner picks on it, the
+  benchmark's procedure: every cell's class, every face Gauss-point state and
+  every residual entry, FP64 and FP32.
+* The launches the autotuner picked on that mesh in earlier benchmark runs,
+  set explicitly, on its 64 x 64 layout (every cell).
+* The ~1M-cell mixed tetrahedron / pyramid / prism / hexahedron box under its
+  tuned FP32 launch: sampled cells of every element type.
+
+Bars as in the other parity tests: FP64 classes bit-exact, states within
+1e-12 of max(|x_ref|, S_v), residuals within 1e-11 of the variable's largest
+|R|; FP32 states within 1e-5, class flips only in cells within 1e-6 of a
+threshold or their face neighbours (states of flipped cells excluded).
+"""
+import numpy as np
+import pytest
+
+from helpers import state_scale, rel_err, near_threshold, gpu_cell_values, oracle_cell_values, states_err
+from oracle import OracleModel, flux
+from paper_2510_25906_amd.inputs import configs
+from paper_2510_25906_amd.inputs.mesh import TET, PYR, PRISM, HEX
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def hfv():
+    from paper_2510_25906_amd import hfv as H
+    H.load()
+    assert torch.cuda.is_available()
+    return H
+
+
+def to_dev(U, dtype):
+    return torch.tensor(np.ascontiguousarray(U.T), dtype=dtype, device="cuda")
+
+
+def dilated(om, flags):
+    nb = om.nbr
+    return flags | np.array([flags[nb[c][nb[c] >= 0]].any() for c in range(len(flags))])
+
+
+def check_all_cells(ctx, w, om, ref, prec, label):
+    """Residual with face states and classes on every cell against the
+    oracle's (R, face states, classes) in `ref`."""
+    R_o, fs_o, cls_o = ref
+    N = w.mesh.n_cells
+    Ud = to_dev(w.U, torch.float64 if prec == 64 else torch.float32)
+    fs = ctx.new_face_states()
+    cls = torch.empty(N, dtype=torch.uint8, device="cuda")
+    R = ctx.residual(Ud, face_states=fs, cell_class=cls)
+    torch.cuda.synchronize()
+    cls_g = cls.cpu().numpy()
+    S = state_scale(w.U)
+    if prec == 64:
+        bad = np.nonzero(cls_g != cls_o)[0]
+        es = states_err(fs, fs_o, om.geo, S)
+        er = rel_err(R.cpu().numpy(), R_o, np.abs(R_o).max(1)[:, None])
+        print(f"{label}: launch {ctx.get_launch()}, classes {np.bincount(cls_g, minlength=4)}, "
+              f"state error {es:.2e}, residual error {er:.2e}", flush=True)
+        assert bad.size == 0, bad[:20]
+        assert es <= 1e-12 and er <= 1e-11
+    else:
+        cells = np.arange(N)
+        flip = cls_g != cls_o
+        flags = dilated(om, near_threshold(om, w.U, cells, 1e-6)) if flip.any() else np.zeros(N, bool)
+        fv_g = gpu_cell_values(fs.cpu().numpy(), om.geo, cells)
+        fv_o = oracle_cell_values(fs_o, om.geo, cells)
+        es = rel_err(fv_g[~flip], fv_o[~flip], S[None, None, :])
+        print(f"{label}: launch {ctx.get_launch()}, flips {int(flip.sum())} (unflagged "
+              f"{int((flip & ~flags).sum())}), state error {es:.2e}", flush=True)
+        assert not np.any(flip & ~flags), np.nonzero(flip & ~flags)[0][:10]
+        assert es <= 1e-5
+
+
+@pytest.fixture(scope="module")
+def c2_full():
+    w = configs.c2_riemann(256, 3)
+    om = OracleModel(w.mesh, w.stencils, w.params)
+    ref = flux.residual(om, w.U)
+    assert not near_threshold(om, w.U, np.arange(w.mesh.n_cells), 1e-12).any()
+    return w, om, ref
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_c2_full_size_autotuned(hfv, c2_full, prec):
+    """Every cell of the benchmark mesh under the autotuner's choice."""
+    w, om, ref = c2_full
+    ctx = hfv.Context(w.mesh, w.stencils, w.params, prec)
+    ctx.autotune(to_dev(w.U, torch.float64 if prec == 64 else torch.float32), reps=3)
+    check_all_cells(ctx, w, om, ref, prec, f"c2 full fp{prec} tuned")
+    ctx.close()
+
+
+# Launches the autotuner picked for the hybrid residual on the benchmark
+# mesh: FP64 two lanes per cell in the class-list kernels, the linear kernel
+# split over stencil members on two lanes, CWENOZ refitting, MUSCL on four
+# lanes; FP32 four lanes, the variable-split linear kernel on two lanes,
+# CWENOZ reusing the kept fit.
+HEADLINE_LAUNCHES = [
+    (64, dict(lanes=2, linear_split=1, linear_lanes=2, cwenoz_reuse=0, muscl_lanes=4, block=256,
+              list_blocks=4096)),
+    (32, dict(lanes=4, linear_split=0, linear_lanes=2, cwenoz_reuse=1, muscl_lanes=0, block=256,
+              list_blocks=0)),
+    (64, dict(lanes=2, linear_split=2, linear_lanes=8, cwenoz_reuse=0, muscl_lanes=0, block=128,
+              list_blocks=4096, xcd_remap=1)),
+]
+
+
+@pytest.fixture(scope="module")
+def c2_small():
+    w = configs.c2_riemann(64, 3)
+    om = OracleModel(w.mesh, w.stencils, w.params)
+    ref = flux.residual(om, w.U)
+    return w, om, ref
+
+
+@pytest.mark.parametrize("prec,cfg", HEADLINE_LAUNCHES)
+def test_c2_headline_launches(hfv, c2_small, prec, cfg):
+    w, om, ref = c2_small
+    counts = np.bincount(ref[2], minlength=4)
+    assert counts[1] > 0 and counts[2] > 0
+    ctx = hfv.Context(w.mesh, w.stencils, w.params, prec)
+    ctx.set_launch(**cfg)
+    check_all_cells(ctx, w, om, ref, prec, f"c2 64x64 fp{prec}")
+    ctx.close()
+
+
+def test_c4_full_size_sampled_tuned(hfv):
+    """The ~1M-cell mixed box under its tuned FP32 launch (and FP64 under its
+    own): sampled cells of every element type, both classes and states."""
+    w = configs.c4_mixed("full", workers=8)
+    om = OracleModel(w.mesh, w.stencils, w.params)
+    rng = np.random.default_rng(13)
+    ct = w.mesh.cell_type
+    cells = np.unique(np.concatenate([rng.choice(np.nonzero(ct == t)[0], 60, replace=False)
+                                      for t in (TET, PYR, PRISM, HEX)]))
+    fv_o, cls_o = om.reconstruct_cells(cells, w.U)
+    print(f"c4 full: N={w.mesh.n_cells}, sampled {cells.size}, classes {np.bincount(cls_o, minlength=4)}",
+          flush=True)
+    assert (cls_o == 1).sum() > 0 and (cls_o == 2).sum() > 0
+    S = state_scale(w.U)
+    for prec in (32, 64):
+        ctx = hfv.Context(w.mesh, w.stencils, w.params, prec)
+        Ud = to_dev(w.U, torch.float64 if prec == 64 else torch.float32)
+        ctx.autotune(Ud, reps=2)
+        fs, cls = ctx.reconstruct(Ud)
+        torch.cuda.synchronize()
+        cls_g = cls.cpu().numpy()[cells]
+        flip = cls_g != cls_o
+        if prec == 64:
+            assert not near_threshold(om, w.U, cells, 1e-12).any()
+            assert not flip.any(), cells[flip][:10]
+        else:
+            flags = near_threshold(om, w.U, cells, 1e-6)
+            assert not np.any(flip & ~flags), cells[flip & ~flags][:10]
+        fv_g = gpu_cell_values(fs.cpu().numpy(), om.geo, cells)
+        e = rel_err(fv_g[~flip], fv_o[~flip], S[None, None, :])
+        print(f"c4 full fp{prec}: launch {ctx.get_launch()}, flips {int(flip.sum())}, state error {e:.2e}",
+              flush=True)
+        assert e <= (1e-12 if prec == 64 else 1e-5)
+        del fs, cls
+        ctx.close()
+        torch.cuda.empty_cache()

@@ -301,3 +301,157 @@ def test_graph_replays_match_eager(hfv, c1, prec):
         assert torch.equal(R_graph, R_eager), k
         assert torch.equal(cls_graph, cls_eager), k
     ctx.close()
+
+
+@pytest.mark.parametrize("mode", [HYBRID, ALL_LINEAR, ALL_CWENOZ])
+def test_c1_near_margin_matches_oracle(hfv, c1, mode):
+    """near_margin in FP64 under every linear mapping equals the oracle's to
+    1e-12 (it is a relative distance, of order 1e-3 to 1 here); +inf exactly
+    where the oracle has no decision."""
+    w, om0 = c1
+    p = w.params.with_(scheme_mode=mode)
+    om = OracleModel(w.mesh, w.stencils, p)
+    om._tab = om0._tab
+    N = w.mesh.n_cells
+    ref = om.near_margin(np.arange(N), w.U)
+    ctx = hfv.Context(w.mesh, w.stencils, p, 64)
+    Ud = to_dev(w.U, torch.float64)
+    for split, ll in ((0, 1), (0, 4), (1, 2), (1, 8), (2, 4)):
+        ctx.set_launch(linear_split=split, linear_lanes=ll)
+        mg = torch.full((N,), -1.0, dtype=torch.float64, device="cuda")
+        ctx.reconstruct(Ud, near_margin=mg)
+        torch.cuda.synchronize()
+        got = mg.cpu().numpy()
+        fin = np.isfinite(ref)
+        assert np.array_equal(np.isfinite(got), fin), (split, ll)
+        err = float(np.abs(got[fin] - ref[fin]).max()) if fin.any() else 0.0
+        print(f"mode {mode} split {split} lanes {ll}: margin error {err:.2e}, min margin "
+              f"{ref[fin].min() if fin.any() else np.inf:.3e}", flush=True)
+        assert err <= 1e-12
+    ctx.close()
+
+
+def test_fp32_flips_only_where_the_library_margin_is_small(hfv):
+    """FP32 class flips against the FP64 path occur only in cells whose FP64
+    near_margin (or a face neighbour's) is within 1e-6, on the 64 x 64
+    mixed Riemann mesh with its seeded 1 % noise."""
+    w = configs.c2_riemann(64, 3)
+    om = OracleModel(w.mesh, w.stencils, w.params)
+    N = w.mesh.n_cells
+    out = {}
+    for prec in (64, 32):
+        dt = torch.float64 if prec == 64 else torch.float32
+        ctx = hfv.Context(w.mesh, w.stencils, w.params, prec)
+        mg = torch.empty(N, dtype=dt, device="cuda")
+        fs, cls = ctx.reconstruct(to_dev(w.U, dt), near_margin=mg)
+        torch.cuda.synchronize()
+        out[prec] = (cls.cpu().numpy(), mg.double().cpu().numpy())
+        ctx.close()
+    flip = out[64][0] != out[32][0]
+    small = out[64][1] <= 1e-6
+    flagged = dilated_flags(om, small, np.arange(N))
+    print(f"flips {flip.sum()}, cells with margin <= 1e-6: {small.sum()}", flush=True)
+    assert not np.any(flip & ~flagged)
+    # the FP32 margins track the FP64 ones to FP32 rounding of the states
+    fin = np.isfinite(out[64][1]) & np.isfinite(out[32][1])
+    assert fin.sum() > 0.99 * N
+    assert np.abs(out[32][1][fin] - out[64][1][fin]).max() <= 1e-4
+
+
+@pytest.mark.parametrize("r", [5, 6])
+def test_2d_high_order_matches_oracle(hfv, r):
+    """Degrees 5 and 6 in 2D (Table 1's P7 runs r = 6): K = 20 and 27
+    unknowns, M = 40 and 54 stencil members.  Periodic triangles with the
+    density jump, FP64, hybrid and all-CWENOZ: classes bit-exact, states
+    within 1e-12, residual within 1e-11; FP32 hybrid with the flip allowance."""
+    w = configs.c1_density_jump(24, r)
+    N = w.mesh.n_cells
+    for mode in (HYBRID, ALL_CWENOZ):
+        p = w.params.with_(scheme_mode=mode)
+        om = OracleModel(w.mesh, w.stencils, p)
+        R_o, fs_o, cls_o = flux.residual(om, w.U)
+        print(f"r={r} mode={mode}: classes {np.bincount(cls_o, minlength=4)}", flush=True)
+        assert not near_threshold(om, w.U, np.arange(N), 1e-12).any()
+        for prec in (64, 32):
+            ctx = hfv.Context(w.mesh, w.stencils, p, prec)
+            for cfg in (dict(linear_split=0, linear_lanes=1, lanes=1),
+                        dict(linear_split=2, linear_lanes=4, lanes=4, cwenoz_reuse=1, list_blocks=0)):
+                ctx.set_launch(**cfg)
+                fs = ctx.new_face_states()
+                cls = torch.empty(N, dtype=torch.uint8, device="cuda")
+                Ud = to_dev(w.U, torch.float64 if prec == 64 else torch.float32)
+                R = ctx.residual(Ud, face_states=fs, cell_class=cls)
+                torch.cuda.synchronize()
+                cls_g = cls.cpu().numpy()
+                S = state_scale(w.U)
+                if prec == 64:
+                    assert np.array_equal(cls_g, cls_o)
+                    es = states_err(fs, fs_o, om.geo, S)
+                    er = rel_err(R.cpu().numpy(), R_o, np.abs(R_o).max(1)[:, None])
+                    print(f"  fp64 {cfg}: state error {es:.2e}, residual error {er:.2e}", flush=True)
+                    assert es <= 1e-12 and er <= 1e-11
+                else:
+                    cells = np.arange(N)
+                    flip = cls_g != cls_o
+                    flags = dilated_flags(om, near_threshold(om, w.U, cells, 1e-6), cells)
+                    assert not np.any(flip & ~flags)
+                    fv_g = gpu_cell_values(fs.cpu().numpy(), om.geo, cells)
+                    fv_o = oracle_cell_values(fs_o, om.geo, cells)
+                    e = rel_err(fv_g[~flip], fv_o[~flip], S[None, None, :])
+                    print(f"  fp32 {cfg}: flips {flip.sum()}, state error {e:.2e}", flush=True)
+                    assert e <= 1e-5
+            ctx.close()
+
+
+FUSE_CASES = {
+    "c1_r2": lambda: configs.c1_density_jump(32, 2),
+    "c2_r3": lambda: configs.c2_riemann(64, 3),
+}
+
+
+@pytest.mark.parametrize("case", sorted(FUSE_CASES))
+@pytest.mark.parametrize("lanes", [1, 2, 4])
+def test_cwenoz_fused_into_linear_pass(hfv, case, lanes):
+    """cwenoz_fuse: CWENOZ of the own-flagged cells inside the variable-split
+    linear pass, the list pass for the cells tagging adds; classes bit-exact,
+    states within 1e-12 and the residual within 1e-11 of the oracle (FP64),
+    the FP32 bar with the flip allowance; the results agree with the unfused
+    launch to rounding."""
+    w = FUSE_CASES[case]()
+    om = OracleModel(w.mesh, w.stencils, w.params)
+    R_o, fs_o, cls_o = flux.residual(om, w.U)
+    N = w.mesh.n_cells
+    assert (cls_o == 1).sum() > 0
+    S = state_scale(w.U)
+    for prec in (64, 32):
+        ctx = hfv.Context(w.mesh, w.stencils, w.params, prec)
+        ctx.set_launch(linear_split=0, linear_lanes=lanes, lanes=lanes, cwenoz_fuse=1, list_blocks=64)
+        assert ctx.get_launch()["cwenoz_fuse"] == 1
+        Ud = to_dev(w.U, torch.float64 if prec == 64 else torch.float32)
+        fs = ctx.new_face_states()
+        cls = torch.empty(N, dtype=torch.uint8, device="cuda")
+        R = ctx.residual(Ud, face_states=fs, cell_class=cls)
+        torch.cuda.synchronize()
+        listed = ctx.query("COUNT_CWENOZ")
+        cls_g = cls.cpu().numpy()
+        print(f"{case} fp{prec} lanes {lanes}: CWENOZ cells {int((cls_g == 1).sum())}, listed {listed}", flush=True)
+        assert listed < (cls_g == 1).sum()
+        if prec == 64:
+            assert np.array_equal(cls_g, cls_o)
+            es = states_err(fs, fs_o, om.geo, S)
+            er = rel_err(R.cpu().numpy(), R_o, np.abs(R_o).max(1)[:, None])
+            print(f"  state error {es:.2e}, residual error {er:.2e}", flush=True)
+            assert es <= 1e-12 and er <= 1e-11
+        else:
+            cells = np.arange(N)
+            flip = cls_g != cls_o
+            flags = dilated_flags(om, near_threshold(om, w.U, cells, 1e-6), cells) if flip.any() \
+                else np.zeros(N, bool)
+            assert not np.any(flip & ~flags)
+            e = rel_err(gpu_cell_values(fs.cpu().numpy(), om.geo, cells)[~flip],
+                        oracle_cell_values(fs_o, om.geo, cells)[~flip], S[None, None, :])
+            assert e <= 1e-5
+        # the split and unknown mappings cannot fuse
+        with pytest.raises(hfv.HfvError):
+            ctx.set_launch(linear_split=1, linear_lanes=2)
+        ctx.close()

@@ -111,23 +111,60 @@ def test_vortex_convergence(hfv):
         print(f"r={r}: L2 orders {np.round(o, 2)}", flush=True)
         assert np.all(np.diff(e2) < 0)
         assert o[-1] >= r + 1 - 0.6, (r, o)
-    # against the printed Table 1 (its meshes are not available: a band, not parity)
+    print("r  n  steps  linear Linf  L2  |  CWENOZ Linf  L2  |  max |hybrid - linear|")
+    for row in table:
+        print("%d %4d %5d  %.3e %.3e | %.3e %.3e | %.1e" % row, flush=True)
+    check_table1({(row[0], row[1]): row[4] for row in table}, (2, 4), band=(0.5, 1.5))
+
+
+def table1_gold():
     import os
     gold = {}
     for line in open(os.path.join(os.path.dirname(__file__), "golden", "vortex_table1_linear_l2.txt")):
         if line.strip() and not line.startswith("#"):
             _, r, n, e = line.split()
             gold[(int(r), int(n))] = float(e)
-    ours = {(row[0], row[1]): row[4] for row in table}
+    return gold
+
+
+def check_table1(ours, orders, band, order_tol=0.3):
+    """Our linear L2 errors against the printed Table 1 (its meshes are not
+    available: a band, not parity) and the final orders within order_tol."""
+    gold = table1_gold()
     for (r, n), e in gold.items():
-        assert 0.5 * e <= ours[(r, n)] <= 1.5 * e, (r, n, ours[(r, n)], e)
-    for r in (2, 4):
+        if r in orders:
+            print(f"r={r} n={n}: ours {ours[(r, n)]:.3e}, Table 1 {e:.3e}, ratio {ours[(r, n)] / e:.2f}", flush=True)
+            assert band[0] * e <= ours[(r, n)] <= band[1] * e, (r, n, ours[(r, n)], e)
+    for r in orders:
         o_ours = np.log2(ours[(r, 64)] / ours[(r, 128)])
         o_gold = np.log2(gold[(r, 64)] / gold[(r, 128)])
-        assert abs(o_ours - o_gold) <= 0.3, (r, o_ours, o_gold)
-    print("r  n  steps  linear Linf  L2  |  CWENOZ Linf  L2  |  max |hybrid - linear|")
-    for row in table:
-        print("%d %4d %5d  %.3e %.3e | %.3e %.3e | %.1e" % row, flush=True)
+        print(f"r={r}: final order {o_ours:.2f}, Table 1 {o_gold:.2f}", flush=True)
+        assert abs(o_ours - o_gold) <= order_tol, (r, o_ours, o_gold)
+
+
+def test_vortex_convergence_p7(hfv):
+    """Table 1's P7 row (r = 6, 7th order): the linear scheme's L2 errors on
+    16 to 128 edges per side, the hybrid equal to it to the four digits
+    Table 1 prints (its states within 1e-9: the few cells the NAD tags carry
+    the linear weights to rounding), order approaching 7 (the paper: 6.41
+    from 64 to 128 edges; within 0.3).  Our meshes split every quad along one
+    diagonal; the paper's triangulations are not available, and at this
+    order the errors depend on them more: the band is 0.4 to 1.5 times the
+    printed values (measured 0.46 to 0.91)."""
+    ns = (16, 32, 64, 128)
+    ours = {}
+    for n in ns:
+        w = configs.vortex_2d(n, 6)
+        l2, li, U_lin, steps = vortex_errors(hfv, w, ALL_LINEAR)
+        hl2, _, U_hyb, _ = vortex_errors(hfv, w, HYBRID)
+        diff = np.abs(U_hyb - U_lin).max()
+        print(f"r=6 n={n}: {steps} steps, linear L2 {l2:.4e} Linf {li:.4e}, hybrid L2 {hl2:.4e}, "
+              f"hybrid - linear max {diff:.1e}", flush=True)
+        assert diff <= 1e-9 and abs(hl2 - l2) <= 1e-4 * l2, n
+        ours[(6, n)] = l2
+    e2 = [ours[(6, n)] for n in ns]
+    assert np.all(np.diff(e2) < 0)
+    check_table1(ours, (6,), band=(0.4, 1.5))
 
 
 @pytest.mark.parametrize("prec", [64, 32])

@@ -489,3 +489,114 @@ def test_venkatakrishnan_muscl_is_exact_on_affine_data_without_limiting():
     om5 = OracleModel(w.mesh, w.stencils, w.params.with_(scheme_mode=ALL_MUSCL, limiter=VENKAT))
     _, info5 = om5.muscl(cells, U)
     assert np.all(info5["theta"] > 0) and np.all(info5["theta"] <= 1.0)
+
+
+# --- near_margin: distance of each class decision to its threshold -----------
+
+def test_near_margin_free_stream_closed_form():
+    """Constant state: no variable has a range (no NAD threshold), dU = 0 so
+    the deactivation margin is |0 - thr| / thr = 1, and every Gauss point
+    equals the average so the Harten margin is |0 - theta s| / s = theta."""
+    w = configs.c1_density_jump(8, 2)
+    U = np.tile(fields.prim_to_cons(np.array([1.3, 0.4, -0.2, 2.0])), (w.mesh.n_cells, 1))
+    om = OracleModel(w.mesh, w.stencils, w.params)
+    parts = om.near_margin(np.arange(w.mesh.n_cells), U, parts=True)
+    assert np.all(np.isinf(parts["nad"]))
+    assert np.all(parts["deact"] == 1.0)
+    assert np.abs(parts["harten"] - 0.9).max() <= 1e-15
+    assert np.abs(parts["total"] - 0.9).max() <= 1e-15
+    for mode in (ALL_CWENOZ, ALL_MUSCL):
+        om.p = w.params.with_(scheme_mode=mode)
+        assert np.all(np.isinf(om.near_margin(np.arange(10), w.U)))
+
+
+def _margin_case():
+    w = configs.c1_density_jump(16, 2)
+    # delta_w = 0.1 R and delta_m = 0.5 R exactly (no absolute floors), so a
+    # change of beta moves a threshold by a known amount
+    p = w.params.with_(alpha_w=0.0, beta_w=0.1, alpha_m=0.0, beta_m=0.5)
+    return w, p
+
+
+def test_near_margin_nad_part_by_threshold_shifts():
+    """Shifting a variable's NAD threshold toward its excursion d by (1 + 1e-6)
+    times the margin changes that variable's class; by (1 - 1e-6) times it,
+    no shift of either threshold does (the margin is the distance from d to
+    the nearer threshold, in units of S = max(|m|, |M|, R))."""
+    w, p = _margin_case()
+    om = OracleModel(w.mesh, w.stencils, p)
+    cells = np.arange(w.mesh.n_cells)
+    parts = om.near_margin(cells, w.U, parts=True)
+    _, info = om.own_class(cells, w.U)
+    nad = parts["nad"]
+    live = np.isfinite(nad).any(1)
+    assert live.sum() > 50
+    assert set(np.unique(info["cls_v"][live])) >= {0, 1, 2}
+    rng = np.random.default_rng(0)
+    for c in rng.choice(np.nonzero(live)[0], 40, replace=False):
+        v = int(np.argmin(nad[c]))
+        mu = nad[c, v]
+        m, M, R = info["m"][c, v], info["M"][c, v], info["R"][c, v]
+        S = max(abs(m), abs(M), R)
+        base = info["cls_v"][c, v]
+        changed = []
+        for scale in (1 - 1e-6, 1 + 1e-6):
+            db = mu * S / R * scale          # threshold shift mu S (scaled), as a change of beta
+            flips = False
+            for key in ("beta_w", "beta_m"):
+                for sgn in (-1.0, 1.0):
+                    om.p = p.with_(**{key: getattr(p, key) + sgn * db})
+                    _, inf2 = om.own_class(np.array([c]), w.U)
+                    flips |= inf2["cls_v"][0, v] != base
+            changed.append(flips)
+        om.p = p
+        assert changed == [False, True], (c, v, mu, changed)
+
+
+def test_near_margin_deactivation_part_by_kappa_shift():
+    """The deactivation decision dU < (kappa h)^n flips when the threshold
+    moves by (1 + 1e-6) times the margin toward dU, and not at (1 - 1e-6)."""
+    w, p = _margin_case()
+    om = OracleModel(w.mesh, w.stencils, p)
+    cells = np.arange(w.mesh.n_cells)
+    parts = om.near_margin(cells, w.U, parts=True)
+    _, info = om.own_class(cells, w.U)
+    assert info["deact"].any() and (~info["deact"]).any()
+    n = p.n_exp
+    for c in np.concatenate([np.nonzero(info["deact"])[0][:15], np.nonzero(~info["deact"])[0][:15]]):
+        mu = parts["deact"][c]
+        got = []
+        for scale in (1 - 1e-6, 1 + 1e-6):
+            # deactivated (thr > dU): lower thr to thr (1 - mu s); active: raise it to thr / (1 - mu s)
+            f = (1 - mu * scale) if info["deact"][c] else 1 / (1 - mu * scale)
+            om.p = p.with_(kappa=p.kappa * f ** (1 / n))
+            _, inf2 = om.own_class(np.array([c]), w.U)
+            got.append(bool(inf2["deact"][0] != info["deact"][c]))
+        om.p = p
+        assert got == [False, True], (c, mu, got)
+
+
+def test_near_margin_harten_part_by_theta_shift():
+    """For cells whose linear candidate passes the Harten check, the margin
+    is theta minus the largest relative density / pressure deviation: the
+    check still passes with theta lowered by (1 - 1e-6) times the margin and
+    fails when it is lowered by (1 + 1e-6) times it."""
+    w, p = _margin_case()
+    p = p.with_(scheme_mode=ALL_LINEAR)
+    om = OracleModel(w.mesh, w.stencils, p)
+    cells = np.arange(w.mesh.n_cells)
+    parts = om.near_margin(cells, w.U, parts=True)
+    assert np.array_equal(parts["total"], parts["harten"])
+    _, fv, _ = om.linear(cells, w.U)
+    ngp = om.geo.c_ngp[cells]
+    ok = om.harten_ok(fv, w.U[cells], ngp)
+    assert ok.sum() > 100
+    rng = np.random.default_rng(1)
+    for c in rng.choice(np.nonzero(ok)[0], 40, replace=False):
+        mu = parts["harten"][c]
+        got = []
+        for scale in (1 - 1e-6, 1 + 1e-6):
+            om.p = p.with_(tvd_theta=p.tvd_theta - mu * scale)
+            got.append(bool(om.harten_ok(fv[c:c + 1], w.U[c:c + 1], ngp[c:c + 1])[0]))
+        om.p = p
+        assert got == [True, False], (c, mu, got)
