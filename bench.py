@@ -203,6 +203,15 @@ class ByteModel:
         return {k: int(v) for k, v in out.items()}
 
 
+def kernel_name(slot, launch):
+    """The kernel a timing slot runs under this launch configuration."""
+    if slot == "flux" and launch.get("fused_residual"):
+        return FUSED_NAME
+    if slot == "linear":
+        return ("k_linear", "k_linear_ms", "k_linear_ks")[launch.get("linear_split", 0)]
+    return KERNELS[slot]
+
+
 def time_steps(fn, steps, warmup, torch):
     for _ in range(warmup):
         fn()
@@ -554,7 +563,7 @@ def measure(w, wl_tag, head_prec, variants, args, torch, hfv, probe, flush, extr
                 avg = k_ms / k_n
                 ach = sbyts[dominant] / (avg * 1e-3) / 1e9
                 ach_m = mbyts[dominant] / (avg * 1e-3) / 1e9
-                kname = FUSED_NAME if (dominant == "flux" and fused) else KERNELS[dominant]
+                kname = kernel_name(dominant, launch)
                 traffic = measured_traffic(kname, wl_tag)
                 roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,

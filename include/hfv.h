@@ -346,19 +346,11 @@ hfv_status hfv_copy_table(const hfv_ctx *ctx, int32_t which, void *host_dst, int
  *                   gathers share that XCD's L2; 0: plain block order
  *   muscl_lanes     lanes per cell of the MUSCL / first-order pass: 0 (the
  *                   same as lanes_per_cell), 1 or nvar (or 2 in 2D)
- *   cwenoz_fuse     1: in hybrid mode with conserved-variable CWENOZ, the
- *                   variable-split linear kernel (linear_split 0 only) runs
- *                   CWENOZ itself, from the fit in registers, on every cell
- *                   its NAD flags for CWENOZ (Section 2.3's central
- *                   polynomial is the linear candidate); the class-1 list
- *                   then holds only the cells that tagging adds, and flagged
- *                   cells that tagging raises to MUSCL are overwritten by the
- *                   MUSCL pass; cwenoz_reuse is then ignored; 0: off
  * hfv_set_launch validates every field (HFV_ERR_PARAM, nothing changed, on
  * an invalid one); hfv_get_launch reads the current configuration. */
 typedef struct {
   int32_t lanes_per_cell, block, list_blocks, linear_split, linear_lanes, cwenoz_reuse, fused_residual, xcd_remap,
-      muscl_lanes, cwenoz_fuse;
+      muscl_lanes;
 } hfv_launch;
 hfv_status hfv_set_launch(hfv_ctx *ctx, const hfv_launch *cfg);
 hfv_status hfv_get_launch(const hfv_ctx *ctx, hfv_launch *cfg);
@@ -368,8 +360,7 @@ hfv_status hfv_get_launch(const hfv_ctx *ctx, hfv_launch *cfg);
  * candidate launch configurations, searched one coordinate at a time (linear
  * kernel mapping; class-list kernel lanes, block and grid;
  * CWENOZ reuse in hybrid mode; fused or two-kernel residual; XCD block
- * order; MUSCL lanes in hybrid mode; CWENOZ fused into the linear pass, with
- * its lane count, in hybrid mode), and keeps the
+ * order; MUSCL lanes in hybrid mode), and keeps the
  * fastest (median of `reps`
  * timed calls after one untimed call, reps in [1, 1000]).  Synchronous; it
  * allocates and frees one residual-sized buffer.  `best` (may be NULL)

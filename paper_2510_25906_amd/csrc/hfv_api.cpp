@@ -275,9 +275,6 @@ hfv_status hfv_set_launch(hfv_ctx *ctx, const hfv_launch *c) {
   const int ml = c->muscl_lanes;
   if (!(ml == 0 || ml == 1 || ml == ctx->nvar || (ctx->dim == 2 && ml == 2)))
     return ctx->err = "muscl_lanes must be 0, 1 or nvar (or 2 in 2D)", HFV_ERR_PARAM;
-  if (c->cwenoz_fuse != 0 && c->cwenoz_fuse != 1) return ctx->err = "cwenoz_fuse must be 0 or 1", HFV_ERR_PARAM;
-  if (c->cwenoz_fuse && c->linear_split != 0)
-    return ctx->err = "cwenoz_fuse needs the variable split (linear_split 0)", HFV_ERR_PARAM;
   ctx->lanes = lanes;
   ctx->block = c->block;
   ctx->list_blocks = c->list_blocks;
@@ -287,7 +284,6 @@ hfv_status hfv_set_launch(hfv_ctx *ctx, const hfv_launch *c) {
   ctx->fused_residual = c->fused_residual;
   ctx->xcd_remap = c->xcd_remap;
   ctx->muscl_lanes = c->muscl_lanes;
-  ctx->cw_fuse = c->cwenoz_fuse;
   return HFV_OK;
 }
 
@@ -302,7 +298,6 @@ hfv_status hfv_get_launch(const hfv_ctx *ctx, hfv_launch *c) {
   c->fused_residual = ctx->fused_residual;
   c->xcd_remap = ctx->xcd_remap;
   c->muscl_lanes = ctx->muscl_lanes;
-  c->cwenoz_fuse = ctx->cw_fuse;
   return HFV_OK;
 }
 

@@ -24,7 +24,6 @@ struct HotArgs {
   int xcd;   // block ids remapped so each XCD takes one contiguous range (block_id)
   int limiter;  // HFV_LIM_*
   T *margin;    // [N] near_margin output of the linear pass, or null
-  bool fuse;    // CWENOZ of own-flagged cells inside the linear pass
 };
 
 // CWENOZ on characteristic variables (hfv_char.cpp) over the class-1 list,

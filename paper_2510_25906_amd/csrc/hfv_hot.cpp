@@ -33,164 +33,8 @@ __device__ inline void keep_fit(const HotArgs<T> &a, int cell, int v0, const T (
     for (int q = 0; q < VPL; ++q) a.coef[((long)k * NV + v0 + q) * a.N + cell] = co[k][q];
 }
 
-// CWENOZ of one cell from its central fit (Section 2.3): directional degree-1
-// fits, p_1, smoothness indicators and nonlinear weights (FP64), the combined
-// polynomial at the face Gauss points and the Harten check.  Writes the
-// cell's states (the first-order state at every point when the check fails)
-// and returns whether it passed.  co holds the central fit on entry and is
-// overwritten.  Shared by the class-list kernel and the linear kernel's fused
-// path.
+// K1: linear candidate, face states, NAD own class, Harten flag.
 template <int DIM, int R, typename T, int G>
-__device__ __forceinline__ bool cwenoz_cell(const HotArgs<T> &a, int cell, const Lane<G> &L,
-                                            const T (&u0)[(DIM + 2) / G], T (&co)[n_unknowns(DIM, R)][(DIM + 2) / G]) {
-  constexpr int NV = DIM + 2, K = n_unknowns(DIM, R), VPL = NV / G, NFM = nf_max(DIM), MD = 2 * DIM;
-  const int N = a.N, v0 = L.sub * VPL;
-  // directional degree-1 fits (Section 2.3)
-  const int nd = a.t.ndir[cell];
-  T ad[NFM][DIM][VPL];
-#pragma unroll
-  for (int s = 0; s < NFM; ++s) {
-#pragma unroll
-    for (int j = 0; j < DIM; ++j)
-#pragma unroll
-      for (int q = 0; q < VPL; ++q) ad[s][j][q] = (T)0;
-    // the guard also keeps the compiler from hoisting every stencil's loads
-    // at once, which would cost occupancy
-    if (s < nd) {
-#pragma unroll
-      for (int m = 0; m < MD; ++m) {
-        const int jc = a.t.dsten[((long)s * MD + m) * N + cell];
-        T du[VPL];
-#pragma unroll
-        for (int q = 0; q < VPL; ++q) du[q] = a.U[(long)(v0 + q) * N + jc] - u0[q];
-#pragma unroll
-        for (int j = 0; j < DIM; ++j) {
-          const T p = a.t.Pdir[(((long)s * DIM + j) * MD + m) * N + cell];
-#pragma unroll
-          for (int q = 0; q < VPL; ++q) ad[s][j][q] += p * du[q];
-        }
-      }
-    }
-  }
-  const T lam1 = (T)1 - (T)1 / a.lam1p;
-  const T lams = ((T)1 - lam1) / (T)nd;
-  // p_1 = (p_opt - sum lambda_s p_s) / lambda_1, in place
-#pragma unroll
-  for (int j = 0; j < DIM; ++j)
-#pragma unroll
-    for (int q = 0; q < VPL; ++q) {
-      T sdir = 0;
-#pragma unroll
-      for (int s = 0; s < NFM; ++s) sdir += ad[s][j][q];
-      co[j][q] = co[j][q] - lams * sdir;
-    }
-#pragma unroll
-  for (int k = 0; k < K; ++k)
-#pragma unroll
-    for (int q = 0; q < VPL; ++q) co[k][q] /= lam1;
-  // smoothness indicators SI = a^T OI a, accumulated in double, then the
-  // nonlinear weights and the CWENOZ coefficients omega_1 p_1 + sum_s
-  // omega_s p_s; one variable at a time keeps few doubles live
-  const double eps = (double)a.eps_w, b = (double)a.b_w;
-#pragma unroll
-  for (int q = 0; q < VPL; ++q) {
-    double si1 = 0, sis[NFM];
-#pragma unroll
-    for (int s = 0; s < NFM; ++s) sis[s] = 0;
-    int pidx = 0;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const double ck = (double)co[k][q];
-      double row = 0;
-#pragma unroll
-      for (int kq = k; kq < K; ++kq, ++pidx) {
-        const double o = (double)a.t.OI[(long)pidx * N + cell];
-        row += (kq == k ? o : 2.0 * o) * (double)co[kq][q];
-        if (kq < DIM) {
-#pragma unroll
-          for (int s = 0; s < NFM; ++s)
-            sis[s] += (kq == k ? o : 2.0 * o) * (double)ad[s][k][q] * (double)ad[s][kq][q];
-        }
-      }
-      si1 += ck * row;
-      // large K in FP64: keep each row's loads from being hoisted over the
-      // others (measured: spills otherwise; FP32 is faster without)
-      if constexpr (K > 20 && sizeof(T) == 8) __builtin_amdgcn_sched_barrier(0);
-    }
-    double tau = 0;
-#pragma unroll
-    for (int s = 0; s < NFM; ++s)
-      if (s < nd) tau += fabs(sis[s] - si1);
-    tau /= (double)nd;
-    const bool zform = a.form == HFV_WENOZ_POW;
-    const double taub = zform ? 0.0 : powb(tau, b, a.ib_w);
-    const double w1 = (double)lam1 * (1.0 + (zform ? powb(tau / (eps + si1), b, a.ib_w) : taub / (eps + si1)));
-    double tot = w1, ws[NFM];
-#pragma unroll
-    for (int s = 0; s < NFM; ++s) {
-      ws[s] = 0;
-      if (s < nd)
-        ws[s] = (double)lams * (1.0 + (zform ? powb(tau / (eps + sis[s]), b, a.ib_w) : taub / (eps + sis[s])));
-      tot += ws[s];
-    }
-    const double it = 1.0 / tot;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      double v = w1 * it * (double)co[k][q];
-      if (k < DIM) {
-#pragma unroll
-        for (int s = 0; s < NFM; ++s) v += ws[s] * it * (double)ad[s][k][q];
-      }
-      co[k][q] = (T)v;
-    }
-  }
-  // face states, Harten check
-  T all0[NV];
-  group_state<NV, G, T>(u0, all0, L.base);
-  const T rho_b = all0[0];
-  const T p_b = pressure<NV, T>(all0, a.gamma);
-  T psb[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k) psb[k] = a.t.psibar[(long)k * N + cell];
-  const int ng = a.t.ngp[cell];
-  bool hok = true;
-  for (int g = 0; g < ng; ++g) {
-    T xi[DIM];
-#pragma unroll
-    for (int j = 0; j < DIM; ++j) xi[j] = a.t.gpxi[((long)g * DIM + j) * N + cell];
-    T phi[K];
-    basis_at<DIM, R, T>(xi, psb, phi);
-    T val[VPL];
-#pragma unroll
-    for (int q = 0; q < VPL; ++q) {
-      T s = 0;
-#pragma unroll
-      for (int k = 0; k < K; ++k) s += co[k][q] * phi[k];
-      val[q] = u0[q] + s;
-    }
-    T all[NV];
-    group_state<NV, G, T>(val, all, L.base);
-    hok = a.frozen || (hok && harten_point<NV, T>(all, rho_b, p_b, a));
-#pragma unroll
-    for (int q = 0; q < VPL; ++q) store<NV, T>(a, g, cell, v0 + q, hok ? val[q] : u0[q]);
-    if (!hok) {
-      // first-order fallback: overwrite every point of the cell with U_i
-      for (int g2 = 0; g2 < ng; ++g2) {
-#pragma unroll
-        for (int q = 0; q < VPL; ++q) store<NV, T>(a, g2, cell, v0 + q, u0[q]);
-      }
-      break;
-    }
-  }
-  return hok;
-}
-
-// K1: linear candidate, face states, NAD own class, Harten flag.  FUSE: a
-// cell the NAD flags for CWENOZ (own class 1, active) takes CWENOZ here, from
-// the fit in registers, instead of its linear states; its own byte records
-// that (bit 3) and whether CWENOZ's Harten check failed (bit 4).  Tagging
-// may still raise it to MUSCL, whose pass then overwrites its states.
-template <int DIM, int R, typename T, int G, bool FUSE = false>
 __global__ __launch_bounds__(256) void k_linear(HotArgs<T> a) {
   constexpr int NV = DIM + 2, K = n_unknowns(DIM, R), VPL = NV / G, NFM = nf_max(DIM);
   if (blockIdx.x == 0 && threadIdx.x < 8) a.counts[threadIdx.x] = 0;
@@ -256,10 +100,8 @@ __global__ __launch_bounds__(256) void k_linear(HotArgs<T> a) {
     group_state<NV, G, T>(val, all, L.base);
     hok = hok && harten_point<NV, T>(all, rho_b, p_b, a);
     if (a.margin) mg = fmin(mg, harten_margin<NV, T>(all, rho_b, p_b, a));
-    if constexpr (!FUSE) {
 #pragma unroll
-      for (int q = 0; q < VPL; ++q) store<NV, T>(a, g, cell, v0 + q, val[q]);
-    }
+    for (int q = 0; q < VPL; ++q) store<NV, T>(a, g, cell, v0 + q, val[q]);
   }
   int c = 0;
   if (a.mode == HFV_HYBRID) {
@@ -279,26 +121,9 @@ __global__ __launch_bounds__(256) void k_linear(HotArgs<T> a) {
     if (dU < a.t.thr[cell]) c = HFV_CLASS_LINEAR;
     if (a.margin) mg = fmin(fmin(mg, group_min<G>(nm, L.base)), deact_margin(dU, a.t.thr[cell]));
   }
-  int own = c | (hok ? 0 : 4);
-  if constexpr (FUSE) {
-    if (c == HFV_CLASS_CWENOZ) {   // the same in every lane of the group
-      own = HFV_CLASS_CWENOZ | 8 | (cwenoz_cell<DIM, R, T, G>(a, cell, L, u0, co) ? 0 : 16);
-    } else {                        // the linear states, whose stores were held back
-      for (int g = 0; g < ng; ++g) {
-        T xi[DIM];
-#pragma unroll
-        for (int j = 0; j < DIM; ++j) xi[j] = a.t.gpxi[((long)g * DIM + j) * N + cell];
-        T val[VPL];
-        poly_at<DIM, R, VPL, T>(xi, co, c0, val);
-#pragma unroll
-        for (int q = 0; q < VPL; ++q) store<NV, T>(a, g, cell, v0 + q, val[q]);
-      }
-    }
-  } else {
-    if (a.coef) keep_fit<NV>(a, cell, v0, co);
-  }
+  if (a.coef) keep_fit<NV>(a, cell, v0, co);
   if (L.sub == 0) {
-    a.own[cell] = (uint8_t)own;
+    a.own[cell] = (uint8_t)(c | (hok ? 0 : 4));
     if (a.margin) a.margin[cell] = mg;
   }
 }
@@ -682,7 +507,6 @@ __global__ __launch_bounds__(CLASSIFY_BLOCK) void k_classify(HotArgs<T> a, int n
   const int cell = (int)(block_id(a.xcd) * blockDim.x + threadIdx.x);
   const bool valid = cell < a.N;
   int c = 0;
-  bool done = false;
   if (valid && a.frozen) {
     c = min((int)a.cls_in[cell], (int)HFV_CLASS_FIRST_ORDER);  // larger values: first order
   } else if (valid) {
@@ -698,14 +522,10 @@ __global__ __launch_bounds__(CLASSIFY_BLOCK) void k_classify(HotArgs<T> a, int n
       c = HFV_CLASS_LINEAR;
     }
     if (c == HFV_CLASS_LINEAR && (o & 4)) c = HFV_CLASS_FIRST_ORDER;
-    if (c == HFV_CLASS_CWENOZ && (o & 8)) {   // CWENOZ already done by the fused linear pass
-      c = (o & 16) ? HFV_CLASS_FIRST_ORDER : HFV_CLASS_CWENOZ;
-      done = true;
-    }
     a.cls[cell] = (uint8_t)c;
   }
   // List of the cell: CWENOZ (0), MUSCL (1), first order (2).
-  const int li = done ? -1 : c - 1;
+  const int li = c - 1;
   // Compaction: wave ballots give each lane its rank inside the wave; the
   // waves of the block combine their counts in LDS and the block reserves its
   // range of each list with one atomic per list.
@@ -908,7 +728,7 @@ __global__ __launch_bounds__(256) void k_cwenoz(HotArgs<T> a, int direct) {
 // states over list 3.
 template <int DIM, int R, typename T, int G>
 __global__ __launch_bounds__(256) void k_muscl(HotArgs<T> a, int direct) {
-  constexpr int NV = DIM + 2, VPL = NV / G, NFM = nf_max(DIM);
+  constexpr int NV = DIM + 2, VPL = NV / G, NFM = nf_max(DIM), NGPC = max_gp_cell(DIM, R);
   constexpr int CPW = 64 / G;
   const int total = direct ? a.N : a.counts[2];
   Lane<G> L(a.xcd);
@@ -961,14 +781,21 @@ __global__ __launch_bounds__(256) void k_muscl(HotArgs<T> a, int direct) {
     const int ng = a.t.ngp[cell];
     const bool venkat = a.limiter == HFV_LIM_VENKAT;
     const T e2 = venkat ? a.t.veps2[cell] : (T)0;
+    // every slot's degree-1 basis values in one batch (slots past the cell's
+    // count hold 0 in the table, so the loads stay in bounds), reused by both
+    // passes over the points
+    T phis[NGPC][DIM];
+#pragma unroll
+    for (int g = 0; g < NGPC; ++g)
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) phis[g][j] = a.t.gpxi[((long)g * DIM + j) * N + cell] - psb[j];
     T th[VPL];
 #pragma unroll
     for (int q = 0; q < VPL; ++q) th[q] = (T)1;
-#pragma unroll 4
-    for (int g = 0; g < ng; ++g) {
-      T phi[DIM];
 #pragma unroll
-      for (int j = 0; j < DIM; ++j) phi[j] = a.t.gpxi[((long)g * DIM + j) * N + cell] - psb[j];
+    for (int g = 0; g < NGPC; ++g) {
+      if (g >= ng) break;
+      const T (&phi)[DIM] = phis[g];
 #pragma unroll
       for (int q = 0; q < VPL; ++q) {
         T d = 0;
@@ -992,11 +819,10 @@ __global__ __launch_bounds__(256) void k_muscl(HotArgs<T> a, int direct) {
     // limited states and their Harten check; the rare failure rewrites the
     // cell's points with the first-order state afterwards
     bool hok = true;
-#pragma unroll 4
-    for (int g = 0; g < ng; ++g) {
-      T phi[DIM];
 #pragma unroll
-      for (int j = 0; j < DIM; ++j) phi[j] = a.t.gpxi[((long)g * DIM + j) * N + cell] - psb[j];
+    for (int g = 0; g < NGPC; ++g) {
+      if (g >= ng) break;
+      const T (&phi)[DIM] = phis[g];
       T val[VPL];
 #pragma unroll
       for (int q = 0; q < VPL; ++q) {
@@ -1149,14 +975,10 @@ static HotArgs<T> make_args(hfv_ctx *ctx, Tables<T> &t, const void *U, void *fs,
   a.cls_in = nullptr;
   a.U = (const T *)U;
   a.fs = (T *)fs;
-  // CWENOZ fused into the variable-split linear pass (hybrid, conserved
-  // variables); then no fit is kept
-  // (and not with viscous fluxes, whose gradients come from the kept fits:
-  // the linear pass then keeps every cell's fit, which CWENOZ also reads)
-  a.fuse = ctx->cw_fuse && ctx->lin_split == 0 && ctx->p.mode == HFV_HYBRID && ctx->p.cvars == HFV_CONSERVED &&
-           !ctx->p.viscous;
+  // the linear pass keeps every cell's central fit for CWENOZ (reuse), and
+  // always with viscous fluxes, whose gradients come from the kept fits
   const bool keep = ctx->p.viscous ? (ctx->p.mode == HFV_HYBRID || ctx->p.mode == HFV_ALL_LINEAR)
-                                   : (ctx->cw_reuse && ctx->p.mode == HFV_HYBRID && !a.fuse);
+                                   : (ctx->cw_reuse && ctx->p.mode == HFV_HYBRID);
   a.coef = keep ? (T *)ctx->coef : nullptr;
   a.xcd = ctx->xcd_remap;
   a.limiter = ctx->p.limiter;
@@ -1198,22 +1020,12 @@ static void launch_linear(const hfv_ctx *ctx, const HotArgs<T> &a, hipStream_t s
   const int B = ctx->block, GL = ctx->lin_lanes;
   const long waves = ((long)ctx->N + 64 / GL - 1) / (64 / GL);
   const unsigned grid = nblk(waves * 64, B);
-  const bool fuse = a.fuse;
   switch (ctx->lin_split * 16 + GL) {
-    case 1:
-      if (fuse) k_linear<DIM, R, T, 1, true><<<grid, B, 0, s>>>(a);
-      else k_linear<DIM, R, T, 1><<<grid, B, 0, s>>>(a);
-      break;
+    case 1: k_linear<DIM, R, T, 1><<<grid, B, 0, s>>>(a); break;
     case 2:
-      if constexpr (DIM == 2) {
-        if (fuse) k_linear<DIM, R, T, 2, true><<<grid, B, 0, s>>>(a);
-        else k_linear<DIM, R, T, 2><<<grid, B, 0, s>>>(a);
-      }
+      if constexpr (DIM == 2) k_linear<DIM, R, T, 2><<<grid, B, 0, s>>>(a);
       break;
-    case DIM + 2:
-      if (fuse) k_linear<DIM, R, T, DIM + 2, true><<<grid, B, 0, s>>>(a);
-      else k_linear<DIM, R, T, DIM + 2><<<grid, B, 0, s>>>(a);
-      break;
+    case DIM + 2: k_linear<DIM, R, T, DIM + 2><<<grid, B, 0, s>>>(a); break;
     case 16 + 2: k_linear_ms<DIM, R, T, 2><<<grid, B, 0, s>>>(a); break;
     case 16 + 4: k_linear_ms<DIM, R, T, 4><<<grid, B, 0, s>>>(a); break;
     case 16 + 8: k_linear_ms<DIM, R, T, 8><<<grid, B, 0, s>>>(a); break;
@@ -1310,7 +1122,6 @@ static hfv_status frozen_impl(hfv_ctx *ctx, Tables<T> &t, const void *U, void *f
   a.cls_in = cls;
   a.mode = HFV_ALL_LINEAR;
   a.coef = nullptr;
-  a.fuse = false;
   const int B = ctx->block;
   const long waves = ((long)ctx->N + 64 / G - 1) / (64 / G);
   const unsigned grid_cells = nblk(waves * 64, B);

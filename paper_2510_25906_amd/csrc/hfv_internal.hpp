@@ -131,7 +131,6 @@ struct hfv_ctx {
   int fused_residual = 0;            // one owner-computes residual kernel instead of flux + gather
   int xcd_remap = 1;                 // XCD-contiguous block order (block_id)
   int muscl_lanes = 0;               // lanes per cell of the MUSCL pass (0: lanes)
-  int cw_fuse = 0;                   // CWENOZ of own-flagged cells in the variable-split linear pass
   int device = 0, n_cu = 256;
   // kernel timing (hfv_profile_*)
   struct ProfEv {

@@ -14,9 +14,7 @@
 //   3. in hybrid mode, whether CWENOZ reuses the linear pass's central fits;
 //   4. the fused (owner-computes) residual kernel against face fluxes + gather;
 //   5. XCD-contiguous block order against plain block order;
-//   6. in hybrid mode, the MUSCL pass's own lane count;
-//   7. in hybrid mode with conserved-variable CWENOZ, CWENOZ fused into the
-//      variable-split linear pass, with that pass's lane count.
+//   6. in hybrid mode, the MUSCL pass's own lane count.
 // Each candidate runs once untimed, then `reps` times with HIP events around
 // each call; its score is the median.
 #include <algorithm>
@@ -162,19 +160,6 @@ extern "C" hfv_status hfv_autotune(hfv_ctx *ctx, const void *U, int32_t reps, hf
           c.muscl_lanes = l;
           cands.push_back(c);
         }
-      tu.pick(cands, best, best_ms);
-    }
-    // 7. CWENOZ inside the linear pass
-    if (ctx->p.mode == HFV_HYBRID && ctx->p.cvars == HFV_CONSERVED) {
-      cands.clear();
-      for (int l : var_lanes) {
-        hfv_launch c = best;
-        c.linear_split = 0;
-        c.linear_lanes = l;
-        c.cwenoz_fuse = 1;
-        c.cwenoz_reuse = 0;
-        cands.push_back(c);
-      }
       tu.pick(cands, best, best_ms);
     }
     if (hfv_set_launch(ctx, &best) != HFV_OK) st = HFV_ERR_PARAM;

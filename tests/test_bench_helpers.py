@@ -76,3 +76,10 @@ def test_fp32_flips_split_by_margin():
                            face_cells)
     assert out["fp32_class_flips"] == 2 and out["fp32_flips_unflagged"] == 1
     assert out["cells_margin_le_1e-6"] == 1
+
+
+def test_kernel_names_follow_the_launch():
+    assert bench.kernel_name("linear", {"linear_split": 1}) == "k_linear_ms"
+    assert bench.kernel_name("linear", {"linear_split": 2}) == "k_linear_ks"
+    assert bench.kernel_name("cwenoz", {"cwenoz_reuse": 1}) == "k_cwenoz"
+    assert bench.kernel_name("flux", {"fused_residual": 1}) == "k_residual"

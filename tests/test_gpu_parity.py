@@ -401,57 +401,3 @@ def test_2d_high_order_matches_oracle(hfv, r):
                     print(f"  fp32 {cfg}: flips {flip.sum()}, state error {e:.2e}", flush=True)
                     assert e <= 1e-5
             ctx.close()
-
-
-FUSE_CASES = {
-    "c1_r2": lambda: configs.c1_density_jump(32, 2),
-    "c2_r3": lambda: configs.c2_riemann(64, 3),
-}
-
-
-@pytest.mark.parametrize("case", sorted(FUSE_CASES))
-@pytest.mark.parametrize("lanes", [1, 2, 4])
-def test_cwenoz_fused_into_linear_pass(hfv, case, lanes):
-    """cwenoz_fuse: CWENOZ of the own-flagged cells inside the variable-split
-    linear pass, the list pass for the cells tagging adds; classes bit-exact,
-    states within 1e-12 and the residual within 1e-11 of the oracle (FP64),
-    the FP32 bar with the flip allowance; the results agree with the unfused
-    launch to rounding."""
-    w = FUSE_CASES[case]()
-    om = OracleModel(w.mesh, w.stencils, w.params)
-    R_o, fs_o, cls_o = flux.residual(om, w.U)
-    N = w.mesh.n_cells
-    assert (cls_o == 1).sum() > 0
-    S = state_scale(w.U)
-    for prec in (64, 32):
-        ctx = hfv.Context(w.mesh, w.stencils, w.params, prec)
-        ctx.set_launch(linear_split=0, linear_lanes=lanes, lanes=lanes, cwenoz_fuse=1, list_blocks=64)
-        assert ctx.get_launch()["cwenoz_fuse"] == 1
-        Ud = to_dev(w.U, torch.float64 if prec == 64 else torch.float32)
-        fs = ctx.new_face_states()
-        cls = torch.empty(N, dtype=torch.uint8, device="cuda")
-        R = ctx.residual(Ud, face_states=fs, cell_class=cls)
-        torch.cuda.synchronize()
-        listed = ctx.query("COUNT_CWENOZ")
-        cls_g = cls.cpu().numpy()
-        print(f"{case} fp{prec} lanes {lanes}: CWENOZ cells {int((cls_g == 1).sum())}, listed {listed}", flush=True)
-        assert listed < (cls_g == 1).sum()
-        if prec == 64:
-            assert np.array_equal(cls_g, cls_o)
-            es = states_err(fs, fs_o, om.geo, S)
-            er = rel_err(R.cpu().numpy(), R_o, np.abs(R_o).max(1)[:, None])
-            print(f"  state error {es:.2e}, residual error {er:.2e}", flush=True)
-            assert es <= 1e-12 and er <= 1e-11
-        else:
-            cells = np.arange(N)
-            flip = cls_g != cls_o
-            flags = dilated_flags(om, near_threshold(om, w.U, cells, 1e-6), cells) if flip.any() \
-                else np.zeros(N, bool)
-            assert not np.any(flip & ~flags)
-            e = rel_err(gpu_cell_values(fs.cpu().numpy(), om.geo, cells)[~flip],
-                        oracle_cell_values(fs_o, om.geo, cells)[~flip], S[None, None, :])
-            assert e <= 1e-5
-        # the split and unknown mappings cannot fuse
-        with pytest.raises(hfv.HfvError):
-            ctx.set_launch(linear_split=1, linear_lanes=2)
-        ctx.close()

@@ -57,8 +57,8 @@ def test_viscous_residual_matches_oracle(hfv, case, mode):
     scale = np.abs(R_o).max(1)[:, None]
     for prec in (64, 32):
         ctx = hfv.Context(w.mesh, w.stencils, p, prec)
-        for cfg in (dict(cwenoz_reuse=0, fused_residual=0), dict(cwenoz_reuse=1, fused_residual=1, cwenoz_fuse=1,
-                                                                 linear_split=0, linear_lanes=1)):
+        for cfg in (dict(cwenoz_reuse=0, fused_residual=0), dict(cwenoz_reuse=1, fused_residual=1, linear_split=0,
+                                                                 linear_lanes=1)):
             ctx.set_launch(**cfg)
             cls = torch.empty(N, dtype=torch.uint8, device="cuda")
             R = ctx.residual(to_dev(w.U, torch.float64 if prec == 64 else torch.float32), cell_class=cls)
