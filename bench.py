@@ -164,10 +164,12 @@ class ByteModel:
         s, nv = self.s, self.nv
         return 2 * self.NF * s * nv + self.N * s * nv
 
-    def s_per_kernel(self, mode, cls, fused):
+    def s_per_kernel(self, mode, cls, fused, merged=False):
         """{kernel: bytes} of one reconstruction + residual in `mode` by the
         scope definition (all-CWENOZ cells count the linear bytes too, with
-        one write of the states: the direct CWENOZ pass does the fit itself)."""
+        one write of the states: the direct CWENOZ pass does the fit itself;
+        merged: the MUSCL and first-order lists' bytes are the CWENOZ
+        launch's)."""
         cw, mu, fo = cls == 1, cls == 2, cls == 3
         if mode == "cwenoz":   # the direct pass writes each cell's states once
             out = {"cwenoz": self.s_linear() + self.s_cwenoz_extra(np.ones(self.N, bool))
@@ -177,6 +179,8 @@ class ByteModel:
             if mode == "hybrid":
                 out["cwenoz"] = self.s_cwenoz_extra(cw)
             out["muscl"] = self.s_muscl_extra(mu) + self.s_first_extra(fo)
+            if merged and mode == "hybrid":
+                out["cwenoz"] += out.pop("muscl")
         if fused:
             out["flux"] = self.s_flux() + self.s_gather() - 3 * self.NF * self.s * self.nv
         else:
@@ -184,7 +188,7 @@ class ByteModel:
             out["gather"] = self.s_gather()
         return {k: int(v) for k, v in out.items()}
 
-    def per_kernel(self, mode, cls, reuse, fused):
+    def per_kernel(self, mode, cls, reuse, fused, merged=False):
         """{kernel: bytes} of one reconstruction + residual in `mode`."""
         cw, mu, fo = cls == 1, cls == 2, cls == 3
         if mode == "cwenoz":
@@ -195,6 +199,8 @@ class ByteModel:
             if mode == "hybrid":
                 out["cwenoz"] = self.cwenoz(cw, reuse=reuse)
             out["muscl"] = self.muscl(mu) + self.first(fo)
+            if merged and mode == "hybrid":
+                out["cwenoz"] += out.pop("muscl")
         if fused:
             out["flux"] = self.residual_fused()
         else:
@@ -554,8 +560,9 @@ def measure(w, wl_tag, head_prec, variants, args, torch, hfv, probe, flush, extr
             ms_res = time_steps(lambda: ctx.residual(U, R, fs, cls), args.steps, 0 if live else args.warmup, torch)
             cl_dev = cls.cpu().numpy()
             reuse, fused = bool(launch["cwenoz_reuse"]), bool(launch["fused_residual"])
-            mbyts = bm.per_kernel(name, cl_dev, reuse, fused)       # the kernels' own byte counts
-            sbyts = bm.s_per_kernel(name, cl_dev, fused)            # the scope definition's bytes
+            merged = bool(launch.get("merged_lists", 0))
+            mbyts = bm.per_kernel(name, cl_dev, reuse, fused, merged)    # the kernels' own byte counts
+            sbyts = bm.s_per_kernel(name, cl_dev, fused, merged)         # the scope definition's bytes
             if live:
                 prof = ctx.profile_read()
                 ctx.profile_enable(0)

@@ -346,11 +346,17 @@ hfv_status hfv_copy_table(const hfv_ctx *ctx, int32_t which, void *host_dst, int
  *                   gathers share that XCD's L2; 0: plain block order
  *   muscl_lanes     lanes per cell of the MUSCL / first-order pass: 0 (the
  *                   same as lanes_per_cell), 1 or nvar (or 2 in 2D)
+ *   merged_lists    1: in hybrid mode with conserved-variable CWENOZ (and in
+ *                   the frozen residual and VJP forward), the CWENOZ launch
+ *                   also serves the MUSCL and first-order lists, after its
+ *                   own, with lanes_per_cell lanes (muscl_lanes unused); their
+ *                   cells fill the waves CWENOZ leaves idle.  0: a launch of
+ *                   their own
  * hfv_set_launch validates every field (HFV_ERR_PARAM, nothing changed, on
  * an invalid one); hfv_get_launch reads the current configuration. */
 typedef struct {
   int32_t lanes_per_cell, block, list_blocks, linear_split, linear_lanes, cwenoz_reuse, fused_residual, xcd_remap,
-      muscl_lanes;
+      muscl_lanes, merged_lists;
 } hfv_launch;
 hfv_status hfv_set_launch(hfv_ctx *ctx, const hfv_launch *cfg);
 hfv_status hfv_get_launch(const hfv_ctx *ctx, hfv_launch *cfg);

@@ -555,12 +555,141 @@ __global__ __launch_bounds__(CLASSIFY_BLOCK) void k_classify(HotArgs<T> a, int n
   if (valid && li >= 0) a.lists[(long)li * a.N + wbase[li][wave] + __popcll(masks[li] & lt)] = cell;
 }
 
+// K4: one cell of the MUSCL list: gradient by least squares over the face
+// neighbours, Barth-Jespersen (or Venkatakrishnan) limiter, Harten check.
+template <int DIM, int R, typename T, int G>
+__device__ __forceinline__ void muscl_cell(const HotArgs<T> &a, int cell, const Lane<G> &L) {
+  constexpr int NV = DIM + 2, VPL = NV / G, NFM = nf_max(DIM);
+  const int N = a.N, v0 = L.sub * VPL;
+  T u0[VPL];
+#pragma unroll
+  for (int q = 0; q < VPL; ++q) u0[q] = a.U[(long)(v0 + q) * N + cell];
+  T gr[DIM][VPL];
+#pragma unroll
+  for (int j = 0; j < DIM; ++j)
+#pragma unroll
+    for (int q = 0; q < VPL; ++q) gr[j][q] = 0;
+  // members past the cell's count are padded with the cell itself and zero
+  // weights (exact zeros), neighbour rows past its face count with -1
+#pragma unroll
+  for (int m = 0; m < NFM; ++m) {
+    const int jc = a.t.msten[(long)m * N + cell];
+    T du[VPL];
+#pragma unroll
+    for (int q = 0; q < VPL; ++q) du[q] = a.U[(long)(v0 + q) * N + jc] - u0[q];
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) {
+      const T p = a.t.Pmus[((long)j * NFM + m) * N + cell];
+#pragma unroll
+      for (int q = 0; q < VPL; ++q) gr[j][q] += p * du[q];
+    }
+  }
+  T mn[VPL], mx[VPL];
+#pragma unroll
+  for (int q = 0; q < VPL; ++q) mn[q] = mx[q] = u0[q];
+#pragma unroll
+  for (int f = 0; f < NFM; ++f) {
+    const int j = a.t.nbr[(long)f * N + cell];
+    if (j >= 0) {
+#pragma unroll
+      for (int q = 0; q < VPL; ++q) {
+        const T u = a.U[(long)(v0 + q) * N + j];
+        mn[q] = fmin(mn[q], u);
+        mx[q] = fmax(mx[q], u);
+      }
+    }
+  }
+  T psb[DIM];
+#pragma unroll
+  for (int j = 0; j < DIM; ++j) psb[j] = a.t.psibar[(long)j * N + cell];
+  const int ng = a.t.ngp[cell];
+  const bool venkat = a.limiter == HFV_LIM_VENKAT;
+  const T e2 = venkat ? a.t.veps2[cell] : (T)0;
+  T th[VPL];
+#pragma unroll
+  for (int q = 0; q < VPL; ++q) th[q] = (T)1;
+#pragma unroll 4
+  for (int g = 0; g < ng; ++g) {
+    T phi[DIM];
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) phi[j] = a.t.gpxi[((long)g * DIM + j) * N + cell] - psb[j];
+#pragma unroll
+    for (int q = 0; q < VPL; ++q) {
+      T d = 0;
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) d += gr[j][q] * phi[j];
+      T ratio = (T)1;
+      if (d != 0) {
+        const T dp = (d > 0 ? mx[q] : mn[q]) - u0[q];   // room to the bound in the direction of d
+        if (venkat)   // smooth limiter function of Venkatakrishnan (1995)
+          ratio = ((dp * dp + e2) * d + (T)2 * d * d * dp) / (d * (dp * dp + (T)2 * d * d + dp * d + e2));
+        else          // Barth-Jespersen
+          ratio = fmin((T)1, dp / d);
+      }
+      th[q] = fmin(th[q], ratio);
+    }
+  }
+  T all0[NV];
+  group_state<NV, G, T>(u0, all0, L.base);
+  const T rho_b = all0[0];
+  const T p_b = pressure<NV, T>(all0, a.gamma);
+  // limited states and their Harten check; the rare failure rewrites the
+  // cell's points with the first-order state afterwards
+  bool hok = true;
+#pragma unroll 4
+  for (int g = 0; g < ng; ++g) {
+    T phi[DIM];
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) phi[j] = a.t.gpxi[((long)g * DIM + j) * N + cell] - psb[j];
+    T val[VPL];
+#pragma unroll
+    for (int q = 0; q < VPL; ++q) {
+      T d = 0;
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) d += gr[j][q] * phi[j];
+      val[q] = u0[q] + th[q] * d;
+    }
+    T all[NV];
+    group_state<NV, G, T>(val, all, L.base);
+    hok = hok && (a.frozen || harten_point<NV, T>(all, rho_b, p_b, a));
+#pragma unroll
+    for (int q = 0; q < VPL; ++q) store<NV, T>(a, g, cell, v0 + q, val[q]);
+  }
+  if (!hok) {
+    for (int g = 0; g < ng; ++g)
+#pragma unroll
+      for (int q = 0; q < VPL; ++q) store<NV, T>(a, g, cell, v0 + q, u0[q]);
+  }
+  if (L.sub == 0 && !a.frozen) a.cls[cell] = hok ? HFV_CLASS_MUSCL : HFV_CLASS_FIRST_ORDER;
+}
+
+// K5: one cell of the first-order list: the cell average at every Gauss point.
+template <int DIM, typename T, int G>
+__device__ __forceinline__ void first_order_cell(const HotArgs<T> &a, int cell, const Lane<G> &L) {
+  constexpr int NV = DIM + 2, VPL = NV / G;
+  const int N = a.N, v0 = L.sub * VPL;
+  T u0[VPL];
+#pragma unroll
+  for (int q = 0; q < VPL; ++q) u0[q] = a.U[(long)(v0 + q) * N + cell];
+  const int ng = a.t.ngp[cell];
+#pragma unroll 4
+  for (int g = 0; g < ng; ++g)
+#pragma unroll
+    for (int q = 0; q < VPL; ++q) store<NV, T>(a, g, cell, v0 + q, u0[q]);
+}
+
 // K3: CWENOZ over the class-1 list (every cell when direct).  REUSE: the
 // central fit is read from the linear pass's copy instead of refitted.  The
-// body is cwenoz_cell's written out: as a call (inlined) it was allocated
-// more registers (2D r = 3 FP64, two lanes: 255 + 12 AGPRs instead of 245,
-// one wave per SIMD instead of two).
-template <int DIM, int R, typename T, int G, bool REUSE>
+// body stays written out in the kernel: moved into a device function (even
+// inlined) it was allocated more registers (2D r = 3 FP64, two lanes: 255 +
+// 12 AGPRs instead of 245, one wave per SIMD instead of two).
+// MERGED (lists only): the same launch then also serves the MUSCL and the
+// first-order lists, as items past the CWENOZ list, so their cells fill the
+// waves CWENOZ leaves idle instead of waiting for a launch of their own.
+// They run in a loop of their own after the CWENOZ loop (each lane continues
+// its item sequence there); a template parameter, so that the plain kernel's
+// code is not changed by them.
+template <int DIM, int R, typename T, int G, bool REUSE, bool MERGED>
 __global__ __launch_bounds__(256) void k_cwenoz(HotArgs<T> a, int direct) {
   constexpr int NV = DIM + 2, K = n_unknowns(DIM, R), VPL = NV / G, NFM = nf_max(DIM), MD = 2 * DIM;
   constexpr int CPW = 64 / G;
@@ -568,7 +697,8 @@ __global__ __launch_bounds__(256) void k_cwenoz(HotArgs<T> a, int direct) {
   Lane<G> L(a.xcd);
   if (!L.ok) return;
   const long stride = (long)gridDim.x * (blockDim.x / 64) * CPW;
-  for (long item = L.item; item < total; item += stride) {
+  long item = L.item;
+  for (; item < total; item += stride) {
     const int cell = direct ? (int)item : a.lists[item];
     const int N = a.N, v0 = L.sub * VPL;
     T u0[VPL];
@@ -722,142 +852,30 @@ __global__ __launch_bounds__(256) void k_cwenoz(HotArgs<T> a, int direct) {
     }
     if (L.sub == 0 && !a.frozen) a.cls[cell] = hok ? HFV_CLASS_CWENOZ : HFV_CLASS_FIRST_ORDER;
   }
+  if constexpr (MERGED) {
+    const int n2 = a.counts[2], n3 = a.counts[3];
+    for (long i2 = item - total; i2 < (long)n2 + n3; i2 += stride) {
+      if (i2 < n2)
+        muscl_cell<DIM, R, T, G>(a, a.lists[(long)a.N + i2], L);
+      else
+        first_order_cell<DIM, T, G>(a, a.lists[2L * a.N + (i2 - n2)], L);
+    }
+  }
 }
 
-// K4: MUSCL with the Barth-Jespersen limiter over list 2, then first-order
-// states over list 3.
+// K4 + K5 as a launch of their own: list 2 (every cell when direct), then
+// list 3.
 template <int DIM, int R, typename T, int G>
 __global__ __launch_bounds__(256) void k_muscl(HotArgs<T> a, int direct) {
-  constexpr int NV = DIM + 2, VPL = NV / G, NFM = nf_max(DIM), NGPC = max_gp_cell(DIM, R);
   constexpr int CPW = 64 / G;
   const int total = direct ? a.N : a.counts[2];
   Lane<G> L(a.xcd);
   if (!L.ok) return;
   const long stride = (long)gridDim.x * (blockDim.x / 64) * CPW;
-  for (long item = L.item; item < total; item += stride) {
-    const int cell = direct ? (int)item : a.lists[(long)a.N + item];
-    const int N = a.N, v0 = L.sub * VPL;
-    T u0[VPL];
-#pragma unroll
-    for (int q = 0; q < VPL; ++q) u0[q] = a.U[(long)(v0 + q) * N + cell];
-    T gr[DIM][VPL];
-#pragma unroll
-    for (int j = 0; j < DIM; ++j)
-#pragma unroll
-      for (int q = 0; q < VPL; ++q) gr[j][q] = 0;
-    // members past the cell's count are padded with the cell itself and zero
-    // weights (exact zeros), neighbour rows past its face count with -1
-#pragma unroll
-    for (int m = 0; m < NFM; ++m) {
-      const int jc = a.t.msten[(long)m * N + cell];
-      T du[VPL];
-#pragma unroll
-      for (int q = 0; q < VPL; ++q) du[q] = a.U[(long)(v0 + q) * N + jc] - u0[q];
-#pragma unroll
-      for (int j = 0; j < DIM; ++j) {
-        const T p = a.t.Pmus[((long)j * NFM + m) * N + cell];
-#pragma unroll
-        for (int q = 0; q < VPL; ++q) gr[j][q] += p * du[q];
-      }
-    }
-    T mn[VPL], mx[VPL];
-#pragma unroll
-    for (int q = 0; q < VPL; ++q) mn[q] = mx[q] = u0[q];
-#pragma unroll
-    for (int f = 0; f < NFM; ++f) {
-      const int j = a.t.nbr[(long)f * N + cell];
-      if (j >= 0) {
-#pragma unroll
-        for (int q = 0; q < VPL; ++q) {
-          const T u = a.U[(long)(v0 + q) * N + j];
-          mn[q] = fmin(mn[q], u);
-          mx[q] = fmax(mx[q], u);
-        }
-      }
-    }
-    T psb[DIM];
-#pragma unroll
-    for (int j = 0; j < DIM; ++j) psb[j] = a.t.psibar[(long)j * N + cell];
-    const int ng = a.t.ngp[cell];
-    const bool venkat = a.limiter == HFV_LIM_VENKAT;
-    const T e2 = venkat ? a.t.veps2[cell] : (T)0;
-    // every slot's degree-1 basis values in one batch (slots past the cell's
-    // count hold 0 in the table, so the loads stay in bounds), reused by both
-    // passes over the points
-    T phis[NGPC][DIM];
-#pragma unroll
-    for (int g = 0; g < NGPC; ++g)
-#pragma unroll
-      for (int j = 0; j < DIM; ++j) phis[g][j] = a.t.gpxi[((long)g * DIM + j) * N + cell] - psb[j];
-    T th[VPL];
-#pragma unroll
-    for (int q = 0; q < VPL; ++q) th[q] = (T)1;
-#pragma unroll
-    for (int g = 0; g < NGPC; ++g) {
-      if (g >= ng) break;
-      const T (&phi)[DIM] = phis[g];
-#pragma unroll
-      for (int q = 0; q < VPL; ++q) {
-        T d = 0;
-#pragma unroll
-        for (int j = 0; j < DIM; ++j) d += gr[j][q] * phi[j];
-        T ratio = (T)1;
-        if (d != 0) {
-          const T dp = (d > 0 ? mx[q] : mn[q]) - u0[q];   // room to the bound in the direction of d
-          if (venkat)   // smooth limiter function of Venkatakrishnan (1995)
-            ratio = ((dp * dp + e2) * d + (T)2 * d * d * dp) / (d * (dp * dp + (T)2 * d * d + dp * d + e2));
-          else          // Barth-Jespersen
-            ratio = fmin((T)1, dp / d);
-        }
-        th[q] = fmin(th[q], ratio);
-      }
-    }
-    T all0[NV];
-    group_state<NV, G, T>(u0, all0, L.base);
-    const T rho_b = all0[0];
-    const T p_b = pressure<NV, T>(all0, a.gamma);
-    // limited states and their Harten check; the rare failure rewrites the
-    // cell's points with the first-order state afterwards
-    bool hok = true;
-#pragma unroll
-    for (int g = 0; g < NGPC; ++g) {
-      if (g >= ng) break;
-      const T (&phi)[DIM] = phis[g];
-      T val[VPL];
-#pragma unroll
-      for (int q = 0; q < VPL; ++q) {
-        T d = 0;
-#pragma unroll
-        for (int j = 0; j < DIM; ++j) d += gr[j][q] * phi[j];
-        val[q] = u0[q] + th[q] * d;
-      }
-      T all[NV];
-      group_state<NV, G, T>(val, all, L.base);
-      hok = hok && (a.frozen || harten_point<NV, T>(all, rho_b, p_b, a));
-#pragma unroll
-      for (int q = 0; q < VPL; ++q) store<NV, T>(a, g, cell, v0 + q, val[q]);
-    }
-    if (!hok) {
-      for (int g = 0; g < ng; ++g)
-#pragma unroll
-        for (int q = 0; q < VPL; ++q) store<NV, T>(a, g, cell, v0 + q, u0[q]);
-    }
-    if (L.sub == 0 && !a.frozen) a.cls[cell] = hok ? HFV_CLASS_MUSCL : HFV_CLASS_FIRST_ORDER;
-  }
-  // K5: first-order states (the cell average at every Gauss point) over list 3
+  for (long item = L.item; item < total; item += stride)
+    muscl_cell<DIM, R, T, G>(a, direct ? (int)item : a.lists[(long)a.N + item], L);
   const int total3 = direct ? 0 : a.counts[3];
-  for (long item = L.item; item < total3; item += stride) {
-    const int cell = a.lists[2L * a.N + item];
-    const int N = a.N, v0 = L.sub * VPL;
-    T u0[VPL];
-#pragma unroll
-    for (int q = 0; q < VPL; ++q) u0[q] = a.U[(long)(v0 + q) * N + cell];
-    const int ng = a.t.ngp[cell];
-#pragma unroll 4
-    for (int g = 0; g < ng; ++g)
-#pragma unroll
-      for (int q = 0; q < VPL; ++q) store<NV, T>(a, g, cell, v0 + q, u0[q]);
-  }
+  for (long item = L.item; item < total3; item += stride) first_order_cell<DIM, T, G>(a, a.lists[2L * a.N + item], L);
 }
 
 // K6: the two sides of face f at its i-th Gauss point are slot gl + i of the
@@ -1085,7 +1103,7 @@ static hfv_status recon_impl(hfv_ctx *ctx, Tables<T> &t, const void *U, void *fs
       hfv_status e = launch_cwenoz_char<T>(ctx, a, 1, s);
       if (e != HFV_OK) return e;
     } else {
-      k_cwenoz<DIM, R, T, G, false><<<grid_list, B, 0, s>>>(a, 1);
+      k_cwenoz<DIM, R, T, G, false, false><<<grid_list, B, 0, s>>>(a, 1);
     }
   } else if (mode == HFV_ALL_MUSCL) {
     k_zero_counts<<<1, 64, 0, s>>>(ctx->counts);
@@ -1093,19 +1111,26 @@ static hfv_status recon_impl(hfv_ctx *ctx, Tables<T> &t, const void *U, void *fs
   } else {
     { ProfScope ps(ctx, HFV_SLOT_LINEAR, s); launch_linear<DIM, R, T>(ctx, a, s); }
     { ProfScope ps(ctx, HFV_SLOT_CLASSIFY, s); k_classify<T><<<nblk(ctx->N, CLASSIFY_BLOCK), CLASSIFY_BLOCK, 0, s>>>(a, ctx->NFM); }
+    // the MUSCL and first-order lists ride in the CWENOZ launch when merged
+    const int merged = mode == HFV_HYBRID && !chr && ctx->merged_lists;
     if (mode == HFV_HYBRID) {
       ProfScope ps(ctx, HFV_SLOT_CWENOZ, s);
       if (chr) {
         hfv_status e = launch_cwenoz_char<T>(ctx, a, 0, s);
         if (e != HFV_OK) return e;
       } else if (a.coef) {
-        k_cwenoz<DIM, R, T, G, true><<<grid_list, B, 0, s>>>(a, 0);
+        if (merged) k_cwenoz<DIM, R, T, G, true, true><<<grid_list, B, 0, s>>>(a, 0);
+        else k_cwenoz<DIM, R, T, G, true, false><<<grid_list, B, 0, s>>>(a, 0);
       } else {
-        k_cwenoz<DIM, R, T, G, false><<<grid_list, B, 0, s>>>(a, 0);
+        if (merged) k_cwenoz<DIM, R, T, G, false, true><<<grid_list, B, 0, s>>>(a, 0);
+        else k_cwenoz<DIM, R, T, G, false, false><<<grid_list, B, 0, s>>>(a, 0);
       }
     }
     // MUSCL list (empty unless hybrid) and the first-order list
-    { ProfScope ps(ctx, HFV_SLOT_MUSCL, s); launch_muscl<DIM, R, T>(ctx, a, 0, s); }
+    if (!merged) {
+      ProfScope ps(ctx, HFV_SLOT_MUSCL, s);
+      launch_muscl<DIM, R, T>(ctx, a, 0, s);
+    }
   }
   HFV_HIP(hipGetLastError());
   return HFV_OK;
@@ -1132,10 +1157,13 @@ static hfv_status frozen_impl(hfv_ctx *ctx, Tables<T> &t, const void *U, void *f
   if (ctx->p.cvars == HFV_CHARACTERISTIC) {
     hfv_status e = launch_cwenoz_char<T>(ctx, a, 0, s);
     if (e != HFV_OK) return e;
+    launch_muscl<DIM, R, T>(ctx, a, 0, s);
+  } else if (ctx->merged_lists) {
+    k_cwenoz<DIM, R, T, G, false, true><<<grid_list, B, 0, s>>>(a, 0);
   } else {
-    k_cwenoz<DIM, R, T, G, false><<<grid_list, B, 0, s>>>(a, 0);
+    k_cwenoz<DIM, R, T, G, false, false><<<grid_list, B, 0, s>>>(a, 0);
+    launch_muscl<DIM, R, T>(ctx, a, 0, s);
   }
-  launch_muscl<DIM, R, T>(ctx, a, 0, s);
   HFV_HIP(hipGetLastError());
   if (ctx->p.viscous) return run_keep_fits(ctx, U, s);   // the viscous gradients' fits
   return HFV_OK;

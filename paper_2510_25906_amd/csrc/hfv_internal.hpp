@@ -19,9 +19,6 @@ __host__ __device__ constexpr int binom(int n, int k) {
 // Non-constant unknowns of a degree-r polynomial in d dimensions (Section 2.1).
 __host__ __device__ constexpr int n_unknowns(int d, int r) { return binom(r + d, d) - 1; }
 __host__ __device__ constexpr int nf_max(int d) { return d == 2 ? 4 : 6; }
-__host__ __device__ constexpr int max_gp_cell(int d, int r) {
-  return d == 2 ? 4 * ((r + 2) / 2) : 6 * ((r + 2) / 2) * ((r + 2) / 2);
-}
 
 // Exponents of the monomials of degree lo..hi, ordered by degree and then in
 // descending lexicographic order (the hierarchical basis order).
@@ -131,6 +128,7 @@ struct hfv_ctx {
   int fused_residual = 0;            // one owner-computes residual kernel instead of flux + gather
   int xcd_remap = 1;                 // XCD-contiguous block order (block_id)
   int muscl_lanes = 0;               // lanes per cell of the MUSCL pass (0: lanes)
+  int merged_lists = 0;              // MUSCL and first-order lists served by the CWENOZ launch
   int device = 0, n_cu = 256;
   // kernel timing (hfv_profile_*)
   struct ProfEv {

@@ -14,7 +14,9 @@
 //   3. in hybrid mode, whether CWENOZ reuses the linear pass's central fits;
 //   4. the fused (owner-computes) residual kernel against face fluxes + gather;
 //   5. XCD-contiguous block order against plain block order;
-//   6. in hybrid mode, the MUSCL pass's own lane count.
+//   6. in hybrid mode, the MUSCL and first-order lists inside the CWENOZ
+//      launch against a launch of their own;
+//   7. in hybrid mode, when that launch is kept, its own lane count.
 // Each candidate runs once untimed, then `reps` times with HIP events around
 // each call; its score is the median.
 #include <algorithm>
@@ -151,8 +153,14 @@ extern "C" hfv_status hfv_autotune(hfv_ctx *ctx, const void *U, int32_t reps, hf
       c.xcd_remap = 1 - best.xcd_remap;
       tu.pick({c}, best, best_ms);
     }
-    // 6. MUSCL lanes (0 = as the other class-list kernels)
+    // 6. MUSCL and first-order lists merged into the CWENOZ launch
     if (ctx->p.mode == HFV_HYBRID) {
+      hfv_launch c = best;
+      c.merged_lists = 1 - best.merged_lists;
+      tu.pick({c}, best, best_ms);
+    }
+    // 7. MUSCL lanes (0 = as the other class-list kernels)
+    if (ctx->p.mode == HFV_HYBRID && !best.merged_lists) {
       cands.clear();
       for (int l : var_lanes)
         if (l != best.lanes_per_cell) {

@@ -40,9 +40,13 @@ def dilated(om, flags):
     return flags | np.array([flags[nb[c][nb[c] >= 0]].any() for c in range(len(flags))])
 
 
-@pytest.mark.parametrize("split,lanes,reuse,mlanes", [(0, 5, 0, 0), (0, 1, 1, 1), (1, 4, 0, 5), (2, 2, 1, 0),
-                                                      (2, 4, 0, 1)])
-def test_c4_small_fp64_hybrid(hfv, small, split, lanes, reuse, mlanes):
+# (linear split, linear lanes, CWENOZ reuse, MUSCL lanes, class-list lanes,
+# MUSCL and first-order lists merged into the CWENOZ launch)
+@pytest.mark.parametrize("split,lanes,reuse,mlanes,cwl,merged", [(0, 5, 0, 0, 1, 0), (0, 1, 1, 1, 1, 0),
+                                                                 (1, 4, 0, 5, 1, 0), (2, 2, 1, 0, 1, 0),
+                                                                 (2, 4, 0, 1, 1, 0), (0, 5, 0, 0, 5, 1),
+                                                                 (1, 4, 1, 0, 5, 1), (2, 2, 0, 0, 1, 1)])
+def test_c4_small_fp64_hybrid(hfv, small, split, lanes, reuse, mlanes, cwl, merged):
     w, om = small
     R_o, fs_o, cls_o = flux.residual(om, w.U)
     counts = np.bincount(cls_o, minlength=4)
@@ -51,7 +55,7 @@ def test_c4_small_fp64_hybrid(hfv, small, split, lanes, reuse, mlanes):
     assert not near_threshold(om, w.U, np.arange(w.mesh.n_cells), 1e-12).any()
     ctx = hfv.Context(w.mesh, w.stencils, w.params, 64)
     ctx.set_launch(linear_split=split, linear_lanes=lanes, cwenoz_reuse=reuse, list_blocks=0 if reuse else 64,
-                   muscl_lanes=mlanes)
+                   muscl_lanes=mlanes, lanes=cwl, merged_lists=merged)
     fs = ctx.new_face_states()
     cls = torch.empty(w.mesh.n_cells, dtype=torch.uint8, device="cuda")
     R = ctx.residual(to_dev(w.U, torch.float64), face_states=fs, cell_class=cls)

@@ -99,7 +99,8 @@ def test_c2_full_size_autotuned(hfv, c2_full, prec):
 # mesh: FP64 two lanes per cell in the class-list kernels, the linear kernel
 # split over stencil members on two lanes, CWENOZ refitting, MUSCL on four
 # lanes; FP32 four lanes, the variable-split linear kernel on two lanes,
-# CWENOZ reusing the kept fit.
+# CWENOZ reusing the kept fit; the first two again with the MUSCL and
+# first-order lists merged into the CWENOZ launch.
 HEADLINE_LAUNCHES = [
     (64, dict(lanes=2, linear_split=1, linear_lanes=2, cwenoz_reuse=0, muscl_lanes=4, block=256,
               list_blocks=4096)),
@@ -107,6 +108,10 @@ HEADLINE_LAUNCHES = [
               list_blocks=0)),
     (64, dict(lanes=2, linear_split=2, linear_lanes=8, cwenoz_reuse=0, muscl_lanes=0, block=128,
               list_blocks=4096, xcd_remap=1)),
+    (64, dict(lanes=2, linear_split=1, linear_lanes=2, cwenoz_reuse=0, merged_lists=1, block=256,
+              list_blocks=4096)),
+    (32, dict(lanes=4, linear_split=0, linear_lanes=2, cwenoz_reuse=1, merged_lists=1, block=256,
+              list_blocks=0)),
 ]
 
 
