@@ -267,6 +267,23 @@ __device__ inline void store(const HotArgs<T> &a, int g, int cell, int v, T val)
   a.fs[((long)g * NV + v) * a.N + cell] = val;
 }
 
+// Frame coordinates of PB of a cell's Gauss-point slots, g0, g0 + step, ...;
+// slots past its count ng (>= 1) repeat its last one, so every load is in
+// bounds and unconditional.  A point loop that stores face states cannot have
+// its later loads moved above those stores (the compiler cannot rule out that
+// they alias), so it would wait for each point's coordinates in turn; loading
+// PB points at once waits once per PB points.
+constexpr int GP_BATCH = 4;
+template <int PB, int DIM, typename T>
+__device__ inline void load_points(const HotArgs<T> &a, int cell, int g0, int step, int ng, T (&xs)[PB][DIM]) {
+#pragma unroll
+  for (int p = 0; p < PB; ++p) {
+    const int g = min(g0 + p * step, ng - 1);
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) xs[p][j] = a.t.gpxi[((long)g * DIM + j) * a.N + cell];
+  }
+}
+
 // Riemann fluxes (Section 2.4): HLLC and HLL with Davis wave-speed estimates.
 template <int DIM, typename T>
 __device__ inline void euler_flux(const T (&q)[DIM + 2], const T (&n)[DIM], T p, T un, T (&F)[DIM + 2]) {

@@ -88,20 +88,25 @@ __global__ __launch_bounds__(256) void k_linear(HotArgs<T> a) {
   bool hok = true;
   T mg = (T)INFINITY;  // near_margin (every lane sees the full state at each point)
   const int ng = a.t.ngp[cell];
-  for (int g = 0; g < ng; ++g) {
-    T xi[DIM];
+  for (int g0 = 0; g0 < ng; g0 += GP_BATCH) {
+    T xs[GP_BATCH][DIM];
+    load_points<GP_BATCH, DIM, T>(a, cell, g0, 1, ng, xs);
 #pragma unroll
-    for (int j = 0; j < DIM; ++j) xi[j] = a.t.gpxi[((long)g * DIM + j) * N + cell];
-    T val[VPL];
-    poly_at<DIM, R, VPL, T>(xi, co, c0, val);
+    for (int p = 0; p < GP_BATCH; ++p) {
+      const int g = g0 + p;
+      if (g < ng) {
+        T val[VPL];
+        poly_at<DIM, R, VPL, T>(xs[p], co, c0, val);
 #pragma unroll
-    for (int q = 0; q < VPL; ++q) exc[q] = fmax(exc[q], fmax(mn[q] - val[q], val[q] - mx[q]));
-    T all[NV];
-    group_state<NV, G, T>(val, all, L.base);
-    hok = hok && harten_point<NV, T>(all, rho_b, p_b, a);
-    if (a.margin) mg = fmin(mg, harten_margin<NV, T>(all, rho_b, p_b, a));
+        for (int q = 0; q < VPL; ++q) exc[q] = fmax(exc[q], fmax(mn[q] - val[q], val[q] - mx[q]));
+        T all[NV];
+        group_state<NV, G, T>(val, all, L.base);
+        hok = hok && harten_point<NV, T>(all, rho_b, p_b, a);
+        if (a.margin) mg = fmin(mg, harten_margin<NV, T>(all, rho_b, p_b, a));
 #pragma unroll
-    for (int q = 0; q < VPL; ++q) store<NV, T>(a, g, cell, v0 + q, val[q]);
+        for (int q = 0; q < VPL; ++q) store<NV, T>(a, g, cell, v0 + q, val[q]);
+      }
+    }
   }
   int c = 0;
   if (a.mode == HFV_HYBRID) {
@@ -234,20 +239,24 @@ __global__ __launch_bounds__(256) void k_linear_ms(HotArgs<T> a) {
   bool hok = true;
   T mg = (T)INFINITY;  // near_margin, this lane's points
   const int ng = a.t.ngp[cell];
-  for (int g = q; g < ng; g += G) {
-    T xi[DIM];
+  constexpr int PB = GP_BATCH / 2;
+  for (int g0 = q; g0 < ng; g0 += PB * G) {
+    T xs[PB][DIM];
+    load_points<PB, DIM, T>(a, cell, g0, G, ng, xs);
 #pragma unroll
-    for (int j = 0; j < DIM; ++j) xi[j] = a.t.gpxi[((long)g * DIM + j) * N + cell];
-    T val[NV];
-    poly_at<DIM, R, NV, T>(xi, co, c0, val);
+    for (int p = 0; p < PB; ++p) {
+      const int g = g0 + p * G;
+      if (g < ng) {
+        T val[NV];
+        poly_at<DIM, R, NV, T>(xs[p], co, c0, val);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      exc[v] = fmax(exc[v], fmax(mn[v] - val[v], val[v] - mx[v]));
+        for (int v = 0; v < NV; ++v) exc[v] = fmax(exc[v], fmax(mn[v] - val[v], val[v] - mx[v]));
+        hok = hok && harten_point<NV, T>(val, rho_b, p_b, a);
+        if (a.margin) mg = fmin(mg, harten_margin<NV, T>(val, rho_b, p_b, a));
+#pragma unroll
+        for (int v = 0; v < NV; ++v) store<NV, T>(a, g, cell, v, val[v]);
+      }
     }
-    hok = hok && harten_point<NV, T>(val, rho_b, p_b, a);
-    if (a.margin) mg = fmin(mg, harten_margin<NV, T>(val, rho_b, p_b, a));
-#pragma unroll
-    for (int v = 0; v < NV; ++v) store<NV, T>(a, g, cell, v, val[v]);
   }
 #pragma unroll
   for (int v = 0; v < NV; ++v) exc[v] = xor_max<G>(exc[v]);
@@ -608,25 +617,28 @@ __device__ __forceinline__ void muscl_cell(const HotArgs<T> &a, int cell, const 
   T th[VPL];
 #pragma unroll
   for (int q = 0; q < VPL; ++q) th[q] = (T)1;
-#pragma unroll 4
-  for (int g = 0; g < ng; ++g) {
-    T phi[DIM];
+  for (int g0 = 0; g0 < ng; g0 += GP_BATCH) {
+    T xs[GP_BATCH][DIM];
+    load_points<GP_BATCH, DIM, T>(a, cell, g0, 1, ng, xs);
 #pragma unroll
-    for (int j = 0; j < DIM; ++j) phi[j] = a.t.gpxi[((long)g * DIM + j) * N + cell] - psb[j];
+    for (int p = 0; p < GP_BATCH; ++p) {
+      if (g0 + p < ng) {
 #pragma unroll
-    for (int q = 0; q < VPL; ++q) {
-      T d = 0;
+        for (int q = 0; q < VPL; ++q) {
+          T d = 0;
 #pragma unroll
-      for (int j = 0; j < DIM; ++j) d += gr[j][q] * phi[j];
-      T ratio = (T)1;
-      if (d != 0) {
-        const T dp = (d > 0 ? mx[q] : mn[q]) - u0[q];   // room to the bound in the direction of d
-        if (venkat)   // smooth limiter function of Venkatakrishnan (1995)
-          ratio = ((dp * dp + e2) * d + (T)2 * d * d * dp) / (d * (dp * dp + (T)2 * d * d + dp * d + e2));
-        else          // Barth-Jespersen
-          ratio = fmin((T)1, dp / d);
+          for (int j = 0; j < DIM; ++j) d += gr[j][q] * (xs[p][j] - psb[j]);
+          T ratio = (T)1;
+          if (d != 0) {
+            const T dp = (d > 0 ? mx[q] : mn[q]) - u0[q];   // room to the bound in the direction of d
+            if (venkat)   // smooth limiter function of Venkatakrishnan (1995)
+              ratio = ((dp * dp + e2) * d + (T)2 * d * d * dp) / (d * (dp * dp + (T)2 * d * d + dp * d + e2));
+            else          // Barth-Jespersen
+              ratio = fmin((T)1, dp / d);
+          }
+          th[q] = fmin(th[q], ratio);
+        }
       }
-      th[q] = fmin(th[q], ratio);
     }
   }
   T all0[NV];
@@ -636,24 +648,27 @@ __device__ __forceinline__ void muscl_cell(const HotArgs<T> &a, int cell, const 
   // limited states and their Harten check; the rare failure rewrites the
   // cell's points with the first-order state afterwards
   bool hok = true;
-#pragma unroll 4
-  for (int g = 0; g < ng; ++g) {
-    T phi[DIM];
+  for (int g0 = 0; g0 < ng; g0 += GP_BATCH) {
+    T xs[GP_BATCH][DIM];
+    load_points<GP_BATCH, DIM, T>(a, cell, g0, 1, ng, xs);
 #pragma unroll
-    for (int j = 0; j < DIM; ++j) phi[j] = a.t.gpxi[((long)g * DIM + j) * N + cell] - psb[j];
-    T val[VPL];
+    for (int p = 0; p < GP_BATCH; ++p) {
+      if (g0 + p < ng) {
+        T val[VPL];
 #pragma unroll
-    for (int q = 0; q < VPL; ++q) {
-      T d = 0;
+        for (int q = 0; q < VPL; ++q) {
+          T d = 0;
 #pragma unroll
-      for (int j = 0; j < DIM; ++j) d += gr[j][q] * phi[j];
-      val[q] = u0[q] + th[q] * d;
+          for (int j = 0; j < DIM; ++j) d += gr[j][q] * (xs[p][j] - psb[j]);
+          val[q] = u0[q] + th[q] * d;
+        }
+        T all[NV];
+        group_state<NV, G, T>(val, all, L.base);
+        hok = hok && (a.frozen || harten_point<NV, T>(all, rho_b, p_b, a));
+#pragma unroll
+        for (int q = 0; q < VPL; ++q) store<NV, T>(a, g0 + p, cell, v0 + q, val[q]);
+      }
     }
-    T all[NV];
-    group_state<NV, G, T>(val, all, L.base);
-    hok = hok && (a.frozen || harten_point<NV, T>(all, rho_b, p_b, a));
-#pragma unroll
-    for (int q = 0; q < VPL; ++q) store<NV, T>(a, g, cell, v0 + q, val[q]);
   }
   if (!hok) {
     for (int g = 0; g < ng; ++g)
@@ -822,32 +837,40 @@ __global__ __launch_bounds__(256) void k_cwenoz(HotArgs<T> a, int direct) {
     for (int k = 0; k < K; ++k) psb[k] = a.t.psibar[(long)k * N + cell];
     const int ng = a.t.ngp[cell];
     bool hok = true;
-    for (int g = 0; g < ng; ++g) {
-      T xi[DIM];
+    // points one at a time in FP64 with one or two lanes per cell (measured:
+    // batched loads made that kernel's schedule slower, 61 -> 85 us on the
+    // 85k-cell mixed mesh; faster everywhere else)
+    constexpr int PB = (sizeof(T) == 8 && G <= 2) ? 1 : GP_BATCH;
+    for (int g0 = 0; g0 < ng && hok; g0 += PB) {
+      T xs[PB][DIM];
+      load_points<PB, DIM, T>(a, cell, g0, 1, ng, xs);
 #pragma unroll
-      for (int j = 0; j < DIM; ++j) xi[j] = a.t.gpxi[((long)g * DIM + j) * N + cell];
-      T phi[K];
-      basis_at<DIM, R, T>(xi, psb, phi);
-      T val[VPL];
+      for (int p = 0; p < PB; ++p) {
+        if (g0 + p < ng && hok) {
+          T phi[K];
+          basis_at<DIM, R, T>(xs[p], psb, phi);
+          T val[VPL];
 #pragma unroll
-      for (int q = 0; q < VPL; ++q) {
-        T s = 0;
+          for (int q = 0; q < VPL; ++q) {
+            T s = 0;
 #pragma unroll
-        for (int k = 0; k < K; ++k) s += co[k][q] * phi[k];
-        val[q] = u0[q] + s;
-      }
-      T all[NV];
-      group_state<NV, G, T>(val, all, L.base);
-      hok = a.frozen || (hok && harten_point<NV, T>(all, rho_b, p_b, a));
+            for (int k = 0; k < K; ++k) s += co[k][q] * phi[k];
+            val[q] = u0[q] + s;
+          }
+          T all[NV];
+          group_state<NV, G, T>(val, all, L.base);
+          hok = a.frozen || harten_point<NV, T>(all, rho_b, p_b, a);
 #pragma unroll
-      for (int q = 0; q < VPL; ++q) store<NV, T>(a, g, cell, v0 + q, hok ? val[q] : u0[q]);
-      if (!hok) {
-        // first-order fallback: overwrite every point of the cell with U_i
-        for (int g2 = 0; g2 < ng; ++g2) {
-#pragma unroll
-          for (int q = 0; q < VPL; ++q) store<NV, T>(a, g2, cell, v0 + q, u0[q]);
+          for (int q = 0; q < VPL; ++q) store<NV, T>(a, g0 + p, cell, v0 + q, val[q]);
         }
-        break;
+      }
+    }
+    if (!hok) {
+      // first-order fallback: every point of the cell takes U_i (the points
+      // after the failing one were not evaluated)
+      for (int g = 0; g < ng; ++g) {
+#pragma unroll
+        for (int q = 0; q < VPL; ++q) store<NV, T>(a, g, cell, v0 + q, u0[q]);
       }
     }
     if (L.sub == 0 && !a.frozen) a.cls[cell] = hok ? HFV_CLASS_CWENOZ : HFV_CLASS_FIRST_ORDER;
