@@ -366,12 +366,13 @@ hfv_status hfv_get_launch(const hfv_ctx *ctx, hfv_launch *cfg);
  * candidate launch configurations, searched one coordinate at a time (linear
  * kernel mapping; class-list kernel lanes, block and grid;
  * CWENOZ reuse in hybrid mode; fused or two-kernel residual; XCD block
- * order; MUSCL lanes in hybrid mode), and keeps the
- * fastest (median of `reps`
- * timed calls after one untimed call, reps in [1, 1000]).  Synchronous; it
+ * order; in hybrid mode the MUSCL and first-order lists merged into the
+ * CWENOZ launch, else their lanes), and keeps the fastest (after one untimed
+ * call, three batches of `reps` calls back to back, reps in [1, 1000]; the
+ * median batch's time per call).  Synchronous; it
  * allocates and frees one residual-sized buffer.  `best` (may be NULL)
  * receives the chosen configuration, which is also applied; up to
- * `max_records` (configuration, median ms) pairs go to `records` (may be NULL
+ * `max_records` (configuration, ms per call) pairs go to `records` (may be NULL
  * when max_records is 0) and the number of configurations timed to
  * `*n_records` (may be NULL).  On failure the starting configuration is
  * restored. */
@@ -382,9 +383,14 @@ typedef struct {
 hfv_status hfv_autotune(hfv_ctx *ctx, const void *U, int32_t reps, hfv_launch *best, hfv_tune_record *records,
                         int32_t max_records, int32_t *n_records, void *stream);
 
-/* Kernel timing with HIP events recorded on the launch stream.
+/* Kernel timing with HIP events recorded on the launch stream (timing-only
+ * events: recording them issues no system-scope memory fence, so the caches
+ * are not written back in the middle of a step; they order nothing).
  * hfv_profile_enable arms up to `capacity` timed launches of the kernels
  * selected by `slot_mask` (bit i = HFV_SLOT_i); capacity 0 disables.
+ * HFV_SLOT_CWENOZ times the CWENOZ launch, which also serves the MUSCL and
+ * first-order lists when merged_lists is 1 (HFV_SLOT_MUSCL then records
+ * nothing in hybrid mode).
  * hfv_profile_read synchronises on the recorded events, writes per-slot sums
  * of the launch durations in milliseconds and launch counts (arrays of
  * HFV_NSLOTS), and re-arms the buffer.  HFV_SLOT_MUSCL times the kernel that

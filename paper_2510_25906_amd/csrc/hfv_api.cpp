@@ -450,7 +450,10 @@ hfv_status hfv_profile_enable(hfv_ctx *ctx, int32_t capacity, int32_t slot_mask)
   ctx->prof_mask = capacity > 0 ? slot_mask : 0;
   for (int i = 0; i < capacity; ++i) {
     hfv_ctx::ProfEv e{0, nullptr, nullptr};
-    if (hipEventCreate(&e.a) != hipSuccess || hipEventCreate(&e.b) != hipSuccess) {
+    // timing-only events: no system-scope fence, so recording one does not
+    // write back and invalidate the caches in the middle of the step
+    if (hipEventCreateWithFlags(&e.a, hipEventDisableSystemFence) != hipSuccess ||
+        hipEventCreateWithFlags(&e.b, hipEventDisableSystemFence) != hipSuccess) {
       ctx->err = "hipEventCreate failed";
       return HFV_ERR_HIP;
     }

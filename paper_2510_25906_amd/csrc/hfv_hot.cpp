@@ -509,10 +509,15 @@ __global__ __launch_bounds__(256) void k_linear_ks(HotArgs<T> a) {
   }
 }
 
-// K2: final class (dilation over face neighbours) and per-class lists.
+// K2: final class (dilation over face neighbours) and per-class lists.  The
+// neighbour rows are read all at once (rows past a cell's face count hold
+// -1, like boundary faces), not in a loop over the cell's count, whose loads
+// would wait on one another.  Blocks of 1024: each block reserves its range
+// of a list with one atomic on the list's length, and on the 1M-cell mixed
+// box blocks of 256 made those atomics the bottleneck (24 -> 50 us).
 constexpr int CLASSIFY_BLOCK = 1024;
-template <typename T>
-__global__ __launch_bounds__(CLASSIFY_BLOCK) void k_classify(HotArgs<T> a, int nfm) {
+template <typename T, int NFM>
+__global__ __launch_bounds__(CLASSIFY_BLOCK) void k_classify(HotArgs<T> a) {
   const int cell = (int)(block_id(a.xcd) * blockDim.x + threadIdx.x);
   const bool valid = cell < a.N;
   int c = 0;
@@ -522,11 +527,12 @@ __global__ __launch_bounds__(CLASSIFY_BLOCK) void k_classify(HotArgs<T> a, int n
     const int o = a.own[cell];
     c = o & 3;
     if (a.mode == HFV_HYBRID) {
-      const int nf = a.t.nfc[cell];
-      for (int f = 0; f < nf; ++f) {
-        const int j = a.t.nbr[(long)f * a.N + cell];
-        if (j >= 0) c = max(c, a.own[j] & 3);
-      }
+      int nb[NFM];
+#pragma unroll
+      for (int f = 0; f < NFM; ++f) nb[f] = a.t.nbr[(long)f * a.N + cell];
+#pragma unroll
+      for (int f = 0; f < NFM; ++f)
+        if (nb[f] >= 0) c = max(c, a.own[nb[f]] & 3);
     } else {
       c = HFV_CLASS_LINEAR;
     }
@@ -1056,6 +1062,11 @@ __global__ __launch_bounds__(256) void k_fill(T *x, int n, T v) {
 
 // The linear + NAD kernel in the configured mapping: variables (split 0),
 // stencil members (1) or unknowns (2) per lane, lin_lanes lanes per cell.
+template <int DIM, typename T>
+static void launch_classify(const hfv_ctx *ctx, const HotArgs<T> &a, hipStream_t s) {
+  k_classify<T, nf_max(DIM)><<<nblk(ctx->N, CLASSIFY_BLOCK), CLASSIFY_BLOCK, 0, s>>>(a);
+}
+
 template <int DIM, int R, typename T>
 static void launch_linear(const hfv_ctx *ctx, const HotArgs<T> &a, hipStream_t s) {
   const int B = ctx->block, GL = ctx->lin_lanes;
@@ -1133,7 +1144,7 @@ static hfv_status recon_impl(hfv_ctx *ctx, Tables<T> &t, const void *U, void *fs
     { ProfScope ps(ctx, HFV_SLOT_MUSCL, s); launch_muscl<DIM, R, T>(ctx, a, 1, s); }
   } else {
     { ProfScope ps(ctx, HFV_SLOT_LINEAR, s); launch_linear<DIM, R, T>(ctx, a, s); }
-    { ProfScope ps(ctx, HFV_SLOT_CLASSIFY, s); k_classify<T><<<nblk(ctx->N, CLASSIFY_BLOCK), CLASSIFY_BLOCK, 0, s>>>(a, ctx->NFM); }
+    { ProfScope ps(ctx, HFV_SLOT_CLASSIFY, s); launch_classify<DIM, T>(ctx, a, s); }
     // the MUSCL and first-order lists ride in the CWENOZ launch when merged
     const int merged = mode == HFV_HYBRID && !chr && ctx->merged_lists;
     if (mode == HFV_HYBRID) {
@@ -1176,7 +1187,7 @@ static hfv_status frozen_impl(hfv_ctx *ctx, Tables<T> &t, const void *U, void *f
   const unsigned grid_list =
       ctx->list_blocks > 0 ? std::min<unsigned>(grid_cells, (unsigned)ctx->list_blocks) : grid_cells;
   launch_linear<DIM, R, T>(ctx, a, s);
-  k_classify<T><<<nblk(ctx->N, CLASSIFY_BLOCK), CLASSIFY_BLOCK, 0, s>>>(a, ctx->NFM);
+  launch_classify<DIM, T>(ctx, a, s);
   if (ctx->p.cvars == HFV_CHARACTERISTIC) {
     hfv_status e = launch_cwenoz_char<T>(ctx, a, 0, s);
     if (e != HFV_OK) return e;
@@ -1313,7 +1324,10 @@ static hfv_status lists_t(hfv_ctx *ctx, Tables<T> &t, const uint8_t *cls, hipStr
   a.frozen = 1;
   a.cls_in = cls;
   k_zero_counts<<<1, 64, 0, s>>>(ctx->counts);
-  k_classify<T><<<nblk(ctx->N, CLASSIFY_BLOCK), CLASSIFY_BLOCK, 0, s>>>(a, ctx->NFM);
+  if (ctx->dim == 2)
+    launch_classify<2, T>(ctx, a, s);
+  else
+    launch_classify<3, T>(ctx, a, s);
   HFV_HIP(hipGetLastError());
   return HFV_OK;
 }

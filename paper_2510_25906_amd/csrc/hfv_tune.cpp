@@ -17,8 +17,8 @@
 //   6. in hybrid mode, the MUSCL and first-order lists inside the CWENOZ
 //      launch against a launch of their own;
 //   7. in hybrid mode, when that launch is kept, its own lane count.
-// Each candidate runs once untimed, then `reps` times with HIP events around
-// each call; its score is the median.
+// Each candidate runs once untimed, then three batches of `reps` calls back
+// to back between HIP events; its score is the median batch's time per call.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -36,22 +36,26 @@ struct Tuner {
   hipEvent_t ea, eb;
   std::vector<hfv_tune_record> rec;
 
-  // median residual time of configuration c in ms; +inf when c is rejected
+  // residual time of configuration c in ms: three batches of `reps` calls
+  // back to back (as a time loop runs them), the median batch's time per
+  // call; +inf when c is rejected
   double time(const hfv_launch &c) {
     if (hfv_set_launch(ctx, &c) != HFV_OK) return INFINITY;
     if (hfv_residual(ctx, U, R, nullptr, nullptr, s) != HFV_OK) return INFINITY;
     if (hipStreamSynchronize(s) != hipSuccess) return INFINITY;
     std::vector<float> t;
-    for (int i = 0; i < reps; ++i) {
+    for (int i = 0; i < 3; ++i) {
       float ms = 0;
-      if (hipEventRecord(ea, s) != hipSuccess || hfv_residual(ctx, U, R, nullptr, nullptr, s) != HFV_OK ||
-          hipEventRecord(eb, s) != hipSuccess || hipEventSynchronize(eb) != hipSuccess ||
+      if (hipEventRecord(ea, s) != hipSuccess) return INFINITY;
+      for (int j = 0; j < reps; ++j)
+        if (hfv_residual(ctx, U, R, nullptr, nullptr, s) != HFV_OK) return INFINITY;
+      if (hipEventRecord(eb, s) != hipSuccess || hipEventSynchronize(eb) != hipSuccess ||
           hipEventElapsedTime(&ms, ea, eb) != hipSuccess)
         return INFINITY;
-      t.push_back(ms);
+      t.push_back(ms / reps);
     }
     std::sort(t.begin(), t.end());
-    const double med = t[t.size() / 2];
+    const double med = t[1];
     rec.push_back(hfv_tune_record{c, med});
     return med;
   }
@@ -89,7 +93,9 @@ extern "C" hfv_status hfv_autotune(hfv_ctx *ctx, const void *U, int32_t reps, hf
   if (hipMalloc(&tu.R, rbytes) != hipSuccess) {
     ctx->err = "autotune: residual buffer allocation failed";
     st = HFV_ERR_OOM;
-  } else if (hipEventCreate(&tu.ea) != hipSuccess || hipEventCreate(&tu.eb) != hipSuccess) {
+  } else if (hipEventCreateWithFlags(&tu.ea, hipEventDisableSystemFence) != hipSuccess ||
+             hipEventCreateWithFlags(&tu.eb, hipEventDisableSystemFence) != hipSuccess) {
+    // timing-only events (no cache write-back and invalidation at each record)
     ctx->err = "autotune: event creation failed";
     st = HFV_ERR_HIP;
   }
