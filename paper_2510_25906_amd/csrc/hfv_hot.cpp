@@ -33,10 +33,14 @@ __device__ inline void keep_fit(const HotArgs<T> &a, int cell, int v0, const T (
     for (int q = 0; q < VPL; ++q) a.coef[((long)k * NV + v0 + q) * a.N + cell] = co[k][q];
 }
 
-// K1: linear candidate, face states, NAD own class, Harten flag.
-template <int DIM, int R, typename T, int G>
+// K1: linear candidate, face states, NAD own class, Harten flag.  MG: the
+// near_margin output is computed (a variant of its own: its code, even
+// unexecuted, was allocated registers that cost the plain kernel occupancy,
+// 3D r = 4 FP64 five lanes 168 -> 204 VGPRs, 3 -> 2 waves/SIMD).
+template <int DIM, int R, typename T, int G, bool MG>
 __global__ __launch_bounds__(256) void k_linear(HotArgs<T> a) {
   constexpr int NV = DIM + 2, K = n_unknowns(DIM, R), VPL = NV / G, NFM = nf_max(DIM);
+  if constexpr (!MG) a.margin = nullptr;
   if (blockIdx.x == 0 && threadIdx.x < 8) a.counts[threadIdx.x] = 0;
   Lane<G> L(a.xcd);
   const int cell = L.item;
@@ -158,9 +162,10 @@ __device__ inline V xor_min(V x) {
   return x;
 }
 
-template <int DIM, int R, typename T, int G>
+template <int DIM, int R, typename T, int G, bool MG>
 __global__ __launch_bounds__(256) void k_linear_ms(HotArgs<T> a) {
   constexpr int NV = DIM + 2, K = n_unknowns(DIM, R), M = 2 * K, NFM = nf_max(DIM);
+  if constexpr (!MG) a.margin = nullptr;
   constexpr int MPL = (M + G - 1) / G;
   static_assert((G & (G - 1)) == 0 && 64 % G == 0, "group size must be a power of two");
   if (blockIdx.x == 0 && threadIdx.x < 8) a.counts[threadIdx.x] = 0;
@@ -303,9 +308,10 @@ __global__ __launch_bounds__(256) void k_linear_ms(HotArgs<T> a) {
 // partial sums of its unknowns at the G points, and a butterfly
 // reduce-scatter over the group leaves lane q with the full state at point q
 // of the batch, which it checks (NAD excursion, Harten) and stores.
-template <int DIM, int R, typename T, int G>
+template <int DIM, int R, typename T, int G, bool MG>
 __global__ __launch_bounds__(256) void k_linear_ks(HotArgs<T> a) {
   constexpr int NV = DIM + 2, K = n_unknowns(DIM, R), M = 2 * K, NFM = nf_max(DIM);
+  if constexpr (!MG) a.margin = nullptr;
   constexpr int KPL = (K + G - 1) / G;
   constexpr Exps<DIM, 1, R> E{};
   static_assert((G & (G - 1)) == 0 && G >= 2 && 64 % G == 0, "group size must be a power of two");
@@ -1067,24 +1073,31 @@ static void launch_classify(const hfv_ctx *ctx, const HotArgs<T> &a, hipStream_t
   k_classify<T, nf_max(DIM)><<<nblk(ctx->N, CLASSIFY_BLOCK), CLASSIFY_BLOCK, 0, s>>>(a);
 }
 
-template <int DIM, int R, typename T>
-static void launch_linear(const hfv_ctx *ctx, const HotArgs<T> &a, hipStream_t s) {
+template <int DIM, int R, typename T, bool MG>
+static void launch_linear_mg(const hfv_ctx *ctx, const HotArgs<T> &a, hipStream_t s) {
   const int B = ctx->block, GL = ctx->lin_lanes;
   const long waves = ((long)ctx->N + 64 / GL - 1) / (64 / GL);
   const unsigned grid = nblk(waves * 64, B);
   switch (ctx->lin_split * 16 + GL) {
-    case 1: k_linear<DIM, R, T, 1><<<grid, B, 0, s>>>(a); break;
+    case 1: k_linear<DIM, R, T, 1, MG><<<grid, B, 0, s>>>(a); break;
     case 2:
-      if constexpr (DIM == 2) k_linear<DIM, R, T, 2><<<grid, B, 0, s>>>(a);
+      if constexpr (DIM == 2) k_linear<DIM, R, T, 2, MG><<<grid, B, 0, s>>>(a);
       break;
-    case DIM + 2: k_linear<DIM, R, T, DIM + 2><<<grid, B, 0, s>>>(a); break;
-    case 16 + 2: k_linear_ms<DIM, R, T, 2><<<grid, B, 0, s>>>(a); break;
-    case 16 + 4: k_linear_ms<DIM, R, T, 4><<<grid, B, 0, s>>>(a); break;
-    case 16 + 8: k_linear_ms<DIM, R, T, 8><<<grid, B, 0, s>>>(a); break;
-    case 32 + 2: k_linear_ks<DIM, R, T, 2><<<grid, B, 0, s>>>(a); break;
-    case 32 + 4: k_linear_ks<DIM, R, T, 4><<<grid, B, 0, s>>>(a); break;
-    case 32 + 8: k_linear_ks<DIM, R, T, 8><<<grid, B, 0, s>>>(a); break;
+    case DIM + 2: k_linear<DIM, R, T, DIM + 2, MG><<<grid, B, 0, s>>>(a); break;
+    case 16 + 2: k_linear_ms<DIM, R, T, 2, MG><<<grid, B, 0, s>>>(a); break;
+    case 16 + 4: k_linear_ms<DIM, R, T, 4, MG><<<grid, B, 0, s>>>(a); break;
+    case 16 + 8: k_linear_ms<DIM, R, T, 8, MG><<<grid, B, 0, s>>>(a); break;
+    case 32 + 2: k_linear_ks<DIM, R, T, 2, MG><<<grid, B, 0, s>>>(a); break;
+    case 32 + 4: k_linear_ks<DIM, R, T, 4, MG><<<grid, B, 0, s>>>(a); break;
+    case 32 + 8: k_linear_ks<DIM, R, T, 8, MG><<<grid, B, 0, s>>>(a); break;
   }
+}
+template <int DIM, int R, typename T>
+static void launch_linear(const hfv_ctx *ctx, const HotArgs<T> &a, hipStream_t s) {
+  if (a.margin)
+    launch_linear_mg<DIM, R, T, true>(ctx, a, s);
+  else
+    launch_linear_mg<DIM, R, T, false>(ctx, a, s);
 }
 
 // The MUSCL / first-order pass with its own lane count (muscl_lanes, or the
