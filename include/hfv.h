@@ -364,10 +364,11 @@ hfv_status hfv_get_launch(const hfv_ctx *ctx, hfv_launch *cfg);
 /* Autotuner (a project addition, not in the paper): times hfv_residual on the
  * caller's state U (device [nvar][n_cells]) under the current parameters for
  * candidate launch configurations, searched one coordinate at a time (linear
- * kernel mapping; class-list kernel lanes, block and grid;
- * CWENOZ reuse in hybrid mode; fused or two-kernel residual; XCD block
- * order; in hybrid mode the MUSCL and first-order lists merged into the
- * CWENOZ launch, else their lanes), and keeps the fastest (after one untimed
+ * kernel mapping; class-list kernel lanes, block and grid, in hybrid mode
+ * jointly with CWENOZ reuse and with the MUSCL and first-order lists merged
+ * into the CWENOZ launch; fused or two-kernel residual; XCD block order; in
+ * hybrid mode, without merged lists, the MUSCL lanes), and keeps the fastest
+ * (after one untimed
  * call, three batches of `reps` calls back to back, reps in [1, 1000]; the
  * median batch's time per call).  Synchronous; it
  * allocates and frees one residual-sized buffer.  `best` (may be NULL)

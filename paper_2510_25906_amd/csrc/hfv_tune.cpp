@@ -8,15 +8,17 @@
 //   1. the linear + NAD kernel's mapping: variables (1, 2 in 2D, nvar lanes),
 //      stencil members or unknowns (2, 4, 8 lanes) per cell;
 //   2. the class-list kernels: lanes per cell x block x grid (capped and
-//      striding, or one list entry per lane group)
+//      striding, or one list entry per lane group), in hybrid mode jointly
+//      with whether CWENOZ reuses the linear pass's central fits and whether
+//      the MUSCL and first-order lists ride in the CWENOZ launch (the best
+//      lane count depends on both: FP64 on the 85k-cell mesh, two lanes
+//      refitting and four lanes reusing are each best for their own setting)
 //      (skipped when no cell can reach a class list's kernels in numbers,
 //      i.e. in all-linear mode, where only first-order cells use them);
-//   3. in hybrid mode, whether CWENOZ reuses the linear pass's central fits;
-//   4. the fused (owner-computes) residual kernel against face fluxes + gather;
-//   5. XCD-contiguous block order against plain block order;
-//   6. in hybrid mode, the MUSCL and first-order lists inside the CWENOZ
-//      launch against a launch of their own;
-//   7. in hybrid mode, when that launch is kept, its own lane count.
+//   3. the fused (owner-computes) residual kernel against face fluxes + gather;
+//   4. XCD-contiguous block order against plain block order;
+//   5. in hybrid mode, when the MUSCL lists keep a launch of their own, its
+//      lane count.
 // Each candidate runs once untimed, then three batches of `reps` calls back
 // to back between HIP events; its score is the median batch's time per call.
 #include <algorithm>
@@ -127,45 +129,41 @@ extern "C" hfv_status hfv_autotune(hfv_ctx *ctx, const void *U, int32_t reps, hf
         cands.push_back(c);
       }
     tu.pick(cands, best, best_ms);
-    // 2. class-list kernels and block size
+    // 2. class-list kernels and block size (with fit reuse and merged lists
+    // in hybrid mode)
     if (ctx->p.mode != HFV_ALL_LINEAR) {
+      const bool hyb = ctx->p.mode == HFV_HYBRID;
       cands.clear();
-      for (int l : var_lanes)
-        for (int b : {128, 256})
-          for (int lb : {0, 4, 8, 16}) {
-            hfv_launch c = best;
-            c.lanes_per_cell = l;
-            c.block = b;
-            c.list_blocks = lb * ctx->n_cu;
-            cands.push_back(c);
-          }
+      for (int reuse = 0; reuse <= (hyb ? 1 : 0); ++reuse)
+        for (int merged = 0; merged <= (hyb ? 1 : 0); ++merged)
+          for (int l : var_lanes)
+            for (int b : {128, 256})
+              for (int lb : {0, 4, 8, 16}) {
+                hfv_launch c = best;
+                c.lanes_per_cell = l;
+                c.block = b;
+                c.list_blocks = lb * ctx->n_cu;
+                if (hyb) {
+                  c.cwenoz_reuse = reuse;
+                  c.merged_lists = merged;
+                }
+                cands.push_back(c);
+              }
       tu.pick(cands, best, best_ms);
     }
-    // 3. CWENOZ reuse of the central fits
-    if (ctx->p.mode == HFV_HYBRID) {
-      hfv_launch c = best;
-      c.cwenoz_reuse = 1 - best.cwenoz_reuse;
-      tu.pick({c}, best, best_ms);
-    }
-    // 4. residual kernel(s)
+    // 3. residual kernel(s)
     {
       hfv_launch c = best;
       c.fused_residual = 1 - best.fused_residual;
       tu.pick({c}, best, best_ms);
     }
-    // 5. block order
+    // 4. block order
     {
       hfv_launch c = best;
       c.xcd_remap = 1 - best.xcd_remap;
       tu.pick({c}, best, best_ms);
     }
-    // 6. MUSCL and first-order lists merged into the CWENOZ launch
-    if (ctx->p.mode == HFV_HYBRID) {
-      hfv_launch c = best;
-      c.merged_lists = 1 - best.merged_lists;
-      tu.pick({c}, best, best_ms);
-    }
-    // 7. MUSCL lanes (0 = as the other class-list kernels)
+    // 5. MUSCL lanes (0 = as the other class-list kernels)
     if (ctx->p.mode == HFV_HYBRID && !best.merged_lists) {
       cands.clear();
       for (int l : var_lanes)

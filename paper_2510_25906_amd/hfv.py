@@ -238,7 +238,7 @@ class Context:
         cur.update({k: int(v) for k, v in new.items() if v is not None})
         self._check(self.lib.hfv_set_launch(self.h, C.byref(HfvLaunch(**cur))))
 
-    def autotune(self, U, reps: int = 5, max_records: int = 64):
+    def autotune(self, U, reps: int = 5, max_records: int = 256):
         """Pick the fastest launch configuration for this state and the current
         parameters (applied); returns (chosen configuration, [(configuration, ms)])."""
         self._chk_u(U)
