@@ -301,7 +301,9 @@ def fp32_error(ref, fs32, cls32, ngp, U, face_cells=None):
     equal class, relative to the variable's largest cell average, and the number
     of cells whose class differs (FP32 flips near an NAD threshold).  With the
     FP64 path's near_margin in `ref` and the mesh's face_cells, also the flips
-    in cells neither within 1e-6 of a threshold nor next to such a cell."""
+    in cells neither within 1e-6 of a threshold nor next to such a cell, and
+    the flag level every flip does meet: the largest over the flipped cells of
+    the smallest margin of the cell and its face neighbours."""
     fs64, cls64 = ref[0], ref[1]
     margin = ref[2] if len(ref) > 2 else None
     same = cls64 == cls32
@@ -321,6 +323,10 @@ def fp32_error(ref, fs32, cls32, ngp, U, face_cells=None):
         np.logical_or.at(flagged, b, small[a])
         out["fp32_flips_unflagged"] = int((~same & ~flagged).sum())
         out["cells_margin_le_1e-6"] = int(small.sum())
+        near = margin.astype(np.float64).copy()
+        np.minimum.at(near, a, margin[b])
+        np.minimum.at(near, b, margin[a])
+        out["fp32_flip_margin_max"] = float(f"{near[~same].max():.3g}") if (~same).any() else None
     return out
 
 

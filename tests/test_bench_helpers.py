@@ -76,6 +76,8 @@ def test_fp32_flips_split_by_margin():
                            face_cells)
     assert out["fp32_class_flips"] == 2 and out["fp32_flips_unflagged"] == 1
     assert out["cells_margin_le_1e-6"] == 1
+    # flip 1 sits next to cell 0 (margin 1e-7), flip 4 among cells at 0.3
+    assert out["fp32_flip_margin_max"] == 0.3
 
 
 def test_kernel_names_follow_the_launch():
