@@ -9,10 +9,11 @@
 * The ~1M-cell mixed tetrahedron / pyramid / prism / hexahedron box under its
   tuned FP32 launch: sampled cells of every element type.
 
-Bars as in the other parity tests: FP64 classes bit-exact, states within
-1e-12 of max(|x_ref|, S_v), residuals within 1e-11 of the variable's largest
-|R|; FP32 states within 1e-5, class flips only in cells within 1e-6 of a
-threshold or their face neighbours (states of flipped cells excluded).
+Bars: FP64 classes bit-exact, states within 1e-12 of max(|x_ref|, S_v),
+residuals within 1e-12 of the variable's largest |R| (the other parity tests
+allow 1e-11 for residuals); FP32 states within 1e-5, class flips only in
+cells within 1e-6 of a threshold or their face neighbours (states of flipped
+cells excluded).
 """
 import numpy as np
 import pytest
@@ -62,7 +63,9 @@ def check_all_cells(ctx, w, om, ref, prec, label):
         print(f"{label}: launch {ctx.get_launch()}, classes {np.bincount(cls_g, minlength=4)}, "
               f"state error {es:.2e}, residual error {er:.2e}", flush=True)
         assert bad.size == 0, bad[:20]
-        assert es <= 1e-12 and er <= 1e-11
+        # residual bar 1e-12 here (1e-11 in the broader parity tests, whose
+        # meshes include near-cancelling face sums); measured <= 2e-15
+        assert es <= 1e-12 and er <= 1e-12
     else:
         cells = np.arange(N)
         flip = cls_g != cls_o
@@ -134,10 +137,15 @@ def test_c2_headline_launches(hfv, c2_small, prec, cfg):
     ctx.close()
 
 
-def test_c4_full_size_sampled_tuned(hfv):
+@pytest.fixture(scope="module")
+def c4_full():
+    return configs.c4_mixed("full", workers=8)
+
+
+def test_c4_full_size_sampled_tuned(hfv, c4_full):
     """The ~1M-cell mixed box under its tuned FP32 launch (and FP64 under its
     own): sampled cells of every element type, both classes and states."""
-    w = configs.c4_mixed("full", workers=8)
+    w = c4_full
     om = OracleModel(w.mesh, w.stencils, w.params)
     rng = np.random.default_rng(13)
     ct = w.mesh.cell_type
@@ -170,3 +178,36 @@ def test_c4_full_size_sampled_tuned(hfv):
         del fs, cls
         ctx.close()
         torch.cuda.empty_cache()
+
+
+def test_c4_full_size_fp32_flips_near_thresholds(hfv, c4_full):
+    """Every cell of the ~1M-cell mixed box: the FP32 path's classes against
+    the FP64 path's (which the parity tests tie to the oracle), with the FP64
+    path's own near_margin.  Every flip lies in a cell within 1e-5 of a
+    threshold (the FP32 state bar) or next to one; the flips outside the
+    1e-6 flag are counted and reported (rounding U to FP32, 3e-8 of |U|, is
+    amplified by the r = 3 reconstruction to the ~2e-6 state error that sets
+    how close to a threshold a decision can go either way)."""
+    w = c4_full
+    N = w.mesh.n_cells
+    res = {}
+    for prec in (64, 32):
+        ctx = hfv.Context(w.mesh, w.stencils, w.params, prec)
+        dt = torch.float64 if prec == 64 else torch.float32
+        mg = torch.empty(N, dtype=dt, device="cuda")
+        fs, cls = ctx.reconstruct(to_dev(w.U, dt), near_margin=mg)
+        torch.cuda.synchronize()
+        res[prec] = (cls.cpu().numpy(), mg.double().cpu().numpy())
+        del fs, cls
+        ctx.close()
+        torch.cuda.empty_cache()
+    (c64, m64), (c32, _) = res[64], res[32]
+    fc = w.mesh.face_cells
+    inner = fc[:, 1] >= 0
+    near = m64.copy()                       # smallest margin of the cell and its face neighbours
+    np.minimum.at(near, fc[inner, 0], m64[fc[inner, 1]])
+    np.minimum.at(near, fc[inner, 1], m64[fc[inner, 0]])
+    flip = c64 != c32
+    print(f"c4 full: {int(flip.sum())} FP32 flips, {int((flip & (near > 1e-6)).sum())} outside the 1e-6 flag, "
+          f"largest flag level {near[flip].max() if flip.any() else 0:.2e}", flush=True)
+    assert not np.any(flip & (near > 1e-5)), np.nonzero(flip & (near > 1e-5))[0][:10]
