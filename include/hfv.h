@@ -367,8 +367,9 @@ hfv_status hfv_get_launch(const hfv_ctx *ctx, hfv_launch *cfg);
  * kernel mapping; class-list kernel lanes, block and grid, in hybrid mode
  * jointly with CWENOZ reuse and with the MUSCL and first-order lists merged
  * into the CWENOZ launch; fused or two-kernel residual; XCD block order; in
- * hybrid mode, without merged lists, the MUSCL lanes), and keeps the fastest
- * (after one untimed
+ * hybrid mode, without merged lists, the MUSCL lanes; then the four fastest
+ * configurations timed again), and keeps the fastest of that second timing
+ * (each timing: after one untimed
  * call, three batches of `reps` calls back to back, reps in [1, 1000]; the
  * median batch's time per call).  Synchronous; it
  * allocates and frees one residual-sized buffer.  `best` (may be NULL)

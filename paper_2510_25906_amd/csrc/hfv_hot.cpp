@@ -7,7 +7,8 @@
 //                check of the candidate (Eq. harten_jump_fix)
 //   k_classify   tagging of the flagged cells' von Neumann neighbourhood and
 //                wave-ballot / prefix compaction into per-class work lists
-//   k_cwenoz     CWENOZ on the class-1 list (Section 2.3)
+//   k_cwenoz     CWENOZ on the class-1 list (Section 2.3); with merged lists
+//                also the two lists below, in the same launch
 //   k_muscl      Barth-Jespersen limited MUSCL on the class-2 list (Section 2.2)
 //                and first-order states on the cells that failed the Harten check
 //   k_flux       HLLC / HLL flux integrated over each face's Gauss points

@@ -18,11 +18,15 @@
 //   3. the fused (owner-computes) residual kernel against face fluxes + gather;
 //   4. XCD-contiguous block order against plain block order;
 //   5. in hybrid mode, when the MUSCL lists keep a launch of their own, its
-//      lane count.
+//      lane count;
+//   6. the four fastest configurations timed so far are timed again and the
+//      fastest of that second timing is kept (among ~100 candidates the
+//      fastest first timing is as likely a fast outlier as a fast launch).
 // Each candidate runs once untimed, then three batches of `reps` calls back
 // to back between HIP events; its score is the median batch's time per call.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 #include "hfv_internal.hpp"
@@ -173,6 +177,32 @@ extern "C" hfv_status hfv_autotune(hfv_ctx *ctx, const void *U, int32_t reps, hf
           cands.push_back(c);
         }
       tu.pick(cands, best, best_ms);
+    }
+    // 6. confirmation of the fastest few
+    {
+      std::vector<hfv_tune_record> top(tu.rec);
+      std::sort(top.begin(), top.end(),
+                [](const hfv_tune_record &x, const hfv_tune_record &y) { return x.ms < y.ms; });
+      std::vector<hfv_launch> few;
+      for (const hfv_tune_record &r : top) {
+        bool seen = false;
+        for (const hfv_launch &c : few) seen = seen || std::memcmp(&c, &r.cfg, sizeof c) == 0;
+        if (!seen) few.push_back(r.cfg);
+        if (few.size() == 4) break;
+      }
+      double again_ms = INFINITY;
+      hfv_launch again = best;
+      for (const hfv_launch &c : few) {
+        const double ms = tu.time(c);
+        if (ms < again_ms) {
+          again_ms = ms;
+          again = c;
+        }
+      }
+      if (std::isfinite(again_ms)) {
+        best = again;
+        best_ms = again_ms;
+      }
     }
     if (hfv_set_launch(ctx, &best) != HFV_OK) st = HFV_ERR_PARAM;
   } else {
