@@ -716,10 +716,14 @@ __device__ __forceinline__ void first_order_cell(const HotArgs<T> &a, int cell, 
 // waves CWENOZ leaves idle instead of waiting for a launch of their own.
 // They run in a loop of their own after the CWENOZ loop (each lane continues
 // its item sequence there); a template parameter, so that the plain kernel's
-// code is not changed by them.
-template <int DIM, int R, typename T, int G, bool REUSE, bool MERGED>
+// code is not changed by them.  CM: OI is read from its cell-major copy (a
+// sparse list then reads each cell's entries from consecutive cache lines;
+// compile-time, since runtime strides cost the kernel registers and
+// occupancy).
+template <int DIM, int R, typename T, int G, bool REUSE, bool MERGED, bool CM>
 __global__ __launch_bounds__(256) void k_cwenoz(HotArgs<T> a, int direct) {
   constexpr int NV = DIM + 2, K = n_unknowns(DIM, R), VPL = NV / G, NFM = nf_max(DIM), MD = 2 * DIM;
+  constexpr int NOI = K * (K + 1) / 2;
   constexpr int CPW = 64 / G;
   const int total = direct ? a.N : a.counts[1];
   Lane<G> L(a.xcd);
@@ -805,7 +809,7 @@ __global__ __launch_bounds__(256) void k_cwenoz(HotArgs<T> a, int direct) {
         double row = 0;
 #pragma unroll
         for (int kq = k; kq < K; ++kq, ++pidx) {
-          const double o = (double)a.t.OI[(long)pidx * N + cell];
+          const double o = CM ? (double)a.t.OIc[(long)cell * NOI + pidx] : (double)a.t.OI[(long)pidx * N + cell];
           row += (kq == k ? o : 2.0 * o) * (double)co[kq][q];
           if (kq < DIM) {
 #pragma unroll
@@ -1128,6 +1132,33 @@ static void launch_muscl(hfv_ctx *ctx, const HotArgs<T> &a, int direct, hipStrea
     launch_muscl_g<DIM, R, T, 2>(ctx, a, direct, s);
 }
 
+// The CWENOZ launch in its compile-time variants: fit kept or refitted, MUSCL
+// and first-order lists merged in, OI read cell-major (not with one lane per
+// cell, which keeps the [entry][cell] reads).
+template <int DIM, int R, typename T, int G, bool CM>
+static void launch_cwenoz_cm(const hfv_ctx *ctx, const HotArgs<T> &a, unsigned grid, int direct, bool reuse,
+                             bool merged, hipStream_t s) {
+  const int B = ctx->block;
+  if (reuse) {
+    if (merged) k_cwenoz<DIM, R, T, G, true, true, CM><<<grid, B, 0, s>>>(a, direct);
+    else k_cwenoz<DIM, R, T, G, true, false, CM><<<grid, B, 0, s>>>(a, direct);
+  } else {
+    if (merged) k_cwenoz<DIM, R, T, G, false, true, CM><<<grid, B, 0, s>>>(a, direct);
+    else k_cwenoz<DIM, R, T, G, false, false, CM><<<grid, B, 0, s>>>(a, direct);
+  }
+}
+template <int DIM, int R, typename T, int G>
+static void launch_cwenoz(const hfv_ctx *ctx, const HotArgs<T> &a, unsigned grid, int direct, bool reuse,
+                          bool merged, hipStream_t s) {
+  if constexpr (G != 1) {
+    if (ctx->cw_cell_major) {
+      launch_cwenoz_cm<DIM, R, T, G, true>(ctx, a, grid, direct, reuse, merged, s);
+      return;
+    }
+  }
+  launch_cwenoz_cm<DIM, R, T, G, false>(ctx, a, grid, direct, reuse, merged, s);
+}
+
 template <int DIM, int R, typename T, int G>
 static hfv_status recon_impl(hfv_ctx *ctx, Tables<T> &t, const void *U, void *fs, uint8_t *cls, void *margin,
                              hipStream_t s) {
@@ -1156,7 +1187,7 @@ static hfv_status recon_impl(hfv_ctx *ctx, Tables<T> &t, const void *U, void *fs
       hfv_status e = launch_cwenoz_char<T>(ctx, a, 1, s);
       if (e != HFV_OK) return e;
     } else {
-      k_cwenoz<DIM, R, T, G, false, false><<<grid_list, B, 0, s>>>(a, 1);
+      launch_cwenoz<DIM, R, T, G>(ctx, a, grid_list, 1, false, false, s);
     }
   } else if (mode == HFV_ALL_MUSCL) {
     k_zero_counts<<<1, 64, 0, s>>>(ctx->counts);
@@ -1171,12 +1202,8 @@ static hfv_status recon_impl(hfv_ctx *ctx, Tables<T> &t, const void *U, void *fs
       if (chr) {
         hfv_status e = launch_cwenoz_char<T>(ctx, a, 0, s);
         if (e != HFV_OK) return e;
-      } else if (a.coef) {
-        if (merged) k_cwenoz<DIM, R, T, G, true, true><<<grid_list, B, 0, s>>>(a, 0);
-        else k_cwenoz<DIM, R, T, G, true, false><<<grid_list, B, 0, s>>>(a, 0);
       } else {
-        if (merged) k_cwenoz<DIM, R, T, G, false, true><<<grid_list, B, 0, s>>>(a, 0);
-        else k_cwenoz<DIM, R, T, G, false, false><<<grid_list, B, 0, s>>>(a, 0);
+        launch_cwenoz<DIM, R, T, G>(ctx, a, grid_list, 0, a.coef != nullptr, merged, s);
       }
     }
     // MUSCL list (empty unless hybrid) and the first-order list
@@ -1212,9 +1239,9 @@ static hfv_status frozen_impl(hfv_ctx *ctx, Tables<T> &t, const void *U, void *f
     if (e != HFV_OK) return e;
     launch_muscl<DIM, R, T>(ctx, a, 0, s);
   } else if (ctx->merged_lists) {
-    k_cwenoz<DIM, R, T, G, false, true><<<grid_list, B, 0, s>>>(a, 0);
+    launch_cwenoz<DIM, R, T, G>(ctx, a, grid_list, 0, false, true, s);
   } else {
-    k_cwenoz<DIM, R, T, G, false, false><<<grid_list, B, 0, s>>>(a, 0);
+    launch_cwenoz<DIM, R, T, G>(ctx, a, grid_list, 0, false, false, s);
     launch_muscl<DIM, R, T>(ctx, a, 0, s);
   }
   HFV_HIP(hipGetLastError());

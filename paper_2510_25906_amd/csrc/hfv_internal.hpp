@@ -62,6 +62,7 @@ struct Tables {
   T *thr = nullptr;        // [N]  NAD deactivation threshold (kappa h)^n
   T *veps2 = nullptr;      // [N]  Venkatakrishnan limiter eps^2 = (kappa h)^3
   T *OI = nullptr;         // [K(K+1)/2][N]
+  T *OIc = nullptr;        // [N][K(K+1)/2]  cell-major copy (CWENOZ over sparse lists)
   int *dsten = nullptr;    // [NFM][Md][N]
   T *Pdir = nullptr;       // [NFM][DIM][Md][N]
   uint8_t *ndir = nullptr; // [N]
@@ -129,6 +130,7 @@ struct hfv_ctx {
   int xcd_remap = 1;                 // XCD-contiguous block order (block_id)
   int muscl_lanes = 0;               // lanes per cell of the MUSCL pass (0: lanes)
   int merged_lists = 0;              // MUSCL and first-order lists served by the CWENOZ launch
+  int cw_cell_major = 0;             // CWENOZ reads the cell-major copy of OI
   int device = 0, n_cu = 256;
   // kernel timing (hfv_profile_*)
   struct ProfEv {

@@ -619,6 +619,13 @@ __global__ void k_convert(long n, const double *src, T *dst) {
   if (i < n) dst[i] = (T)src[i];
 }
 
+// [rows][n] -> [n][rows] (cell-major copy of a per-cell table)
+template <typename T>
+__global__ void k_cell_major(long n, int rows, const double *src, T *dst) {
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n * rows) dst[i] = (T)src[(i % rows) * n + i / rows];
+}
+
 // 1 / h_c per cell, and per face 1 / L_int, the distance between the two
 // cell centres with the right cell's periodic image next to the left cell
 // (0 at boundary faces): the penalty of Eq. viscous_jump.
@@ -882,6 +889,12 @@ static hfv_status setup_dr(hfv_ctx *ctx, const hfv_mesh *mesh, const hfv_stencil
     if ((e = conv(&tabs.psibar, psibar, (size_t)K * N))) return e;
     if ((e = conv(&tabs.gpxi, gpxi, (size_t)NGPC * DIM * N))) return e;
     if ((e = conv(&tabs.OI, OI, (size_t)K * (K + 1) / 2 * N))) return e;
+    {  // cell-major copy of OI: a sparse CWENOZ list reads each cell's rows contiguously
+      const int noi = K * (K + 1) / 2;
+      if ((e = dev_alloc(ctx, (void **)&tabs.OIc, (size_t)noi * N * sizeof(T)))) return e;
+      k_cell_major<T><<<nblk((long)noi * N, 256), 256, 0, s>>>((long)N, noi, OI, tabs.OIc);
+      ctx->table_bytes += (size_t)noi * N * sizeof(T);
+    }
     if ((e = conv(&tabs.Pdir, Pdir, (size_t)NFM * DIM * Md * N))) return e;
     if ((e = conv(&tabs.Pmus, Pmus, (size_t)DIM * NFM * N))) return e;
     if ((e = conv(&tabs.fnormal, fn, (size_t)DIM * NF))) return e;

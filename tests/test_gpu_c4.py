@@ -41,12 +41,14 @@ def dilated(om, flags):
 
 
 # (linear split, linear lanes, CWENOZ reuse, MUSCL lanes, class-list lanes,
-# MUSCL and first-order lists merged into the CWENOZ launch)
-@pytest.mark.parametrize("split,lanes,reuse,mlanes,cwl,merged", [(0, 5, 0, 0, 1, 0), (0, 1, 1, 1, 1, 0),
-                                                                 (1, 4, 0, 5, 1, 0), (2, 2, 1, 0, 1, 0),
-                                                                 (2, 4, 0, 1, 1, 0), (0, 5, 0, 0, 5, 1),
-                                                                 (1, 4, 1, 0, 5, 1), (2, 2, 0, 0, 1, 1)])
-def test_c4_small_fp64_hybrid(hfv, small, split, lanes, reuse, mlanes, cwl, merged):
+# MUSCL and first-order lists merged into the CWENOZ launch, CWENOZ's OI
+# read from its cell-major copy)
+@pytest.mark.parametrize("split,lanes,reuse,mlanes,cwl,merged,cm", [(0, 5, 0, 0, 1, 0, 0), (0, 1, 1, 1, 1, 0, 0),
+                                                                    (1, 4, 0, 5, 1, 0, 0), (2, 2, 1, 0, 1, 0, 0),
+                                                                    (2, 4, 0, 1, 1, 0, 0), (0, 5, 0, 0, 5, 1, 0),
+                                                                    (1, 4, 1, 0, 5, 1, 0), (2, 2, 0, 0, 1, 1, 0),
+                                                                    (0, 5, 1, 0, 5, 1, 1), (1, 4, 0, 0, 1, 0, 1)])
+def test_c4_small_fp64_hybrid(hfv, small, split, lanes, reuse, mlanes, cwl, merged, cm):
     w, om = small
     R_o, fs_o, cls_o = flux.residual(om, w.U)
     counts = np.bincount(cls_o, minlength=4)
@@ -55,7 +57,7 @@ def test_c4_small_fp64_hybrid(hfv, small, split, lanes, reuse, mlanes, cwl, merg
     assert not near_threshold(om, w.U, np.arange(w.mesh.n_cells), 1e-12).any()
     ctx = hfv.Context(w.mesh, w.stencils, w.params, 64)
     ctx.set_launch(linear_split=split, linear_lanes=lanes, cwenoz_reuse=reuse, list_blocks=0 if reuse else 64,
-                   muscl_lanes=mlanes, lanes=cwl, merged_lists=merged)
+                   muscl_lanes=mlanes, lanes=cwl, merged_lists=merged, cwenoz_cell_major=cm)
     fs = ctx.new_face_states()
     cls = torch.empty(w.mesh.n_cells, dtype=torch.uint8, device="cuda")
     R = ctx.residual(to_dev(w.U, torch.float64), face_states=fs, cell_class=cls)
@@ -78,16 +80,18 @@ def test_c4_small_fp64_forced_modes(hfv, small, mode):
     om._tab = om0._tab
     R_o, fs_o, cls_o = flux.residual(om, w.U)
     ctx = hfv.Context(w.mesh, w.stencils, p, 64)
-    fs = ctx.new_face_states()
-    cls = torch.empty(w.mesh.n_cells, dtype=torch.uint8, device="cuda")
-    R = ctx.residual(to_dev(w.U, torch.float64), face_states=fs, cell_class=cls)
-    torch.cuda.synchronize()
-    assert np.array_equal(cls.cpu().numpy(), cls_o)
     S = state_scale(w.U)
-    es = states_err(fs, fs_o, om.geo, S)
-    er = rel_err(R.cpu().numpy(), R_o, np.abs(R_o).max(1)[:, None])
-    print(f"state error {es:.2e}, residual error {er:.2e}", flush=True)
-    assert es <= 1e-12 and er <= 1e-11
+    for cm in (0, 1):       # CWENOZ's OI from the [entry][cell] table or its cell-major copy
+        ctx.set_launch(cwenoz_cell_major=cm)
+        fs = ctx.new_face_states()
+        cls = torch.empty(w.mesh.n_cells, dtype=torch.uint8, device="cuda")
+        R = ctx.residual(to_dev(w.U, torch.float64), face_states=fs, cell_class=cls)
+        torch.cuda.synchronize()
+        assert np.array_equal(cls.cpu().numpy(), cls_o)
+        es = states_err(fs, fs_o, om.geo, S)
+        er = rel_err(R.cpu().numpy(), R_o, np.abs(R_o).max(1)[:, None])
+        print(f"cell-major OI {cm}: state error {es:.2e}, residual error {er:.2e}", flush=True)
+        assert es <= 1e-12 and er <= 1e-11
     ctx.close()
 
 

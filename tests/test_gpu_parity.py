@@ -123,14 +123,15 @@ def test_c1_tables_match_oracle(hfv, c1):
     ctx.close()
 
 
-@pytest.mark.parametrize("lanes,split,lin_lanes,reuse,mlanes,merged",
-                         [(1, 0, 1, 0, 0, 0), (2, 0, 2, 1, 4, 0), (4, 0, 4, 0, 1, 0), (4, 1, 2, 1, 2, 0),
-                          (4, 1, 4, 0, 0, 0), (2, 1, 8, 1, 1, 0), (2, 2, 2, 1, 0, 0), (2, 2, 4, 0, 4, 0),
-                          (1, 2, 8, 1, 2, 0), (1, 0, 1, 0, 0, 1), (2, 1, 2, 0, 4, 1), (4, 0, 2, 1, 0, 1),
-                          (2, 2, 8, 1, 0, 1)])
-def test_c1_launch_shapes_agree(hfv, c1, lanes, split, lin_lanes, reuse, mlanes, merged):
+@pytest.mark.parametrize("lanes,split,lin_lanes,reuse,mlanes,merged,cm",
+                         [(1, 0, 1, 0, 0, 0, 0), (2, 0, 2, 1, 4, 0, 0), (4, 0, 4, 0, 1, 0, 0), (4, 1, 2, 1, 2, 0, 0),
+                          (4, 1, 4, 0, 0, 0, 0), (2, 1, 8, 1, 1, 0, 0), (2, 2, 2, 1, 0, 0, 0), (2, 2, 4, 0, 4, 0, 0),
+                          (1, 2, 8, 1, 2, 0, 0), (1, 0, 1, 0, 0, 1, 0), (2, 1, 2, 0, 4, 1, 0), (4, 0, 2, 1, 0, 1, 0),
+                          (2, 2, 8, 1, 0, 1, 0), (1, 0, 1, 1, 0, 0, 1), (2, 1, 2, 0, 0, 1, 1), (4, 0, 2, 1, 0, 1, 1)])
+def test_c1_launch_shapes_agree(hfv, c1, lanes, split, lin_lanes, reuse, mlanes, merged, cm):
     """Every work mapping, with and without the CWENOZ reuse of the linear
-    pass's central fits, with the MUSCL pass on its own lane count or with
+    pass's central fits, with CWENOZ's OI from its cell-major copy, with the
+    MUSCL pass on its own lane count or with
     the MUSCL and first-order lists merged into the CWENOZ launch, gives the
     oracle's classes and states."""
     w, om = c1
@@ -138,8 +139,9 @@ def test_c1_launch_shapes_agree(hfv, c1, lanes, split, lin_lanes, reuse, mlanes,
     assert (cls_o == 2).sum() > 0
     ctx = hfv.Context(w.mesh, w.stencils, w.params, 64)
     ctx.set_launch(lanes=lanes, block=128, list_blocks=0 if reuse else 3, linear_split=split, linear_lanes=lin_lanes,
-                   cwenoz_reuse=reuse, muscl_lanes=mlanes, merged_lists=merged)
+                   cwenoz_reuse=reuse, muscl_lanes=mlanes, merged_lists=merged, cwenoz_cell_major=cm)
     assert ctx.get_launch()["cwenoz_reuse"] == reuse and ctx.get_launch()["merged_lists"] == merged
+    assert ctx.get_launch()["cwenoz_cell_major"] == cm
     fs, cls = ctx.reconstruct(to_dev(w.U, torch.float64))
     torch.cuda.synchronize()
     assert ctx.query("COUNT_CWENOZ") == int((cls_o == 1).sum()) > 0
