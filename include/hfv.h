@@ -352,17 +352,21 @@ hfv_status hfv_copy_table(const hfv_ctx *ctx, int32_t which, void *host_dst, int
  *                   own, with lanes_per_cell lanes (muscl_lanes unused); their
  *                   cells fill the waves CWENOZ leaves idle.  0: a launch of
  *                   their own
- *   cwenoz_cell_major 1: the CWENOZ pass (conserved variables) reads the
- *                   smoothness-indicator matrices OI from a cell-major copy
- *                   ([cell][entry], built at create), so a sparse class list
- *                   reads each listed cell's entries from consecutive cache
- *                   lines; 0: from the [entry][cell] table, contiguous across
- *                   the consecutive cells of a dense list
+ *   lists_cell_major 1: the class-list kernels read their per-cell tables
+ *                   from cell-major copies ([cell][entry], built at create):
+ *                   CWENOZ (conserved variables, two or more lanes per cell)
+ *                   its OI matrices, directional ids and fits, basis means and
+ *                   Gauss-point coordinates; MUSCL its member ids and fits,
+ *                   face neighbours, basis means and Gauss-point coordinates.
+ *                   A sparse class list then reads each listed cell's entries
+ *                   from consecutive cache lines; 0: from the [entry][cell]
+ *                   tables, contiguous across the consecutive cells of a
+ *                   dense list
  * hfv_set_launch validates every field (HFV_ERR_PARAM, nothing changed, on
  * an invalid one); hfv_get_launch reads the current configuration. */
 typedef struct {
   int32_t lanes_per_cell, block, list_blocks, linear_split, linear_lanes, cwenoz_reuse, fused_residual, xcd_remap,
-      muscl_lanes, merged_lists, cwenoz_cell_major;
+      muscl_lanes, merged_lists, lists_cell_major;
 } hfv_launch;
 hfv_status hfv_set_launch(hfv_ctx *ctx, const hfv_launch *cfg);
 hfv_status hfv_get_launch(const hfv_ctx *ctx, hfv_launch *cfg);
@@ -373,8 +377,8 @@ hfv_status hfv_get_launch(const hfv_ctx *ctx, hfv_launch *cfg);
  * kernel mapping; class-list kernel lanes, block and grid, in hybrid mode
  * jointly with CWENOZ reuse and with the MUSCL and first-order lists merged
  * into the CWENOZ launch; fused or two-kernel residual; XCD block order; in
- * hybrid mode, without merged lists, the MUSCL lanes; CWENOZ's OI layout;
- * then the four fastest configurations timed again), and keeps the fastest of that second timing
+ * hybrid mode, without merged lists, the MUSCL lanes; the class-list
+ * tables' layout; then the four fastest configurations timed again), and keeps the fastest of that second timing
  * (each timing: after one untimed
  * call, three batches of `reps` calls back to back, reps in [1, 1000]; the
  * median batch's time per call).  Synchronous; it

@@ -276,8 +276,8 @@ hfv_status hfv_set_launch(hfv_ctx *ctx, const hfv_launch *c) {
   if (!(ml == 0 || ml == 1 || ml == ctx->nvar || (ctx->dim == 2 && ml == 2)))
     return ctx->err = "muscl_lanes must be 0, 1 or nvar (or 2 in 2D)", HFV_ERR_PARAM;
   if (c->merged_lists != 0 && c->merged_lists != 1) return ctx->err = "merged_lists must be 0 or 1", HFV_ERR_PARAM;
-  if (c->cwenoz_cell_major != 0 && c->cwenoz_cell_major != 1)
-    return ctx->err = "cwenoz_cell_major must be 0 or 1", HFV_ERR_PARAM;
+  if (c->lists_cell_major != 0 && c->lists_cell_major != 1)
+    return ctx->err = "lists_cell_major must be 0 or 1", HFV_ERR_PARAM;
   ctx->lanes = lanes;
   ctx->block = c->block;
   ctx->list_blocks = c->list_blocks;
@@ -288,7 +288,7 @@ hfv_status hfv_set_launch(hfv_ctx *ctx, const hfv_launch *c) {
   ctx->xcd_remap = c->xcd_remap;
   ctx->muscl_lanes = c->muscl_lanes;
   ctx->merged_lists = c->merged_lists;
-  ctx->cw_cell_major = c->cwenoz_cell_major;
+  ctx->lists_cm = c->lists_cell_major;
   return HFV_OK;
 }
 
@@ -304,7 +304,7 @@ hfv_status hfv_get_launch(const hfv_ctx *ctx, hfv_launch *c) {
   c->xcd_remap = ctx->xcd_remap;
   c->muscl_lanes = ctx->muscl_lanes;
   c->merged_lists = ctx->merged_lists;
-  c->cwenoz_cell_major = ctx->cw_cell_major;
+  c->lists_cell_major = ctx->lists_cm;
   return HFV_OK;
 }
 

@@ -24,6 +24,7 @@ struct HotArgs {
   int xcd;   // block ids remapped so each XCD takes one contiguous range (block_id)
   int limiter;  // HFV_LIM_*
   T *margin;    // [N] near_margin output of the linear pass, or null
+  int NGPC;     // Gauss-point slots per cell (row length of the cell-major gpxi copy)
 };
 
 // CWENOZ on characteristic variables (hfv_char.cpp) over the class-1 list,
@@ -274,13 +275,15 @@ __device__ inline void store(const HotArgs<T> &a, int g, int cell, int v, T val)
 // they alias), so it would wait for each point's coordinates in turn; loading
 // PB points at once waits once per PB points.
 constexpr int GP_BATCH = 4;
-template <int PB, int DIM, typename T>
+// CM: from the cell-major copy.
+template <int PB, int DIM, typename T, bool CM = false>
 __device__ inline void load_points(const HotArgs<T> &a, int cell, int g0, int step, int ng, T (&xs)[PB][DIM]) {
 #pragma unroll
   for (int p = 0; p < PB; ++p) {
     const int g = min(g0 + p * step, ng - 1);
 #pragma unroll
-    for (int j = 0; j < DIM; ++j) xs[p][j] = a.t.gpxi[((long)g * DIM + j) * a.N + cell];
+    for (int j = 0; j < DIM; ++j)
+      xs[p][j] = CM ? a.t.gpxiC[((long)cell * a.NGPC + g) * DIM + j] : a.t.gpxi[((long)g * DIM + j) * a.N + cell];
   }
 }
 

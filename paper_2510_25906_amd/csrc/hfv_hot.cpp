@@ -579,7 +579,7 @@ __global__ __launch_bounds__(CLASSIFY_BLOCK) void k_classify(HotArgs<T> a) {
 
 // K4: one cell of the MUSCL list: gradient by least squares over the face
 // neighbours, Barth-Jespersen (or Venkatakrishnan) limiter, Harten check.
-template <int DIM, int R, typename T, int G>
+template <int DIM, int R, typename T, int G, bool CM = false>
 __device__ __forceinline__ void muscl_cell(const HotArgs<T> &a, int cell, const Lane<G> &L) {
   constexpr int NV = DIM + 2, VPL = NV / G, NFM = nf_max(DIM);
   const int N = a.N, v0 = L.sub * VPL;
@@ -595,13 +595,13 @@ __device__ __forceinline__ void muscl_cell(const HotArgs<T> &a, int cell, const 
   // weights (exact zeros), neighbour rows past its face count with -1
 #pragma unroll
   for (int m = 0; m < NFM; ++m) {
-    const int jc = a.t.msten[(long)m * N + cell];
+    const int jc = CM ? a.t.mstenC[(long)cell * NFM + m] : a.t.msten[(long)m * N + cell];
     T du[VPL];
 #pragma unroll
     for (int q = 0; q < VPL; ++q) du[q] = a.U[(long)(v0 + q) * N + jc] - u0[q];
 #pragma unroll
     for (int j = 0; j < DIM; ++j) {
-      const T p = a.t.Pmus[((long)j * NFM + m) * N + cell];
+      const T p = CM ? a.t.PmusC[((long)cell * DIM + j) * NFM + m] : a.t.Pmus[((long)j * NFM + m) * N + cell];
 #pragma unroll
       for (int q = 0; q < VPL; ++q) gr[j][q] += p * du[q];
     }
@@ -611,7 +611,7 @@ __device__ __forceinline__ void muscl_cell(const HotArgs<T> &a, int cell, const 
   for (int q = 0; q < VPL; ++q) mn[q] = mx[q] = u0[q];
 #pragma unroll
   for (int f = 0; f < NFM; ++f) {
-    const int j = a.t.nbr[(long)f * N + cell];
+    const int j = CM ? a.t.nbrC[(long)cell * NFM + f] : a.t.nbr[(long)f * N + cell];
     if (j >= 0) {
 #pragma unroll
       for (int q = 0; q < VPL; ++q) {
@@ -623,7 +623,8 @@ __device__ __forceinline__ void muscl_cell(const HotArgs<T> &a, int cell, const 
   }
   T psb[DIM];
 #pragma unroll
-  for (int j = 0; j < DIM; ++j) psb[j] = a.t.psibar[(long)j * N + cell];
+  for (int j = 0; j < DIM; ++j)
+    psb[j] = CM ? a.t.psibarC[(long)cell * n_unknowns(DIM, R) + j] : a.t.psibar[(long)j * N + cell];
   const int ng = a.t.ngp[cell];
   const bool venkat = a.limiter == HFV_LIM_VENKAT;
   const T e2 = venkat ? a.t.veps2[cell] : (T)0;
@@ -632,7 +633,7 @@ __device__ __forceinline__ void muscl_cell(const HotArgs<T> &a, int cell, const 
   for (int q = 0; q < VPL; ++q) th[q] = (T)1;
   for (int g0 = 0; g0 < ng; g0 += GP_BATCH) {
     T xs[GP_BATCH][DIM];
-    load_points<GP_BATCH, DIM, T>(a, cell, g0, 1, ng, xs);
+    load_points<GP_BATCH, DIM, T, CM>(a, cell, g0, 1, ng, xs);
 #pragma unroll
     for (int p = 0; p < GP_BATCH; ++p) {
       if (g0 + p < ng) {
@@ -663,7 +664,7 @@ __device__ __forceinline__ void muscl_cell(const HotArgs<T> &a, int cell, const 
   bool hok = true;
   for (int g0 = 0; g0 < ng; g0 += GP_BATCH) {
     T xs[GP_BATCH][DIM];
-    load_points<GP_BATCH, DIM, T>(a, cell, g0, 1, ng, xs);
+    load_points<GP_BATCH, DIM, T, CM>(a, cell, g0, 1, ng, xs);
 #pragma unroll
     for (int p = 0; p < GP_BATCH; ++p) {
       if (g0 + p < ng) {
@@ -718,8 +719,8 @@ __device__ __forceinline__ void first_order_cell(const HotArgs<T> &a, int cell, 
 // its item sequence there); a template parameter, so that the plain kernel's
 // code is not changed by them.  CM: OI is read from its cell-major copy (a
 // sparse list then reads each cell's entries from consecutive cache lines;
-// compile-time, since runtime strides cost the kernel registers and
-// occupancy).
+// the directional stencils' ids and fits likewise; compile-time, since runtime
+// strides cost the kernel registers and occupancy).
 template <int DIM, int R, typename T, int G, bool REUSE, bool MERGED, bool CM>
 __global__ __launch_bounds__(256) void k_cwenoz(HotArgs<T> a, int direct) {
   constexpr int NV = DIM + 2, K = n_unknowns(DIM, R), VPL = NV / G, NFM = nf_max(DIM), MD = 2 * DIM;
@@ -764,13 +765,14 @@ __global__ __launch_bounds__(256) void k_cwenoz(HotArgs<T> a, int direct) {
       if ((REUSE && G >= 4) || s < nd) {
 #pragma unroll
         for (int m = 0; m < MD; ++m) {
-          const int jc = a.t.dsten[((long)s * MD + m) * N + cell];
+          const int jc = CM ? a.t.dstenC[((long)cell * NFM + s) * MD + m] : a.t.dsten[((long)s * MD + m) * N + cell];
           T du[VPL];
 #pragma unroll
           for (int q = 0; q < VPL; ++q) du[q] = a.U[(long)(v0 + q) * N + jc] - u0[q];
 #pragma unroll
           for (int j = 0; j < DIM; ++j) {
-            const T p = a.t.Pdir[(((long)s * DIM + j) * MD + m) * N + cell];
+            const T p = CM ? a.t.PdirC[(((long)cell * NFM + s) * DIM + j) * MD + m]
+                           : a.t.Pdir[(((long)s * DIM + j) * MD + m) * N + cell];
 #pragma unroll
             for (int q = 0; q < VPL; ++q) ad[s][j][q] += p * du[q];
           }
@@ -856,7 +858,7 @@ __global__ __launch_bounds__(256) void k_cwenoz(HotArgs<T> a, int direct) {
     const T p_b = pressure<NV, T>(all0, a.gamma);
     T psb[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) psb[k] = a.t.psibar[(long)k * N + cell];
+    for (int k = 0; k < K; ++k) psb[k] = CM ? a.t.psibarC[(long)cell * K + k] : a.t.psibar[(long)k * N + cell];
     const int ng = a.t.ngp[cell];
     bool hok = true;
     // points one at a time in FP64 with one or two lanes per cell (measured:
@@ -865,7 +867,7 @@ __global__ __launch_bounds__(256) void k_cwenoz(HotArgs<T> a, int direct) {
     constexpr int PB = (sizeof(T) == 8 && G <= 2) ? 1 : GP_BATCH;
     for (int g0 = 0; g0 < ng && hok; g0 += PB) {
       T xs[PB][DIM];
-      load_points<PB, DIM, T>(a, cell, g0, 1, ng, xs);
+      load_points<PB, DIM, T, CM>(a, cell, g0, 1, ng, xs);
 #pragma unroll
       for (int p = 0; p < PB; ++p) {
         if (g0 + p < ng && hok) {
@@ -901,7 +903,7 @@ __global__ __launch_bounds__(256) void k_cwenoz(HotArgs<T> a, int direct) {
     const int n2 = a.counts[2], n3 = a.counts[3];
     for (long i2 = item - total; i2 < (long)n2 + n3; i2 += stride) {
       if (i2 < n2)
-        muscl_cell<DIM, R, T, G>(a, a.lists[(long)a.N + i2], L);
+        muscl_cell<DIM, R, T, G, CM>(a, a.lists[(long)a.N + i2], L);
       else
         first_order_cell<DIM, T, G>(a, a.lists[2L * a.N + (i2 - n2)], L);
     }
@@ -910,7 +912,7 @@ __global__ __launch_bounds__(256) void k_cwenoz(HotArgs<T> a, int direct) {
 
 // K4 + K5 as a launch of their own: list 2 (every cell when direct), then
 // list 3.
-template <int DIM, int R, typename T, int G>
+template <int DIM, int R, typename T, int G, bool CM>
 __global__ __launch_bounds__(256) void k_muscl(HotArgs<T> a, int direct) {
   constexpr int CPW = 64 / G;
   const int total = direct ? a.N : a.counts[2];
@@ -918,7 +920,7 @@ __global__ __launch_bounds__(256) void k_muscl(HotArgs<T> a, int direct) {
   if (!L.ok) return;
   const long stride = (long)gridDim.x * (blockDim.x / 64) * CPW;
   for (long item = L.item; item < total; item += stride)
-    muscl_cell<DIM, R, T, G>(a, direct ? (int)item : a.lists[(long)a.N + item], L);
+    muscl_cell<DIM, R, T, G, CM>(a, direct ? (int)item : a.lists[(long)a.N + item], L);
   const int total3 = direct ? 0 : a.counts[3];
   for (long item = L.item; item < total3; item += stride) first_order_cell<DIM, T, G>(a, a.lists[2L * a.N + item], L);
 }
@@ -1063,6 +1065,7 @@ static HotArgs<T> make_args(hfv_ctx *ctx, Tables<T> &t, const void *U, void *fs,
   const double bw = ctx->p.b_w;
   a.ib_w = (bw >= 1.0 && bw <= 8.0 && bw == (double)(int)bw) ? (int)bw : 0;
   a.margin = nullptr;
+  a.NGPC = ctx->NGPC;
   return a;
 }
 
@@ -1119,7 +1122,10 @@ static void launch_muscl_g(hfv_ctx *ctx, const HotArgs<T> &a, int direct, hipStr
   const unsigned grid_cells = nblk(waves * 64, B);
   const unsigned grid =
       ctx->list_blocks > 0 ? std::min<unsigned>(grid_cells, (unsigned)ctx->list_blocks) : grid_cells;
-  k_muscl<DIM, R, T, G><<<grid, B, 0, s>>>(a, direct);
+  if (ctx->lists_cm)
+    k_muscl<DIM, R, T, G, true><<<grid, B, 0, s>>>(a, direct);
+  else
+    k_muscl<DIM, R, T, G, false><<<grid, B, 0, s>>>(a, direct);
 }
 template <int DIM, int R, typename T>
 static void launch_muscl(hfv_ctx *ctx, const HotArgs<T> &a, int direct, hipStream_t s) {
@@ -1151,7 +1157,7 @@ template <int DIM, int R, typename T, int G>
 static void launch_cwenoz(const hfv_ctx *ctx, const HotArgs<T> &a, unsigned grid, int direct, bool reuse,
                           bool merged, hipStream_t s) {
   if constexpr (G != 1) {
-    if (ctx->cw_cell_major) {
+    if (ctx->lists_cm) {
       launch_cwenoz_cm<DIM, R, T, G, true>(ctx, a, grid, direct, reuse, merged, s);
       return;
     }

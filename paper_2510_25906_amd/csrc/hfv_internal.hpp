@@ -65,6 +65,14 @@ struct Tables {
   T *OIc = nullptr;        // [N][K(K+1)/2]  cell-major copy (CWENOZ over sparse lists)
   int *dsten = nullptr;    // [NFM][Md][N]
   T *Pdir = nullptr;       // [NFM][DIM][Md][N]
+  // cell-major copies for the class-list kernels over sparse lists
+  int *dstenC = nullptr;   // [N][NFM][Md]
+  T *PdirC = nullptr;      // [N][NFM][DIM][Md]
+  T *psibarC = nullptr;    // [N][K]
+  T *gpxiC = nullptr;      // [N][NGPC][DIM]
+  int *mstenC = nullptr;   // [N][NFM]
+  T *PmusC = nullptr;      // [N][DIM][NFM]
+  int *nbrC = nullptr;     // [N][NFM]
   uint8_t *ndir = nullptr; // [N]
   int *msten = nullptr;    // [NFM][N]
   T *Pmus = nullptr;       // [DIM][NFM][N]
@@ -130,7 +138,7 @@ struct hfv_ctx {
   int xcd_remap = 1;                 // XCD-contiguous block order (block_id)
   int muscl_lanes = 0;               // lanes per cell of the MUSCL pass (0: lanes)
   int merged_lists = 0;              // MUSCL and first-order lists served by the CWENOZ launch
-  int cw_cell_major = 0;             // CWENOZ reads the cell-major copy of OI
+  int lists_cm = 0;                  // class-list kernels read the cell-major table copies
   int device = 0, n_cu = 256;
   // kernel timing (hfv_profile_*)
   struct ProfEv {

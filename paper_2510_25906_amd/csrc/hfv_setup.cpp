@@ -889,11 +889,20 @@ static hfv_status setup_dr(hfv_ctx *ctx, const hfv_mesh *mesh, const hfv_stencil
     if ((e = conv(&tabs.psibar, psibar, (size_t)K * N))) return e;
     if ((e = conv(&tabs.gpxi, gpxi, (size_t)NGPC * DIM * N))) return e;
     if ((e = conv(&tabs.OI, OI, (size_t)K * (K + 1) / 2 * N))) return e;
-    {  // cell-major copy of OI: a sparse CWENOZ list reads each cell's rows contiguously
-      const int noi = K * (K + 1) / 2;
-      if ((e = dev_alloc(ctx, (void **)&tabs.OIc, (size_t)noi * N * sizeof(T)))) return e;
-      k_cell_major<T><<<nblk((long)noi * N, 256), 256, 0, s>>>((long)N, noi, OI, tabs.OIc);
-      ctx->table_bytes += (size_t)noi * N * sizeof(T);
+    {  // cell-major copies of the class-list kernels' tables: a sparse list
+       // reads each cell's rows contiguously
+      auto cm = [&](T **dst, const double *src, int rows) -> hfv_status {
+        hfv_status e3 = dev_alloc(ctx, (void **)dst, (size_t)rows * N * sizeof(T));
+        if (e3 != HFV_OK) return e3;
+        k_cell_major<T><<<nblk((long)rows * N, 256), 256, 0, s>>>((long)N, rows, src, *dst);
+        ctx->table_bytes += (size_t)rows * N * sizeof(T);
+        return HFV_OK;
+      };
+      if ((e = cm(&tabs.OIc, OI, K * (K + 1) / 2))) return e;
+      if ((e = cm(&tabs.PdirC, Pdir, NFM * DIM * Md))) return e;
+      if ((e = cm(&tabs.psibarC, psibar, K))) return e;
+      if ((e = cm(&tabs.gpxiC, gpxi, NGPC * DIM))) return e;
+      if ((e = cm(&tabs.PmusC, Pmus, DIM * NFM))) return e;
     }
     if ((e = conv(&tabs.Pdir, Pdir, (size_t)NFM * DIM * Md * N))) return e;
     if ((e = conv(&tabs.Pmus, Pmus, (size_t)DIM * NFM * N))) return e;
@@ -994,7 +1003,8 @@ hfv_status setup_tables(hfv_ctx *ctx, const hfv_mesh *mesh, const hfv_stencils *
   if (e != HFV_OK) return e;
   // integer tables in hot-path layouts
   const int M = ctx->M, Md = ctx->Md;
-  std::vector<int> sten((size_t)M * N), dsten((size_t)NFM * Md * N), msten((size_t)NFM * N);
+  std::vector<int> sten((size_t)M * N), dsten((size_t)NFM * Md * N), dstenC((size_t)NFM * Md * N),
+      msten((size_t)NFM * N), mstenC((size_t)NFM * N), nbrC((size_t)NFM * N);
   std::vector<uint8_t> ndir(N), nmus(N);
   for (int c = 0; c < N; ++c) {
     for (int m = 0; m < M; ++m) sten[(size_t)m * N + c] = st->central[(size_t)c * M + m];
@@ -1002,10 +1012,13 @@ hfv_status setup_tables(hfv_ctx *ctx, const hfv_mesh *mesh, const hfv_stencils *
       for (int q = 0; q < Md; ++q) {
         int v = st->dir[((size_t)c * NFM + sidx) * Md + q];
         dsten[((size_t)sidx * Md + q) * N + c] = v >= 0 ? v : c;
+        dstenC[((size_t)c * NFM + sidx) * Md + q] = v >= 0 ? v : c;
       }
     for (int q = 0; q < NFM; ++q) {
       int v = st->muscl[(size_t)c * NFM + q];
       msten[(size_t)q * N + c] = v >= 0 ? v : c;
+      mstenC[(size_t)c * NFM + q] = v >= 0 ? v : c;
+      nbrC[(size_t)c * NFM + q] = nbr[(size_t)q * N + c];
     }
     ndir[c] = (uint8_t)st->n_dir[c];
     nmus[c] = (uint8_t)st->n_muscl[c];
@@ -1021,15 +1034,18 @@ hfv_status setup_tables(hfv_ctx *ctx, const hfv_mesh *mesh, const hfv_stencils *
     if ((e2 = upload(ctx, &tabs.nbr, nbr.data(), nbr.size(), s))) return e2;
     if ((e2 = upload(ctx, &tabs.nfc, nfc.data(), nfc.size(), s))) return e2;
     if ((e2 = upload(ctx, &tabs.dsten, dsten.data(), dsten.size(), s))) return e2;
+    if ((e2 = upload(ctx, &tabs.dstenC, dstenC.data(), dstenC.size(), s))) return e2;
     if ((e2 = upload(ctx, &tabs.ndir, ndir.data(), ndir.size(), s))) return e2;
     if ((e2 = upload(ctx, &tabs.msten, msten.data(), msten.size(), s))) return e2;
+    if ((e2 = upload(ctx, &tabs.mstenC, mstenC.data(), mstenC.size(), s))) return e2;
+    if ((e2 = upload(ctx, &tabs.nbrC, nbrC.data(), nbrC.size(), s))) return e2;
     if ((e2 = upload(ctx, &tabs.nmus, nmus.data(), nmus.size(), s))) return e2;
     if ((e2 = upload(ctx, &tabs.gp_off, gp_off.data(), gp_off.size(), s))) return e2;
     if ((e2 = upload(ctx, &tabs.face_cells, fcells.data(), fcells.size(), s))) return e2;
     if ((e2 = upload(ctx, &tabs.fgb, fgb.data(), fgb.size(), s))) return e2;
     if ((e2 = upload(ctx, &tabs.cf_off, cf_off.data(), cf_off.size(), s))) return e2;
     if ((e2 = upload(ctx, &tabs.cf, cf.data(), cf.size(), s))) return e2;
-    ctx->table_bytes += sizeof(int) * (sten.size() + nbr.size() + dsten.size() + msten.size());
+    ctx->table_bytes += sizeof(int) * (sten.size() + 2 * nbr.size() + 2 * dsten.size() + 2 * msten.size());
     return HFV_OK;
   };
   e = ctx->prec == 64 ? put(ctx->t64) : put(ctx->t32);

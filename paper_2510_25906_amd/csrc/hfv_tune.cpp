@@ -19,8 +19,8 @@
 //   4. XCD-contiguous block order against plain block order;
 //   5. in hybrid mode, when the MUSCL lists keep a launch of their own, its
 //      lane count;
-//   6. in hybrid and all-CWENOZ modes, CWENOZ's OI read from its cell-major
-//      copy against the [entry][cell] table;
+//   6. in the modes with class lists, the list kernels' tables read from
+//      their cell-major copies against the [entry][cell] tables;
 //   7. the four fastest configurations timed so far are timed again and the
 //      fastest of that second timing is kept (among ~100 candidates the
 //      fastest first timing is as likely a fast outlier as a fast launch).
@@ -180,10 +180,10 @@ extern "C" hfv_status hfv_autotune(hfv_ctx *ctx, const void *U, int32_t reps, hf
         }
       tu.pick(cands, best, best_ms);
     }
-    // 6. layout of CWENOZ's OI reads
-    if (ctx->p.mode == HFV_HYBRID || ctx->p.mode == HFV_ALL_CWENOZ) {
+    // 6. layout of the class-list kernels' table reads
+    if (ctx->p.mode != HFV_ALL_LINEAR) {
       hfv_launch c = best;
-      c.cwenoz_cell_major = 1 - best.cwenoz_cell_major;
+      c.lists_cell_major = 1 - best.lists_cell_major;
       tu.pick({c}, best, best_ms);
     }
     // 7. confirmation of the fastest few

@@ -107,7 +107,7 @@ def load():
 class HfvLaunch(C.Structure):
     _fields_ = [(n, C.c_int32) for n in ("lanes_per_cell", "block", "list_blocks", "linear_split",
                                          "linear_lanes", "cwenoz_reuse", "fused_residual", "xcd_remap",
-                                         "muscl_lanes", "merged_lists", "cwenoz_cell_major")]
+                                         "muscl_lanes", "merged_lists", "lists_cell_major")]
 
 
 class HfvTuneRecord(C.Structure):
@@ -228,13 +228,13 @@ class Context:
 
     def set_launch(self, lanes=None, block=None, list_blocks=None, linear_split=None, linear_lanes=None,
                    cwenoz_reuse=None, fused_residual=None, xcd_remap=None, muscl_lanes=None,
-                   merged_lists=None, cwenoz_cell_major=None):
+                   merged_lists=None, lists_cell_major=None):
         """Change the launch configuration; fields left None keep their current value."""
         cur = self.get_launch()
         new = dict(lanes_per_cell=lanes, block=block, list_blocks=list_blocks, linear_split=linear_split,
                    linear_lanes=linear_lanes, cwenoz_reuse=cwenoz_reuse, fused_residual=fused_residual,
                    xcd_remap=xcd_remap, muscl_lanes=muscl_lanes,
-                   merged_lists=merged_lists, cwenoz_cell_major=cwenoz_cell_major)
+                   merged_lists=merged_lists, lists_cell_major=lists_cell_major)
         cur.update({k: int(v) for k, v in new.items() if v is not None})
         self._check(self.lib.hfv_set_launch(self.h, C.byref(HfvLaunch(**cur))))
 

@@ -57,7 +57,7 @@ def test_c4_small_fp64_hybrid(hfv, small, split, lanes, reuse, mlanes, cwl, merg
     assert not near_threshold(om, w.U, np.arange(w.mesh.n_cells), 1e-12).any()
     ctx = hfv.Context(w.mesh, w.stencils, w.params, 64)
     ctx.set_launch(linear_split=split, linear_lanes=lanes, cwenoz_reuse=reuse, list_blocks=0 if reuse else 64,
-                   muscl_lanes=mlanes, lanes=cwl, merged_lists=merged, cwenoz_cell_major=cm)
+                   muscl_lanes=mlanes, lanes=cwl, merged_lists=merged, lists_cell_major=cm)
     fs = ctx.new_face_states()
     cls = torch.empty(w.mesh.n_cells, dtype=torch.uint8, device="cuda")
     R = ctx.residual(to_dev(w.U, torch.float64), face_states=fs, cell_class=cls)
@@ -82,7 +82,7 @@ def test_c4_small_fp64_forced_modes(hfv, small, mode):
     ctx = hfv.Context(w.mesh, w.stencils, p, 64)
     S = state_scale(w.U)
     for cm in (0, 1):       # CWENOZ's OI from the [entry][cell] table or its cell-major copy
-        ctx.set_launch(cwenoz_cell_major=cm)
+        ctx.set_launch(lists_cell_major=cm)
         fs = ctx.new_face_states()
         cls = torch.empty(w.mesh.n_cells, dtype=torch.uint8, device="cuda")
         R = ctx.residual(to_dev(w.U, torch.float64), face_states=fs, cell_class=cls)

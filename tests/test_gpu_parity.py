@@ -139,9 +139,9 @@ def test_c1_launch_shapes_agree(hfv, c1, lanes, split, lin_lanes, reuse, mlanes,
     assert (cls_o == 2).sum() > 0
     ctx = hfv.Context(w.mesh, w.stencils, w.params, 64)
     ctx.set_launch(lanes=lanes, block=128, list_blocks=0 if reuse else 3, linear_split=split, linear_lanes=lin_lanes,
-                   cwenoz_reuse=reuse, muscl_lanes=mlanes, merged_lists=merged, cwenoz_cell_major=cm)
+                   cwenoz_reuse=reuse, muscl_lanes=mlanes, merged_lists=merged, lists_cell_major=cm)
     assert ctx.get_launch()["cwenoz_reuse"] == reuse and ctx.get_launch()["merged_lists"] == merged
-    assert ctx.get_launch()["cwenoz_cell_major"] == cm
+    assert ctx.get_launch()["lists_cell_major"] == cm
     fs, cls = ctx.reconstruct(to_dev(w.U, torch.float64))
     torch.cuda.synchronize()
     assert ctx.query("COUNT_CWENOZ") == int((cls_o == 1).sum()) > 0
