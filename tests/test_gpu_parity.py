@@ -244,6 +244,22 @@ def test_rank_deficient_stencil_is_reported(hfv):
     assert "HFV_ERR_RANK" in str(ei.value) and "cell 5" in str(ei.value)
 
 
+def test_set_launch_rejects_invalid_fields(hfv, c1):
+    """An invalid launch field is refused with HFV_ERR_PARAM and leaves the
+    configuration as it was."""
+    w, _ = c1
+    ctx = hfv.Context(w.mesh, w.stencils, w.params, 64)
+    ctx.set_launch(lists_cell_major=1, merged_lists=1)
+    before = ctx.get_launch()
+    for bad in (dict(lists_cell_major=2), dict(lists_cell_major=-1), dict(merged_lists=2), dict(linear_lanes=3),
+                dict(lanes=3), dict(block=96), dict(list_blocks=-1), dict(linear_split=3), dict(cwenoz_reuse=2)):
+        with pytest.raises(hfv.HfvError) as ei:
+            ctx.set_launch(**bad)
+        assert "HFV_ERR_PARAM" in str(ei.value)
+        assert ctx.get_launch() == before
+    ctx.close()
+
+
 def test_autotune_keeps_results(hfv, c1):
     """The autotuner applies the fastest configuration it timed, and the
     results under it are still the oracle's."""
