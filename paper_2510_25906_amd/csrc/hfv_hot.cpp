@@ -329,19 +329,28 @@ __global__ __launch_bounds__(256) void k_linear_ks(HotArgs<T> a) {
   for (int j = 0; j < KPL; ++j)
 #pragma unroll
     for (int v = 0; v < NV; ++v) co[j][v] = (T)0;
-#pragma unroll 2
-  for (int m = 0; m < M; ++m) {
-    const int jc = a.t.sten[(long)m * N + cell];
-    T du[NV];
+  // members in pairs (M = 2K is even), their stencil ids loaded one pair
+  // ahead: a pair's averages are requested with its pseudo-inverse rows
+  int jn0 = a.t.sten[cell], jn1 = a.t.sten[(long)N + cell];
+#pragma unroll 1
+  for (int m = 0; m < M; m += 2) {
+    const int jp[2] = {jn0, jn1};
+    jn0 = a.t.sten[(long)min(m + 2, M - 2) * N + cell];
+    jn1 = a.t.sten[(long)min(m + 3, M - 1) * N + cell];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) du[v] = a.U[(long)v * N + jc] - u0[v];
+    for (int h = 0; h < 2; ++h) {
+      const int jc = jp[h];
+      T du[NV];
 #pragma unroll
-    for (int j = 0; j < KPL; ++j) {
-      const int k = q + j * G;
-      if (j * G + G <= K || k < K) {
-        const T p = a.t.P[((long)k * M + m) * N + cell];
+      for (int v = 0; v < NV; ++v) du[v] = a.U[(long)v * N + jc] - u0[v];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) co[j][v] += p * du[v];
+      for (int j = 0; j < KPL; ++j) {
+        const int k = q + j * G;
+        if (j * G + G <= K || k < K) {
+          const T p = a.t.P[((long)k * M + m + h) * N + cell];
+#pragma unroll
+          for (int v = 0; v < NV; ++v) co[j][v] += p * du[v];
+        }
       }
     }
   }
@@ -943,18 +952,30 @@ __global__ __launch_bounds__(256) void k_flux(int NF, int N, const T *fs, const 
   const T *pL = fs + (long)(code & 255) * NV * N + cL;
   const T *pR = fs + (long)((code >> 8) & 255) * NV * N + cR;
   T acc[NV] = {};
-  for (int g = gp_off[f], i = 0; g < gp_off[f + 1]; ++g, ++i) {
-    T qL[NV], qR[NV];
+  // Gauss points two at a time: both points' states are requested before the
+  // first solve (an odd count repeats its last point, which is loaded but not
+  // added); the sum keeps the point order
+  const int g0 = gp_off[f], ng = gp_off[f + 1] - g0;
+  for (int i = 0; i < ng; i += 2) {
+    const int i1 = min(i + 1, ng - 1);
+    T qL[2][NV], qR[2][NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      qL[v] = pL[((long)i * NV + v) * N];
-      qR[v] = pR[((long)i * NV + v) * N];
+      qL[0][v] = pL[((long)i * NV + v) * N];
+      qR[0][v] = pR[((long)i * NV + v) * N];
+      qL[1][v] = pL[((long)i1 * NV + v) * N];
+      qR[1][v] = pR[((long)i1 * NV + v) * N];
     }
+    const T w0 = gpw[g0 + i], w1 = gpw[g0 + i1];
     T F[NV];
-    riemann<DIM, T>(qL, qR, n, gamma, hllc, F);
-    const T w = gpw[g];
+    riemann<DIM, T>(qL[0], qR[0], n, gamma, hllc, F);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) acc[v] += w * F[v];
+    for (int v = 0; v < NV; ++v) acc[v] += w0 * F[v];
+    if (i + 1 < ng) {
+      riemann<DIM, T>(qL[1], qR[1], n, gamma, hllc, F);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) acc[v] += w1 * F[v];
+    }
   }
 #pragma unroll
   for (int v = 0; v < NV; ++v) Ff[(long)v * NF + f] = acc[v];
@@ -965,14 +986,27 @@ __global__ __launch_bounds__(256) void k_gather(int N, int NF, const int *cf_off
                                                 const T *ivol, T *R, int xcd) {
   const int c = (int)(block_id(xcd) * blockDim.x + threadIdx.x);
   if (c >= N) return;
-  T acc[NV] = {};
-  for (int e = cf_off[c]; e < cf_off[c + 1]; ++e) {
-    const int code = cf[e];
-    const int f = code & 0x7fffffff;
-    const T sg = (code < 0) ? (T)1 : (T)-1;
+  // every face of the cell (3 to nf_max, checked at create) requested at once:
+  // the codes, then the fluxes; entries past the count repeat the last face
+  // and are not added, and the sum keeps the face order
+  constexpr int FB = nf_max(NV - 2);
+  const int e0 = cf_off[c], ne = cf_off[c + 1] - e0;
+  int code[FB];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) acc[v] += sg * Ff[(long)v * NF + f];
-  }
+  for (int b = 0; b < FB; ++b) code[b] = cf[e0 + min(b, ne - 1)];
+  T fv[FB][NV];
+#pragma unroll
+  for (int b = 0; b < FB; ++b)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) fv[b][v] = Ff[(long)v * NF + (code[b] & 0x7fffffff)];
+  T acc[NV] = {};
+#pragma unroll
+  for (int b = 0; b < FB; ++b)
+    if (b < ne) {
+      const T sg = (code[b] < 0) ? (T)1 : (T)-1;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) acc[v] += sg * fv[b][v];
+    }
   const T iv = ivol[c];
 #pragma unroll
   for (int v = 0; v < NV; ++v) R[(long)v * N + c] = acc[v] * iv;

@@ -471,11 +471,28 @@ __global__ __launch_bounds__(256) void k_gather_vjp(int N, const int *inv_off, c
   T acc[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) acc[v] = S[(long)v * N + j];
-  for (int e = inv_off[j]; e < inv_off[j + 1]; ++e) {
-    const int code = inv_idx[e];
-    const int m = code / N, i = code - m * N;
+  // four entries at a time: their codes, then their contributions, requested
+  // at once (a short last batch repeats its last entry, which is not added);
+  // the sum keeps the entry order
+  constexpr int EB = 4;
+  const int e1 = inv_off[j + 1];
+  for (int e0 = inv_off[j]; e0 < e1; e0 += EB) {
+    int code[EB];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) acc[v] += C[((long)m * N + i) * NV + v];  // one cache line per entry
+    for (int b = 0; b < EB; ++b) code[b] = inv_idx[min(e0 + b, e1 - 1)];
+    T cv[EB][NV];
+#pragma unroll
+    for (int b = 0; b < EB; ++b) {
+      const int m = code[b] / N, i = code[b] - m * N;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) cv[b][v] = C[((long)m * N + i) * NV + v];  // one cache line per entry
+    }
+#pragma unroll
+    for (int b = 0; b < EB; ++b)
+      if (e0 + b < e1) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[v] += cv[b][v];
+      }
   }
 #pragma unroll
   for (int v = 0; v < NV; ++v) gU[(long)v * N + j] = acc[v];
