@@ -1,0 +1,138 @@
+"""Time-integrated supersonic viscous Taylor-Green vortex (Section 3.6, Eqs.
+tgveq1-tgveq5) on one GPU: the hybrid scheme against all-CWENOZ, both with
+the Navier-Stokes viscous fluxes at Re = 1600 and M_ref = 1.25, HLLC fluxes,
+CWENOZ central weight lambda_1' = 10^3 and the SSP(5,4) time loop, on a
+periodic n^3 hexahedral mesh of [0, 2 pi)^3.
+
+The paper integrates this flow to t = 20 on 128^3 cells at r = 5 (6th order)
+and reports its hybrid 2.5 times faster than CWENOZ on CPUs, the savings
+coming from the small share of cells that need CWENOZ before the dissipation
+peak (its Fig. TGVS_SPECTRA, right).  The library's 3D kernels stop at r = 4,
+so this study runs r = 3 or 4 on the meshes one GPU holds.
+
+Non-dimensionalisation (the viscous reading of the library: T = p / rho):
+mean density 1, velocity amplitude 1, length 1, so mu = 1 / Re at the
+reference temperature T_ref = 1 / (gamma M_ref^2), the initial temperature;
+Sutherland's constant is 110.4 / 273.15 of T_ref; Pr = 0.72.
+
+For every mode and precision it prints one JSON line: steps, device time,
+time per step, the time-averaged cell-class fractions, and sampled histories
+of the class fractions and of the normalised kinetic energy
+E_K(t) / E_K(0), E_K = (1 / |Omega|) int 1/2 rho u.u (the mesh is uniform,
+so the integral is the cell mean); then a summary line with the hybrid's
+speed-up over all-CWENOZ per precision.  A run whose solution stops being
+physical, or whose step size collapses, is reported with that status.
+
+    python -m paper_2510_25906_amd.tgv_study [--n 64] [--r 3] [--t-end 12] [--cfl 1.4] [--prec 64,32]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+from .inputs import configs
+from .inputs.params import HYBRID, ALL_CWENOZ, HLLC
+
+RE, MACH, GAMMA = 1600.0, 1.25, 1.4
+MODES = {"hybrid": HYBRID, "cwenoz": ALL_CWENOZ}
+
+
+def viscous_params(params):
+    """The study's parameters on top of a workload's (see the module text)."""
+    t_ref = 1.0 / (GAMMA * MACH ** 2)
+    return params.with_(viscous=1, mu0=1.0 / RE, T0=t_ref, sutherland_S=110.4 / 273.15 * t_ref, prandtl=0.72,
+                        riemann=HLLC, lambda1_prime=1e3, gamma=GAMMA)
+
+
+def kinetic_energy(U):
+    """(1 / |Omega|) int 1/2 rho |u|^2 on a uniform mesh: the cell mean."""
+    m = U[1:4]
+    return float((0.5 * (m * m).sum(0) / U[0]).mean().item())
+
+
+def run_mode(w, name, mode, t_end, cfl, prec, samples=48, tune=True):
+    import torch
+    from . import hfv
+    from .timestep import SSPRK54
+    params = viscous_params(w.params).with_(scheme_mode=mode)
+    ctx = hfv.Context(w.mesh, w.stencils, params, prec)
+    dt = torch.float64 if prec == 64 else torch.float32
+    U = torch.tensor(np.ascontiguousarray(w.U.T), dtype=dt, device="cuda")
+    if tune:
+        ctx.autotune(U.clone(), reps=3)
+    N = w.mesh.n_cells
+    rk = SSPRK54(ctx)
+    e0 = kinetic_energy(U.double())
+    acc = torch.zeros(4, dtype=torch.int64, device="cuda")
+    hist, ke = [], [(0.0, 1.0)]
+    every = max(t_end / samples, 1e-12)
+    nxt = [every]
+    sample_ms = [0.0]
+
+    def on_step(n, t):
+        acc.add_(torch.bincount(rk.cls.to(torch.int64), minlength=4))
+        if t >= nxt[0] * (1 - 1e-12) or t >= t_end * (1 - 1e-14):
+            # samples are read back to the host: timed apart and taken out of
+            # the integration's time
+            s0 = time.perf_counter()
+            fr = torch.bincount(rk.cls.to(torch.int64), minlength=4).cpu().numpy() / N
+            hist.append((round(t, 4), [round(float(x), 5) for x in fr]))
+            ke.append((round(t, 4), round(kinetic_energy(U.double()) / e0, 6)))
+            nxt[0] += every
+            sample_ms[0] += (time.perf_counter() - s0) * 1e3
+            print(f"[tgv] {name} fp{prec}: step {n}, t = {t:.3f}, classes {hist[-1][1]}, E_K {ke[-1][1]}",
+                  file=sys.stderr, flush=True)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    status = "ok"
+    try:
+        steps, t = rk.run_cfl(U, t_end, cfl, on_step=on_step)
+    except FloatingPointError as e:
+        steps, t, status = rk.steps, float("nan"), str(e)
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t0) * 1e3 - sample_ms[0]
+    ctx.close()
+    fr = acc.cpu().numpy() / max(steps, 1) / N
+    return dict(mode=name, prec=prec, status=status, steps=int(steps), t_end=t_end, cfl=cfl,
+                ms_total=round(wall_ms, 2), ms_per_step=round(wall_ms / max(steps, 1), 4),
+                class_fractions=dict(linear=round(float(fr[0]), 5), cwenoz=round(float(fr[1]), 5),
+                                     muscl=round(float(fr[2]), 5), first_order=round(float(fr[3]), 5)),
+                class_history=hist, kinetic_energy=ke)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--n", type=int, default=64)
+    ap.add_argument("--r", type=int, default=3)
+    ap.add_argument("--t-end", type=float, default=12.0)
+    ap.add_argument("--cfl", type=float, default=1.4)
+    ap.add_argument("--prec", default="64,32")
+    ap.add_argument("--modes", default="hybrid,cwenoz")
+    args = ap.parse_args(argv)
+    w = configs.tgv_hex(args.n, args.r, perturb=False)
+    from . import hfv
+    hfv.load()
+    out = {}
+    for prec in (int(p) for p in args.prec.split(",")):
+        for name in args.modes.split(","):
+            rec = run_mode(w, name, MODES[name], args.t_end, args.cfl, prec)
+            rec.update(n_cells=w.mesh.n_cells, order_r=args.r, re=RE, mach=MACH)
+            out[(name, prec)] = rec
+            print(json.dumps(rec), flush=True)
+    summ = {}
+    for prec in (32, 64):
+        h, c = out.get(("hybrid", prec)), out.get(("cwenoz", prec))
+        if h and c and h["status"] == "ok" and c["status"] == "ok":
+            summ[f"fp{prec}_cwenoz_time_over_hybrid"] = round(c["ms_total"] / h["ms_total"], 3)
+            summ[f"fp{prec}_cwenoz_ms_per_step_over_hybrid"] = round(c["ms_per_step"] / h["ms_per_step"], 3)
+    print(json.dumps({"summary": summ}), flush=True)
+    return out
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])

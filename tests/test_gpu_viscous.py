@@ -7,6 +7,8 @@ hexahedron box (3D).  FP64: classes bit-exact, residual within 1e-11 of the
 variable's largest |R|; FP32: residual within 1e-4 of it (the viscous flux
 differences gradients, about 1e-3 of the convective flux here, so its FP32
 rounding sits near 1e-7 / 1e-3 of its own scale)."""
+import json
+
 import numpy as np
 import pytest
 
@@ -96,3 +98,44 @@ def test_viscous_frozen_residual_and_refusals(hfv):
             call()
         assert "HFV_ERR_STATE" in str(ei.value)
     ctx.close()
+
+
+def test_viscous_tgv_time_loop_matches_oracle(hfv):
+    """The study's supersonic viscous Taylor-Green setting (Section 3.6: Re =
+    1600, M_ref = 1.25, periodic hexahedra) advanced two SSP(5,4) steps on the
+    GPU equals the oracle's time loop (FP64 states within 1e-12 of each
+    variable's largest value)."""
+    from oracle import timestep as otime
+    from paper_2510_25906_amd.timestep import SSPRK54, cfl_dt
+    from paper_2510_25906_amd.tgv_study import viscous_params
+    w = configs.tgv_hex(8, 2, perturb=False)
+    p = viscous_params(w.params)
+    ctx = hfv.Context(w.mesh, w.stencils, p, 64)
+    U = to_dev(w.U, torch.float64)
+    dt = cfl_dt(ctx, U, 1.4)
+    rk = SSPRK54(ctx)
+    for _ in range(2):
+        rk.step(U, dt)
+    torch.cuda.synchronize()
+    om = OracleModel(w.mesh, w.stencils, p)
+    U_o = otime.advance(om, w.U, dt, 2)
+    err = (np.abs(U.cpu().numpy().T - U_o) / np.abs(U_o).max(0)).max()
+    print(f"viscous TGV 8^3 r=2: dt {dt:.4g}, 2 steps, max relative state error {err:.2e}", flush=True)
+    assert err <= 1e-12
+    ctx.close()
+
+
+def test_tgv_study_runs(hfv, capsys):
+    """The time-integrated study on a tiny mesh: both modes in both precisions
+    finish, class fractions sum to one, and the kinetic energy decays."""
+    from paper_2510_25906_amd import tgv_study
+    out = tgv_study.main(["--n", "8", "--r", "2", "--t-end", "0.2", "--prec", "64,32"])
+    assert len(out) == 4
+    for rec in out.values():
+        assert rec["status"] == "ok" and rec["steps"] > 0
+        assert abs(sum(rec["class_fractions"].values()) - 1.0) < 1e-9
+        assert rec["kinetic_energy"][0] == (0.0, 1.0)
+        assert 0.9 < rec["kinetic_energy"][-1][1] < 1.0
+    summary = json.loads(capsys.readouterr().out.strip().splitlines()[-1])["summary"]
+    assert set(summary) == {f"fp{p}_{k}" for p in (32, 64) for k in ("cwenoz_time_over_hybrid",
+                                                                    "cwenoz_ms_per_step_over_hybrid")}
