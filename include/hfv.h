@@ -163,7 +163,11 @@ hfv_status hfv_create(const hfv_mesh *mesh, const hfv_stencils *st, const hfv_pa
 
 /* Change run-time parameters (scheme_mode, riemann, cweno_form, margins,
  * deactivation, CWENOZ and Harten constants).  order_r and precision must
- * equal the values given at create (HFV_ERR_PARAM otherwise). */
+ * equal the values given at create (HFV_ERR_PARAM otherwise).  In an FP64
+ * context, the first call that turns the viscous fluxes on in a context
+ * created without them allocates their gradient buffer (N x ngp_cell_max x
+ * dim x nvar doubles; HFV_ERR_OOM, nothing changed, if that fails); a
+ * context created with them has it from hfv_create. */
 hfv_status hfv_set_params(hfv_ctx *ctx, const hfv_params *p);
 
 /* Reconstruction (Section 2.5 flowchart): linear candidate and NAD on every

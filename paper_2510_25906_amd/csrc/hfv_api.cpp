@@ -174,6 +174,15 @@ static hfv_status validate(const hfv_mesh *m, const hfv_stencils *st, const hfv_
 
 extern "C" {
 
+// The viscous fluxes' gradient buffer of FP64 contexts ([N][NGPC][dim][nvar]):
+// allocated once, at create or when hfv_set_params first turns the viscous
+// fluxes on (FP32 contexts evaluate the gradients in the face kernel).
+static hfv_status viscous_buffer(hfv_ctx *ctx) {
+  if (ctx->vgrad || ctx->prec != 64) return HFV_OK;
+  const size_t ts = ctx->prec == 64 ? 8 : 4;
+  return dev_alloc(ctx, &ctx->vgrad, ts * (size_t)ctx->NGPC * ctx->dim * ctx->nvar * ctx->N);
+}
+
 hfv_status hfv_create(const hfv_mesh *mesh, const hfv_stencils *st, const hfv_params *p, void *stream,
                       hfv_ctx **out) {
   if (!out) return HFV_ERR_PARAM;
@@ -218,7 +227,8 @@ hfv_status hfv_create(const hfv_mesh *mesh, const hfv_stencils *st, const hfv_pa
         (e = dev_alloc(ctx, &ctx->coef, ts * ctx->K * ctx->nvar * (size_t)N)) == HFV_OK &&
         (e = dev_alloc(ctx, &ctx->fs_ws, ts * ctx->nvar * (size_t)ctx->NGPC * ctx->N)) == HFV_OK &&
         (e = dev_alloc(ctx, &ctx->fflux, ts * ctx->nvar * (size_t)ctx->NF)) == HFV_OK &&
-        (e = dev_alloc(ctx, (void **)&ctx->red, sizeof(double) * RED_BLOCKS)) == HFV_OK) {
+        (e = dev_alloc(ctx, (void **)&ctx->red, sizeof(double) * RED_BLOCKS)) == HFV_OK &&
+        (!ctx->p.viscous || (e = viscous_buffer(ctx)) == HFV_OK)) {
       if (hipMemsetAsync(ctx->counts, 0, sizeof(int) * 8, s) != hipSuccess ||
           hipStreamSynchronize(s) != hipSuccess) {
         ctx->err = "workspace initialisation failed";
@@ -244,6 +254,7 @@ hfv_status hfv_set_params(hfv_ctx *ctx, const hfv_params *p) {
   hfv_status e = check_params(p, ctx->err);
   if (e != HFV_OK) return e;
   const bool thr = p->kappa != ctx->p.kappa || p->n_exp != ctx->p.n_exp;
+  if (p->viscous && (e = viscous_buffer(ctx)) != HFV_OK) return e;   // before anything changes
   copy_params(ctx, p);
   if (thr) {
     e = refresh_thresholds(ctx, nullptr);

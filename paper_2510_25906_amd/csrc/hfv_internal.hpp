@@ -122,6 +122,7 @@ struct hfv_ctx {
   void *coef = nullptr;        // [K][nvar][N] central fits kept by the linear pass for CWENOZ
   void *fs_ws = nullptr;       // [NGPC][nvar][N] Gauss-point states, cell-major
   void *fflux = nullptr;       // [nvar][NF]
+  void *vgrad = nullptr;       // viscous: fit gradients at the Gauss-point slots [N][NGPC][dim][nvar]
   double *red = nullptr;       // [RED_BLOCKS] per-block partial results of reductions
   void *noalloc_scratch = nullptr;  // this device's static scratch array (hfv_residual_noalloc)
   void *vjp_C = nullptr;       // adjoint: per stencil slot contributions [M][N][nvar]

@@ -4,11 +4,20 @@
 //   k_keep_fits   the central least-squares fit of every cell, [K][NV][N],
 //                 for the modes without a linear pass (the linear pass keeps
 //                 it itself when the context is viscous)
-//   k_flux_visc   per face: at each Gauss point, both sides' gradients from
-//                 their kept fits, grad U = (1/h_c) sum_k a_k grad_xi phi_k,
-//                 averaged with the penalty (alpha / L_int) (U_R - U_L) n;
-//                 F_v . n at the mean state; w |S| F_v subtracted from the
-//                 face's integrated flux, before the gather.
+//   k_slot_grads  FP64: per Gauss-point slot of a cell (one lane each, a
+//                 cell's slots in neighbouring lanes, so they share its fit's
+//                 loads), the gradient of the cell's kept fit there, grad U =
+//                 (1/h_c) sum_k a_k grad_xi phi_k, stored cell-major
+//                 [N][NGPC][DIM][NV] (a face reads each side's DIM x NV
+//                 values from one line)
+//   k_flux_visc   per face: at each Gauss point, both sides' gradients (the
+//                 slot pass's in FP64, evaluated here in FP32) averaged with
+//                 the penalty (alpha / L_int) (U_R - U_L) n; F_v . n at the
+//                 mean state; w |S| F_v subtracted from the face's integrated
+//                 flux, before the gather.
+// (Evaluated in the face kernel, both sides at every point, the FP64
+// gradients held so many registers that 3D r = 4 spilled 1988 B per lane; the
+// slot pass holds one gradient at a time.)
 //
 // Temperature T = p / rho; viscosity by Sutherland's law; conduction
 // (mu / Pr) gamma / (gamma - 1) grad T.  Velocity and temperature gradients
@@ -146,11 +155,35 @@ __device__ inline void viscous_flux(const T (&qL)[DIM + 2], const T (&qR)[DIM + 
   F[NV - 1] = work + kc * cond;
 }
 
+// FP64 takes the slot pass (its face kernel with both gradients spilled:
+// 3D r = 4, 1988 B per lane); FP32 evaluates the gradients in the face kernel
+// (no spill there, and no gradient array to write and read back).
+template <typename T>
+constexpr bool visc_slots() { return sizeof(T) == 8; }
+
 template <int DIM, int R, typename T>
-__global__ __launch_bounds__(256) void k_flux_visc(int NF, int N, const T *fs, const T *coef, const T *gpxi,
-                                                   const int *gp_off, const int *fc, const int *fgb, const T *fn,
-                                                   const T *gpw, const T *hinv, const T *linv, ViscParams<T> vp,
-                                                   T *Ff, int xcd) {
+__global__ __launch_bounds__(256) void k_slot_grads(int N, int NGPC, const T *coef, const T *gpxi,
+                                                    const uint8_t *ngp, const T *hinv, T *vgrad) {
+  constexpr int NV = DIM + 2;
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)N * NGPC) return;
+  const int c = (int)(t / NGPC), g = (int)(t - (long)c * NGPC);
+  if (g >= ngp[c]) return;
+  T gr[DIM][NV];
+  fit_gradient<DIM, R, T>(coef, gpxi, N, c, g, hinv[c], gr);
+#pragma unroll
+  for (int j = 0; j < DIM; ++j)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) vgrad[(t * DIM + j) * NV + v] = gr[j][v];
+}
+
+// SLOTS: the gradients come from k_slot_grads; otherwise the face evaluates
+// both sides' fits at each of its points itself.
+template <int DIM, int R, typename T, bool SLOTS>
+__global__ __launch_bounds__(256) void k_flux_visc(int NF, int N, int NGPC, const T *fs, const T *vgrad,
+                                                   const T *coef, const T *gpxi, const T *hinv, const int *gp_off,
+                                                   const int *fc, const int *fgb, const T *fn, const T *gpw,
+                                                   const T *linv, ViscParams<T> vp, T *Ff, int xcd) {
   constexpr int NV = DIM + 2;
   const int f = (int)(block_id(xcd) * blockDim.x + threadIdx.x);
   if (f >= NF) return;
@@ -159,7 +192,7 @@ __global__ __launch_bounds__(256) void k_flux_visc(int NF, int N, const T *fs, c
   for (int j = 0; j < DIM; ++j) n[j] = fn[(long)j * NF + f];
   const int cL = fc[f], cR0 = fc[NF + f], cR = cR0 >= 0 ? cR0 : cL;
   const int code = fgb[f], sL = code & 255, sR = (code >> 8) & 255;
-  const T hL = hinv[cL], hR = hinv[cR], il = linv[f];
+  const T il = linv[f];
   T acc[NV] = {};
   for (int g = gp_off[f], i = 0; g < gp_off[f + 1]; ++g, ++i) {
     T qL[NV], qR[NV];
@@ -169,8 +202,18 @@ __global__ __launch_bounds__(256) void k_flux_visc(int NF, int N, const T *fs, c
       qR[v] = fs[((long)(sR + i) * NV + v) * N + cR];
     }
     T gL[DIM][NV], gR[DIM][NV];
-    fit_gradient<DIM, R, T>(coef, gpxi, N, cL, sL + i, hL, gL);
-    fit_gradient<DIM, R, T>(coef, gpxi, N, cR, sR + i, hR, gR);
+    if constexpr (SLOTS) {
+#pragma unroll
+      for (int j = 0; j < DIM; ++j)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          gL[j][v] = vgrad[(((long)cL * NGPC + sL + i) * DIM + j) * NV + v];
+          gR[j][v] = vgrad[(((long)cR * NGPC + sR + i) * DIM + j) * NV + v];
+        }
+    } else {
+      fit_gradient<DIM, R, T>(coef, gpxi, N, cL, sL + i, hinv[cL], gL);
+      fit_gradient<DIM, R, T>(coef, gpxi, N, cR, sR + i, hinv[cR], gR);
+    }
     T F[NV];
     viscous_flux<DIM, T>(qL, qR, gL, gR, n, il, vp, F);
     const T w = gpw[g];
@@ -185,9 +228,19 @@ template <int DIM, int R, typename T>
 static void launch_dr(hfv_ctx *ctx, Tables<T> &t, const void *fs, void *Ff, hipStream_t s) {
   const ViscParams<T> vp{(T)ctx->p.gamma, (T)ctx->p.mu0, (T)ctx->p.T0, (T)ctx->p.suth_S, (T)ctx->p.prandtl,
                          (T)ctx->p.visc_alpha};
-  k_flux_visc<DIM, R, T><<<(ctx->NF + 255) / 256, 256, 0, s>>>(
-      ctx->NF, ctx->N, (const T *)fs, (const T *)ctx->coef, t.gpxi, t.gp_off, t.face_cells, t.fgb, t.fnormal,
-      t.gpw, t.hinv, t.linv, vp, (T *)Ff, ctx->xcd_remap);
+  const unsigned gf = (ctx->NF + 255) / 256;
+  if constexpr (visc_slots<T>()) {
+    const long slots = (long)ctx->N * ctx->NGPC;
+    k_slot_grads<DIM, R, T><<<(unsigned)((slots + 255) / 256), 256, 0, s>>>(
+        ctx->N, ctx->NGPC, (const T *)ctx->coef, t.gpxi, t.ngp, t.hinv, (T *)ctx->vgrad);
+    k_flux_visc<DIM, R, T, true><<<gf, 256, 0, s>>>(
+        ctx->NF, ctx->N, ctx->NGPC, (const T *)fs, (const T *)ctx->vgrad, nullptr, nullptr, nullptr, t.gp_off,
+        t.face_cells, t.fgb, t.fnormal, t.gpw, t.linv, vp, (T *)Ff, ctx->xcd_remap);
+  } else {
+    k_flux_visc<DIM, R, T, false><<<gf, 256, 0, s>>>(
+        ctx->NF, ctx->N, ctx->NGPC, (const T *)fs, nullptr, (const T *)ctx->coef, t.gpxi, t.hinv, t.gp_off,
+        t.face_cells, t.fgb, t.fnormal, t.gpw, t.linv, vp, (T *)Ff, ctx->xcd_remap);
+  }
 }
 
 template <int DIM, int R, typename T>
@@ -245,6 +298,7 @@ static hfv_status keep_t(hfv_ctx *ctx, Tables<T> &t, const void *U, hipStream_t 
 }
 
 hfv_status run_viscous_flux(hfv_ctx *ctx, const void *fs, void *Ff, hipStream_t s) {
+  if (ctx->prec == 64 && !ctx->vgrad) return ctx->err = "viscous gradient buffer missing", HFV_ERR_STATE;
   return ctx->prec == 64 ? visc_t<double>(ctx, ctx->t64, fs, Ff, s) : visc_t<float>(ctx, ctx->t32, fs, Ff, s);
 }
 
