@@ -343,17 +343,25 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, workload):
+def launch_string(launch):
+    """A launch configuration as the profile records write it: k=v,... in field order."""
+    return ",".join(f"{k}={v}" for k, v in launch.items())
+
+
+def measured_traffic(kernel, workload, launch=None):
     """HBM bytes per launch from the committed rocprofv3 counter summary of
-    this kernel and workload, or None when absent or taken on other sources."""
+    this kernel and workload under this launch configuration (a record holds
+    one, or a list under "records"), or None when there is none, or it was
+    taken on other sources or another launch."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    if rec.get("source_hash") != source_hash():
-        return None
-    return rec.get("bytes_per_launch")
+    for r in rec.get("records", [rec]):
+        if r.get("source_hash") == source_hash() and (launch is None or r.get("launch") == launch_string(launch)):
+            return r.get("bytes_per_launch")
+    return None
 
 
 def cpu_baseline(w, cells_target=None, min_seconds=10.0):
@@ -577,7 +585,7 @@ def measure(w, wl_tag, head_prec, variants, args, torch, hfv, probe, flush, extr
                 ach = sbyts[dominant] / (avg * 1e-3) / 1e9
                 ach_m = mbyts[dominant] / (avg * 1e-3) / 1e9
                 kname = kernel_name(dominant, launch)
-                traffic = measured_traffic(kname, wl_tag)
+                traffic = measured_traffic(kname, wl_tag, launch)
                 roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
                         "traffic_over_bytes": round(traffic / sbyts[dominant], 3) if traffic else None,

@@ -85,3 +85,25 @@ def test_kernel_names_follow_the_launch():
     assert bench.kernel_name("linear", {"linear_split": 2}) == "k_linear_ks"
     assert bench.kernel_name("cwenoz", {"cwenoz_reuse": 1}) == "k_cwenoz"
     assert bench.kernel_name("flux", {"fused_residual": 1}) == "k_residual"
+
+
+def test_measured_traffic_matches_sources_and_launch(tmp_path, monkeypatch):
+    """A counter record counts only for the sources it was taken on and, when
+    a launch is given, for that launch; a file may hold several records."""
+    import json
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    (tmp_path / "profiles").mkdir()
+    la = dict(lanes_per_cell=4, block=256)
+    lb = dict(lanes_per_cell=2, block=128)
+    assert bench.launch_string(la) == "lanes_per_cell=4,block=256"
+    h = bench.source_hash()
+    recs = [dict(launch=bench.launch_string(la), source_hash=h, bytes_per_launch=100),
+            dict(launch=bench.launch_string(lb), source_hash="0" * 16, bytes_per_launch=200)]
+    (tmp_path / "profiles" / "traffic_k_x_w.json").write_text(json.dumps({"records": recs}))
+    assert bench.measured_traffic("k_x", "w", la) == 100
+    assert bench.measured_traffic("k_x", "w", lb) is None          # other sources
+    assert bench.measured_traffic("k_x", "w", dict(lanes_per_cell=1, block=64)) is None
+    assert bench.measured_traffic("k_x", "w") == 100               # any launch
+    assert bench.measured_traffic("k_y", "w", la) is None          # no record
+    (tmp_path / "profiles" / "traffic_k_z_w.json").write_text(json.dumps(recs[0]))   # a single record
+    assert bench.measured_traffic("k_z", "w", la) == 100
