@@ -348,18 +348,36 @@ def launch_string(launch):
     return ",".join(f"{k}={v}" for k, v in launch.items())
 
 
-def measured_traffic(kernel, workload, launch=None):
+def kernel_instance(slot, launch, dim, r, prec):
+    """The compiled kernel (template instance, as rocprofv3 names it) that a
+    hybrid-mode timing slot runs under this launch configuration; None for
+    slots whose instance is not modelled here."""
+    T = "double" if prec == 64 else "float"
+    tf = lambda b: "true" if b else "false"
+    if slot == "linear":
+        return f"{kernel_name(slot, launch)}<{dim}, {r}, {T}, {launch['linear_lanes']}, false>"
+    if slot == "cwenoz":
+        g = launch["lanes_per_cell"]
+        cm = launch.get("lists_cell_major", 0) and g != 1      # one lane per cell keeps the [entry][cell] reads
+        return (f"k_cwenoz<{dim}, {r}, {T}, {g}, {tf(launch['cwenoz_reuse'])}, "
+                f"{tf(launch.get('merged_lists', 0))}, {tf(cm)}>")
+    return None
+
+
+def measured_traffic(kernel, workload, instance=None):
     """HBM bytes per launch from the committed rocprofv3 counter summary of
-    this kernel and workload under this launch configuration (a record holds
-    one, or a list under "records"), or None when there is none, or it was
-    taken on other sources or another launch."""
+    this kernel and workload (a file holds one record, or a list under
+    "records", one per kernel instance), or None when there is none for this
+    instance, or it was taken on other sources.  The launch's grid shape is
+    not matched: it changes how the kernel is spread over the chip, not the
+    kernel."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
     for r in rec.get("records", [rec]):
-        if r.get("source_hash") == source_hash() and (launch is None or r.get("launch") == launch_string(launch)):
+        if r.get("source_hash") == source_hash() and (instance is None or r.get("kernel") == instance):
             return r.get("bytes_per_launch")
     return None
 
@@ -585,7 +603,8 @@ def measure(w, wl_tag, head_prec, variants, args, torch, hfv, probe, flush, extr
                 ach = sbyts[dominant] / (avg * 1e-3) / 1e9
                 ach_m = mbyts[dominant] / (avg * 1e-3) / 1e9
                 kname = kernel_name(dominant, launch)
-                traffic = measured_traffic(kname, wl_tag, launch)
+                traffic = measured_traffic(kname, wl_tag,
+                                           kernel_instance(dominant, launch, mesh.dim, w.params.order_r, prec))
                 roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
                         "traffic_over_bytes": round(traffic / sbyts[dominant], 3) if traffic else None,

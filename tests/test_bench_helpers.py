@@ -87,23 +87,35 @@ def test_kernel_names_follow_the_launch():
     assert bench.kernel_name("flux", {"fused_residual": 1}) == "k_residual"
 
 
-def test_measured_traffic_matches_sources_and_launch(tmp_path, monkeypatch):
+def test_measured_traffic_matches_sources_and_kernel_instance(tmp_path, monkeypatch):
     """A counter record counts only for the sources it was taken on and, when
-    a launch is given, for that launch; a file may hold several records."""
+    a kernel instance is given, for that instance; a file may hold several
+    records."""
     import json
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     (tmp_path / "profiles").mkdir()
-    la = dict(lanes_per_cell=4, block=256)
-    lb = dict(lanes_per_cell=2, block=128)
-    assert bench.launch_string(la) == "lanes_per_cell=4,block=256"
+    assert bench.launch_string(dict(lanes_per_cell=4, block=256)) == "lanes_per_cell=4,block=256"
     h = bench.source_hash()
-    recs = [dict(launch=bench.launch_string(la), source_hash=h, bytes_per_launch=100),
-            dict(launch=bench.launch_string(lb), source_hash="0" * 16, bytes_per_launch=200)]
+    recs = [dict(kernel="k_x<1>", source_hash=h, bytes_per_launch=100),
+            dict(kernel="k_x<2>", source_hash="0" * 16, bytes_per_launch=200)]
     (tmp_path / "profiles" / "traffic_k_x_w.json").write_text(json.dumps({"records": recs}))
-    assert bench.measured_traffic("k_x", "w", la) == 100
-    assert bench.measured_traffic("k_x", "w", lb) is None          # other sources
-    assert bench.measured_traffic("k_x", "w", dict(lanes_per_cell=1, block=64)) is None
-    assert bench.measured_traffic("k_x", "w") == 100               # any launch
-    assert bench.measured_traffic("k_y", "w", la) is None          # no record
+    assert bench.measured_traffic("k_x", "w", "k_x<1>") == 100
+    assert bench.measured_traffic("k_x", "w", "k_x<2>") is None          # other sources
+    assert bench.measured_traffic("k_x", "w", "k_x<3>") is None
+    assert bench.measured_traffic("k_x", "w") == 100                     # any instance
+    assert bench.measured_traffic("k_y", "w", "k_x<1>") is None          # no record
     (tmp_path / "profiles" / "traffic_k_z_w.json").write_text(json.dumps(recs[0]))   # a single record
-    assert bench.measured_traffic("k_z", "w", la) == 100
+    assert bench.measured_traffic("k_z", "w", "k_x<1>") == 100
+
+
+def test_kernel_instance_names_match_the_profiler():
+    """The instances the committed counter records were taken on, rebuilt from their launches."""
+    import json
+    import os
+    for f in ("traffic_k_cwenoz_mixed2d_85k_r3.json", "traffic_k_linear_mixed3d_1m_r3.json"):
+        rec = json.load(open(os.path.join(os.path.dirname(bench.__file__), "profiles", f)))
+        for r in rec.get("records", [rec]):
+            launch = {k: int(v) for k, v in (kv.split("=") for kv in r["launch"].split(","))}
+            slot = "cwenoz" if "cwenoz" in f else "linear"
+            dim, prec = (2, 64) if "2d" in r["workload"] else (3, 32)
+            assert bench.kernel_instance(slot, launch, dim, 3, prec) == r["kernel"]
