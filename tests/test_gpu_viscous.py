@@ -2,8 +2,9 @@
 HeatConduct, Stresses; Section 2.4, Eq. viscous_jump), GPU path through the
 C ABI against the FP64 oracle: periodic triangles with the density jump (2D,
 r = 2, 3: jumps exercise the penalty term), the mixed Riemann mesh
-(transmissive boundaries) and the mixed tetrahedron / pyramid / prism /
-hexahedron box (3D).  FP64: classes bit-exact, residual within 1e-11 of the
+(transmissive boundaries), the mixed tetrahedron / pyramid / prism /
+hexahedron box (3D, r = 3) and periodic hexahedra at r = 4 (the largest fits
+of the FP64 slot-gradient pass).  FP64: classes bit-exact, residual within 1e-11 of the
 variable's largest |R|; FP32: residual within 1e-4 of it (the viscous flux
 differences gradients, about 1e-3 of the convective flux here, so its FP32
 rounding sits near 1e-7 / 1e-3 of its own scale)."""
@@ -40,6 +41,7 @@ CASES = {
     "c1_r3": lambda: configs.c1_density_jump(16, 3),
     "c2_r3": lambda: configs.c2_riemann(32, 3),
     "c4_small": lambda: configs.c4_mixed("small"),
+    "tgv_r4": lambda: configs.tgv_hex(8, 4),
 }
 
 
