@@ -103,7 +103,9 @@ def test_c2_full_size_autotuned(hfv, c2_full, prec):
 # split over stencil members on two lanes, CWENOZ refitting, MUSCL on four
 # lanes; FP32 four lanes, the variable-split linear kernel on two lanes,
 # CWENOZ reusing the kept fit; the first two again with the MUSCL and
-# first-order lists merged into the CWENOZ launch.
+# first-order lists merged into the CWENOZ launch; the final kernels' choices:
+# FP64 four lanes with the kept fit or two lanes refitting, both with merged
+# lists and cell-major class-list tables, FP32 four lanes with the kept fit.
 HEADLINE_LAUNCHES = [
     (64, dict(lanes=2, linear_split=1, linear_lanes=2, cwenoz_reuse=0, muscl_lanes=4, block=256,
               list_blocks=4096)),
@@ -115,6 +117,12 @@ HEADLINE_LAUNCHES = [
               list_blocks=4096)),
     (32, dict(lanes=4, linear_split=0, linear_lanes=2, cwenoz_reuse=1, merged_lists=1, block=256,
               list_blocks=0)),
+    (64, dict(lanes=4, linear_split=1, linear_lanes=2, cwenoz_reuse=1, merged_lists=1, lists_cell_major=1,
+              block=256, list_blocks=0, xcd_remap=1)),
+    (64, dict(lanes=2, linear_split=1, linear_lanes=2, cwenoz_reuse=0, merged_lists=1, lists_cell_major=1,
+              block=256, list_blocks=1024, xcd_remap=1)),
+    (32, dict(lanes=4, linear_split=0, linear_lanes=2, cwenoz_reuse=1, merged_lists=1, lists_cell_major=0,
+              block=256, list_blocks=2048, xcd_remap=1)),
 ]
 
 
