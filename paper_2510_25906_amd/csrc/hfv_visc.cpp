@@ -34,20 +34,39 @@ struct ViscParams {
   T gamma, mu0, T0, S, prandtl, alpha;
 };
 
+// Large FP64 fits (K > 20) take one lane per (cell, variable): a lane then
+// holds K coefficients instead of K nvar (3D r = 4: one thread per cell held
+// 256 VGPRs, one wave per SIMD, 4.5 ms per pass on 64^3 cells); the same sums
+// per variable, so the same fits.  Elsewhere one thread per cell, which loads
+// each pseudo-inverse entry once for all variables, measured faster.
+template <int DIM, int R, typename T>
+constexpr bool keep_split() { return sizeof(T) == 8 && n_unknowns(DIM, R) > 20; }
+
 template <int DIM, int R, typename T>
 __global__ __launch_bounds__(256) void k_keep_fits(HotArgs<T> a) {
   constexpr int NV = DIM + 2, K = n_unknowns(DIM, R);
-  const int cell = (int)(block_id(a.xcd) * blockDim.x + threadIdx.x);
-  if (cell >= a.N) return;
-  T u0[NV];
+  if constexpr (keep_split<DIM, R, T>()) {
+    Lane<NV> L(a.xcd);
+    const int cell = L.item, v = L.sub;
+    if (!L.ok || cell >= a.N) return;
+    T u0[1] = {a.U[(long)v * a.N + cell]};
+    T co[K][1];
+    lsq_coeffs<DIM, R, 1, T>(a, cell, v, u0, co);
 #pragma unroll
-  for (int v = 0; v < NV; ++v) u0[v] = a.U[(long)v * a.N + cell];
-  T co[K][NV];
-  lsq_coeffs<DIM, R, NV, T>(a, cell, 0, u0, co);
+    for (int k = 0; k < K; ++k) a.coef[((long)k * NV + v) * a.N + cell] = co[k][0];
+  } else {
+    const int cell = (int)(block_id(a.xcd) * blockDim.x + threadIdx.x);
+    if (cell >= a.N) return;
+    T u0[NV];
 #pragma unroll
-  for (int k = 0; k < K; ++k)
+    for (int v = 0; v < NV; ++v) u0[v] = a.U[(long)v * a.N + cell];
+    T co[K][NV];
+    lsq_coeffs<DIM, R, NV, T>(a, cell, 0, u0, co);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) a.coef[((long)k * NV + v) * a.N + cell] = co[k][v];
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) a.coef[((long)k * NV + v) * a.N + cell] = co[k][v];
+  }
 }
 
 // Gradient of the conserved variables of cell c at its slot g from its kept
@@ -252,7 +271,9 @@ static void keep_dr(hfv_ctx *ctx, Tables<T> &t, const void *U, hipStream_t s) {
   a.coef = (T *)ctx->coef;
   a.t = t;
   a.xcd = ctx->xcd_remap;
-  k_keep_fits<DIM, R, T><<<(ctx->N + 255) / 256, 256, 0, s>>>(a);
+  constexpr int CPW = keep_split<DIM, R, T>() ? 64 / (DIM + 2) : 64;
+  const long waves = ((long)ctx->N + CPW - 1) / CPW;
+  k_keep_fits<DIM, R, T><<<(unsigned)((waves * 64 + 255) / 256), 256, 0, s>>>(a);
 }
 
 template <typename T>
